@@ -1,0 +1,429 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every test here checks the oracle against something other than itself: the
+paper's worked examples, closed forms, exact discrete identities, a direct
+steady solve, an independent formulation, or a textbook Fourier symbol.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import flowgen
+import oracle
+from oracle import DIAG, OFF12, OFF21
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- band split
+
+def _closed_rule(kmax, thresh):
+    """Independent formulation: level from min(|k1|,|k2|), part from max."""
+    L = len(thresh) + 1
+    edges = [-1] + list(thresh) + [10 ** 9]
+    span = 2 * kmax + 1
+    lev = np.full((span, span), -1, np.int8)
+    part = np.full((span, span), -1, np.int8)
+    for b in range(span):
+        for a in range(span):
+            k1, k2 = a - kmax, b - kmax
+            if k1 == 0 and k2 == 0:
+                continue
+            m, M = min(abs(k1), abs(k2)), max(abs(k1), abs(k2))
+            l = next(l for l in range(L) if edges[l] < m <= edges[l + 1])
+            lev[b, a] = l
+            if l == L - 1 or M <= edges[l + 1]:
+                part[b, a] = DIAG
+            elif abs(k1) <= edges[l + 1]:
+                part[b, a] = OFF12
+            else:
+                part[b, a] = OFF21
+    return lev, part
+
+
+@pytest.mark.parametrize("kmax,thresh", [(12, [2]), (20, [1, 4, 9]), (40, [3, 10, 25]), (64, [2, 8, 32])])
+def test_band_split_matches_min_max_rule(kmax, thresh):
+    lv, pt = oracle.band_split(kmax, thresh)
+    lv2, pt2 = _closed_rule(kmax, thresh)
+    assert np.array_equal(lv, lv2) and np.array_equal(pt, pt2)
+
+
+def test_band_split_worked_examples():
+    names = {"diag": DIAG, "off12": OFF12, "off21": OFF21}
+    lv, pt = oracle.band_split(60, [5])
+    n = 0
+    for line in open(os.path.join(GOLDEN, "band_split_examples.txt")):
+        line = line.split("#")[0].split()
+        if not line:
+            continue
+        k1, k2, level, part = int(line[0]), int(line[1]), int(line[2]), names[line[3]]
+        for s1 in (1, -1):
+            for s2 in (1, -1):
+                assert lv[s2 * k2 + 60, s1 * k1 + 60] == level
+                assert pt[s2 * k2 + 60, s1 * k1 + 60] == part
+        n += 1
+    assert n == 6
+
+
+def test_band_split_partitions_spectrum():
+    lv, pt = oracle.band_split(30, [3, 9])
+    assert (lv >= 0).sum() == 61 * 61 - 1
+    # the finest level only holds diagonal modes
+    assert np.all(pt[lv == 2] == DIAG)
+
+
+# ---------------------------------------------------------------- synthesis
+
+def test_synthesis_matches_analytic_cellular():
+    kmax = 16
+    ph = np.zeros((2 * kmax + 1,) * 2, complex)
+    flowgen.add_cellular(ph, kmax, 3, 3, 0.7, 0.4, 1.1)
+    flowgen.add_cellular(ph, kmax, 16, 16, 0.2, 2.0, 0.3)
+    flowgen.add_cos_x(ph, kmax, 5, 0.3)
+    N, n, I0, J0 = 96, 24, 17, 70
+    mask = np.ones_like(ph.real, np.int8)
+    psi = oracle.synth_patch(ph, kmax, mask, N, I0, J0, n)
+    i = np.arange(n)
+    X, Y = np.meshgrid(2 * np.pi * (I0 + i) / N, 2 * np.pi * (J0 + i) / N, indexing="xy")
+    exact = (0.7 * np.sin(3 * X + 0.4) * np.sin(3 * Y + 1.1)
+             + 0.2 * np.sin(16 * X + 2.0) * np.sin(16 * Y + 0.3) + 0.3 * np.cos(5 * X))
+    assert np.max(np.abs(psi - exact)) < 1e-13
+
+
+def test_random_spectrum_fast_matches_loop():
+    a = flowgen.random_power_spectrum(7, 12, -7.0 / 3.0)
+    b = flowgen.random_power_spectrum_fast(7, 12, -7.0 / 3.0)
+    assert np.allclose(a, b, rtol=0, atol=1e-15 * np.abs(a).max())   # libm vs numpy last bits
+    assert np.array_equal(b, np.conj(b[::-1, ::-1]))   # Hermitian -> real psi
+    assert b[12, 12] == 0
+
+
+# ---------------------------------------------------------------- velocity
+
+def test_discrete_divergence_and_forcing_vanish():
+    p = flowgen.config_continuous(seed=3, radius=20, kappa=1e-2, n=32, lattice=2, levels=2)
+    lv, pt = oracle.band_split(p.kmax, p.thresh)
+    mask = (lv >= 0).astype(np.int8)
+    psi = oracle.synth_patch(p.psi_hat, p.kmax, mask, 64, 5, 9, 32)
+    h = 2 * np.pi / 64
+    vx, vy, f1, f2 = oracle.staggered(psi, h)
+    vmax = max(np.abs(vx).max(), np.abs(vy).max())
+    assert np.abs(oracle.divergence(vx, vy, h)).max() <= 1e-13 * vmax / h
+    assert abs(f1.sum()) <= 1e-12 * np.abs(f1).sum() and abs(f2.sum()) <= 1e-12 * np.abs(f2).sum()
+
+
+def test_operator_second_order_consistency():
+    """div(v u + K grad u) on a smooth field converges to v.grad u + K:grad grad u
+    at second order (pins the advection sign, v = (-d2 psi, d1 psi), and the
+    cross-derivative term)."""
+    K = np.array([0.3, 0.11, 0.2])
+    errs = []
+    for n in (32, 64):
+        h = 2 * np.pi / n
+        xn = np.arange(n) * h                      # nodes
+        xc = (np.arange(n) + 0.5) * h              # centres
+        Xn, Yn = np.meshgrid(xn, xn, indexing="xy")
+        psi = np.sin(Xn + 0.2) * np.cos(2 * Yn) + 0.5 * np.cos(Xn - Yn)
+        vx, vy, _, _ = oracle.staggered(psi, h)
+        X, Y = np.meshgrid(xc, xc, indexing="xy")
+        u = np.sin(X + 0.3) * np.cos(2 * Y) + 0.2 * np.sin(2 * X - Y)
+        ux = np.cos(X + 0.3) * np.cos(2 * Y) + 0.4 * np.cos(2 * X - Y)
+        uy = -2 * np.sin(X + 0.3) * np.sin(2 * Y) - 0.2 * np.cos(2 * X - Y)
+        uxx = -np.sin(X + 0.3) * np.cos(2 * Y) - 0.8 * np.sin(2 * X - Y)
+        uyy = -4 * np.sin(X + 0.3) * np.cos(2 * Y) - 0.2 * np.sin(2 * X - Y)
+        uxy = -2 * np.cos(X + 0.3) * np.sin(2 * Y) + 0.4 * np.sin(2 * X - Y)
+        psx = np.cos(X + 0.2) * np.cos(2 * Y) - 0.5 * np.sin(X - Y)
+        psy = -2 * np.sin(X + 0.2) * np.sin(2 * Y) + 0.5 * np.sin(X - Y)
+        exact = (-psy) * ux + psx * uy + K[0] * uxx + 2 * K[1] * uxy + K[2] * uyy
+        got = oracle.operator(vx, vy, K, None, u, h)
+        errs.append(np.abs(got - exact).max())
+    rate = math.log2(errs[0] / errs[1])
+    assert errs[1] < 2e-2 and 1.8 < rate < 2.3, (errs, rate)
+
+
+# ---------------------------------------------------------------- local solve
+
+def _shear_patch(n, amp, k, kappa_b, delta=1e-10):
+    """psi = amp cos(k x) on one whole-domain patch; returns the oracle's K and the
+    discrete closed form K22_b + mean((psi - mean psi)^2)/K11_b."""
+    h = 2 * np.pi / n
+    x = np.arange(n) * h
+    psi = np.tile(amp * np.cos(k * x), (n, 1))
+    vx, vy, f1, f2 = oracle.staggered(psi, h)
+    Kb = np.asarray(kappa_b, float)
+    Vb = 2 * abs(0.5 * amp) * k
+    dt, ns = oracle.plan_steps(n, h, Kb, Vb, 0.5, delta)
+    w = oracle.local_solve_batch([n], [h], vx.ravel(), vy.ravel(), f1.ravel(), f2.ravel(),
+                                 Kb[None, :], [dt], [ns])
+    K = oracle.estimate(f1, f2, w[0].reshape(n, n), w[1].reshape(n, n), Kb)
+    pt = psi[0] - psi[0].mean()
+    return K, Kb[2] + np.mean(pt * pt) / Kb[0], (vx, vy, f1, f2, w, h, Kb)
+
+
+@pytest.mark.parametrize("Kb", [[0.1, 0.0, 0.1], [0.07, 0.02, 0.13]])
+def test_local_solve_discrete_taylor_identity(Kb):
+    """eq:shearhomoX holds exactly for the staggered scheme:
+    K22 = K22_b + mean(psi~^2)/K11_b, K11 and K12 unchanged."""
+    K, K22, _ = _shear_patch(32, 0.4, 3, Kb)
+    assert abs(K[2] - K22) <= 1e-9 * K22
+    assert abs(K[0] - Kb[0]) <= 1e-12 and abs(K[1] - Kb[1]) <= 1e-12
+
+
+def test_taylor_dispersion_north_star_value():
+    """v = (0, sin 16 x), kappa = 1e-2: K_yy = kappa + V^2/(2 kappa k^2) = 0.2053125.
+    On a 64-cell grid the node samples of cos^2 average to exactly 1/2."""
+    K, K22, _ = _shear_patch(64, -1.0 / 16, 16, [1e-2, 0.0, 1e-2])
+    assert abs(K22 - 0.2053125) < 1e-15
+    assert abs(K[2] - 0.2053125) <= 1e-9 * 0.2053125
+    # and through the closed-form path (off-diagonal component of a 2-level split)
+    p = flowgen.config_shear(k=16, V=1.0, kappa=1e-2, n=32, levels=2, thresh=[8])
+    r = oracle.run_hierarchy(p)
+    assert abs(r.K_total()[0][2] - 0.2053125) <= 1e-14
+    assert abs(r.K_total()[0][0] - 0.01) <= 1e-16
+
+
+def test_proposition1_orthogonal_shears_iterate():
+    """Prop. 1: K[psi1 + psi2, kappa] = K[psi1, K[psi2, kappa]] for L2-orthogonal
+    same-direction shears (exact for the discrete scheme too)."""
+    n = 32
+    h = 2 * np.pi / n
+    x = np.arange(n) * h
+    p1 = np.tile(0.3 * np.cos(2 * x), (n, 1))
+    p2 = np.tile(0.2 * np.sin(5 * x), (n, 1))
+
+    def solve(psi, Kb, Vb):
+        vx, vy, f1, f2 = oracle.staggered(psi, h)
+        dt, ns = oracle.plan_steps(n, h, Kb, Vb, 0.5, 1e-11)
+        w = oracle.local_solve_batch([n], [h], vx.ravel(), vy.ravel(), f1.ravel(), f2.ravel(),
+                                     np.asarray(Kb)[None, :], [dt], [ns])
+        return oracle.estimate(f1, f2, w[0].reshape(n, n), w[1].reshape(n, n), Kb)
+
+    kap = np.array([0.1, 0.0, 0.1])
+    direct = solve(p1 + p2, kap, 0.3 * 2 + 0.2 * 5)
+    inner = solve(p2, kap, 0.2 * 5)
+    iterated = solve(p1, inner, 0.3 * 2)
+    assert np.allclose(direct, iterated, rtol=1e-9, atol=1e-12)
+
+
+def _generic_patch(n, seed=1, amp=0.6):
+    p = flowgen.config_continuous(seed=seed, radius=3, p=-1.0, kappa=0.1, n=n, lattice=1, levels=1)
+    lv, pt = oracle.band_split(p.kmax, p.thresh)
+    psi = oracle.synth_patch(amp * p.psi_hat, p.kmax, (lv >= 0).astype(np.int8), n, 0, 0, n)
+    h = 2 * np.pi / n
+    return psi, h, amp * oracle.band_speed_bound(p.psi_hat, p.kmax, (lv >= 0).astype(np.int8))
+
+
+def _rk4_K(psi, h, Kb, Vb, delta):
+    n = psi.shape[0]
+    vx, vy, f1, f2 = oracle.staggered(psi, h)
+    dt, ns = oracle.plan_steps(n, h, Kb, Vb, 0.5, delta)
+    w = oracle.local_solve_batch([n], [h], vx.ravel(), vy.ravel(), f1.ravel(), f2.ravel(),
+                                 np.asarray(Kb)[None, :], [dt], [ns])
+    return (vx, vy, f1, f2), w.reshape(2, n, n)
+
+
+def test_time_integration_reaches_dense_steady_cell_problem():
+    """RK4 to the quasi-stationary state matches a direct (dense LU) solve of the
+    discrete cell problem eq:cell."""
+    psi, h, Vb = _generic_patch(8)
+    Kb = np.array([0.12, 0.03, 0.09])
+    (vx, vy, f1, f2), w = _rk4_K(psi, h, Kb, Vb, 1e-12)
+    K_rk = oracle.estimate(f1, f2, w[0], w[1], Kb)
+    K_lu = oracle.cell_problem_dense(vx, vy, f1, f2, Kb, h)
+    assert np.allclose(K_rk, K_lu, rtol=1e-10, atol=1e-13)
+    assert np.min(np.linalg.eigvalsh([[K_rk[0] - Kb[0], K_rk[1] - Kb[1]],
+                                      [K_rk[1] - Kb[1], K_rk[2] - Kb[2]]])) > -1e-14
+
+
+def test_energy_form_equals_flux_form_and_mass_conserved():
+    psi, h, Vb = _generic_patch(16)
+    Kb = np.array([0.1, -0.02, 0.15])
+    (vx, vy, f1, f2), w = _rk4_K(psi, h, Kb, Vb, 1e-11)
+    Kf = oracle.estimate(f1, f2, w[0], w[1], Kb)
+    Ke = oracle.estimate_energy(w[0], w[1], Kb, h)
+    assert np.allclose(Kf, Ke, rtol=1e-9, atol=1e-12)
+    for j in range(2):
+        assert abs(w[j].sum()) <= 1e-13 * np.abs(w[j]).sum()
+
+
+def test_reversed_flow_and_transpose_symmetries():
+    psi, h, Vb = _generic_patch(16, seed=4)
+    Kb = np.array([0.1, 0.0, 0.1])
+    f = lambda ps: oracle.estimate(*_rk4_K(ps, h, Kb, Vb, 1e-9)[0][2:], *_rk4_K(ps, h, Kb, Vb, 1e-9)[1], Kb)
+    K = f(psi)
+    Kneg = f(-psi)
+    Kt = f(np.ascontiguousarray(psi.T))
+    assert np.allclose(K, Kneg, rtol=1e-12, atol=1e-15)
+    assert np.allclose([K[2], K[1], K[0]], Kt, rtol=1e-11, atol=1e-14)
+
+
+def test_small_peclet_cellular_asymptotics():
+    """For psi = A sin x sin y and Pe = A/kappa -> 0, K/kappa -> 1 + Pe^2/8
+    (perturbation solution of eq:cell); asymptotic pin only."""
+    n = 32
+    h = 2 * np.pi / n
+    x = np.arange(n) * h
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    A, kap = 0.05, 1.0
+    psi = A * np.sin(X) * np.sin(Y)
+    Kb = np.array([kap, 0.0, kap])
+    (vx, vy, f1, f2), w = _rk4_K(psi, h, Kb, 2 * A, 1e-10)
+    K = oracle.estimate(f1, f2, w[0], w[1], Kb)
+    enh = K[0] / kap - 1
+    assert abs(enh - A * A / 8) <= 0.02 * A * A / 8
+    assert abs(K[0] - K[2]) < 1e-14
+
+
+# ---------------------------------------------------------------- closed forms
+
+def test_line_energies_are_line_means_of_band_squared():
+    """Parseval line energies equal the brute-force mean of psi_12^2 along x2."""
+    p = flowgen.config_continuous(seed=5, radius=24, kappa=1e-2, n=16, lattice=1, levels=2)
+    p.thresh = [4]
+    lv, pt = oracle.band_split(p.kmax, p.thresh)
+    m12 = oracle.band_mask(lv, pt, 0, OFF12)
+    m21 = oracle.band_mask(lv, pt, 0, OFF21)
+    N, I0, n = 64, 7, 6
+    s = oracle.line_energies(p.psi_hat, p.kmax, m12, N, I0, n, 0)
+    t = oracle.line_energies(p.psi_hat, p.kmax, m21, N, I0, n, 1)
+    G = 2 * N  # the lines sit at half-integer indices of the level grid: use the doubled grid
+    J = np.arange(G)
+    for i in range(n):
+        I = np.full(G, 2 * (I0 + i) + 1)
+        vals = oracle.synth_points(p.psi_hat, p.kmax, m12, G, I, J)
+        assert abs(np.mean(vals ** 2) - s[i]) <= 1e-12 * s[i]
+        vals = oracle.synth_points(p.psi_hat, p.kmax, m21, G, J, I)
+        assert abs(np.mean(vals ** 2) - t[i]) <= 1e-12 * t[i]
+
+
+def test_offdiag_closed_form_equals_local_solve_for_pure_shear():
+    """Algorithm 1 on a pure x2-shear (no x1 dependence) is eq:shearhomoY, which the
+    time-integrated local solve reproduces exactly on the grid."""
+    n = 32
+    amp, k = 0.25, 3
+    h = 2 * np.pi / n
+    y = np.arange(n) * h
+    psi = np.tile((amp * np.cos(k * y))[:, None], (1, n))
+    Kb = np.array([0.08, 0.01, 0.12])
+    (vx, vy, f1, f2), w = _rk4_K(psi, h, Kb, amp * k, 1e-11)
+    K_ls = oracle.estimate(f1, f2, w[0], w[1], Kb)
+    s = np.full(n, np.mean((psi[:, 0] - psi[:, 0].mean()) ** 2))
+    K_cf = oracle.offdiag_closed_form(Kb, s, 0)
+    assert np.allclose(K_ls, K_cf, rtol=1e-9, atol=1e-13)
+
+
+def test_offdiag_layered_harmonic_mean_matches_resolved_solve():
+    """A slowly modulated fine shear psi = A cos(x) cos(q y), q >> 1, behaves as a
+    layered medium: the resolved local solve approaches the harmonic mean of the
+    line-wise shear formula (Algorithm 1).  Scale-separation check (1%)."""
+    n, q = 64, 16
+    h = 2 * np.pi / n
+    x = np.arange(n) * h
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    A = 0.05
+    psi = A * (1.0 + 0.5 * np.cos(X)) * np.cos(q * Y)
+    Kb = np.array([0.05, 0.0, 0.05])
+    (vx, vy, f1, f2), w = _rk4_K(psi, h, Kb, A * 1.5 * (q + 1), 1e-7)
+    K_ls = oracle.estimate(f1, f2, w[0], w[1], Kb)
+    xc = (np.arange(n) + 0.5) * h
+    s = (A * (1.0 + 0.5 * np.cos(xc))) ** 2 / 2
+    K_cf = oracle.offdiag_closed_form(Kb, s, 0)
+    assert abs(K_ls[0] - K_cf[0]) <= 0.01 * K_cf[0]
+
+
+def test_empty_bands_reduce_chain_to_single_level():
+    """A two-level hierarchy whose second level is empty reproduces the one-level
+    direct solve (no off-diagonals -> K_off = K_in, empty LS -> K_b)."""
+    base = flowgen.config_continuous(seed=2, radius=3, p=-1.0, kappa=0.1, n=16, lattice=1, levels=1)
+    base.psi_hat *= 0.5
+    base.delta = 1e-8
+    r1 = oracle.run_hierarchy(base)
+    two = flowgen.Problem(kappa=0.1, kmax=3, psi_hat=base.psi_hat, thresh=[5], n_cells=[16, 16],
+                          n_global=[16, 64], lattice=[1, 1], delta=1e-8)
+    r2 = oracle.run_hierarchy(two)
+    assert np.allclose(r2.K_off[0], [0.1, 0.0, 0.1], rtol=0, atol=1e-16)
+    assert np.array_equal(r2.K_solve[1], r2.K_base[1])
+    assert np.allclose(r1.K_total(), r2.K_total(), rtol=1e-14, atol=1e-16)
+
+
+def test_algorithm3_two_level_hand_case():
+    """Algorithm 3 with hand-computable pieces: a fine-level pure shear in x2
+    (psi_22 along y only would be off-diagonal, so use an x-shear on level 2 that
+    the local solve turns into eq:shearhomoX exactly) and an off-diagonal x2-shear
+    on level 1.  Every intermediate has a closed form."""
+    kap = 0.1
+    kmax = 12
+    ph = np.zeros((2 * kmax + 1,) * 2, complex)
+    flowgen.add_cos_y(ph, kmax, 6, 0.2)            # (0, 6): level 0, off12 for a_1 = 3
+    flowgen.add_cellular(ph, kmax, 8, 8, 0.16)     # (8, 8): level 1 diag
+    p = flowgen.Problem(kappa=kap, kmax=kmax, psi_hat=ph, thresh=[3], n_cells=[16, 16],
+                        n_global=[16, 32], lattice=[1, 1], delta=1e-11)
+    r = oracle.run_hierarchy(p)
+    # Algorithm 2: off12 shear amplitude 0.2 -> line energy 0.02 on every line
+    Koff = np.array([kap + 0.02 / kap, 0.0, kap])
+    assert np.allclose(r.K_off[0], Koff, rtol=1e-13)
+    assert np.allclose(r.K_base[1], Koff, rtol=1e-13)          # K_in of the fine level
+    Kstar = r.R[1]
+    Knet = Kstar - Koff + np.array([kap, 0, kap])
+    assert np.allclose(r.K_base[0], Knet, rtol=1e-13)
+    # level 0 has an empty diagonal band: LS = K_net, so
+    # R = K_net + S12(K_net) + S21(K_net) - 2 K_net = S12(K_net) with S21 = K_net
+    expect = np.array([Knet[0] + 0.02 / Knet[2], Knet[1], Knet[2]])
+    assert np.allclose(r.K_total()[0], expect, rtol=1e-13)
+
+
+# ---------------------------------------------------------------- macro
+
+def test_macro_rk4_matches_fourier_closed_form():
+    """v = 0, constant K: each Fourier mode is multiplied by R(dt mu_k)^nsteps,
+    R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24 (classic RK4), mu_k the symbol of the
+    9-point operator K11 dxx + K22 dyy + 2 K12 dxdy."""
+    N = 32
+    h = 2 * np.pi / N
+    rng = np.random.default_rng(0)
+    u0 = rng.standard_normal((N, N))
+    K = np.array([0.3, 0.12, 0.2])
+    dt, ns = oracle.macro_plan(N, K, 0.0, 0.2, 0.4)
+    u = oracle.macro_run(N, None, None, K, u0, dt, ns)
+    th = 2 * np.pi * np.fft.fftfreq(N)
+    TX, TY = np.meshgrid(th, th, indexing="xy")
+    mu = -(K[0] * 4 * np.sin(TX / 2) ** 2 + K[2] * 4 * np.sin(TY / 2) ** 2
+           + 2 * K[1] * np.sin(TX) * np.sin(TY)) / h ** 2
+    z = dt * mu
+    R = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    exact = np.real(np.fft.ifft2(np.fft.fft2(u0) * R ** ns))
+    assert np.max(np.abs(u - exact)) <= 1e-12 * np.max(np.abs(u0))
+
+
+def test_macro_conserves_mass_with_advection_and_field():
+    N = 24
+    h = 2 * np.pi / N
+    x = np.arange(N) * h
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    vx, vy, _, _ = oracle.staggered(np.sin(X) * np.sin(Y), h)
+    Kc = np.stack([0.1 + 0.05 * np.cos(X), 0.01 * np.sin(Y), 0.2 + 0.0 * X], -1)
+    u0 = flowgen.macro_initial_gaussian(N)
+    dt, ns = oracle.macro_plan(N, Kc, 2.0, 0.2, 0.3)
+    u = oracle.macro_run(N, vx, vy, Kc, u0, dt, ns)
+    assert abs(u.sum() - u0.sum()) <= 1e-13 * abs(u0.sum())
+
+
+# ---------------------------------------------------------------- bookkeeping
+
+def test_domain_table_geometry():
+    p = flowgen.config_four_level_cellular(n=32, lattice=4)
+    doms = oracle.domain_table(p)
+    assert len(doms) == 4 * 16
+    for d in doms:
+        # the centre 2 pi (c + 1/2)/M is the patch middle: I0 + n/2 == N (c + 1/2)/M mod N
+        assert (2 * (d.I0 + d.n // 2) * 4) % (2 * d.N) == (d.N * (2 * d.cx + 1)) % (2 * d.N)
+        if d.level > 0:
+            par = doms[d.parent]
+            assert par.level == d.level - 1 and (par.cx, par.cy) == (d.cx, d.cy)
+    assert doms[-1].offset + doms[-1].n ** 2 == sum(d.n ** 2 for d in doms)
+    with pytest.raises(oracle.BookkeepingError):
+        bad = flowgen.config_four_level_cellular(n=32, lattice=4)
+        bad.lattice = [3, 4, 4, 4]
+        oracle.domain_table(bad)
