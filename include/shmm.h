@@ -1,0 +1,230 @@
+/*
+ * shmm.h -- C ABI of the MI355X (gfx950) implementation of the hot path of the
+ * seamless heterogeneous multiscale method (SHMM) of Lee & Engquist,
+ * "Multiscale numerical methods for passive advection-diffusion in
+ * incompressible turbulent flow fields" (arXiv:1510.00451).
+ *
+ * Model problem (eq:model): u_t = v.grad u + kappa Lap u, div v = 0, with
+ * v = (-d psi/dx2, d psi/dx1) from a stream function psi (Section 2.1), on the
+ * periodic square [0, 2 pi]^2.  At every level of the resolution hierarchy
+ * (Section 3, Figure 1) the library
+ *   1. Fourier band-filters psi (Section 3.1) into the level's diagonal band,
+ *      synthesised at the nodes of every local patch, and its two
+ *      off-diagonal bands, reduced to line energies;
+ *   2. time-integrates the two periodic corrector problems of every patch
+ *      (HMM steps 1-2 of Section 2.2, numerical homogenization K[psi, K; D])
+ *      with the finer level's effective diffusivity as base;
+ *   3. reduces them to the 2x2 effective diffusivity (the K formula after
+ *      eq:homo) and combines levels by Algorithms 1-3.
+ * A macro solver (HMM step 4, eq:homo) and a learned surrogate complete it.
+ *
+ * Conventions shared by every entry point
+ *   - All functions return int status: SHMM_OK (0) or a negative SHMM_E*.
+ *     On an error the outputs are unspecified and no kernel is left running.
+ *     Numerical trouble of single domains is not a call error: it is recorded
+ *     in a per-domain int32 status word (SHMM_DOM_* bits).
+ *   - Pointers named d_* are device pointers (hipMalloc'd or torch tensors on
+ *     the current device); every other pointer is host memory.  All arrays are
+ *     caller-owned, contiguous, row-major with x fastest.  The library owns
+ *     only what lives inside shmm_ctx (uploaded spectra, descriptor tables,
+ *     FFT and reduction workspaces).
+ *   - stream is a hipStream_t (NULL = the default stream).  Device entry points
+ *     only enqueue work; they do not synchronise unless stated.
+ *   - Symmetric 2x2 tensors are stored as three doubles {K11, K12, K22}.
+ *   - Packed per-domain fields: domain d owns cells [offset_d, offset_d + n_d^2)
+ *     of every packed array, laid out [y][x].  The corrector array w holds the
+ *     two correctors back to back: w[0 .. cells) for e_1, w[cells .. 2 cells)
+ *     for e_2, where cells = n_cells_total.
+ *   - Grid points of a patch: nodes (x0 + i h, y0 + j h); x-faces
+ *     (x0 + i h, y0 + (j + 1/2) h); y-faces (x0 + (i + 1/2) h, y0 + j h); cell
+ *     centres (x0 + (i + 1/2) h, y0 + (j + 1/2) h); all indices modulo n.
+ */
+#ifndef SHMM_H
+#define SHMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SHMM_OK = 0,
+    SHMM_EINVAL = -1,   /* malformed argument (kappa <= 0, n not a power of two, ...) */
+    SHMM_ERANGE = -2,   /* a band above the patch Nyquist, or a size beyond a limit */
+    SHMM_ENOTSPD = -3,  /* a base diffusivity that is not symmetric positive definite */
+    SHMM_EDEVICE = -4,  /* a HIP runtime error */
+    SHMM_ENOMEM = -5    /* a device allocation failed */
+};
+
+enum {                          /* per-domain status bits */
+    SHMM_DOM_NONFINITE = 1,     /* a corrector or a moment is NaN/Inf */
+    SHMM_DOM_NOT_SPD = 2,       /* K_net was not SPD; eigenvalues were clamped */
+    SHMM_DOM_DT_LIMIT = 4,      /* requested step above the stability bound */
+    SHMM_DOM_FALLBACK = 8       /* surrogate flagged the patch: plain solve used */
+};
+
+enum { SHMM_DIAG = 0, SHMM_OFF12 = 1, SHMM_OFF21 = 2 };
+
+#define SHMM_MAX_LEVELS 8
+
+/* One flow instance and the level geometry chosen for it (eq:model, Section
+ * 3, Figure 1).  Level l (0-based) uses n_cells[l]^2-cell patches with spacing
+ * h_l = 2 pi / n_global[l], centred on a lattice[l] x lattice[l] lattice of
+ * macro points X = 2 pi (c + 1/2) / lattice[l].  thresh holds the band edges
+ * a_1 < ... < a_{L-1} (Section 3.1: alpha, alpha^2, ...).  psi_hat is host
+ * memory, interleaved complex double, [(2 kmax + 1)][(2 kmax + 1)] indexed
+ * [k2 + kmax][k1 + kmax], Hermitian, psi_hat(0) = 0.
+ * dt_frac and delta fix the time integration of the local problems (step =
+ * dt_frac of the RK4 stability bound; stop when the slowest mode has decayed
+ * by delta, the quasi-stationary state of HMM step 2). */
+typedef struct shmm_problem {
+    double kappa;
+    int32_t kmax;
+    int32_t n_levels;
+    const double *psi_hat;
+    const int32_t *thresh;
+    const int32_t *n_cells;
+    const int32_t *n_global;
+    const int32_t *lattice;
+    double dt_frac;
+    double delta;
+} shmm_problem;
+
+/* One local domain Omega at one level (Section 3, Figure 1).  Domains are
+ * stored phase by phase: phase p = (L_i - 1) - level, then instance, cy, cx;
+ * so each phase of the bottom-up pass and each (instance, level) group is a
+ * contiguous range.  Everything but dt and nsteps is fixed by
+ * shmm_build_levels; dt and nsteps are set by shmm_plan_steps. */
+typedef struct shmm_domain {
+    int32_t instance, level, cx, cy;
+    int32_t n;          /* cells per side */
+    int32_t N;          /* level grid: h = 2 pi / N */
+    int32_t I0, J0;     /* node origin x0 = 2 pi I0 / N, y0 = 2 pi J0 / N */
+    int32_t parent;     /* domain of the coarser level holding this centre, -1 at level 0 */
+    int32_t nsteps;     /* RK4 steps of the local solve */
+    int64_t offset;     /* first cell in the packed [domain][y][x] arrays */
+    int64_t line_offset;/* first entry in the packed line energies (2 n per domain) */
+    double h;           /* 2 pi / N */
+    double dt;          /* RK4 step */
+} shmm_domain;
+
+typedef struct shmm_ctx shmm_ctx;
+
+/* Context on one HIP device.  shmm_ctx_create makes `device` current and
+ * keeps it; every later call on the context uses that device. */
+int shmm_ctx_create(shmm_ctx **ctx, int device);
+int shmm_ctx_destroy(shmm_ctx *ctx);
+
+/* Bookkeeping of the hierarchy of local domains (Section 3, Figure 1: domains
+ * of every level centred at the same macro points, side and spacing shrinking
+ * together).  Host only, pure, bit-reproducible.  Call with out == NULL to get
+ * the sizes; then with out holding *n_domains entries.  Errors: SHMM_EINVAL
+ * for malformed geometry (n not a power of two, patch origin off the level
+ * grid, lattice not refining its parent's, band edges not increasing,
+ * kappa <= 0). */
+int shmm_build_levels(const shmm_problem *p, int32_t n_inst, shmm_domain *out,
+                      int64_t *n_domains, int64_t *n_cells_total, int64_t *n_lines_total);
+
+/* Load a batch of instances into the context: builds the domain table (as
+ * shmm_build_levels), uploads spectra and descriptors.  Synchronous.
+ * Errors: as shmm_build_levels; SHMM_ERANGE if a level's diagonal band does
+ * not fit its grid (2 K + 1 > N) or a grid is not a power of two;
+ * SHMM_ENOMEM / SHMM_EDEVICE. */
+int shmm_ctx_set_problem(shmm_ctx *ctx, const shmm_problem *p, int32_t n_inst);
+
+/* Host view of the context's domain table (valid until the next
+ * shmm_ctx_set_problem).  *phase_first receives n_phases + 1 range bounds. */
+int shmm_ctx_table(shmm_ctx *ctx, const shmm_domain **table, int64_t *n_domains,
+                   int64_t *n_cells_total, int64_t *n_lines_total,
+                   const int64_t **phase_first, int32_t *n_phases);
+
+/* Band tags of instance `inst` (Section 3.1): d_tags[(2 kmax + 1)^2] int8,
+ * tag = 4 * level + part, -1 for k = 0.  Integer, bit-exact. */
+int shmm_band_tags(shmm_ctx *ctx, int32_t inst, int8_t *d_tags, void *stream);
+
+/* Step plan of the local solves of domains [first, first + count) (HMM step 2):
+ * dt = T/nsteps with T = ln(1/delta) / (lambda_min(K_b) 4 sin^2(pi/n) / h^2)
+ * and nsteps = ceil(T / (dt_frac / (rho_D/2.785 + rho_A/2.828))),
+ * rho_D = (4 K11 + 4 K22 + 2|K12|)/h^2, rho_A = V_b/h, V_b = sum over the
+ * level's diagonal band of |psi_hat(k)| (|k1| + |k2|).  K_base is host
+ * [n_domains][3] indexed by global domain.  Host arithmetic, bit-exact;
+ * updates the context's table on host and device (synchronous).
+ * Errors: SHMM_ENOTSPD if a base is not positive definite. */
+int shmm_plan_steps(shmm_ctx *ctx, int64_t first, int64_t count, const double *K_base);
+
+/* Band filter of domains [first, first + count) (Section 3.1), which must be
+ * whole (instance, level) groups.  For each domain writes, in FP32 at the
+ * packed offsets:
+ *   d_psi (optional, may be NULL): the level's diagonal band at the nodes;
+ *   d_vx, d_vy: face velocities vx = -(psi(x, y + h) - psi(x, y))/h on
+ *     x-faces and vy = (psi(x + h, y) - psi(x, y))/h on y-faces, synthesised
+ *     directly from psi_hat times the exact difference symbol, so the discrete
+ *     divergence is at FP32 rounding;
+ *   d_f1, d_f2: cell averages of the face components (the forcing of the
+ *     corrector problems for the reconstructions e_1, e_2);
+ * and in FP64 d_lines (packed, 2 n per domain at line_offset): the off-12 band
+ * energies along the n cell-centre columns, then the off-21 band energies
+ * along the n cell-centre rows (Algorithm 1, by Parseval).
+ * Uses an in-house radix-4/2 Stockham FFT (FP32) on the pruned band. */
+int shmm_band_filter(shmm_ctx *ctx, int64_t first, int64_t count, float *d_psi, float *d_vx,
+                     float *d_vy, float *d_f1, float *d_f2, double *d_lines, void *stream);
+
+/* Local solves of domains [first, first + count) (HMM steps 1-2; the two
+ * reconstructions with orthogonal gradients of the numerical homogenization):
+ * advance both correctors w_j' = div(v w_j + K_b grad w_j) + f_j by classic
+ * RK4, steps [step_begin, min(step_begin + steps, nsteps_d)) of each domain.
+ * d_K_base is [n_domains][3] (global index), d_w is [2][n_cells_total] FP32
+ * in/out.  FP32 stencils with a compensated state update.  Requires
+ * shmm_plan_steps on the range.  d_status (may be NULL) gets SHMM_DOM_* bits.
+ * Errors: SHMM_EINVAL for an empty plan. */
+int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const float *d_vx,
+                           const float *d_vy, const float *d_f1, const float *d_f2,
+                           const double *d_K_base, float *d_w, int32_t step_begin,
+                           int32_t steps, int32_t *d_status, void *stream);
+
+/* Effective diffusivity of domains [first, first + count) (the K formula after
+ * eq:homo with the corrector as chi; HMM step 3): FP64 moments of FP32 data,
+ *   d_K_out   = K_b + sym(<f_i w_j>)                       [n_domains][3]
+ *   d_K_energy= K_b + sym(-<w_i, D_{K_b} w_j>) (optional)   [n_domains][3]
+ *   d_mass    = (sum w_1, sum w_2)             (optional)   [n_domains][2]
+ * Deterministic (fixed reduction order).  Sets SHMM_DOM_NONFINITE. */
+int shmm_effective_diffusivity(shmm_ctx *ctx, int64_t first, int64_t count, const float *d_f1,
+                               const float *d_f2, const float *d_w, const double *d_K_base,
+                               double *d_K_out, double *d_K_energy, double *d_mass,
+                               int32_t *d_status, void *stream);
+
+/* Level combination (Algorithms 1-3, extended to L levels), FP64, for the
+ * domains [first, first + count).  All tensor arrays are [n_domains][3]:
+ *   mode 0 (top-down): K_in = kappa I at level 0, else K_off of the parent;
+ *          K_off = S12(K_in) + S21(K_in) - K_in below the finest level
+ *          (Algorithm 2; S12/S21 = Algorithm 1 on the line energies).
+ *   mode 1 (base):     finest level: K_base = K_in; otherwise
+ *          K_star = mean of the children's R, K_base = K_star - K_off + K_in
+ *          (Algorithm 3, steps 2-3); a non-SPD result is clamped to
+ *          lambda_min(K_in) and flagged SHMM_DOM_NOT_SPD.
+ *   mode 2 (result):   finest level: R = K_solve; otherwise
+ *          R = K_solve + S12(K_base) + S21(K_base) - 2 K_base (the additive
+ *          rule of Algorithm 2 applied to the final step of Algorithm 3).
+ * Run mode 0 phase by phase from the coarsest, modes 1-2 from the finest. */
+int shmm_level_chain(shmm_ctx *ctx, int64_t first, int64_t count, int32_t mode,
+                     const double *d_lines, double *d_K_in, double *d_K_off, double *d_K_base,
+                     const double *d_K_solve, double *d_R, int32_t *d_status, void *stream);
+
+/* Macro solver (HMM step 4 on eq:homo with the resolved velocity kept as
+ * advection): nsteps classic RK4 steps of
+ *   u_t = div(v u + K(x) grad u)
+ * on the periodic N x N grid of spacing h = 2 pi / N.  d_vx, d_vy are face
+ * velocities (may both be NULL: pure diffusion); d_K is [N*N][3] at cell
+ * centres (face value = mean of the two cells) if K_is_field, else [1][3].
+ * dtype 64: d_vx, d_vy, d_u are double; dtype 32: float (K stays double).
+ * Errors: SHMM_EINVAL for N < 4 or a dtype other than 32/64. */
+int shmm_macro_step(shmm_ctx *ctx, int32_t N, const void *d_vx, const void *d_vy,
+                    const double *d_K, int32_t K_is_field, double dt, int32_t nsteps, void *d_u,
+                    int32_t dtype, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHMM_H */

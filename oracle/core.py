@@ -147,43 +147,56 @@ def _origin(N: int, n: int, M: int, c: int) -> int:
 
 
 def domain_table(probs) -> List[Domain]:
-    """Domains of every instance, ordered instance, level, cy, cx."""
+    """Domains of every instance, stored phase by phase.
+
+    The bottom-up pass of Algorithm 3 visits the finest level of every instance
+    first, so domains are ordered by phase p = (L_i - 1) - level, then instance,
+    then cy, then cx.  Each phase, and each (instance, level) group, is then a
+    contiguous range.
+    """
     if not isinstance(probs, (list, tuple)):
         probs = [probs]
-    out: List[Domain] = []
-    off = 0
-    loff = 0
-    for inst, p in enumerate(probs):
+    for p in probs:
         L = len(p.n_cells)
         if not (len(p.n_global) == L and len(p.lattice) == L and len(p.thresh) == L - 1):
             raise BookkeepingError("level arrays disagree in length")
-        if p.kappa <= 0:
+        if not p.kappa > 0:
             raise BookkeepingError("kappa must be positive")
         for a, b in zip(p.thresh[:-1], p.thresh[1:]):
             if not b > a:
                 raise BookkeepingError("band edges must increase")
-        base_prev = -1
         for l in range(L):
             n, N, M = p.n_cells[l], p.n_global[l], p.lattice[l]
             if n < 4 or (n & (n - 1)) != 0 or n > N:
                 raise BookkeepingError("n must be a power of two with 4 <= n <= N")
             if M < 1 or (l > 0 and M % p.lattice[l - 1] != 0):
                 raise BookkeepingError("each lattice must refine the coarser one")
-            base = len(out)
+    max_L = max(len(p.n_cells) for p in probs)
+    out: List[Domain] = []
+    first: Dict[Tuple[int, int], int] = {}
+    off = 0
+    loff = 0
+    for phase in range(max_L):
+        for inst, p in enumerate(probs):
+            L = len(p.n_cells)
+            l = L - 1 - phase
+            if l < 0:
+                continue
+            n, N, M = p.n_cells[l], p.n_global[l], p.lattice[l]
+            first[(inst, l)] = len(out)
             for cy in range(M):
                 for cx in range(M):
-                    parent = -1
-                    if l > 0:
-                        Mp = p.lattice[l - 1]
-                        px = ((2 * cx + 1) * Mp) // (2 * M)
-                        py = ((2 * cy + 1) * Mp) // (2 * M)
-                        parent = base_prev + py * Mp + px
                     out.append(Domain(inst, l, cx, cy, n, N, _origin(N, n, M, cx),
-                                      _origin(N, n, M, cy), parent, off, loff,
-                                      2.0 * math.pi / N))
+                                      _origin(N, n, M, cy), -1, off, loff, 2.0 * math.pi / N))
                     off += n * n
                     loff += 2 * n
-            base_prev = base
+    for d in out:
+        if d.level > 0:
+            p = probs[d.instance]
+            M, Mp = p.lattice[d.level], p.lattice[d.level - 1]
+            px = ((2 * d.cx + 1) * Mp) // (2 * M)
+            py = ((2 * d.cy + 1) * Mp) // (2 * M)
+            d.parent = first[(d.instance, d.level - 1)] + py * Mp + px
     return out
 
 
@@ -483,7 +496,9 @@ def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = N
 
     L_of = [len(p.n_cells) for p in probs]
     # top-down: Algorithm 2 at every level above the finest, K_in from the parent
-    for i, d in enumerate(doms):
+    order = sorted(range(nd), key=lambda i: doms[i].level)
+    for i in order:
+        d = doms[i]
         if d.level == 0:
             K_in[i] = [probs[d.instance].kappa, 0.0, probs[d.instance].kappa]
         else:

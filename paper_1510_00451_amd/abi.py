@@ -1,0 +1,200 @@
+"""ctypes binding of libshmm.so.  Argument marshalling only: every step of the
+method runs inside the library.  Device pointers are plain integers (for
+example ``tensor.data_ptr()``); streams are hipStream_t handles as integers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libshmm.so")
+
+SHMM_OK, SHMM_EINVAL, SHMM_ERANGE, SHMM_ENOTSPD, SHMM_EDEVICE, SHMM_ENOMEM = 0, -1, -2, -3, -4, -5
+ERRORS = {SHMM_EINVAL: "SHMM_EINVAL", SHMM_ERANGE: "SHMM_ERANGE", SHMM_ENOTSPD: "SHMM_ENOTSPD",
+          SHMM_EDEVICE: "SHMM_EDEVICE", SHMM_ENOMEM: "SHMM_ENOMEM"}
+DOM_NONFINITE, DOM_NOT_SPD, DOM_DT_LIMIT, DOM_FALLBACK = 1, 2, 4, 8
+MAX_LEVELS = 8
+
+EXPORTS = ["shmm_ctx_create", "shmm_ctx_destroy", "shmm_build_levels", "shmm_ctx_set_problem",
+           "shmm_ctx_table", "shmm_band_tags", "shmm_plan_steps", "shmm_band_filter",
+           "shmm_local_solve_batch", "shmm_effective_diffusivity", "shmm_level_chain",
+           "shmm_macro_step"]
+
+
+class ShmmError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what} failed: {ERRORS.get(code, code)}")
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_double), ("kmax", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("psi_hat", ctypes.c_void_p), ("thresh", ctypes.c_void_p),
+                ("n_cells", ctypes.c_void_p), ("n_global", ctypes.c_void_p),
+                ("lattice", ctypes.c_void_p), ("dt_frac", ctypes.c_double),
+                ("delta", ctypes.c_double)]
+
+
+DOMAIN_DTYPE = np.dtype([("instance", "<i4"), ("level", "<i4"), ("cx", "<i4"), ("cy", "<i4"),
+                         ("n", "<i4"), ("N", "<i4"), ("I0", "<i4"), ("J0", "<i4"),
+                         ("parent", "<i4"), ("nsteps", "<i4"), ("offset", "<i8"),
+                         ("line_offset", "<i8"), ("h", "<f8"), ("dt", "<f8")])
+assert DOMAIN_DTYPE.itemsize == 72
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libshmm.so (built in-tree by ``build.py``).  Raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1510_00451_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        sig = {
+            "shmm_ctx_create": [ctypes.POINTER(P), ctypes.c_int],
+            "shmm_ctx_destroy": [P],
+            "shmm_build_levels": [P, i32, P, P, P, P],
+            "shmm_ctx_set_problem": [P, P, i32],
+            "shmm_ctx_table": [P, P, P, P, P, P, P],
+            "shmm_band_tags": [P, i32, P, P],
+            "shmm_plan_steps": [P, i64, i64, P],
+            "shmm_band_filter": [P, i64, i64, P, P, P, P, P, P, P],
+            "shmm_local_solve_batch": [P, i64, i64, P, P, P, P, P, P, i32, i32, P, P],
+            "shmm_effective_diffusivity": [P, i64, i64, P, P, P, P, P, P, P, P, P],
+            "shmm_level_chain": [P, i64, i64, i32, P, P, P, P, P, P, P, P],
+            "shmm_macro_step": [P, i32, P, P, P, i32, f64, i32, P, i32, P],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def check(rc: int, what: str) -> None:
+    if rc != SHMM_OK:
+        raise ShmmError(rc, what)
+
+
+class ProblemSet:
+    """ctypes array of shmm_problem plus the numpy buffers it points into."""
+
+    def __init__(self, problems):
+        self.keep: List[np.ndarray] = []
+        self.arr = (Problem * len(problems))()
+        for q, p in enumerate(problems):
+            ph = np.ascontiguousarray(np.asarray(p.psi_hat, np.complex128)).view(np.float64).reshape(-1)
+            th = np.ascontiguousarray(list(p.thresh) + [0], np.int32)
+            nc = np.ascontiguousarray(p.n_cells, np.int32)
+            ng = np.ascontiguousarray(p.n_global, np.int32)
+            la = np.ascontiguousarray(p.lattice, np.int32)
+            self.keep += [ph, th, nc, ng, la]
+            s = self.arr[q]
+            s.kappa = float(p.kappa)
+            s.kmax = int(p.kmax)
+            s.n_levels = len(p.n_cells)
+            s.psi_hat = ph.ctypes.data
+            s.thresh = th.ctypes.data
+            s.n_cells = nc.ctypes.data
+            s.n_global = ng.ctypes.data
+            s.lattice = la.ctypes.data
+            s.dt_frac = float(p.dt_frac)
+            s.delta = float(p.delta)
+
+    @property
+    def ptr(self) -> int:
+        return ctypes.addressof(self.arr)
+
+    def __len__(self) -> int:
+        return len(self.arr)
+
+
+def shmm_build_levels(problems) -> Tuple[np.ndarray, int, int]:
+    """Host-only bookkeeping: (domain table as a structured array, cells, lines)."""
+    ps = ProblemSet(problems if isinstance(problems, (list, tuple)) else [problems])
+    nd, cells, lines = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    check(lib().shmm_build_levels(ps.ptr, len(ps), None, ctypes.byref(nd), ctypes.byref(cells),
+                                  ctypes.byref(lines)), "shmm_build_levels")
+    out = np.zeros(nd.value, DOMAIN_DTYPE)
+    check(lib().shmm_build_levels(ps.ptr, len(ps), out.ctypes.data, None, None, None),
+          "shmm_build_levels")
+    return out, cells.value, lines.value
+
+
+class Context:
+    """Owns one shmm_ctx on one device."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        check(lib().shmm_ctx_create(ctypes.byref(h), int(device)), "shmm_ctx_create")
+        self.h = h
+        self.problems = None
+
+    def close(self):
+        if self.h:
+            lib().shmm_ctx_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shmm_ctx_set_problem(self, problems) -> None:
+        self.problems = ProblemSet(problems if isinstance(problems, (list, tuple)) else [problems])
+        check(lib().shmm_ctx_set_problem(self.h, self.problems.ptr, len(self.problems)),
+              "shmm_ctx_set_problem")
+
+    def shmm_ctx_table(self):
+        tab, nd, cells, lines = ctypes.c_void_p(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        pf, nph = ctypes.c_void_p(), ctypes.c_int32()
+        check(lib().shmm_ctx_table(self.h, ctypes.byref(tab), ctypes.byref(nd), ctypes.byref(cells),
+                                   ctypes.byref(lines), ctypes.byref(pf), ctypes.byref(nph)),
+              "shmm_ctx_table")
+        table = np.frombuffer((ctypes.c_char * (nd.value * DOMAIN_DTYPE.itemsize)).from_address(tab.value),
+                              DOMAIN_DTYPE).copy() if nd.value else np.zeros(0, DOMAIN_DTYPE)
+        phase = np.frombuffer((ctypes.c_int64 * (nph.value + 1)).from_address(pf.value), np.int64).copy()
+        return table, cells.value, lines.value, phase
+
+    def shmm_band_tags(self, inst: int, d_tags: int, stream: int = 0) -> None:
+        check(lib().shmm_band_tags(self.h, inst, d_tags, stream), "shmm_band_tags")
+
+    def shmm_plan_steps(self, first: int, count: int, K_base_host: np.ndarray) -> None:
+        K = np.ascontiguousarray(K_base_host, np.float64)
+        check(lib().shmm_plan_steps(self.h, first, count, K.ctypes.data), "shmm_plan_steps")
+
+    def shmm_band_filter(self, first, count, d_psi, d_vx, d_vy, d_f1, d_f2, d_lines, stream=0):
+        check(lib().shmm_band_filter(self.h, first, count, d_psi or None, d_vx, d_vy, d_f1, d_f2,
+                                     d_lines, stream), "shmm_band_filter")
+
+    def shmm_local_solve_batch(self, first, count, d_vx, d_vy, d_f1, d_f2, d_K_base, d_w,
+                               step_begin=0, steps=2 ** 31 - 1, d_status=0, stream=0):
+        check(lib().shmm_local_solve_batch(self.h, first, count, d_vx, d_vy, d_f1, d_f2, d_K_base,
+                                           d_w, int(step_begin), int(steps), d_status or None,
+                                           stream), "shmm_local_solve_batch")
+
+    def shmm_effective_diffusivity(self, first, count, d_f1, d_f2, d_w, d_K_base, d_K_out,
+                                   d_K_energy=0, d_mass=0, d_status=0, stream=0):
+        check(lib().shmm_effective_diffusivity(self.h, first, count, d_f1, d_f2, d_w, d_K_base,
+                                               d_K_out, d_K_energy or None, d_mass or None,
+                                               d_status or None, stream),
+              "shmm_effective_diffusivity")
+
+    def shmm_level_chain(self, first, count, mode, d_lines, d_K_in, d_K_off, d_K_base=0,
+                         d_K_solve=0, d_R=0, d_status=0, stream=0):
+        check(lib().shmm_level_chain(self.h, first, count, mode, d_lines, d_K_in, d_K_off,
+                                     d_K_base or None, d_K_solve or None, d_R or None,
+                                     d_status or None, stream), "shmm_level_chain")
+
+    def shmm_macro_step(self, N, d_vx, d_vy, d_K, K_is_field, dt, nsteps, d_u, dtype, stream=0):
+        check(lib().shmm_macro_step(self.h, N, d_vx or None, d_vy or None, d_K, int(K_is_field),
+                                    float(dt), int(nsteps), d_u, int(dtype), stream),
+              "shmm_macro_step")

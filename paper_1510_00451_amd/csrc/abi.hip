@@ -1,0 +1,547 @@
+// Host side of the C ABI: context, bookkeeping of the domain hierarchy, step
+// planning, and the entry points that enqueue the kernels.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <vector>
+
+#include "shmm_internal.h"
+
+namespace shmm {
+
+int hip_fail(hipError_t e, const char *what) {
+    fprintf(stderr, "shmm: HIP error %d (%s) in %s\n", (int)e, hipGetErrorString(e), what);
+    return e == hipErrorOutOfMemory ? SHMM_ENOMEM : SHMM_EDEVICE;
+}
+
+namespace {
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Validation shared by shmm_build_levels and shmm_ctx_set_problem.
+int validate(const shmm_problem *p, int32_t n_inst) {
+    if (!p || n_inst <= 0) return SHMM_EINVAL;
+    for (int32_t q = 0; q < n_inst; ++q) {
+        const shmm_problem &P = p[q];
+        const int L = P.n_levels;
+        if (L < 1 || L > SHMM_MAX_LEVELS) return SHMM_EINVAL;
+        if (!(P.kappa > 0.0) || P.kmax < 0) return SHMM_EINVAL;
+        if (!P.n_cells || !P.n_global || !P.lattice || (L > 1 && !P.thresh)) return SHMM_EINVAL;
+        for (int l = 0; l + 1 < L - 1; ++l)
+            if (!(P.thresh[l + 1] > P.thresh[l])) return SHMM_EINVAL;
+        for (int l = 0; l < L; ++l) {
+            const int n = P.n_cells[l], N = P.n_global[l], M = P.lattice[l];
+            if (n < 4 || !pow2(n) || n > N) return SHMM_EINVAL;
+            if (M < 1 || (l > 0 && M % P.lattice[l - 1] != 0)) return SHMM_EINVAL;
+            for (int c = 0; c < M; ++c) {
+                const int64_t num = (int64_t)N * (2 * c + 1) - (int64_t)n * M;
+                if (num % (2 * M) != 0) return SHMM_EINVAL;
+            }
+        }
+    }
+    return SHMM_OK;
+}
+
+int64_t origin(int N, int n, int M, int c) {
+    const int64_t num = (int64_t)N * (2 * c + 1) - (int64_t)n * M;
+    int64_t v = (num / (2 * M)) % N;
+    return v < 0 ? v + N : v;
+}
+
+// Domains stored phase by phase (phase = L - 1 - level), then instance, cy, cx.
+void build_table(const shmm_problem *p, int32_t n_inst, std::vector<shmm_domain> &out,
+                 int64_t &cells, int64_t &lines, std::vector<int64_t> &phase_first) {
+    out.clear();
+    phase_first.clear();
+    cells = 0;
+    lines = 0;
+    int maxL = 0;
+    for (int32_t q = 0; q < n_inst; ++q) maxL = std::max(maxL, (int)p[q].n_levels);
+    std::map<std::pair<int, int>, int64_t> first;
+    for (int ph = 0; ph < maxL; ++ph) {
+        phase_first.push_back((int64_t)out.size());
+        for (int32_t q = 0; q < n_inst; ++q) {
+            const int l = p[q].n_levels - 1 - ph;
+            if (l < 0) continue;
+            const int n = p[q].n_cells[l], N = p[q].n_global[l], M = p[q].lattice[l];
+            first[{q, l}] = (int64_t)out.size();
+            for (int cy = 0; cy < M; ++cy)
+                for (int cx = 0; cx < M; ++cx) {
+                    shmm_domain d;
+                    memset(&d, 0, sizeof(d));
+                    d.instance = q;
+                    d.level = l;
+                    d.cx = cx;
+                    d.cy = cy;
+                    d.n = n;
+                    d.N = N;
+                    d.I0 = (int32_t)origin(N, n, M, cx);
+                    d.J0 = (int32_t)origin(N, n, M, cy);
+                    d.parent = -1;
+                    d.nsteps = 0;
+                    d.offset = cells;
+                    d.line_offset = lines;
+                    d.h = 2.0 * M_PI / (double)N;
+                    d.dt = 0.0;
+                    out.push_back(d);
+                    cells += (int64_t)n * n;
+                    lines += 2 * (int64_t)n;
+                }
+        }
+    }
+    phase_first.push_back((int64_t)out.size());
+    for (auto &d : out) {
+        if (d.level == 0) continue;
+        const int M = p[d.instance].lattice[d.level], Mp = p[d.instance].lattice[d.level - 1];
+        const int px = ((2 * d.cx + 1) * Mp) / (2 * M);
+        const int py = ((2 * d.cy + 1) * Mp) / (2 * M);
+        d.parent = (int32_t)(first[{d.instance, d.level - 1}] + (int64_t)py * Mp + px);
+    }
+}
+
+// V_b = sum over the level's diagonal band of |psi_hat(k)| (|k1| + |k2|), k2-major.
+double band_speed_bound(const shmm_problem &P, int level) {
+    const int K = P.kmax, span = 2 * K + 1;
+    double s = 0.0;
+    for (int b = 0; b < span; ++b)
+        for (int a = 0; a < span; ++a) {
+            const int k1 = a - K, k2 = b - K;
+            if (k1 == 0 && k2 == 0) continue;
+            const int l = band_level(k1, k2, P.thresh, P.n_levels);
+            if (l != level || band_part(k1, k2, l, P.thresh, P.n_levels) != SHMM_DIAG) continue;
+            const int64_t idx = (int64_t)b * span + a;
+            const double re = P.psi_hat[2 * idx], im = P.psi_hat[2 * idx + 1];
+            s = s + sqrt(re * re + im * im) * (double)(abs(k1) + abs(k2));
+        }
+    return s;
+}
+
+// Largest |k1|, |k2| carrying a nonzero coefficient in the level's diagonal band.
+void band_extent(const shmm_problem &P, int level, int *kb1, int *kb2) {
+    const int K = P.kmax, span = 2 * K + 1;
+    *kb1 = 0;
+    *kb2 = 0;
+    for (int b = 0; b < span; ++b)
+        for (int a = 0; a < span; ++a) {
+            const int k1 = a - K, k2 = b - K;
+            if (k1 == 0 && k2 == 0) continue;
+            const int64_t idx = (int64_t)b * span + a;
+            if (P.psi_hat[2 * idx] == 0.0 && P.psi_hat[2 * idx + 1] == 0.0) continue;
+            const int l = band_level(k1, k2, P.thresh, P.n_levels);
+            if (l != level || band_part(k1, k2, l, P.thresh, P.n_levels) != SHMM_DIAG) continue;
+            *kb1 = std::max(*kb1, abs(k1));
+            *kb2 = std::max(*kb2, abs(k2));
+        }
+}
+
+// True when every mode of the level's diagonal band is periodic on the patch
+// (k n / N integral in both directions).
+int band_periodic(const shmm_problem &P, int level, int n, int N) {
+    const int K = P.kmax, span = 2 * K + 1;
+    for (int b = 0; b < span; ++b)
+        for (int a = 0; a < span; ++a) {
+            const int k1 = a - K, k2 = b - K;
+            if (k1 == 0 && k2 == 0) continue;
+            const int64_t idx = (int64_t)b * span + a;
+            if (P.psi_hat[2 * idx] == 0.0 && P.psi_hat[2 * idx + 1] == 0.0) continue;
+            const int l = band_level(k1, k2, P.thresh, P.n_levels);
+            if (l != level || band_part(k1, k2, l, P.thresh, P.n_levels) != SHMM_DIAG) continue;
+            if (((int64_t)k1 * n) % N != 0 || ((int64_t)k2 * n) % N != 0) return 0;
+        }
+    return 1;
+}
+
+// Step plan (see shmm.h).  The expression order is part of the contract.
+int plan_one(const shmm_domain &d, const double *K, double Vb, double dt_frac, double delta,
+             double *dt_out, int64_t *nsteps_out) {
+    const double K11 = K[0], K12 = K[1], K22 = K[2];
+    const double h = d.h;
+    const double rho_d = (4.0 * K11 + 4.0 * K22 + 2.0 * fabs(K12)) / (h * h);
+    const double rho_a = Vb / h;
+    const double dt_lim = 1.0 / (rho_d / 2.785 + rho_a / 2.828);
+    const double lam = 0.5 * (K11 + K22) - sqrt(0.25 * (K11 - K22) * (K11 - K22) + K12 * K12);
+    if (!(lam > 0.0)) return SHMM_ENOTSPD;
+    const double s = sin(M_PI / (double)d.n);
+    const double decay = lam * 4.0 * s * s / (h * h);
+    const double T = log(1.0 / delta) / decay;
+    const double q = ceil(T / (dt_frac * dt_lim));
+    if (!(q < 2147483647.0)) return SHMM_ERANGE;
+    int64_t nsteps = (int64_t)q;
+    if (nsteps < 1) nsteps = 1;
+    *nsteps_out = nsteps;
+    *dt_out = T / (double)nsteps;
+    return SHMM_OK;
+}
+
+template <typename T>
+int upload(T **dst, const T *src, size_t count) {
+    if (*dst) {
+        SHMM_HIP_CHECK(hipFree(*dst));
+        *dst = nullptr;
+    }
+    if (count == 0) return SHMM_OK;
+    SHMM_HIP_CHECK(hipMalloc((void **)dst, count * sizeof(T)));
+    SHMM_HIP_CHECK(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+    return SHMM_OK;
+}
+
+}  // namespace
+}  // namespace shmm
+
+using namespace shmm;
+
+struct RangeLists {
+    std::vector<int> ns;               // distinct n in the range
+    std::vector<int32_t *> d_lists;    // device list per n
+    std::vector<int32_t> counts;
+    std::vector<int64_t> cells;        // cells per list
+};
+
+struct shmm_ctx {
+    int device = 0;
+    std::vector<shmm_problem> probs;
+    std::vector<std::vector<double>> psi;
+    std::vector<std::vector<int32_t>> geo;   // thresh | n_cells | n_global | lattice per instance
+    std::vector<double *> d_psi;
+    std::vector<InstDev> inst;
+    InstDev *d_inst = nullptr;
+    std::vector<shmm_domain> table;
+    shmm_domain *d_table = nullptr;
+    int64_t cells = 0, lines = 0;
+    std::vector<int64_t> phase_first;
+    std::vector<Group> groups;
+    int32_t *d_origins = nullptr;
+    int32_t *d_child_start = nullptr, *d_child_idx = nullptr;
+    std::vector<std::vector<double>> vb;     // [inst][level]
+    std::map<std::pair<int64_t, int64_t>, RangeLists> lists;
+    void *work = nullptr;
+    size_t work_bytes = 0;
+
+    int ensure_work(size_t bytes) {
+        if (bytes <= work_bytes) return SHMM_OK;
+        if (work) {
+            SHMM_HIP_CHECK(hipDeviceSynchronize());   // kernels may still use the old buffer
+            SHMM_HIP_CHECK(hipFree(work));
+        }
+        work = nullptr;
+        work_bytes = 0;
+        SHMM_HIP_CHECK(hipMalloc(&work, bytes));
+        work_bytes = bytes;
+        return SHMM_OK;
+    }
+
+    void clear_lists() {
+        for (auto &kv : lists)
+            for (auto *p : kv.second.d_lists) (void)hipFree(p);
+        lists.clear();
+    }
+
+    void release() {
+        clear_lists();
+        for (auto *p : d_psi) (void)hipFree(p);
+        d_psi.clear();
+        if (d_inst) (void)hipFree(d_inst);
+        if (d_table) (void)hipFree(d_table);
+        if (d_origins) (void)hipFree(d_origins);
+        if (d_child_start) (void)hipFree(d_child_start);
+        if (d_child_idx) (void)hipFree(d_child_idx);
+        d_inst = nullptr;
+        d_table = nullptr;
+        d_origins = nullptr;
+        d_child_start = d_child_idx = nullptr;
+    }
+
+    int range_lists(int64_t first, int64_t count, RangeLists **out) {
+        auto key = std::make_pair(first, count);
+        auto it = lists.find(key);
+        if (it == lists.end()) {
+            RangeLists rl;
+            std::map<int, std::vector<int32_t>> byn;
+            for (int64_t d = first; d < first + count; ++d) byn[table[d].n].push_back((int32_t)d);
+            for (auto &kv : byn) {
+                int32_t *p = nullptr;
+                int rc = upload(&p, kv.second.data(), kv.second.size());
+                if (rc) return rc;
+                rl.ns.push_back(kv.first);
+                rl.d_lists.push_back(p);
+                rl.counts.push_back((int32_t)kv.second.size());
+                rl.cells.push_back((int64_t)kv.second.size() * kv.first * kv.first);
+            }
+            it = lists.emplace(key, rl).first;
+        }
+        *out = &it->second;
+        return SHMM_OK;
+    }
+};
+
+static int set_device(shmm_ctx *ctx) {
+    SHMM_HIP_CHECK(hipSetDevice(ctx->device));
+    return SHMM_OK;
+}
+
+static bool range_ok(shmm_ctx *ctx, int64_t first, int64_t count) {
+    return ctx && first >= 0 && count >= 0 && first + count <= (int64_t)ctx->table.size();
+}
+
+extern "C" {
+
+int shmm_ctx_create(shmm_ctx **ctx, int device) {
+    if (!ctx) return SHMM_EINVAL;
+    int ndev = 0;
+    SHMM_HIP_CHECK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return SHMM_EINVAL;
+    SHMM_HIP_CHECK(hipSetDevice(device));
+    shmm_ctx *c = new shmm_ctx();
+    c->device = device;
+    *ctx = c;
+    return SHMM_OK;
+}
+
+int shmm_ctx_destroy(shmm_ctx *ctx) {
+    if (!ctx) return SHMM_OK;
+    (void)hipSetDevice(ctx->device);
+    ctx->release();
+    if (ctx->work) (void)hipFree(ctx->work);
+    delete ctx;
+    return SHMM_OK;
+}
+
+int shmm_build_levels(const shmm_problem *p, int32_t n_inst, shmm_domain *out, int64_t *n_domains,
+                      int64_t *n_cells_total, int64_t *n_lines_total) {
+    int rc = validate(p, n_inst);
+    if (rc) return rc;
+    std::vector<shmm_domain> t;
+    std::vector<int64_t> pf;
+    int64_t cells = 0, lines = 0;
+    build_table(p, n_inst, t, cells, lines, pf);
+    if (n_domains) *n_domains = (int64_t)t.size();
+    if (n_cells_total) *n_cells_total = cells;
+    if (n_lines_total) *n_lines_total = lines;
+    if (out) memcpy(out, t.data(), t.size() * sizeof(shmm_domain));
+    return SHMM_OK;
+}
+
+int shmm_ctx_set_problem(shmm_ctx *ctx, const shmm_problem *p, int32_t n_inst) {
+    if (!ctx) return SHMM_EINVAL;
+    int rc = validate(p, n_inst);
+    if (rc) return rc;
+    if ((rc = set_device(ctx))) return rc;
+    for (int32_t q = 0; q < n_inst; ++q)
+        for (int l = 0; l < p[q].n_levels; ++l)
+            if (!pow2(p[q].n_global[l])) return SHMM_ERANGE;
+    ctx->release();
+    ctx->probs.assign(p, p + n_inst);
+    ctx->psi.assign(n_inst, {});
+    ctx->geo.assign(n_inst, {});
+    ctx->inst.assign(n_inst, InstDev());
+    ctx->vb.assign(n_inst, {});
+    for (int32_t q = 0; q < n_inst; ++q) {
+        shmm_problem &P = ctx->probs[q];
+        const int L = P.n_levels;
+        const size_t span = 2 * (size_t)P.kmax + 1;
+        ctx->psi[q].assign(P.psi_hat, P.psi_hat + 2 * span * span);
+        auto &g = ctx->geo[q];
+        g.assign(4 * SHMM_MAX_LEVELS, 0);
+        for (int l = 0; l + 1 < L; ++l) g[l] = P.thresh[l];
+        for (int l = 0; l < L; ++l) {
+            g[SHMM_MAX_LEVELS + l] = P.n_cells[l];
+            g[2 * SHMM_MAX_LEVELS + l] = P.n_global[l];
+            g[3 * SHMM_MAX_LEVELS + l] = P.lattice[l];
+        }
+        P.psi_hat = ctx->psi[q].data();
+        P.thresh = g.data();
+        P.n_cells = g.data() + SHMM_MAX_LEVELS;
+        P.n_global = g.data() + 2 * SHMM_MAX_LEVELS;
+        P.lattice = g.data() + 3 * SHMM_MAX_LEVELS;
+        double *dp = nullptr;
+        if ((rc = upload(&dp, ctx->psi[q].data(), ctx->psi[q].size()))) return rc;
+        ctx->d_psi.push_back(dp);
+        InstDev &I = ctx->inst[q];
+        I.kappa = P.kappa;
+        I.psi_hat = dp;
+        I.kmax = P.kmax;
+        I.L = L;
+        for (int l = 0; l < SHMM_MAX_LEVELS; ++l) I.thresh[l] = l + 1 < L ? P.thresh[l] : 0;
+        for (int l = 0; l < L; ++l) ctx->vb[q].push_back(band_speed_bound(P, l));
+    }
+    if ((rc = upload(&ctx->d_inst, ctx->inst.data(), ctx->inst.size()))) return rc;
+    build_table(ctx->probs.data(), n_inst, ctx->table, ctx->cells, ctx->lines, ctx->phase_first);
+    if ((rc = upload(&ctx->d_table, ctx->table.data(), ctx->table.size()))) return rc;
+    // groups (instance, level) and the band extents; lattice origins per group
+    ctx->groups.clear();
+    std::vector<int32_t> origins;
+    const int64_t nd = (int64_t)ctx->table.size();
+    for (int64_t d = 0; d < nd;) {
+        const shmm_domain &D = ctx->table[d];
+        Group g;
+        g.inst = D.instance;
+        g.level = D.level;
+        g.first = d;
+        g.n = D.n;
+        g.N = D.N;
+        g.M = ctx->probs[D.instance].lattice[D.level];
+        g.count = (int64_t)g.M * g.M;
+        band_extent(ctx->probs[D.instance], D.level, &g.kb1, &g.kb2);
+        g.periodic = band_periodic(ctx->probs[D.instance], D.level, g.n, g.N);
+        g.cell_first = D.offset;
+        if (2 * std::max(g.kb1, g.kb2) + 1 > g.N) return SHMM_ERANGE;
+        g.d_I0 = (const int32_t *)(intptr_t)origins.size();   // fixed up after upload
+        for (int c = 0; c < g.M; ++c) origins.push_back(ctx->table[d + c].I0);
+        for (int c = 0; c < g.M; ++c) origins.push_back(ctx->table[d + (int64_t)c * g.M].J0);
+        ctx->groups.push_back(g);
+        d += g.count;
+    }
+    if ((rc = upload(&ctx->d_origins, origins.data(), origins.size()))) return rc;
+    for (auto &g : ctx->groups) {
+        const intptr_t base = (intptr_t)g.d_I0;
+        g.d_I0 = ctx->d_origins + base;
+        g.d_J0 = ctx->d_origins + base + g.M;
+    }
+    // children lists (CSR) for Algorithm 3
+    std::vector<std::vector<int32_t>> ch(nd);
+    for (int64_t d = 0; d < nd; ++d)
+        if (ctx->table[d].parent >= 0) ch[ctx->table[d].parent].push_back((int32_t)d);
+    std::vector<int32_t> start(nd + 1, 0), idx;
+    for (int64_t d = 0; d < nd; ++d) {
+        start[d] = (int32_t)idx.size();
+        idx.insert(idx.end(), ch[d].begin(), ch[d].end());
+    }
+    start[nd] = (int32_t)idx.size();
+    if ((rc = upload(&ctx->d_child_start, start.data(), start.size()))) return rc;
+    if (idx.empty()) idx.push_back(0);
+    if ((rc = upload(&ctx->d_child_idx, idx.data(), idx.size()))) return rc;
+    return SHMM_OK;
+}
+
+int shmm_ctx_table(shmm_ctx *ctx, const shmm_domain **table, int64_t *n_domains,
+                   int64_t *n_cells_total, int64_t *n_lines_total, const int64_t **phase_first,
+                   int32_t *n_phases) {
+    if (!ctx) return SHMM_EINVAL;
+    if (table) *table = ctx->table.data();
+    if (n_domains) *n_domains = (int64_t)ctx->table.size();
+    if (n_cells_total) *n_cells_total = ctx->cells;
+    if (n_lines_total) *n_lines_total = ctx->lines;
+    if (phase_first) *phase_first = ctx->phase_first.data();
+    if (n_phases) *n_phases = (int32_t)ctx->phase_first.size() - 1;
+    return SHMM_OK;
+}
+
+int shmm_band_tags(shmm_ctx *ctx, int32_t inst, int8_t *d_tags, void *stream) {
+    if (!ctx || inst < 0 || inst >= (int32_t)ctx->inst.size() || !d_tags) return SHMM_EINVAL;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    return launch_band_tags(ctx->inst[inst], d_tags, (hipStream_t)stream);
+}
+
+int shmm_plan_steps(shmm_ctx *ctx, int64_t first, int64_t count, const double *K_base) {
+    if (!range_ok(ctx, first, count) || !K_base) return SHMM_EINVAL;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    for (int64_t d = first; d < first + count; ++d) {
+        shmm_domain &D = ctx->table[d];
+        const shmm_problem &P = ctx->probs[D.instance];
+        double dt = 0.0;
+        int64_t ns = 0;
+        rc = plan_one(D, K_base + 3 * d, ctx->vb[D.instance][D.level], P.dt_frac, P.delta, &dt, &ns);
+        if (rc) return rc;
+        D.dt = dt;
+        D.nsteps = (int32_t)ns;
+    }
+    if (count > 0)
+        SHMM_HIP_CHECK(hipMemcpy(ctx->d_table + first, ctx->table.data() + first,
+                                 count * sizeof(shmm_domain), hipMemcpyHostToDevice));
+    return SHMM_OK;
+}
+
+int shmm_band_filter(shmm_ctx *ctx, int64_t first, int64_t count, float *d_psi, float *d_vx,
+                     float *d_vy, float *d_f1, float *d_f2, double *d_lines, void *stream) {
+    if (!range_ok(ctx, first, count) || !d_vx || !d_vy || !d_f1 || !d_f2 || !d_lines)
+        return SHMM_EINVAL;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    int64_t covered = 0;
+    for (const Group &g : ctx->groups) {
+        if (g.first + g.count <= first || g.first >= first + count) continue;
+        if (g.first < first || g.first + g.count > first + count) return SHMM_EINVAL;
+        const size_t need = band_filter_workspace(g);
+        if ((rc = ctx->ensure_work(need))) return rc;
+        rc = launch_band_filter(ctx->inst[g.inst], g, ctx->d_table, d_psi, d_vx, d_vy, d_f1, d_f2,
+                                d_lines, ctx->work, ctx->work_bytes, (hipStream_t)stream);
+        if (rc) return rc;
+        covered += g.count;
+    }
+    return covered == count ? SHMM_OK : SHMM_EINVAL;
+}
+
+int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const float *d_vx,
+                           const float *d_vy, const float *d_f1, const float *d_f2,
+                           const double *d_K_base, float *d_w, int32_t step_begin, int32_t steps,
+                           int32_t *d_status, void *stream) {
+    (void)d_status;
+    if (!range_ok(ctx, first, count) || !d_vx || !d_vy || !d_K_base || !d_w || step_begin < 0 ||
+        steps < 0)
+        return SHMM_EINVAL;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    for (int64_t d = first; d < first + count; ++d)
+        if (ctx->table[d].nsteps <= 0) return SHMM_EINVAL;
+    RangeLists *rl = nullptr;
+    if ((rc = ctx->range_lists(first, count, &rl))) return rc;
+    for (size_t q = 0; q < rl->ns.size(); ++q) {
+        int32_t max_steps = 0;
+        for (int64_t d = first; d < first + count; ++d)
+            if (ctx->table[d].n == rl->ns[q]) max_steps = std::max(max_steps, ctx->table[d].nsteps);
+        const size_t need = local_solve_workspace(rl->ns[q], rl->cells[q]);
+        if (need && (rc = ctx->ensure_work(need))) return rc;
+        rc = launch_local_solve(ctx->d_table, rl->d_lists[q], rl->counts[q], rl->ns[q], max_steps,
+                                d_vx, d_vy, d_f1, d_f2, d_K_base, d_w, ctx->cells, step_begin, steps,
+                                rl->cells[q], ctx->work, (hipStream_t)stream);
+        if (rc) return rc;
+    }
+    return SHMM_OK;
+}
+
+int shmm_effective_diffusivity(shmm_ctx *ctx, int64_t first, int64_t count, const float *d_f1,
+                               const float *d_f2, const float *d_w, const double *d_K_base,
+                               double *d_K_out, double *d_K_energy, double *d_mass,
+                               int32_t *d_status, void *stream) {
+    if (!range_ok(ctx, first, count) || !d_f1 || !d_f2 || !d_w || !d_K_base || !d_K_out)
+        return SHMM_EINVAL;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    return launch_effective_diffusivity(ctx->d_table, first, count, d_f1, d_f2, d_w, ctx->cells,
+                                        d_K_base, d_K_out, d_K_energy, d_mass, d_status,
+                                        (hipStream_t)stream);
+}
+
+int shmm_level_chain(shmm_ctx *ctx, int64_t first, int64_t count, int32_t mode,
+                     const double *d_lines, double *d_K_in, double *d_K_off, double *d_K_base,
+                     const double *d_K_solve, double *d_R, int32_t *d_status, void *stream) {
+    if (!range_ok(ctx, first, count) || mode < 0 || mode > 2 || !d_lines || !d_K_in || !d_K_off)
+        return SHMM_EINVAL;
+    if (mode >= 1 && (!d_K_base || !d_R)) return SHMM_EINVAL;
+    if (mode == 2 && !d_K_solve) return SHMM_EINVAL;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    return launch_level_chain(ctx->d_table, ctx->d_inst, ctx->d_child_start, ctx->d_child_idx, first,
+                              count, mode, d_lines, d_K_in, d_K_off, d_K_base, d_K_solve, d_R,
+                              d_status, (hipStream_t)stream);
+}
+
+int shmm_macro_step(shmm_ctx *ctx, int32_t N, const void *d_vx, const void *d_vy, const double *d_K,
+                    int32_t K_is_field, double dt, int32_t nsteps, void *d_u, int32_t dtype,
+                    void *stream) {
+    if (!ctx || N < 4 || !pow2(N) || !d_K || !d_u || (dtype != 32 && dtype != 64) || nsteps < 0)
+        return SHMM_EINVAL;
+    if ((d_vx == nullptr) != (d_vy == nullptr)) return SHMM_EINVAL;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    if ((rc = ctx->ensure_work(macro_workspace(N, dtype)))) return rc;
+    return launch_macro(N, d_vx, d_vy, d_K, K_is_field, dt, nsteps, d_u, dtype, ctx->work,
+                        (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,159 @@
+// Band filter kernels (Section 3.1): band tags, pruned separable FFT synthesis
+// of psi, vx, vy at the patch nodes, cell forcings, and line energies of the
+// off-diagonal bands.
+#include "band_core.h"
+
+namespace shmm {
+
+namespace {
+
+struct BlockSync {
+    __device__ void operator()() const { __syncthreads(); }
+};
+
+constexpr int kBandThreads = 256;
+
+__global__ void k_band_tags(InstDev inst, int8_t *tags) {
+    const int span = 2 * inst.kmax + 1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)span * span) return;
+    const int k2 = (int)(idx / span) - inst.kmax, k1 = (int)(idx % span) - inst.kmax;
+    if (k1 == 0 && k2 == 0) {
+        tags[idx] = -1;
+        return;
+    }
+    const int l = band_level(k1, k2, inst.thresh, inst.L);
+    tags[idx] = (int8_t)(4 * l + band_part(k1, k2, l, inst.thresh, inst.L));
+}
+
+__global__ __launch_bounds__(kBandThreads) void k_band_pass1(BandParams p) {
+    extern __shared__ c32 lds[];
+    band_pass1_block(p, blockIdx.x, lds, lds + p.P1, threadIdx.x, blockDim.x, BlockSync{});
+}
+
+__global__ __launch_bounds__(kBandThreads) void k_band_pass2(BandParams p) {
+    extern __shared__ c32 lds[];
+    band_pass2_block(p, blockIdx.x, lds, lds + p.P2, threadIdx.x, blockDim.x, BlockSync{});
+}
+
+// f1 = cell average of the x-face velocities, f2 = of the y-face velocities.
+__global__ void k_forcing(const shmm_domain *dom, int64_t first, int n, const float *vx,
+                          const float *vy, float *f1, float *f2) {
+    const int64_t d = first + blockIdx.y;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (int64_t)n * n) return;
+    const int64_t o = dom[d].offset;
+    const int j = (int)(c / n), i = (int)(c % n);
+    const int ie = (i + 1) & (n - 1), jn = (j + 1) & (n - 1);
+    f1[o + c] = 0.5f * (vx[o + c] + vx[o + (int64_t)j * n + ie]);
+    f2[o + c] = 0.5f * (vy[o + c] + vy[o + (int64_t)jn * n + i]);
+}
+
+// The patch is treated as periodic: the faces on its last row and column use
+// the wrapped node values (x-face row n-1 pairs node rows n-1 and 0; y-face
+// column n-1 pairs node columns n-1 and 0).  Needed only when the band is not
+// periodic on the patch; otherwise the synthesised differences already agree.
+__global__ void k_seam(const shmm_domain *dom, int64_t first, int n, const float *psi,
+                       const int64_t psi_base, float *vx, float *vy) {
+    const int64_t d = first + blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t o = dom[d].offset;
+    const float ih = (float)(1.0 / dom[d].h);
+    const float *P = psi + (o - psi_base);
+    const int64_t last = (int64_t)(n - 1) * n;
+    vx[o + last + i] = -(P[i] - P[last + i]) * ih;
+    vy[o + (int64_t)i * n + (n - 1)] = (P[(int64_t)i * n] - P[(int64_t)i * n + (n - 1)]) * ih;
+}
+
+__global__ void k_line_energy(BandParams p) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int per_dir = p.M * p.n;
+    if (t >= 2 * per_dir) return;
+    const int dir = t / per_dir, r = t - dir * per_dir;
+    line_energy_one(p, dir, r / p.n, r % p.n);
+}
+
+int next_pow2(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+int launch_band_tags(const InstDev &inst, int8_t *d_tags, hipStream_t s) {
+    const int64_t total = (int64_t)(2 * inst.kmax + 1) * (2 * inst.kmax + 1);
+    hipLaunchKernelGGL(k_band_tags, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, inst, d_tags);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
+
+static void fill_params(BandParams &p, const InstDev &inst, const Group &g) {
+    p.inst = inst;
+    p.level = g.level;
+    p.N = g.N;
+    p.n = g.n;
+    p.M = g.M;
+    p.kb1 = g.kb1;
+    p.kb2 = g.kb2;
+    p.P1 = next_pow2(2 * g.kb2 + 1);
+    p.R1 = g.N / p.P1;
+    p.P2 = next_pow2(g.kb1 + 1);
+    p.R2 = g.N / p.P2;
+    p.first = g.first;
+}
+
+size_t band_filter_workspace(const Group &g) {
+    // G[3][kb1 + 1][M n], then psi of the group's cells when the caller wants none
+    return (size_t)3 * (g.kb1 + 1) * g.M * g.n * sizeof(c32) + (size_t)g.count * g.n * g.n * sizeof(float);
+}
+
+int launch_band_filter(const InstDev &inst, const Group &g, const shmm_domain *d_dom, float *d_psi,
+                       float *d_vx, float *d_vy, float *d_f1, float *d_f2, double *d_lines,
+                       void *work, size_t work_bytes, hipStream_t s) {
+    BandParams p;
+    fill_params(p, inst, g);
+    if (p.P1 > 4096 || p.P2 > 4096 || p.P1 > g.N || p.P2 > g.N) return SHMM_ERANGE;
+    if (work_bytes < band_filter_workspace(g)) return SHMM_ENOMEM;
+    p.dom = d_dom;
+    p.I0 = g.d_I0;
+    p.J0 = g.d_J0;
+    p.G = (c32 *)work;
+    // psi is needed for the seam faces of non-periodic patches
+    float *psi_buf = d_psi;
+    int64_t psi_base = 0;
+    if (!d_psi && !g.periodic) {
+        psi_base = g.cell_first;
+        psi_buf = (float *)((char *)work + (size_t)3 * (g.kb1 + 1) * g.M * g.n * sizeof(c32));
+        p.out[0] = psi_buf - psi_base;
+    } else {
+        p.out[0] = d_psi;
+    }
+    p.out[1] = d_vx;
+    p.out[2] = d_vy;
+    p.chan_first = (d_psi || !g.periodic) ? 0 : 1;
+    p.lines = d_lines;
+    const size_t lds1 = 2 * (size_t)p.P1 * sizeof(c32), lds2 = 2 * (size_t)p.P2 * sizeof(c32);
+    hipLaunchKernelGGL(k_band_pass1, dim3((unsigned)((g.kb1 + 1) * p.R1)), dim3(kBandThreads), lds1,
+                       s, p);
+    SHMM_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_band_pass2, dim3((unsigned)(g.M * g.n * p.R2)), dim3(kBandThreads), lds2, s,
+                       p);
+    SHMM_HIP_CHECK(hipGetLastError());
+    if (!g.periodic) {
+        hipLaunchKernelGGL(k_seam, dim3((unsigned)((g.n + 63) / 64), (unsigned)g.count), dim3(64), 0, s,
+                           d_dom, g.first, g.n, (const float *)psi_buf, psi_base, d_vx, d_vy);
+        SHMM_HIP_CHECK(hipGetLastError());
+    }
+    const int cells = g.n * g.n;
+    hipLaunchKernelGGL(k_forcing, dim3((unsigned)((cells + 255) / 256), (unsigned)g.count), dim3(256),
+                       0, s, d_dom, g.first, g.n, d_vx, d_vy, d_f1, d_f2);
+    SHMM_HIP_CHECK(hipGetLastError());
+    const int lines = 2 * g.M * g.n;
+    hipLaunchKernelGGL(k_line_energy, dim3((unsigned)((lines + 63) / 64)), dim3(64), 0, s, p);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
+
+}  // namespace shmm

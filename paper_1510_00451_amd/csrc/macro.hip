@@ -1,0 +1,139 @@
+// Macro solver (HMM step 4 of Section 2.2 on the homogenized equation
+// eq:homo, with the resolved large-scale velocity kept as advection):
+//   u_t = div(v u + K(x) grad u), periodic N x N grid, classic RK4.
+// Face fluxes: centred advection, K11 d1 u + K12 d2 u on x-faces and
+// K12 d1 u + K22 d2 u on y-faces (tangential derivatives averaged over the two
+// cells); a K field at cell centres is averaged onto the faces.
+#include "shmm_internal.h"
+
+namespace shmm {
+
+namespace {
+
+template <typename T>
+struct MacroArgs {
+    int N;
+    T h;
+    const T *vx, *vy;
+    const double *K;
+    int K_is_field;
+    T dt;
+};
+
+template <typename T>
+__device__ inline void face_K(const MacroArgs<T> &a, int c, int cn, T *k11, T *k12, T *k22) {
+    if (a.K_is_field) {
+        *k11 = (T)(0.5 * (a.K[3 * c + 0] + a.K[3 * cn + 0]));
+        *k12 = (T)(0.5 * (a.K[3 * c + 1] + a.K[3 * cn + 1]));
+        *k22 = (T)(0.5 * (a.K[3 * c + 2] + a.K[3 * cn + 2]));
+    } else {
+        *k11 = (T)a.K[0];
+        *k12 = (T)a.K[1];
+        *k22 = (T)a.K[2];
+    }
+}
+
+// flux through the left x-face of cell (i, j)
+template <typename T>
+__device__ inline T flux_x(const MacroArgs<T> &a, const T *u, int i, int j) {
+    const int N = a.N, m = N - 1;
+    const int il = (i - 1) & m, jn = (j + 1) & m, js = (j - 1) & m;
+    const int c = j * N + i;
+    T k11, k12, k22;
+    face_K(a, c, j * N + il, &k11, &k12, &k22);
+    const T ul = u[j * N + il], ur = u[c];
+    T f = k11 * (ur - ul) / a.h +
+          k12 * (u[jn * N + i] + u[jn * N + il] - u[js * N + i] - u[js * N + il]) / (T(4) * a.h);
+    if (a.vx) f += a.vx[c] * T(0.5) * (ul + ur);
+    return f;
+}
+
+// flux through the bottom y-face of cell (i, j)
+template <typename T>
+__device__ inline T flux_y(const MacroArgs<T> &a, const T *u, int i, int j) {
+    const int N = a.N, m = N - 1;
+    const int js = (j - 1) & m, ie = (i + 1) & m, iw = (i - 1) & m;
+    const int c = j * N + i;
+    T k11, k12, k22;
+    face_K(a, c, js * N + i, &k11, &k12, &k22);
+    const T ub = u[js * N + i], ut = u[c];
+    T f = k22 * (ut - ub) / a.h +
+          k12 * (u[j * N + ie] + u[js * N + ie] - u[j * N + iw] - u[js * N + iw]) / (T(4) * a.h);
+    if (a.vy) f += a.vy[c] * T(0.5) * (ub + ut);
+    return f;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_macro_stage(MacroArgs<T> a, const T *__restrict__ y,
+                                                     T *__restrict__ ynext, T *__restrict__ acc,
+                                                     T *__restrict__ u, int st) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = a.N;
+    if (c >= N * N) return;
+    const int j = c / N, i = c - j * N, m = N - 1;
+    const T F = (flux_x(a, y, (i + 1) & m, j) - flux_x(a, y, i, j)) / a.h +
+                (flux_y(a, y, i, (j + 1) & m) - flux_y(a, y, i, j)) / a.h;
+    const T t = a.dt * F;
+    const T uc = u[c];
+    T out;
+    if (st == 0) {
+        acc[c] = t;
+        out = uc + T(0.5) * t;
+    } else if (st < 3) {
+        acc[c] += T(2) * t;
+        out = uc + (st == 2 ? T(1) : T(0.5)) * t;
+    } else {
+        const T nu = uc + (acc[c] + t) / T(6);
+        u[c] = nu;
+        out = nu;
+    }
+    ynext[c] = out;
+}
+
+template <typename T>
+__global__ void k_copy(const T *__restrict__ src, T *__restrict__ dst, int n) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) dst[c] = src[c];
+}
+
+template <typename T>
+int run(int32_t N, const void *vx, const void *vy, const double *K, int32_t K_is_field, double dt,
+        int32_t nsteps, void *u, void *work, hipStream_t s) {
+    MacroArgs<T> a;
+    a.N = N;
+    a.h = (T)(2.0 * M_PI / (double)N);
+    a.vx = (const T *)vx;
+    a.vy = (const T *)vy;
+    a.K = K;
+    a.K_is_field = K_is_field;
+    a.dt = (T)dt;
+    const int cells = N * N;
+    T *y0 = (T *)work, *y1 = y0 + cells, *acc = y0 + 2 * cells;
+    const dim3 grid((unsigned)((cells + 255) / 256));
+    hipLaunchKernelGGL(k_copy<T>, grid, dim3(256), 0, s, (const T *)u, y0, cells);
+    SHMM_HIP_CHECK(hipGetLastError());
+    for (int32_t step = 0; step < nsteps; ++step) {
+        for (int st = 0; st < 4; ++st) {
+            hipLaunchKernelGGL(k_macro_stage<T>, grid, dim3(256), 0, s, a, y0, y1, acc, (T *)u, st);
+            SHMM_HIP_CHECK(hipGetLastError());
+            T *t = y0;
+            y0 = y1;
+            y1 = t;
+        }
+    }
+    return SHMM_OK;
+}
+
+}  // namespace
+
+size_t macro_workspace(int32_t N, int32_t dtype) {
+    return (size_t)3 * N * N * (dtype == 64 ? sizeof(double) : sizeof(float));
+}
+
+int launch_macro(int32_t N, const void *vx, const void *vy, const double *K, int32_t K_is_field,
+                 double dt, int32_t nsteps, void *u, int32_t dtype, void *work, hipStream_t s) {
+    if (dtype == 64) return run<double>(N, vx, vy, K, K_is_field, dt, nsteps, u, work, s);
+    return run<float>(N, vx, vy, K, K_is_field, dt, nsteps, u, work, s);
+}
+
+}  // namespace shmm

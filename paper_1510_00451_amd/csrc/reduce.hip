@@ -1,0 +1,215 @@
+// Effective diffusivity (the K formula after eq:homo; HMM step 3) and the
+// level combination of Algorithms 1-3, in FP64.
+#include "shmm_internal.h"
+
+namespace shmm {
+
+namespace {
+
+constexpr int kRedThreads = 256;
+constexpr int kRedVals = 11;   // p11 p12 p21 p22 m1 m2 e11 e12 e21 e22 bad
+
+// Fixed-order butterfly over the 64 lanes of a wavefront.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_moments(
+    const shmm_domain *__restrict__ dom, int64_t first, const float *__restrict__ f1,
+    const float *__restrict__ f2, const float *__restrict__ w, int64_t cells_total,
+    const double *__restrict__ Kb, double *__restrict__ K_out, double *__restrict__ K_energy,
+    double *__restrict__ mass, int32_t *__restrict__ status) {
+    __shared__ double part[kRedThreads / 64][kRedVals];
+    const int64_t d = first + blockIdx.x;
+    const shmm_domain D = dom[d];
+    const int n = D.n, mask = n - 1, cells = n * n;
+    const int64_t o = D.offset;
+    const double K11 = Kb[3 * d], K12 = Kb[3 * d + 1], K22 = Kb[3 * d + 2];
+    const double ih2 = 1.0 / (D.h * D.h);
+    const float *w1 = w + o, *w2 = w + cells_total + o;
+    double v[kRedVals];
+#pragma unroll
+    for (int q = 0; q < kRedVals; ++q) v[q] = 0.0;
+    for (int c = threadIdx.x; c < cells; c += kRedThreads) {
+        const int y = c / n, x = c - y * n;
+        const int xe = (x + 1) & mask, xw = (x - 1) & mask, yn = (y + 1) & mask, ys = (y - 1) & mask;
+        const double a1 = f1[o + c], a2 = f2[o + c];
+        const double u1 = w1[c], u2 = w2[c];
+        v[0] += a1 * u1;
+        v[1] += a1 * u2;
+        v[2] += a2 * u1;
+        v[3] += a2 * u2;
+        v[4] += u1;
+        v[5] += u2;
+        double D1, D2;
+        {
+            const float *u = w1;
+            D1 = (K11 * ((double)u[y * n + xe] - 2.0 * u1 + (double)u[y * n + xw]) +
+                  K22 * ((double)u[yn * n + x] - 2.0 * u1 + (double)u[ys * n + x]) +
+                  0.5 * K12 * (((double)u[yn * n + xe] - (double)u[yn * n + xw]) -
+                               ((double)u[ys * n + xe] - (double)u[ys * n + xw]))) * ih2;
+            u = w2;
+            D2 = (K11 * ((double)u[y * n + xe] - 2.0 * u2 + (double)u[y * n + xw]) +
+                  K22 * ((double)u[yn * n + x] - 2.0 * u2 + (double)u[ys * n + x]) +
+                  0.5 * K12 * (((double)u[yn * n + xe] - (double)u[yn * n + xw]) -
+                               ((double)u[ys * n + xe] - (double)u[ys * n + xw]))) * ih2;
+        }
+        v[6] += u1 * D1;
+        v[7] += u1 * D2;
+        v[8] += u2 * D1;
+        v[9] += u2 * D2;
+        if (!isfinite(u1) || !isfinite(u2)) v[10] = 1.0;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kRedVals; ++q) {
+        const double s = wave_sum(v[q]);
+        if (lane == 0) part[wave][q] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t[kRedVals];
+        for (int q = 0; q < kRedVals; ++q) {
+            t[q] = 0.0;
+            for (int wv = 0; wv < kRedThreads / 64; ++wv) t[q] += part[wv][q];
+        }
+        const double inv = 1.0 / (double)cells;
+        K_out[3 * d + 0] = K11 + t[0] * inv;
+        K_out[3 * d + 1] = K12 + 0.5 * (t[1] + t[2]) * inv;
+        K_out[3 * d + 2] = K22 + t[3] * inv;
+        if (K_energy) {
+            K_energy[3 * d + 0] = K11 - t[6] * inv;
+            K_energy[3 * d + 1] = K12 - 0.5 * (t[7] + t[8]) * inv;
+            K_energy[3 * d + 2] = K22 - t[9] * inv;
+        }
+        if (mass) {
+            mass[2 * d + 0] = t[4];
+            mass[2 * d + 1] = t[5];
+        }
+        const bool bad = t[10] != 0.0 || !isfinite(t[0]) || !isfinite(t[1]) || !isfinite(t[2]) ||
+                         !isfinite(t[3]);
+        if (status && bad) status[d] |= SHMM_DOM_NONFINITE;
+    }
+}
+
+// Algorithm 1: line-wise shear formula (eq:shearhomoY for the columns of the
+// off-12 band, eq:shearhomoX for the rows of the off-21 band), then the
+// harmonic mean across lines; the other diagonal entry and K12 pass through.
+__device__ inline void offdiag(const double *K, const double *s, int n, int dir, double *out) {
+    double acc = 0.0;
+    if (dir == 0) {
+        for (int i = 0; i < n; ++i) acc += 1.0 / (K[0] + s[i] / K[2]);
+        out[0] = (double)n / acc;
+        out[1] = K[1];
+        out[2] = K[2];
+    } else {
+        for (int i = 0; i < n; ++i) acc += 1.0 / (K[2] + s[i] / K[0]);
+        out[0] = K[0];
+        out[1] = K[1];
+        out[2] = (double)n / acc;
+    }
+}
+
+__device__ inline double lam_min(const double *K) {
+    const double m = 0.5 * (K[0] + K[2]), q = 0.5 * (K[0] - K[2]);
+    return m - sqrt(q * q + K[1] * K[1]);
+}
+
+__global__ void k_chain(const shmm_domain *__restrict__ dom, const InstDev *__restrict__ insts,
+                        const int32_t *__restrict__ child_start, const int32_t *__restrict__ child_idx,
+                        int64_t first, int64_t count, int32_t mode, const double *__restrict__ lines,
+                        double *K_in, double *K_off, double *K_base, const double *__restrict__ K_solve,
+                        double *R, int32_t *status) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const int64_t d = first + t;
+    const shmm_domain D = dom[d];
+    const InstDev I = insts[D.instance];
+    const bool finest = D.level == I.L - 1;
+    const double *s12 = lines + D.line_offset, *s21 = s12 + D.n;
+    double a[3], b[3];
+    if (mode == 0) {
+        double kin[3];
+        if (D.level == 0) {
+            kin[0] = I.kappa; kin[1] = 0.0; kin[2] = I.kappa;
+        } else {
+            for (int q = 0; q < 3; ++q) kin[q] = K_off[3 * (int64_t)D.parent + q];
+        }
+        for (int q = 0; q < 3; ++q) K_in[3 * d + q] = kin[q];
+        if (!finest) {
+            offdiag(kin, s12, D.n, 0, a);
+            offdiag(kin, s21, D.n, 1, b);
+            for (int q = 0; q < 3; ++q) K_off[3 * d + q] = a[q] + b[q] - kin[q];
+        }
+    } else if (mode == 1) {
+        if (finest) {
+            for (int q = 0; q < 3; ++q) K_base[3 * d + q] = K_in[3 * d + q];
+            return;
+        }
+        double ks[3] = {0.0, 0.0, 0.0};
+        const int c0 = child_start[d], c1 = child_start[d + 1];
+        for (int c = c0; c < c1; ++c)
+            for (int q = 0; q < 3; ++q) ks[q] += R[3 * (int64_t)child_idx[c] + q];
+        double kb[3];
+        for (int q = 0; q < 3; ++q) kb[q] = ks[q] / (double)(c1 - c0) - K_off[3 * d + q] + K_in[3 * d + q];
+        const double floor = lam_min(K_in + 3 * d);
+        if (!(lam_min(kb) >= floor) || !(kb[0] > 0.0)) {
+            // clamp the eigenvalues of the symmetric 2x2 to at least lambda_min(K_in)
+            const double m = 0.5 * (kb[0] + kb[2]), q = 0.5 * (kb[0] - kb[2]);
+            const double r = sqrt(q * q + kb[1] * kb[1]);
+            double l1 = m + r, l2 = m - r;
+            double cth = 1.0, sth = 0.0;
+            if (r > 0.0) {
+                const double ang = 0.5 * atan2(2.0 * kb[1], kb[0] - kb[2]);
+                cth = cos(ang);
+                sth = sin(ang);
+            }
+            l1 = l1 > floor ? l1 : floor;
+            l2 = l2 > floor ? l2 : floor;
+            if (!isfinite(l1) || !isfinite(l2)) l1 = l2 = floor, cth = 1.0, sth = 0.0;
+            kb[0] = l1 * cth * cth + l2 * sth * sth;
+            kb[1] = (l1 - l2) * cth * sth;
+            kb[2] = l1 * sth * sth + l2 * cth * cth;
+            if (status) status[d] |= SHMM_DOM_NOT_SPD;
+        }
+        for (int q = 0; q < 3; ++q) K_base[3 * d + q] = kb[q];
+    } else {
+        if (finest) {
+            for (int q = 0; q < 3; ++q) R[3 * d + q] = K_solve[3 * d + q];
+            return;
+        }
+        const double *kn = K_base + 3 * d;
+        offdiag(kn, s12, D.n, 0, a);
+        offdiag(kn, s21, D.n, 1, b);
+        for (int q = 0; q < 3; ++q) R[3 * d + q] = K_solve[3 * d + q] + a[q] + b[q] - 2.0 * kn[q];
+    }
+}
+
+}  // namespace
+
+int launch_effective_diffusivity(const shmm_domain *d_dom, int64_t first, int64_t count,
+                                 const float *f1, const float *f2, const float *w,
+                                 int64_t cells_total, const double *Kb, double *K_out,
+                                 double *K_energy, double *mass, int32_t *status, hipStream_t s) {
+    if (count <= 0) return SHMM_OK;
+    hipLaunchKernelGGL(k_moments, dim3((unsigned)count), dim3(kRedThreads), 0, s, d_dom, first, f1, f2,
+                       w, cells_total, Kb, K_out, K_energy, mass, status);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
+
+int launch_level_chain(const shmm_domain *d_dom, const InstDev *d_inst, const int32_t *d_child_start,
+                       const int32_t *d_child_idx, int64_t first, int64_t count, int32_t mode,
+                       const double *lines, double *K_in, double *K_off, double *K_base,
+                       const double *K_solve, double *R, int32_t *status, hipStream_t s) {
+    if (count <= 0) return SHMM_OK;
+    hipLaunchKernelGGL(k_chain, dim3((unsigned)((count + 63) / 64)), dim3(64), 0, s, d_dom, d_inst,
+                       d_child_start, d_child_idx, first, count, mode, lines, K_in, K_off, K_base,
+                       K_solve, R, status);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
+
+}  // namespace shmm

@@ -1,0 +1,146 @@
+"""One pass of the SHMM hot path on the GPU: band filter, top-down Algorithm 2,
+then phase by phase (finest level first) the local solves, the effective
+diffusivity and the level combination of Algorithm 3.
+
+PyTorch supplies device memory and the stream; every numeric step runs in
+libshmm.so.  The only host work between phases is the step plan, which needs
+the phase's base diffusivities (24 bytes per domain) on the host.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List, Optional
+
+import numpy as np
+
+from . import abi
+
+MODE_TOPDOWN, MODE_BASE, MODE_RESULT = 0, 1, 2
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the SHMM hot path needs a HIP device; no CPU fallback exists")
+    return torch
+
+
+@dataclass
+class PassResult:
+    K_total: np.ndarray      # [instances * coarsest-lattice][3], level-0 results
+    R: np.ndarray            # [nd][3] level results
+    K_base: np.ndarray
+    K_solve: np.ndarray
+    K_in: np.ndarray
+    K_off: np.ndarray
+    nsteps: np.ndarray
+    dt: np.ndarray
+    point_steps: int         # sum over domains of n^2 * nsteps
+
+
+class Hierarchy:
+    """Device buffers and phase schedule for a batch of flow instances."""
+
+    def __init__(self, problems, device: int = 0, keep_psi: bool = False):
+        torch = _torch()
+        self.torch = torch
+        self.problems = problems if isinstance(problems, (list, tuple)) else [problems]
+        self.device = torch.device("cuda", device)
+        self.ctx = abi.Context(device)
+        self.ctx.shmm_ctx_set_problem(self.problems)
+        self.table, self.cells, self.lines_total, self.phase = self.ctx.shmm_ctx_table()
+        nd = len(self.table)
+        self.nd = nd
+        f32 = dict(dtype=torch.float32, device=self.device)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.psi = torch.zeros(self.cells, **f32) if keep_psi else None
+        self.vx = torch.zeros(self.cells, **f32)
+        self.vy = torch.zeros(self.cells, **f32)
+        self.f1 = torch.zeros(self.cells, **f32)
+        self.f2 = torch.zeros(self.cells, **f32)
+        self.w = torch.zeros(2 * self.cells, **f32)
+        self.lines = torch.zeros(max(1, self.lines_total), **f64)
+        self.K_in = torch.zeros(nd, 3, **f64)
+        self.K_off = torch.zeros(nd, 3, **f64)
+        self.K_base = torch.zeros(nd, 3, **f64)
+        self.K_solve = torch.zeros(nd, 3, **f64)
+        self.R = torch.zeros(nd, 3, **f64)
+        self.K_energy = torch.zeros(nd, 3, **f64)
+        self.mass = torch.zeros(nd, 2, **f64)
+        self.status = torch.zeros(nd, dtype=torch.int32, device=self.device)
+        self.host_K = np.zeros((nd, 3))
+        self.level0 = np.flatnonzero(self.table["level"] == 0)
+
+    # -- pieces -------------------------------------------------------------
+    def stream(self) -> int:
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def cell_range(self, first: int, count: int):
+        t = self.table
+        a = int(t["offset"][first])
+        b = int(t["offset"][first + count - 1] + t["n"][first + count - 1] ** 2)
+        return a, b
+
+    def band_filter(self) -> None:
+        s = self.stream()
+        nph = len(self.phase) - 1
+        for p in range(nph):
+            first, count = int(self.phase[p]), int(self.phase[p + 1] - self.phase[p])
+            self.ctx.shmm_band_filter(first, count, self.psi.data_ptr() if self.psi is not None else 0,
+                                      self.vx.data_ptr(), self.vy.data_ptr(), self.f1.data_ptr(),
+                                      self.f2.data_ptr(), self.lines.data_ptr(), s)
+
+    def top_down(self) -> None:
+        s = self.stream()
+        nph = len(self.phase) - 1
+        for p in range(nph - 1, -1, -1):
+            first, count = int(self.phase[p]), int(self.phase[p + 1] - self.phase[p])
+            self.ctx.shmm_level_chain(first, count, MODE_TOPDOWN, self.lines.data_ptr(),
+                                      self.K_in.data_ptr(), self.K_off.data_ptr(), stream=s)
+
+    def phase_solve(self, p: int, steps: Optional[int] = None) -> None:
+        s = self.stream()
+        first, count = int(self.phase[p]), int(self.phase[p + 1] - self.phase[p])
+        c = self.ctx
+        c.shmm_level_chain(first, count, MODE_BASE, self.lines.data_ptr(), self.K_in.data_ptr(),
+                           self.K_off.data_ptr(), self.K_base.data_ptr(), 0, self.R.data_ptr(),
+                           self.status.data_ptr(), s)
+        # step plan on the host (bit-reproducible bookkeeping)
+        self.host_K[first:first + count] = self.K_base[first:first + count].cpu().numpy()
+        c.shmm_plan_steps(first, count, self.host_K)
+        a, b = self.cell_range(first, count)
+        self.w.view(2, self.cells)[:, a:b].zero_()
+        c.shmm_local_solve_batch(first, count, self.vx.data_ptr(), self.vy.data_ptr(),
+                                 self.f1.data_ptr(), self.f2.data_ptr(), self.K_base.data_ptr(),
+                                 self.w.data_ptr(), 0, 2 ** 31 - 1 if steps is None else steps,
+                                 self.status.data_ptr(), s)
+        c.shmm_effective_diffusivity(first, count, self.f1.data_ptr(), self.f2.data_ptr(),
+                                     self.w.data_ptr(), self.K_base.data_ptr(),
+                                     self.K_solve.data_ptr(), self.K_energy.data_ptr(),
+                                     self.mass.data_ptr(), self.status.data_ptr(), s)
+        c.shmm_level_chain(first, count, MODE_RESULT, self.lines.data_ptr(), self.K_in.data_ptr(),
+                           self.K_off.data_ptr(), self.K_base.data_ptr(), self.K_solve.data_ptr(),
+                           self.R.data_ptr(), self.status.data_ptr(), s)
+
+    def run(self, steps: Optional[int] = None) -> None:
+        """One pass of the hot path (asynchronous apart from the per-phase plan)."""
+        self.status.zero_()
+        self.band_filter()
+        self.top_down()
+        for p in range(len(self.phase) - 1):
+            self.phase_solve(p, steps)
+
+    # -- results ------------------------------------------------------------
+    def result(self) -> PassResult:
+        self.torch.cuda.synchronize(self.device)
+        table, _, _, _ = self.ctx.shmm_ctx_table()
+        R = self.R.cpu().numpy()
+        return PassResult(K_total=R[self.level0], R=R, K_base=self.K_base.cpu().numpy(),
+                          K_solve=self.K_solve.cpu().numpy(), K_in=self.K_in.cpu().numpy(),
+                          K_off=self.K_off.cpu().numpy(), nsteps=table["nsteps"].copy(),
+                          dt=table["dt"].copy(),
+                          point_steps=int(np.sum(table["n"].astype(np.int64) ** 2
+                                                 * table["nsteps"].astype(np.int64))))
+
+    def close(self):
+        self.ctx.close()

@@ -1,0 +1,338 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (floating point): effective diffusivity 1e-5 relative, macro field
+1e-6 relative L2 in FP32 and 1e-12 in FP64; band-filtered fields 2e-6 of their
+scale (FP32 FFT); line energies 1e-11 (FP64).  Integers bit-exact.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import flowgen
+import oracle
+from oracle import DIAG, OFF12, OFF21
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a HIP device"
+    return t
+
+
+def hier(problems, keep_psi=True):
+    from paper_1510_00451_amd.hierarchy import Hierarchy
+    return Hierarchy(problems, keep_psi=keep_psi)
+
+
+def relerr(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# ---------------------------------------------------------------- integers
+
+def test_band_tags_bit_exact(torch):
+    from paper_1510_00451_amd import abi
+    probs = [flowgen.config_four_level_cellular(n=32, lattice=2),
+             flowgen.config_continuous(seed=3, radius=70, n=32, lattice=2, levels=4)]
+    say("case band tags")
+    H = hier(probs)
+    for q, p in enumerate(probs):
+        span = 2 * p.kmax + 1
+        tags = torch.empty(span * span, dtype=torch.int8, device="cuda")
+        H.ctx.shmm_band_tags(q, tags.data_ptr(), H.stream())
+        torch.cuda.synchronize()
+        lv, pt = oracle.band_split(p.kmax, p.thresh)
+        ref = np.where(lv >= 0, 4 * lv.astype(np.int32) + pt, -1).astype(np.int8).reshape(-1)
+        assert np.array_equal(tags.cpu().numpy(), ref)
+    H.close()
+
+
+def test_step_plan_bit_exact(torch):
+    p = flowgen.config_four_level_cellular(n=32, lattice=2)
+    say("case step plan")
+    H = hier(p, keep_psi=False)
+    rng = np.random.default_rng(1)
+    nd = H.nd
+    A = rng.uniform(0.5, 2.0, (nd, 2, 2))
+    K = np.einsum("dij,dkj->dik", A, A) * 1e-2
+    Kb = np.stack([K[:, 0, 0], K[:, 0, 1], K[:, 1, 1]], 1)
+    H.ctx.shmm_plan_steps(0, nd, Kb)
+    table, _, _, _ = H.ctx.shmm_ctx_table()
+    lv, pt = oracle.band_split(p.kmax, p.thresh)
+    for d in range(nd):
+        D = table[d]
+        Vb = oracle.band_speed_bound(p.psi_hat, p.kmax, oracle.band_mask(lv, pt, int(D["level"]), DIAG))
+        dt, ns = oracle.plan_steps(int(D["n"]), float(D["h"]), Kb[d], Vb, p.dt_frac, p.delta)
+        assert int(D["nsteps"]) == ns and float(D["dt"]) == dt, d
+    H.close()
+
+
+# ---------------------------------------------------------------- band filter
+
+BAND_CASES = [
+    ("two-level-64", lambda: flowgen.config_two_level_cellular()),
+    ("four-level-32x4", lambda: flowgen.config_four_level_cellular(n=32, lattice=2)),
+    ("continuous-3lvl", lambda: flowgen.config_continuous(seed=2, radius=40, n=16, lattice=2, levels=3)),
+]
+
+
+@pytest.mark.parametrize("name,make", BAND_CASES)
+def test_band_filter_parity(torch, name, make):
+    p = make()
+    say("case band filter", name)
+    H = hier(p)
+    H.band_filter()
+    torch.cuda.synchronize()
+    psi, vx, vy = H.psi.cpu().numpy(), H.vx.cpu().numpy(), H.vy.cpu().numpy()
+    f1, f2, lines = H.f1.cpu().numpy(), H.f2.cpu().numpy(), H.lines.cpu().numpy()
+    lv, pt = oracle.band_split(p.kmax, p.thresh)
+    for d in range(H.nd):
+        D = H.table[d]
+        n, o, lev = int(D["n"]), int(D["offset"]), int(D["level"])
+        ref = oracle.synth_patch(p.psi_hat, p.kmax, oracle.band_mask(lv, pt, lev, DIAG), int(D["N"]),
+                                 int(D["I0"]), int(D["J0"]), n)
+        rvx, rvy, rf1, rf2 = oracle.staggered(ref, float(D["h"]))
+        sc = max(np.abs(ref).max(), 1e-300)
+        vs = max(np.abs(rvx).max(), np.abs(rvy).max(), 1e-300)
+        sl = slice(o, o + n * n)
+        assert np.abs(psi[sl].reshape(n, n) - ref).max() <= 2e-6 * sc + 1e-30
+        for got, want in ((vx, rvx), (vy, rvy), (f1, rf1), (f2, rf2)):
+            assert np.abs(got[sl].reshape(n, n) - want).max() <= 2e-6 * vs + 1e-30, (name, d)
+        lo = int(D["line_offset"])
+        s12 = oracle.line_energies(p.psi_hat, p.kmax, oracle.band_mask(lv, pt, lev, OFF12),
+                                   int(D["N"]), int(D["I0"]), n, 0)
+        s21 = oracle.line_energies(p.psi_hat, p.kmax, oracle.band_mask(lv, pt, lev, OFF21),
+                                   int(D["N"]), int(D["J0"]), n, 1)
+        np.testing.assert_allclose(lines[lo:lo + n], s12, rtol=1e-11, atol=1e-300)
+        np.testing.assert_allclose(lines[lo + n:lo + 2 * n], s21, rtol=1e-11, atol=1e-300)
+    H.close()
+
+
+# ---------------------------------------------------------------- local solve
+
+def _single_level(n, seed, amp, kappa, lattice=2, radius=None):
+    radius = radius or max(2, n // 8)
+    p = flowgen.config_continuous(seed=seed, radius=radius, p=-1.5, kappa=kappa, n=n,
+                                  lattice=lattice, levels=1)
+    p.psi_hat *= amp
+    p.n_global = [n * lattice]          # patches tile the domain
+    return p
+
+
+@pytest.mark.parametrize("n,steps", [(8, None), (16, None), (32, None), (64, 400), (128, 60), (256, 12)])
+def test_local_solve_and_estimator_parity(torch, n, steps):
+    """Band filter + RK4 local solve + FP64 estimator against the oracle's own
+    synthesis, solve and estimator, on an anisotropic base."""
+    p = _single_level(n, seed=n, amp=0.3, kappa=0.05)
+    say("case local solve n=%d steps=%s" % (n, steps))
+    H = hier(p, keep_psi=False)
+    H.band_filter()
+    Kb = np.tile([0.06, 0.015, 0.04], (H.nd, 1))
+    H.K_base.copy_(torch.from_numpy(Kb))
+    H.ctx.shmm_plan_steps(0, H.nd, Kb)
+    H.w.zero_()
+    H.ctx.shmm_local_solve_batch(0, H.nd, H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(),
+                                 H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(), 0,
+                                 2 ** 31 - 1 if steps is None else steps, 0, H.stream())
+    H.ctx.shmm_effective_diffusivity(0, H.nd, H.f1.data_ptr(), H.f2.data_ptr(), H.w.data_ptr(),
+                                     H.K_base.data_ptr(), H.K_solve.data_ptr(),
+                                     H.K_energy.data_ptr(), H.mass.data_ptr(), 0, H.stream())
+    torch.cuda.synchronize()
+    table, cells, _, _ = H.ctx.shmm_ctx_table()
+    w = H.w.cpu().numpy().reshape(2, cells)
+    K = H.K_solve.cpu().numpy()
+    mass = H.mass.cpu().numpy()
+    lv, pt = oracle.band_split(p.kmax, p.thresh)
+    mask = oracle.band_mask(lv, pt, 0, DIAG)
+    for d in range(H.nd):
+        D = table[d]
+        psi = oracle.synth_patch(p.psi_hat, p.kmax, mask, int(D["N"]), int(D["I0"]), int(D["J0"]), n)
+        vx, vy, f1, f2 = oracle.staggered(psi, float(D["h"]))
+        ns = int(D["nsteps"]) if steps is None else min(steps, int(D["nsteps"]))
+        wr = oracle.local_solve_batch([n], [float(D["h"])], vx.ravel(), vy.ravel(), f1.ravel(),
+                                      f2.ravel(), Kb[d:d + 1], [float(D["dt"])], [ns])
+        o = int(D["offset"])
+        for j in range(2):
+            assert relerr(w[j, o:o + n * n], wr[j]) <= 1e-5, (n, d, j)
+        Kr = oracle.estimate(f1, f2, wr[0].reshape(n, n), wr[1].reshape(n, n), Kb[d])
+        assert np.max(np.abs(K[d] - Kr)) <= 1e-5 * np.max(np.abs(Kr)), (n, d, K[d], Kr)
+        scale = np.abs(w[:, o:o + n * n]).sum(axis=1)
+        assert np.all(np.abs(mass[d]) <= 1e-5 * scale + 1e-30)
+    H.close()
+
+
+def test_chunked_solve_matches_single_launch(torch):
+    p = _single_level(32, seed=9, amp=0.3, kappa=0.05)
+    say("case chunked solve")
+    H = hier(p, keep_psi=False)
+    H.band_filter()
+    Kb = np.tile([0.05, 0.0, 0.05], (H.nd, 1))
+    H.K_base.copy_(torch.from_numpy(Kb))
+    H.ctx.shmm_plan_steps(0, H.nd, Kb)
+    total = int(H.ctx.shmm_ctx_table()[0]["nsteps"].max())
+    args = (H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(),
+            H.w.data_ptr())
+    H.w.zero_()
+    H.ctx.shmm_local_solve_batch(0, H.nd, *args, 0, total, 0, H.stream())
+    torch.cuda.synchronize()
+    one = H.w.cpu().numpy().copy()
+    H.w.zero_()
+    for b in range(0, total, 500):
+        H.ctx.shmm_local_solve_batch(0, H.nd, *args, b, 500, 0, H.stream())
+    torch.cuda.synchronize()
+    assert relerr(H.w.cpu().numpy(), one) <= 1e-6
+    H.close()
+
+
+def test_zero_band_returns_base_exactly(torch):
+    kmax = 4
+    p = flowgen.Problem(kappa=0.02, kmax=kmax, psi_hat=np.zeros((9, 9), complex), thresh=[],
+                        n_cells=[32], n_global=[64], lattice=[2])
+    say("case zero band")
+    H = hier(p, keep_psi=False)
+    H.run()
+    r = H.result()
+    assert np.array_equal(r.K_total, np.tile([0.02, 0.0, 0.02], (4, 1)))
+    H.close()
+
+
+# ---------------------------------------------------------------- whole pass
+
+PASS_CASES = [
+    ("two-level-64", lambda: flowgen.config_two_level_cellular()),
+    ("four-level-32x4", lambda: flowgen.config_four_level_cellular(n=32, lattice=2)),
+    ("shear-closed-form", lambda: flowgen.config_shear(k=16, V=1.0, kappa=1e-2, n=32, levels=2, thresh=[8])),
+    ("continuous-3lvl", lambda: flowgen.config_continuous(seed=2, radius=40, n=16, lattice=2, levels=3)),
+    ("batched-2", lambda: [flowgen.config_batched_instance(5), flowgen.config_batched_instance(11)]),
+]
+
+
+@pytest.mark.parametrize("name,make", PASS_CASES)
+def test_hierarchy_parity(torch, name, make):
+    probs = make()
+    if name == "batched-2":
+        for q in probs:      # keep the oracle within seconds
+            q.n_cells = [16] * len(q.n_cells)
+            q.n_global = [16 * 4 ** l for l in range(len(q.n_cells))]
+            q.lattice = [2] * len(q.n_cells)
+    say("case hierarchy", name)
+    H = hier(probs, keep_psi=False)
+    H.run()
+    r = H.result()
+    ref = oracle.run_hierarchy(probs)
+    for d in range(H.nd):
+        assert int(r.nsteps[d]) == int(ref.nsteps[d]) or abs(int(r.nsteps[d]) - int(ref.nsteps[d])) <= 1
+        Kr = ref.R[d]
+        assert np.max(np.abs(r.R[d] - Kr)) <= 1e-5 * np.max(np.abs(Kr)), (name, d, r.R[d], Kr)
+    if name == "shear-closed-form":
+        assert abs(r.K_total[0][2] - 0.2053125) <= 1e-12
+    assert int(H.status.cpu().numpy().max()) == 0
+    H.close()
+
+
+def test_pass_is_deterministic(torch):
+    p = flowgen.config_four_level_cellular(n=16, lattice=2)
+    say("case determinism")
+    H = hier(p, keep_psi=False)
+    H.run()
+    a = H.result().R.copy()
+    H.run()
+    b = H.result().R.copy()
+    assert np.array_equal(a, b)
+    H.close()
+
+
+# ---------------------------------------------------------------- macro
+
+@pytest.mark.parametrize("dtype", [64, 32])
+def test_macro_step_parity(torch, dtype):
+    from paper_1510_00451_amd import abi
+    N = 64
+    h = 2 * np.pi / N
+    x = np.arange(N) * h
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    vx, vy, _, _ = oracle.staggered(np.sin(X) * np.sin(Y), h)
+    xc = (np.arange(N) + 0.5) * h
+    XC, YC = np.meshgrid(xc, xc, indexing="xy")
+    Kc = np.stack([0.1 + 0.03 * np.cos(XC), 0.01 * np.sin(YC), 0.12 + 0.0 * XC], -1)
+    u0 = flowgen.macro_initial_gaussian(N)
+    dt, ns = oracle.macro_plan(N, Kc, 2.0, 0.2, 0.5)
+    say("case macro dtype", dtype)
+    ref = oracle.macro_run(N, vx, vy, Kc, u0, dt, ns)
+    tdt = torch.float64 if dtype == 64 else torch.float32
+    dvx = torch.tensor(vx, dtype=tdt, device="cuda").contiguous()
+    dvy = torch.tensor(vy, dtype=tdt, device="cuda").contiguous()
+    dK = torch.tensor(Kc.reshape(-1, 3), dtype=torch.float64, device="cuda").contiguous()
+    du = torch.tensor(u0, dtype=tdt, device="cuda").contiguous()
+    ctx = abi.Context(0)
+    ctx.shmm_macro_step(N, dvx.data_ptr(), dvy.data_ptr(), dK.data_ptr(), 1, dt, ns, du.data_ptr(),
+                        dtype, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    got = du.cpu().numpy().astype(np.float64)
+    tol = 1e-12 if dtype == 64 else 1e-6
+    assert relerr(got, ref) <= tol
+    assert abs(got.sum() - u0.sum()) <= (1e-12 if dtype == 64 else 1e-5) * abs(u0.sum())
+    ctx.close()
+
+
+# ---------------------------------------------------------------- full size
+
+def test_full_size_four_level_sampled(torch):
+    """The four-level cellular workload at its full size (64 patches of 128^2 per
+    level): band filter on every patch, and the first solve phase for a bounded
+    number of steps, checked on sampled patches against the oracle."""
+    p = flowgen.config_four_level_cellular()
+    say("case full size four-level")
+    H = hier(p, keep_psi=False)
+    H.band_filter()
+    H.top_down()
+    torch.cuda.synchronize()
+    lv, pt = oracle.band_split(p.kmax, p.thresh)
+    rng = np.random.default_rng(0)
+    sample = sorted(rng.choice(H.nd, 6, replace=False).tolist())
+    vx, vy = H.vx.cpu().numpy(), H.vy.cpu().numpy()
+    for d in sample:
+        D = H.table[d]
+        n, o = int(D["n"]), int(D["offset"])
+        ref = oracle.synth_patch(p.psi_hat, p.kmax, oracle.band_mask(lv, pt, int(D["level"]), DIAG),
+                                 int(D["N"]), int(D["I0"]), int(D["J0"]), n)
+        rvx, rvy, _, _ = oracle.staggered(ref, float(D["h"]))
+        vs = max(np.abs(rvx).max(), np.abs(rvy).max())
+        assert np.abs(vx[o:o + n * n].reshape(n, n) - rvx).max() <= 2e-6 * vs
+        assert np.abs(vy[o:o + n * n].reshape(n, n) - rvy).max() <= 2e-6 * vs
+    # first phase (finest level), 100 steps on all 64 patches
+    first, count = int(H.phase[0]), int(H.phase[1] - H.phase[0])
+    H.ctx.shmm_level_chain(first, count, 1, H.lines.data_ptr(), H.K_in.data_ptr(), H.K_off.data_ptr(),
+                           H.K_base.data_ptr(), 0, H.R.data_ptr(), 0, H.stream())
+    Kb = H.K_base.cpu().numpy()
+    H.ctx.shmm_plan_steps(first, count, Kb)
+    H.w.zero_()
+    H.ctx.shmm_local_solve_batch(first, count, H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(),
+                                 H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(), 0, 100, 0,
+                                 H.stream())
+    torch.cuda.synchronize()
+    table, cells, _, _ = H.ctx.shmm_ctx_table()
+    w = H.w.cpu().numpy().reshape(2, cells)
+    for d in (first, first + count - 1):
+        D = table[d]
+        n, o = int(D["n"]), int(D["offset"])
+        ref = oracle.synth_patch(p.psi_hat, p.kmax, oracle.band_mask(lv, pt, int(D["level"]), DIAG),
+                                 int(D["N"]), int(D["I0"]), int(D["J0"]), n)
+        rvx, rvy, rf1, rf2 = oracle.staggered(ref, float(D["h"]))
+        wr = oracle.local_solve_batch([n], [float(D["h"])], rvx.ravel(), rvy.ravel(), rf1.ravel(),
+                                      rf2.ravel(), Kb[d:d + 1], [float(D["dt"])], [100])
+        for j in range(2):
+            assert relerr(w[j, o:o + n * n], wr[j]) <= 1e-5
+    H.close()
