@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark of the SHMM hot path on one MI355X.
+
+One step = one pass of the hot path over the four-level cellular workload
+(psi = sum_{k=1,4,16,64} k^(-4/3) sin(kx+p1) sin(ky+p2), kappa = 1e-2, 4 levels
+of 64 patches of 128^2 cells) plus the shear check instance v = (0, sin 16x):
+band filter, top-down Algorithm 2, then every phase (base, step plan, local
+solves, FP64 effective diffusivity, level combination), all on the GPU with
+the inputs resident in HBM.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "κ_eff estimates/s + Gpoint-steps/s; surrogate vs plain at ≤1% κ_eff error"
+# Algorithmic FP32 work of one point-step (one cell of one patch, one classic
+# RK4 step, both correctors): per corrector 4 evaluations of the 9-point
+# operator with forcing (6 FMA + 4 ADD = 16 flop), 3 stage inputs (2 flop each)
+# and the final update (8 flop): 78 flop; two correctors.
+FLOP_PER_POINT_STEP = 156
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (256 CU, 2.4 GHz)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload():
+    import flowgen
+    main = flowgen.config_four_level_cellular(seed=0, n=128, lattice=8)
+    shear = flowgen.config_shear(k=16, V=1.0, kappa=1e-2, n=128, levels=2, thresh=[8])
+    return [main, shear]
+
+
+def cpu_baseline(steps_sample: int = 2000, domains_sample: int = 32):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload:
+    the finest-level patches of the four-level instance, a fixed number of RK4
+    steps each, OpenMP over (patch, corrector)."""
+    import oracle
+    import flowgen
+    p = flowgen.config_four_level_cellular(seed=0, n=128, lattice=8)
+    doms = [d for d in oracle.domain_table(p) if d.level == 3][:domains_sample]
+    lv, pt = oracle.band_split(p.kmax, p.thresh)
+    fields = [oracle.level_fields(p, lv, pt, d) for d in doms]
+    vx = np.concatenate([f[1].ravel() for f in fields])
+    vy = np.concatenate([f[2].ravel() for f in fields])
+    f1 = np.concatenate([f[3].ravel() for f in fields])
+    f2 = np.concatenate([f[4].ravel() for f in fields])
+    Kb = np.tile([p.kappa, 0.0, p.kappa], (len(doms), 1))
+    Vb = oracle.band_speed_bound(p.psi_hat, p.kmax, oracle.band_mask(lv, pt, 3, oracle.DIAG))
+    dt, _ = oracle.plan_steps(128, doms[0].h, Kb[0], Vb, p.dt_frac, p.delta)
+    t0 = time.perf_counter()
+    oracle.local_solve_batch([d.n for d in doms], [d.h for d in doms], vx, vy, f1, f2, Kb,
+                             [dt] * len(doms), [steps_sample] * len(doms))
+    el = time.perf_counter() - t0
+    pts = sum(d.n * d.n for d in doms) * steps_sample
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": pts / el / 1e9, "unit": "Gpoint-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(doms)} finest-level 128^2 patches x {steps_sample} RK4 steps "
+                      f"(both correctors, FP64), {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        log("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
+            "(patches are independent; see the sharding note in DESIGN.md). Use --gpus 1.")
+        sys.exit(2)
+
+    import torch
+    from paper_1510_00451_amd.hierarchy import Hierarchy
+    if not torch.cuda.is_available():
+        log("no HIP device: the benchmark needs an MI355X")
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    probs = workload()
+    H = Hierarchy(probs, keep_psi=False)
+    log(f"domains {H.nd}, cells {H.cells}, phases {len(H.phase) - 1}")
+
+    events = []
+
+    def timed_solve(first, count, fn):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        events.append((first, count, a, b))
+
+    H.solve_hook = timed_solve
+    for i in range(args.warmup):
+        H.run()
+        torch.cuda.synchronize()
+        log(f"warmup pass {i} done")
+    events.clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        H.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    el = t1 - t0
+    res = H.result()
+    log(f"timed {args.steps} passes in {el:.3f} s")
+
+    # per-launch kernel time of the local solves (HIP events on the launch stream)
+    table = H.ctx.shmm_ctx_table()[0]
+    pts_launch, ms_launch = [], []
+    for first, count, a, b in events:
+        ms_launch.append(a.elapsed_time(b))
+        pts_launch.append(int(np.sum(table["n"][first:first + count].astype(np.int64) ** 2
+                                     * table["nsteps"][first:first + count].astype(np.int64))))
+    avg_ms = float(np.mean(ms_launch))
+    avg_flop = FLOP_PER_POINT_STEP * float(np.mean(pts_launch))
+    achieved_tflops = avg_flop / (avg_ms * 1e-3) / 1e12
+
+    pass_pts = res.point_steps
+    gpts = pass_pts * args.steps / el / 1e9
+    est = H.nd * args.steps / el
+    shear_idx = [i for i, d in enumerate(table) if d["instance"] == 1 and d["level"] == 0][0]
+    out = {
+        "metric": METRIC,
+        "value": round(gpts, 3),
+        "unit": "Gpoint-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(el / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 stencils, f64 reductions",
+        "data": "synthetic",
+        "config": {"workload": "cellular-4level-64x128 + shear-k16",
+                   "levels": 4, "patches_per_level": 64, "n": 128, "kappa": 1e-2,
+                   "band_edges": [2, 8, 32], "delta": 1e-6, "dt_frac": 0.5,
+                   "point_steps_per_pass": pass_pts, "estimates_per_pass": int(H.nd)},
+        "kappa_eff_estimates_per_s": round(est, 2),
+        "K_total_mean": np.mean(res.K_total[:64], axis=0).round(10).tolist(),
+        "shear_Kyy": float(res.R[shear_idx][2]),
+        "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3),
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+                     "traffic": None,
+                     "kernel": "k_solve_resident<128,32>",
+                     "launches": len(ms_launch), "avg_launch_ms": round(avg_ms, 3)},
+    }
+    H.close()
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -94,14 +94,14 @@ __device__ __forceinline__ void rk_stage(const float *__restrict__ C, int offW, 
 }
 
 template <int NN, int R, int FIELD>
-__global__ __launch_bounds__(NN *NN / R) void k_solve_resident(
-    const shmm_domain *__restrict__ dom, const int32_t *__restrict__ list,
-    const float *__restrict__ vx, const float *__restrict__ vy, const double *__restrict__ Kb,
-    float *__restrict__ w, int64_t cells_total, int32_t step_begin, int32_t steps) {
+__device__ __forceinline__ void solve_body(float *__restrict__ buf, const shmm_domain *__restrict__ dom,
+                                           const int32_t *__restrict__ list,
+                                           const float *__restrict__ vx, const float *__restrict__ vy,
+                                           const double *__restrict__ Kb, float *__restrict__ w,
+                                           int64_t cells_total, int32_t step_begin, int32_t steps) {
     constexpr int MASK = NN - 1;
     constexpr int PLANE = NN * NN;
-    __shared__ float buf[2 * PLANE];
-    const int64_t d = list[blockIdx.x];
+    const int64_t d = list[blockIdx.x >> 1];
     const shmm_domain D = dom[d];
     const int64_t s_end64 = (int64_t)step_begin + steps;
     const int32_t s_end = (int32_t)(s_end64 < D.nsteps ? s_end64 : D.nsteps);
@@ -155,6 +155,20 @@ __global__ __launch_bounds__(NN *NN / R) void k_solve_resident(
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) wf[r * NN] = wv[r];
+}
+
+// Workgroup 2 i + j advances corrector j of patch list[i]: both correctors of
+// every patch of the phase run in one launch.
+template <int NN, int R>
+__global__ __launch_bounds__(NN *NN / R) void k_solve_resident(
+    const shmm_domain *__restrict__ dom, const int32_t *__restrict__ list,
+    const float *__restrict__ vx, const float *__restrict__ vy, const double *__restrict__ Kb,
+    float *__restrict__ w, int64_t cells_total, int32_t step_begin, int32_t steps) {
+    __shared__ float buf[2 * NN * NN];
+    if (blockIdx.x & 1)
+        solve_body<NN, R, 1>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
+    else
+        solve_body<NN, R, 0>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
 }
 
 // Fallback for patches that do not fit in LDS: one launch per RK stage, state
@@ -233,10 +247,7 @@ template <int NN, int R>
 int launch_resident(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, const float *vx,
                     const float *vy, const double *Kb, float *w, int64_t cells_total,
                     int32_t step_begin, int32_t steps, hipStream_t s) {
-    hipLaunchKernelGGL((k_solve_resident<NN, R, 0>), dim3((unsigned)nlist), dim3(NN * NN / R), 0, s,
-                       d_dom, d_list, vx, vy, Kb, w, cells_total, step_begin, steps);
-    SHMM_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL((k_solve_resident<NN, R, 1>), dim3((unsigned)nlist), dim3(NN * NN / R), 0, s,
+    hipLaunchKernelGGL((k_solve_resident<NN, R>), dim3((unsigned)(2 * nlist)), dim3(NN * NN / R), 0, s,
                        d_dom, d_list, vx, vy, Kb, w, cells_total, step_begin, steps);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;

@@ -70,6 +70,8 @@ class Hierarchy:
         self.status = torch.zeros(nd, dtype=torch.int32, device=self.device)
         self.host_K = np.zeros((nd, 3))
         self.level0 = np.flatnonzero(self.table["level"] == 0)
+        # optional callable(first, count, launch) wrapped around each solve launch
+        self.solve_hook = None
 
     # -- pieces -------------------------------------------------------------
     def stream(self) -> int:
@@ -110,10 +112,16 @@ class Hierarchy:
         c.shmm_plan_steps(first, count, self.host_K)
         a, b = self.cell_range(first, count)
         self.w.view(2, self.cells)[:, a:b].zero_()
-        c.shmm_local_solve_batch(first, count, self.vx.data_ptr(), self.vy.data_ptr(),
-                                 self.f1.data_ptr(), self.f2.data_ptr(), self.K_base.data_ptr(),
-                                 self.w.data_ptr(), 0, 2 ** 31 - 1 if steps is None else steps,
-                                 self.status.data_ptr(), s)
+        def launch():
+            c.shmm_local_solve_batch(first, count, self.vx.data_ptr(), self.vy.data_ptr(),
+                                     self.f1.data_ptr(), self.f2.data_ptr(), self.K_base.data_ptr(),
+                                     self.w.data_ptr(), 0, 2 ** 31 - 1 if steps is None else steps,
+                                     self.status.data_ptr(), s)
+
+        if self.solve_hook is None:
+            launch()
+        else:
+            self.solve_hook(first, count, launch)
         c.shmm_effective_diffusivity(first, count, self.f1.data_ptr(), self.f2.data_ptr(),
                                      self.w.data_ptr(), self.K_base.data_ptr(),
                                      self.K_solve.data_ptr(), self.K_energy.data_ptr(),
