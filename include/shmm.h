@@ -106,7 +106,7 @@ typedef struct shmm_domain {
     int64_t offset;     /* first cell in the packed [domain][y][x] arrays */
     int64_t line_offset;/* first entry in the packed line energies (2 n per domain) */
     double h;           /* 2 pi / N */
-    double dt;          /* RK4 step */
+    double dt;          /* RK4 step (-1 until planned) */
 } shmm_domain;
 
 typedef struct shmm_ctx shmm_ctx;
@@ -147,8 +147,10 @@ int shmm_band_tags(shmm_ctx *ctx, int32_t inst, int8_t *d_tags, void *stream);
  * dt = T/nsteps with T = ln(1/delta) / (lambda_min(K_b) 4 sin^2(pi/n) / h^2)
  * and nsteps = ceil(T / (dt_frac / (rho_D/2.785 + rho_A/2.828))),
  * rho_D = (4 K11 + 4 K22 + 2|K12|)/h^2, rho_A = V_b/h, V_b = sum over the
- * level's diagonal band of |psi_hat(k)| (|k1| + |k2|).  K_base is host
- * [n_domains][3] indexed by global domain.  Host arithmetic, bit-exact;
+ * level's diagonal band of |psi_hat(k)| (|k1| + |k2|).  A patch whose diagonal
+ * band holds no coefficient has zero forcing, so its corrector stays zero: it
+ * gets nsteps = 0, dt = 0 and the local solve leaves it untouched.  K_base is
+ * host [n_domains][3] indexed by global domain.  Host arithmetic, bit-exact;
  * updates the context's table on host and device (synchronous).
  * Errors: SHMM_ENOTSPD if a base is not positive definite. */
 int shmm_plan_steps(shmm_ctx *ctx, int64_t first, int64_t count, const double *K_base);
@@ -176,8 +178,9 @@ int shmm_band_filter(shmm_ctx *ctx, int64_t first, int64_t count, float *d_psi, 
  * RK4, steps [step_begin, min(step_begin + steps, nsteps_d)) of each domain.
  * d_K_base is [n_domains][3] (global index), d_w is [2][n_cells_total] FP32
  * in/out.  FP32 stencils with a compensated state update.  Requires
- * shmm_plan_steps on the range.  d_status (may be NULL) gets SHMM_DOM_* bits.
- * Errors: SHMM_EINVAL for an empty plan. */
+ * shmm_plan_steps on the range; patches planned with zero steps are skipped.
+ * d_status (may be NULL) gets SHMM_DOM_* bits.
+ * Errors: SHMM_EINVAL for a range that was never planned. */
 int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const float *d_vx,
                            const float *d_vy, const float *d_f1, const float *d_f2,
                            const double *d_K_base, float *d_w, int32_t step_begin,
@@ -210,6 +213,16 @@ int shmm_effective_diffusivity(shmm_ctx *ctx, int64_t first, int64_t count, cons
 int shmm_level_chain(shmm_ctx *ctx, int64_t first, int64_t count, int32_t mode,
                      const double *d_lines, double *d_K_in, double *d_K_off, double *d_K_base,
                      const double *d_K_solve, double *d_R, int32_t *d_status, void *stream);
+
+/* Kernel selection for the autotuner (no effect on results beyond rounding
+ * order).  key = a patch size n (power of two): select local-solve kernel
+ * variant `value` for patches of that size, 0 <= value < the count returned by
+ * key = SHMM_TUNE_SOLVE_VARIANT_COUNT with value = n (a non-negative return).
+ * Variants for n = 64 and 128: 0 = whole patch staged in LDS, column strips;
+ * 1 = rows per wavefront, 16 rows per thread; 2 = rows per wavefront, 8 rows
+ * per thread.  Errors: SHMM_EINVAL for an unknown key or value. */
+#define SHMM_TUNE_SOLVE_VARIANT_COUNT 0
+int shmm_ctx_tune(shmm_ctx *ctx, int32_t key, int32_t value);
 
 /* Macro solver (HMM step 4 on eq:homo with the resolved velocity kept as
  * advection): nsteps classic RK4 steps of

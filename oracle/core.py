@@ -475,6 +475,7 @@ def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = N
     nsteps = np.zeros(nd, np.int64)
     lines = np.zeros(sum(2 * d.n for d in doms))
     vb_cache: Dict[Tuple[int, int], float] = {}
+    empty_band: Dict[Tuple[int, int], bool] = {}
     for i, d in enumerate(doms):
         p = probs[d.instance]
         lv, pt = splits[d.instance]
@@ -484,7 +485,9 @@ def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = N
             p.psi_hat, p.kmax, band_mask(lv, pt, d.level, OFF21), d.N, d.J0, d.n, 1)
         key = (d.instance, d.level)
         if key not in vb_cache:
-            vb_cache[key] = band_speed_bound(p.psi_hat, p.kmax, band_mask(lv, pt, d.level, DIAG))
+            dm = band_mask(lv, pt, d.level, DIAG)
+            vb_cache[key] = band_speed_bound(p.psi_hat, p.kmax, dm)
+            empty_band[key] = not np.any((dm != 0) & (p.psi_hat != 0))
 
     def s12(i):
         d = doms[i]
@@ -527,6 +530,9 @@ def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = N
             p = probs[d.instance]
             dt[i], nsteps[i] = plan_steps(d.n, d.h, K_base[i], vb_cache[(d.instance, lev)],
                                           p.dt_frac, p.delta)
+            if empty_band[(d.instance, lev)]:
+                # zero forcing: the corrector stays zero, nothing is integrated
+                dt[i], nsteps[i] = 0.0, 0
         # fields and solves of this level (one batch)
         fields = [level_fields(probs[doms[i].instance], *splits[doms[i].instance], doms[i]) for i in idx]
         vx = np.concatenate([f[1].reshape(-1) for f in fields])

@@ -22,7 +22,7 @@ MAX_LEVELS = 8
 EXPORTS = ["shmm_ctx_create", "shmm_ctx_destroy", "shmm_build_levels", "shmm_ctx_set_problem",
            "shmm_ctx_table", "shmm_band_tags", "shmm_plan_steps", "shmm_band_filter",
            "shmm_local_solve_batch", "shmm_effective_diffusivity", "shmm_level_chain",
-           "shmm_macro_step"]
+           "shmm_macro_step", "shmm_ctx_tune"]
 
 
 class ShmmError(RuntimeError):
@@ -69,6 +69,7 @@ def lib() -> ctypes.CDLL:
             "shmm_effective_diffusivity": [P, i64, i64, P, P, P, P, P, P, P, P, P],
             "shmm_level_chain": [P, i64, i64, i32, P, P, P, P, P, P, P, P],
             "shmm_macro_step": [P, i32, P, P, P, i32, f64, i32, P, i32, P],
+            "shmm_ctx_tune": [P, i32, i32],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -193,6 +194,15 @@ class Context:
         check(lib().shmm_level_chain(self.h, first, count, mode, d_lines, d_K_in, d_K_off,
                                      d_K_base or None, d_K_solve or None, d_R or None,
                                      d_status or None, stream), "shmm_level_chain")
+
+    def shmm_ctx_tune(self, key: int, value: int) -> int:
+        rc = lib().shmm_ctx_tune(self.h, int(key), int(value))
+        if rc < 0:
+            raise ShmmError(rc, "shmm_ctx_tune")
+        return rc
+
+    def solve_variants(self, n: int) -> int:
+        return self.shmm_ctx_tune(0, n)
 
     def shmm_macro_step(self, N, d_vx, d_vy, d_K, K_is_field, dt, nsteps, d_u, dtype, stream=0):
         check(lib().shmm_macro_step(self.h, N, d_vx or None, d_vy or None, d_K, int(K_is_field),

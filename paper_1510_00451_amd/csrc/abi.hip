@@ -85,7 +85,7 @@ void build_table(const shmm_problem *p, int32_t n_inst, std::vector<shmm_domain>
                     d.offset = cells;
                     d.line_offset = lines;
                     d.h = 2.0 * M_PI / (double)N;
-                    d.dt = 0.0;
+                    d.dt = -1.0;   // not planned yet
                     out.push_back(d);
                     cells += (int64_t)n * n;
                     lines += 2 * (int64_t)n;
@@ -216,7 +216,9 @@ struct shmm_ctx {
     int32_t *d_origins = nullptr;
     int32_t *d_child_start = nullptr, *d_child_idx = nullptr;
     std::vector<std::vector<double>> vb;     // [inst][level]
+    std::vector<std::vector<int>> empty;     // [inst][level]: diagonal band without coefficients
     std::map<std::pair<int64_t, int64_t>, RangeLists> lists;
+    std::map<int, int> solve_variant;          // patch size n -> kernel variant
     void *work = nullptr;
     size_t work_bytes = 0;
 
@@ -260,7 +262,8 @@ struct shmm_ctx {
         if (it == lists.end()) {
             RangeLists rl;
             std::map<int, std::vector<int32_t>> byn;
-            for (int64_t d = first; d < first + count; ++d) byn[table[d].n].push_back((int32_t)d);
+            for (int64_t d = first; d < first + count; ++d)
+                if (!empty[table[d].instance][table[d].level]) byn[table[d].n].push_back((int32_t)d);
             for (auto &kv : byn) {
                 int32_t *p = nullptr;
                 int rc = upload(&p, kv.second.data(), kv.second.size());
@@ -276,6 +279,10 @@ struct shmm_ctx {
         return SHMM_OK;
     }
 };
+
+// Kernel variant per patch size when no tuning result was set: the
+// LDS-staged kernel (the fastest in the measurements on MI355X).
+static int default_solve_variant(int n) { (void)n; return 0; }
 
 static int set_device(shmm_ctx *ctx) {
     SHMM_HIP_CHECK(hipSetDevice(ctx->device));
@@ -338,6 +345,7 @@ int shmm_ctx_set_problem(shmm_ctx *ctx, const shmm_problem *p, int32_t n_inst) {
     ctx->geo.assign(n_inst, {});
     ctx->inst.assign(n_inst, InstDev());
     ctx->vb.assign(n_inst, {});
+    ctx->empty.assign(n_inst, {});
     for (int32_t q = 0; q < n_inst; ++q) {
         shmm_problem &P = ctx->probs[q];
         const int L = P.n_levels;
@@ -365,7 +373,12 @@ int shmm_ctx_set_problem(shmm_ctx *ctx, const shmm_problem *p, int32_t n_inst) {
         I.kmax = P.kmax;
         I.L = L;
         for (int l = 0; l < SHMM_MAX_LEVELS; ++l) I.thresh[l] = l + 1 < L ? P.thresh[l] : 0;
-        for (int l = 0; l < L; ++l) ctx->vb[q].push_back(band_speed_bound(P, l));
+        for (int l = 0; l < L; ++l) {
+            ctx->vb[q].push_back(band_speed_bound(P, l));
+            int kb1 = 0, kb2 = 0;
+            band_extent(P, l, &kb1, &kb2);
+            ctx->empty[q].push_back(kb1 == 0 && kb2 == 0 ? 1 : 0);
+        }
     }
     if ((rc = upload(&ctx->d_inst, ctx->inst.data(), ctx->inst.size()))) return rc;
     build_table(ctx->probs.data(), n_inst, ctx->table, ctx->cells, ctx->lines, ctx->phase_first);
@@ -447,6 +460,11 @@ int shmm_plan_steps(shmm_ctx *ctx, int64_t first, int64_t count, const double *K
         int64_t ns = 0;
         rc = plan_one(D, K_base + 3 * d, ctx->vb[D.instance][D.level], P.dt_frac, P.delta, &dt, &ns);
         if (rc) return rc;
+        if (ctx->empty[D.instance][D.level]) {
+            // zero forcing: the corrector stays zero, nothing to integrate
+            dt = 0.0;
+            ns = 0;
+        }
         D.dt = dt;
         D.nsteps = (int32_t)ns;
     }
@@ -487,7 +505,7 @@ int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const fl
     int rc = set_device(ctx);
     if (rc) return rc;
     for (int64_t d = first; d < first + count; ++d)
-        if (ctx->table[d].nsteps <= 0) return SHMM_EINVAL;
+        if (ctx->table[d].nsteps < 0 || ctx->table[d].dt < 0.0) return SHMM_EINVAL;   // unplanned
     RangeLists *rl = nullptr;
     if ((rc = ctx->range_lists(first, count, &rl))) return rc;
     for (size_t q = 0; q < rl->ns.size(); ++q) {
@@ -496,9 +514,11 @@ int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const fl
             if (ctx->table[d].n == rl->ns[q]) max_steps = std::max(max_steps, ctx->table[d].nsteps);
         const size_t need = local_solve_workspace(rl->ns[q], rl->cells[q]);
         if (need && (rc = ctx->ensure_work(need))) return rc;
+        const auto it = ctx->solve_variant.find(rl->ns[q]);
+        const int variant = it == ctx->solve_variant.end() ? default_solve_variant(rl->ns[q]) : it->second;
         rc = launch_local_solve(ctx->d_table, rl->d_lists[q], rl->counts[q], rl->ns[q], max_steps,
                                 d_vx, d_vy, d_f1, d_f2, d_K_base, d_w, ctx->cells, step_begin, steps,
-                                rl->cells[q], ctx->work, (hipStream_t)stream);
+                                rl->cells[q], ctx->work, variant, (hipStream_t)stream);
         if (rc) return rc;
     }
     return SHMM_OK;
@@ -529,6 +549,17 @@ int shmm_level_chain(shmm_ctx *ctx, int64_t first, int64_t count, int32_t mode,
     return launch_level_chain(ctx->d_table, ctx->d_inst, ctx->d_child_start, ctx->d_child_idx, first,
                               count, mode, d_lines, d_K_in, d_K_off, d_K_base, d_K_solve, d_R,
                               d_status, (hipStream_t)stream);
+}
+
+int shmm_ctx_tune(shmm_ctx *ctx, int32_t key, int32_t value) {
+    if (!ctx) return SHMM_EINVAL;
+    if (key == SHMM_TUNE_SOLVE_VARIANT_COUNT) return local_solve_variants(value);
+    if (key > 0 && key <= 4096 && (key & (key - 1)) == 0) {
+        if (value < 0 || value >= local_solve_variants(key)) return SHMM_EINVAL;
+        ctx->solve_variant[key] = value;
+        return SHMM_OK;
+    }
+    return SHMM_EINVAL;
 }
 
 int shmm_macro_step(shmm_ctx *ctx, int32_t N, const void *d_vx, const void *d_vy, const double *d_K,

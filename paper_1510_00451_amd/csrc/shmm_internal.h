@@ -68,8 +68,9 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
                        int32_t max_steps, const float *vx, const float *vy, const float *f1,
                        const float *f2, const double *Kb, float *w, int64_t cells_total,
                        int32_t step_begin, int32_t steps, int64_t list_cells, void *work,
-                       hipStream_t s);
+                       int variant, hipStream_t s);
 bool local_solve_resident(int n);
+int local_solve_variants(int n);
 size_t local_solve_workspace(int n, int64_t list_cells);
 
 int launch_effective_diffusivity(const shmm_domain *d_dom, int64_t first, int64_t count,

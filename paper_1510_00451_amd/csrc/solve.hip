@@ -171,6 +171,197 @@ __global__ __launch_bounds__(NN *NN / R) void k_solve_resident(
         solve_body<NN, R, 0>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
 }
 
+// Row-resident variant for patches whose row fits one wavefront (n = 64 C):
+// lane l owns columns [C l, C l + C) of R consecutive rows; a wavefront owns
+// whole rows, so the x-neighbours across lanes come from wave-wide DPP
+// rotations (which also realise the periodic wrap) and the stage input stays
+// in registers.  Only the first and last row of each wavefront's strip go
+// through LDS (double-buffered), read by the wavefronts above and below.
+__device__ __forceinline__ float from_prev_lane(float v) {   // lane i <- lane (i - 1) mod 64
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x13C, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float from_next_lane(float v) {   // lane i <- lane (i + 1) mod 64
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xF, 0xF, false));
+}
+
+template <int C>
+struct RowTuple {
+    float w, v[C], e;   // west neighbour, own cells, east neighbour
+};
+
+template <int C>
+__device__ __forceinline__ RowTuple<C> make_tuple(const float (&v)[C]) {
+    RowTuple<C> t;
+#pragma unroll
+    for (int c = 0; c < C; ++c) t.v[c] = v[c];
+    t.w = from_prev_lane(v[C - 1]);
+    t.e = from_next_lane(v[0]);
+    return t;
+}
+
+template <int C>
+__device__ __forceinline__ float left_of(const RowTuple<C> &t, int c) { return c == 0 ? t.w : t.v[c - 1]; }
+template <int C>
+__device__ __forceinline__ float right_of(const RowTuple<C> &t, int c) { return c == C - 1 ? t.e : t.v[c + 1]; }
+
+template <int NN, int C, int R, int FIELD, int KIND>
+__device__ __forceinline__ void row_stage(const float *__restrict__ edge_in, float *__restrict__ edge_out,
+                                          int wave, int x0, const SolveConsts &k, float cw,
+                                          float (&aE)[R][C], float (&b)[R + 1][C], float (&y)[R][C],
+                                          float (&wv)[R][C], float (&comp)[R][C], float (&rr)[R][C]) {
+    constexpr int WAVES = NN / R;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c) asm volatile("" : "+v"(aE[r][c]));
+#pragma unroll
+    for (int r = 0; r <= R; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c) asm volatile("" : "+v"(b[r][c]));
+    // row above the strip: last row of the previous wavefront (periodic)
+    const int up = (wave + WAVES - 1) % WAVES, down = (wave + 1) % WAVES;
+    float tmp[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) tmp[c] = edge_in[(up * 2 + 1) * NN + x0 + c];
+    RowTuple<C> S = make_tuple<C>(tmp);
+    RowTuple<C> M = make_tuple<C>(y[0]);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        RowTuple<C> N;
+        if (r + 1 < R) {
+            N = make_tuple<C>(y[r + 1]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) tmp[c] = edge_in[(down * 2 + 0) * NN + x0 + c];
+            N = make_tuple<C>(tmp);
+        }
+        // west face of the first owned cell: east face of the previous lane's last cell
+        const float aW0 = from_prev_lane(aE[r][C - 1]);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float ae = aE[r][c], aw = c == 0 ? aW0 : aE[r][c - 1];
+            const float bs = b[r][c], bn = b[r + 1][c];
+            const float cC = M.v[c], cE = right_of(M, c), cW = left_of(M, c);
+            const float nC = N.v[c], nE = right_of(N, c), nW = left_of(N, c);
+            const float sC = S.v[c], sE = right_of(S, c), sW = left_of(S, c);
+            float t = k.cc * cC;
+            t = fmaf(ae, cE, t);
+            t = fmaf(-aw, cW, t);
+            t = fmaf(bn, nC, t);
+            t = fmaf(-bs, sC, t);
+            t = fmaf(k.cxx, cE + cW, t);
+            t = fmaf(k.cyy, nC + sC, t);
+            t = fmaf(k.cxy, (nE - nW) - (sE - sW), t);
+            float o;
+            if (KIND == 0) {
+                const float ff = FIELD == 0 ? k.fh * (ae + aw) : k.fh * (bs + bn);
+                rr[r][c] = t + ff;
+                o = rr[r][c];
+            } else if (KIND == 1) {
+                o = fmaf(cw, t, rr[r][c]);
+            } else {
+                const float q1 = fmaf(0.5f, t, rr[r][c]);
+                const float yk = q1 - comp[r][c];
+                const float tk = wv[r][c] + yk;
+                comp[r][c] = (tk - wv[r][c]) - yk;
+                wv[r][c] = tk;
+                o = tk;
+            }
+            y[r][c] = o;
+        }
+        S = M;
+        M = N;
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        edge_out[(wave * 2 + 0) * NN + x0 + c] = y[0][c];
+        edge_out[(wave * 2 + 1) * NN + x0 + c] = y[R - 1][c];
+    }
+}
+
+template <int NN, int C, int R, int FIELD>
+__device__ __forceinline__ void rows_body(float *__restrict__ edges, const shmm_domain *__restrict__ dom,
+                                          const int32_t *__restrict__ list, const float *__restrict__ vx,
+                                          const float *__restrict__ vy, const double *__restrict__ Kb,
+                                          float *__restrict__ w, int64_t cells_total, int32_t step_begin,
+                                          int32_t steps) {
+    constexpr int WAVES = NN / R;
+    constexpr int EDGE = WAVES * 2 * NN;   // one buffer of boundary rows
+    const int64_t d = list[blockIdx.x >> 1];
+    const shmm_domain D = dom[d];
+    const int64_t s_end64 = (int64_t)step_begin + steps;
+    const int32_t s_end = (int32_t)(s_end64 < D.nsteps ? s_end64 : D.nsteps);
+    if (step_begin >= s_end) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int x0 = lane * C, y0 = wave * R;
+    const SolveConsts k = solve_consts(D, Kb, d);
+    const int64_t o = D.offset;
+    float aE[R][C], b[R + 1][C], y[R][C], wv[R][C], comp[R][C], rr[R][C];
+#pragma unroll
+    for (int r = 0; r <= R; ++r) {
+        const int yy = (y0 + r) & (NN - 1);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            b[r][c] = k.a * vy[o + yy * NN + x0 + c];
+            if (r < R) aE[r][c] = k.a * vx[o + yy * NN + ((x0 + c + 1) & (NN - 1))];
+        }
+    }
+    float *wf = w + (int64_t)FIELD * cells_total + o;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            wv[r][c] = wf[(y0 + r) * NN + x0 + c];
+            y[r][c] = wv[r][c];
+            comp[r][c] = 0.0f;
+            rr[r][c] = 0.0f;
+        }
+    float *e0 = edges, *e1 = edges + EDGE;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        e0[(wave * 2 + 0) * NN + x0 + c] = y[0][c];
+        e0[(wave * 2 + 1) * NN + x0 + c] = y[R - 1][c];
+    }
+    __syncthreads();
+    for (int32_t s = step_begin; s < s_end; ++s) {
+        row_stage<NN, C, R, FIELD, 0>(e0, e1, wave, x0, k, 0.0f, aE, b, y, wv, comp, rr);
+        __syncthreads();
+        row_stage<NN, C, R, FIELD, 1>(e1, e0, wave, x0, k, 0.25f, aE, b, y, wv, comp, rr);
+        __syncthreads();
+        row_stage<NN, C, R, FIELD, 1>(e0, e1, wave, x0, k, 1.0f / 3.0f, aE, b, y, wv, comp, rr);
+        __syncthreads();
+        row_stage<NN, C, R, FIELD, 2>(e1, e0, wave, x0, k, 0.5f, aE, b, y, wv, comp, rr);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c) wf[(y0 + r) * NN + x0 + c] = wv[r][c];
+}
+
+template <int NN, int C, int R>
+__global__ __launch_bounds__(64 * (NN / R)) void k_solve_rows(
+    const shmm_domain *__restrict__ dom, const int32_t *__restrict__ list,
+    const float *__restrict__ vx, const float *__restrict__ vy, const double *__restrict__ Kb,
+    float *__restrict__ w, int64_t cells_total, int32_t step_begin, int32_t steps) {
+    __shared__ float edges[2 * (NN / R) * 2 * NN];
+    if (blockIdx.x & 1)
+        rows_body<NN, C, R, 1>(edges, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
+    else
+        rows_body<NN, C, R, 0>(edges, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
+}
+
+template <int NN, int C, int R>
+int launch_rows(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, const float *vx,
+                const float *vy, const double *Kb, float *w, int64_t cells_total, int32_t step_begin,
+                int32_t steps, hipStream_t s) {
+    static_assert(NN == 64 * C, "a row must fill one wavefront");
+    hipLaunchKernelGGL((k_solve_rows<NN, C, R>), dim3((unsigned)(2 * nlist)), dim3(64 * (NN / R)), 0, s,
+                       d_dom, d_list, vx, vy, Kb, w, cells_total, step_begin, steps);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
+
 // Fallback for patches that do not fit in LDS: one launch per RK stage, state
 // in global memory.  Same arithmetic as the resident kernel.
 __global__ __launch_bounds__(256) void k_solve_stage(
@@ -257,6 +448,8 @@ int launch_resident(const shmm_domain *d_dom, const int32_t *d_list, int32_t nli
 
 bool local_solve_resident(int n) { return n == 8 || n == 16 || n == 32 || n == 64 || n == 128; }
 
+int local_solve_variants(int n) { return (n == 64 || n == 128) ? 3 : 1; }
+
 size_t local_solve_workspace(int n, int64_t list_cells) {
     if (local_solve_resident(n)) return 0;
     return (size_t)4 * 2 * list_cells * sizeof(float);   // ycur, ynext, acc, comp; 2 fields
@@ -266,7 +459,7 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
                        int32_t max_steps, const float *vx, const float *vy, const float *f1,
                        const float *f2, const double *Kb, float *w, int64_t cells_total,
                        int32_t step_begin, int32_t steps, int64_t list_cells, void *work,
-                       hipStream_t s) {
+                       int variant, hipStream_t s) {
     (void)f1;
     (void)f2;   // the forcing is rebuilt from the face velocities in registers
     if (nlist <= 0) return SHMM_OK;
@@ -274,8 +467,14 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
         case 8: return launch_resident<8, 2>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
         case 16: return launch_resident<16, 4>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
         case 32: return launch_resident<32, 8>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
-        case 64: return launch_resident<64, 16>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
-        case 128: return launch_resident<128, 32>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+        case 64:
+            if (variant == 1) return launch_rows<64, 1, 16>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            if (variant == 2) return launch_rows<64, 1, 8>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            return launch_resident<64, 16>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+        case 128:
+            if (variant == 1) return launch_rows<128, 2, 16>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            if (variant == 2) return launch_rows<128, 2, 8>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            return launch_resident<128, 32>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
         default: break;
     }
     // generic path

@@ -131,13 +131,16 @@ def _single_level(n, seed, amp, kappa, lattice=2, radius=None):
     return p
 
 
-@pytest.mark.parametrize("n,steps", [(8, None), (16, None), (32, None), (64, 400), (128, 60), (256, 12)])
-def test_local_solve_and_estimator_parity(torch, n, steps):
+@pytest.mark.parametrize("n,steps,variant", [(8, None, 0), (16, None, 0), (32, None, 0),
+                                             (64, 400, 0), (64, 400, 1), (64, 400, 2),
+                                             (128, 60, 0), (128, 60, 1), (128, 60, 2), (256, 12, 0)])
+def test_local_solve_and_estimator_parity(torch, n, steps, variant):
     """Band filter + RK4 local solve + FP64 estimator against the oracle's own
-    synthesis, solve and estimator, on an anisotropic base."""
+    synthesis, solve and estimator, on an anisotropic base (every kernel variant)."""
     p = _single_level(n, seed=n, amp=0.3, kappa=0.05)
-    say("case local solve n=%d steps=%s" % (n, steps))
+    say("case local solve n=%d steps=%s variant=%d" % (n, steps, variant))
     H = hier(p, keep_psi=False)
+    H.ctx.shmm_ctx_tune(n, variant)
     H.band_filter()
     Kb = np.tile([0.06, 0.015, 0.04], (H.nd, 1))
     H.K_base.copy_(torch.from_numpy(Kb))
@@ -173,8 +176,9 @@ def test_local_solve_and_estimator_parity(torch, n, steps):
     H.close()
 
 
-def test_chunked_solve_matches_single_launch(torch):
-    p = _single_level(32, seed=9, amp=0.3, kappa=0.05)
+@pytest.mark.parametrize("n", [32, 128])
+def test_chunked_solve_matches_single_launch(torch, n):
+    p = _single_level(n, seed=9, amp=0.3, kappa=0.05)
     say("case chunked solve")
     H = hier(p, keep_psi=False)
     H.band_filter()
