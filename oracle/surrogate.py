@@ -1,0 +1,232 @@
+"""FP64 oracle of the learned surrogate of the local solve.  TEST INFRASTRUCTURE
+ONLY (see the package docstring).
+
+The paper has no surrogate; these definitions are this project's readings:
+
+* Features of a patch (33): the patch velocity spectrum binned into 32
+  log-spaced radial bins of the patch-relative wavenumber q = |k| (units of
+  2 pi / L, L the patch side), edges 2^(b/8) for b = 0..32 (q in [1, 16)),
+  E_b = sum over the bin of |vx^(k)|^2 + |vy^(k)|^2 with the patch samples
+  treated as periodic and normalised so that sum_k = mean(vx^2 + vy^2), times
+  (L / 2 pi)^2 so the features carry stream-function units (K / kappa is
+  invariant under rescaling space); feature_b = log(E_b + 1e-8 E_tot + 1e-30)
+  with E_tot the sum of the 32 bins (the floor sits far above the rounding
+  noise of an FP32 transform, about 1e-12 E_tot, so empty bins read the same in
+  FP32 and FP64).  Feature 32 is log sqrt(det K_b) of the base diffusivity.
+* Network: 33 -> 256 -> 256 -> 256 -> 3 with exact (erf) GELU; inputs are
+  standardised with stored means and scales.  Head: L = [[e^o1, 0], [o2, e^o3]],
+  K = sqrt(det K_b) L L^T.
+* Loss: mean over the batch of |K_hat - K|_F^2 / |K|_F^2 (Frobenius norm of the
+  full 2x2 tensor).
+* Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 master weights.
+* Precision emulation: `bf16=True` rounds the network's inputs, weights and
+  hidden activations to bfloat16 (round to nearest even) exactly where the
+  GPU kernels feed its matrix cores, so both sides decide the same roundings.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+N_BINS = 32
+N_IN = 33
+WIDTH = 256
+N_OUT = 3
+LAYERS = [(N_IN, WIDTH), (WIDTH, WIDTH), (WIDTH, WIDTH), (WIDTH, N_OUT)]
+
+
+# ---------------------------------------------------------------- features
+
+def bin_edges() -> np.ndarray:
+    return np.array([2.0 ** (b / 8.0) for b in range(N_BINS + 1)])
+
+
+def patch_features(vx: np.ndarray, vy: np.ndarray, n: int, N: int, K_base) -> np.ndarray:
+    """33 features of one n x n patch (velocities [y][x]) with spacing 2 pi / N."""
+    vx = np.asarray(vx, np.float64).reshape(n, n)
+    vy = np.asarray(vy, np.float64).reshape(n, n)
+    ex = np.abs(np.fft.fft2(vx)) ** 2
+    ey = np.abs(np.fft.fft2(vy)) ** 2
+    e = (ex + ey) / float(n) ** 4 * (n / N) ** 2     # (L / 2 pi)^2 with L = n 2 pi / N
+    k = np.fft.fftfreq(n, 1.0 / n)
+    K1, K2 = np.meshgrid(k, k, indexing="xy")
+    q = np.sqrt(K1 ** 2 + K2 ** 2)
+    edges = bin_edges()
+    E = np.zeros(N_BINS)
+    for b in range(N_BINS):
+        sel = (q >= edges[b]) & (q < edges[b + 1])
+        E[b] = float(np.sum(e[sel]))
+    floor = 1e-8 * float(np.sum(E)) + 1e-30
+    out = np.zeros(N_IN)
+    for b in range(N_BINS):
+        out[b] = math.log(E[b] + floor)
+    K11, K12, K22 = [float(v) for v in K_base]
+    out[N_BINS] = 0.5 * math.log(K11 * K22 - K12 * K12)
+    return out
+
+
+# ---------------------------------------------------------------- bf16
+
+def bf16(x: np.ndarray) -> np.ndarray:
+    """Round float32 values to bfloat16 (nearest, ties to even), returned as float64."""
+    a = np.asarray(x, np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    r = ((u + np.uint64(0x7FFF) + lsb) >> np.uint64(16)) << np.uint64(16)
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+# ---------------------------------------------------------------- network
+
+def gelu(z):
+    return 0.5 * z * (1.0 + _erf(z / math.sqrt(2.0)))
+
+
+def gelu_grad(z):
+    return 0.5 * (1.0 + _erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+
+
+def _erf(z):
+    from scipy.special import erf
+    return erf(z)
+
+
+@dataclass
+class Net:
+    """Weights W_l of shape (out, in) and biases b_l; input standardisation."""
+    W: List[np.ndarray]
+    b: List[np.ndarray]
+    mu: np.ndarray = field(default_factory=lambda: np.zeros(N_IN))
+    sigma: np.ndarray = field(default_factory=lambda: np.ones(N_IN))
+
+    def copy(self) -> "Net":
+        return Net([w.copy() for w in self.W], [v.copy() for v in self.b], self.mu.copy(), self.sigma.copy())
+
+
+def init_net(seed: int) -> Net:
+    """He-uniform weights from a seeded generator (an input, not method arithmetic)."""
+    rng = np.random.default_rng(seed)
+    W, b = [], []
+    for fi, fo in LAYERS:
+        lim = math.sqrt(6.0 / fi)
+        W.append(rng.uniform(-lim, lim, (fo, fi)))
+        b.append(np.zeros(fo))
+    W[-1] *= 0.1
+    return Net(W, b)
+
+
+def forward(net: Net, x: np.ndarray, bf16_mode: bool = False):
+    """Forward pass; returns (outputs o [B][3], cache for the backward)."""
+    x = (np.asarray(x, np.float64) - net.mu) / net.sigma
+    rnd = bf16 if bf16_mode else (lambda a: np.asarray(a, np.float64))
+    acts = [rnd(x)]
+    pre = []
+    h = acts[0]
+    for l in range(4):
+        z = h @ rnd(net.W[l]).T + net.b[l]
+        pre.append(z)
+        if l < 3:
+            h = rnd(gelu(z))
+            acts.append(h)
+        else:
+            h = z
+    return h, (acts, pre)
+
+
+def head(o: np.ndarray, K_base: np.ndarray) -> np.ndarray:
+    """Cholesky head: K = sqrt(det K_b) L L^T, L = [[e^o1, 0], [o2, e^o3]]; returns [B][3]."""
+    o = np.atleast_2d(o)
+    Kb = np.atleast_2d(K_base)
+    s = np.sqrt(Kb[:, 0] * Kb[:, 2] - Kb[:, 1] ** 2)
+    l11, l21, l22 = np.exp(o[:, 0]), o[:, 1], np.exp(o[:, 2])
+    return np.stack([s * l11 * l11, s * l11 * l21, s * (l21 * l21 + l22 * l22)], 1)
+
+
+def loss_and_grad_o(o: np.ndarray, K_base: np.ndarray, K_true: np.ndarray):
+    """Mean relative Frobenius loss and its gradient with respect to the outputs."""
+    o = np.atleast_2d(o)
+    Kb = np.atleast_2d(K_base)
+    Kt = np.atleast_2d(K_true)
+    B = o.shape[0]
+    s = np.sqrt(Kb[:, 0] * Kb[:, 2] - Kb[:, 1] ** 2)
+    l11, l21, l22 = np.exp(o[:, 0]), o[:, 1], np.exp(o[:, 2])
+    Kh = head(o, Kb)
+    d = Kh - Kt
+    nrm = Kt[:, 0] ** 2 + 2 * Kt[:, 1] ** 2 + Kt[:, 2] ** 2
+    loss = float(np.mean((d[:, 0] ** 2 + 2 * d[:, 1] ** 2 + d[:, 2] ** 2) / nrm))
+    # dloss/dK_hat components (the off-diagonal appears twice in the norm)
+    g = np.stack([2 * d[:, 0], 4 * d[:, 1], 2 * d[:, 2]], 1) / nrm[:, None] / B
+    # K11 = s l11^2, K12 = s l11 l21, K22 = s (l21^2 + l22^2)
+    go = np.zeros_like(o)
+    go[:, 0] = (g[:, 0] * 2 * s * l11 * l11 + g[:, 1] * s * l11 * l21)     # dl11/do1 = l11
+    go[:, 1] = g[:, 1] * s * l11 + g[:, 2] * 2 * s * l21
+    go[:, 2] = g[:, 2] * 2 * s * l22 * l22
+    return loss, go
+
+
+def backward(net: Net, cache, go: np.ndarray, bf16_mode: bool = False):
+    """Gradients of the weights and biases for the output gradient go."""
+    acts, pre = cache
+    rnd = bf16 if bf16_mode else (lambda a: np.asarray(a, np.float64))
+    gW = [None] * 4
+    gb = [None] * 4
+    dz = go
+    for l in range(3, -1, -1):
+        dzr = rnd(dz)                       # matrix-core operand
+        gW[l] = dzr.T @ acts[l]
+        gb[l] = dz.sum(axis=0)
+        if l > 0:
+            dh = dzr @ rnd(net.W[l])
+            dz = dh * gelu_grad(pre[l - 1])
+    return gW, gb
+
+
+@dataclass
+class Adam:
+    lr: float = 1e-3
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    t: int = 0
+    m: Optional[List[np.ndarray]] = None
+    v: Optional[List[np.ndarray]] = None
+
+    def step(self, params: List[np.ndarray], grads: List[np.ndarray], lr: Optional[float] = None):
+        """One Adam update with bias correction (Kingma & Ba), in place."""
+        if self.m is None:
+            self.m = [np.zeros_like(p) for p in params]
+            self.v = [np.zeros_like(p) for p in params]
+        self.t += 1
+        a = self.lr if lr is None else lr
+        c1 = 1.0 - self.beta1 ** self.t
+        c2 = 1.0 - self.beta2 ** self.t
+        for p, g, m, v in zip(params, grads, self.m, self.v):
+            m *= self.beta1
+            m += (1.0 - self.beta1) * g
+            v *= self.beta2
+            v += (1.0 - self.beta2) * g * g
+            p -= a * (m / c1) / (np.sqrt(v / c2) + self.eps)
+
+
+def cosine_lr(step: int, total: int, lr0: float) -> float:
+    return 0.5 * lr0 * (1.0 + math.cos(math.pi * min(step, total) / total))
+
+
+# ---------------------------------------------------------------- gate
+
+def ensemble_gate(K_members: np.ndarray, features: np.ndarray, lo: np.ndarray, hi: np.ndarray,
+                  tau: float):
+    """Mean prediction and fallback flag of an ensemble.
+
+    K_members [E][B][3].  Flag a patch when any feature lies outside [lo, hi]
+    (the training range) or when the largest member deviation from the mean,
+    in Frobenius norm relative to the mean, exceeds tau."""
+    Km = K_members.mean(axis=0)
+    d = K_members - Km[None]
+    fro = lambda a: np.sqrt(a[..., 0] ** 2 + 2 * a[..., 1] ** 2 + a[..., 2] ** 2)
+    spread = fro(d).max(axis=0) / fro(Km)
+    out = np.any((features < lo) | (features > hi), axis=1)
+    return Km, (spread > tau) | out, spread
