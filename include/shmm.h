@@ -146,8 +146,11 @@ int shmm_band_tags(shmm_ctx *ctx, int32_t inst, int8_t *d_tags, void *stream);
 /* Step plan of the local solves of domains [first, first + count) (HMM step 2):
  * dt = T/nsteps with T = ln(1/delta) / (lambda_min(K_b) 4 sin^2(pi/n) / h^2)
  * and nsteps = ceil(T / (dt_frac / (rho_D/2.785 + rho_A/2.828))),
- * rho_D = (4 K11 + 4 K22 + 2|K12|)/h^2, rho_A = V_b/h, V_b = sum over the
- * level's diagonal band of |psi_hat(k)| (|k1| + |k2|).  A patch whose diagonal
+ * rho_D = (4 K11 + 4 K22 + 2|K12|)/h^2, rho_A = (V_b + s)/h, V_b = sum over the
+ * level's diagonal band of |psi_hat(k)| (|k1| + |k2|); s = 0 when the band is
+ * periodic on the patch (k n / N integral for all its modes), otherwise
+ * s = 2 Psi_b / h with Psi_b = sum of |psi_hat(k)| over the band (the faces
+ * across the wrapped seam of the patch carry the jump of psi).  A patch whose diagonal
  * band holds no coefficient has zero forcing, so its corrector stays zero: it
  * gets nsteps = 0, dt = 0 and the local solve leaves it untouched.  K_base is
  * host [n_domains][3] indexed by global domain.  Host arithmetic, bit-exact;
@@ -235,6 +238,73 @@ int shmm_ctx_tune(shmm_ctx *ctx, int32_t key, int32_t value);
 int shmm_macro_step(shmm_ctx *ctx, int32_t N, const void *d_vx, const void *d_vy,
                     const double *d_K, int32_t K_is_field, double dt, int32_t nsteps, void *d_u,
                     int32_t dtype, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned surrogate of the local solve (not part of the paper's method).
+ * A patch is described by 33 features: 32 log-spaced radial bins (edges
+ * 2^(b/8), b = 0..32, of the patch-relative wavenumber |k| L / 2 pi) of the
+ * velocity energy spectrum of the patch samples (treated as periodic, scaled
+ * by (L / 2 pi)^2), feature_b = log(E_b + 1e-8 sum_b E_b + 1e-30), and
+ * log sqrt(det K_b).  A 33 -> 256 -> 256 -> 256 -> 3 GELU network maps the
+ * standardised features to o, and K = sqrt(det K_b) L L^T with
+ * L = [[e^o1, 0], [o2, e^o3]].  Matrix products run on the matrix cores with
+ * BF16 operands and FP32 accumulation.
+ *
+ * One ensemble member ("model") is SHMM_SURR_MODEL_BYTES of device memory:
+ *   float    params[SHMM_SURR_PARAMS_PADDED]  W1 b1 W2 b2 W3 b3 W4 b4, W_l row-major [out][in]
+ *   float    mu[64], sigma[64]                input standardisation (first 33 used)
+ *   uint16_t bf16[SHMM_SURR_PARAMS_PADDED]    bfloat16 copy of params
+ * Members of an ensemble are stored back to back.
+ * ------------------------------------------------------------------------- */
+#define SHMM_SURR_BINS 32
+#define SHMM_SURR_IN 33
+#define SHMM_SURR_WIDTH 256
+#define SHMM_SURR_OUT 3
+#define SHMM_SURR_PARAMS 141059
+#define SHMM_SURR_PARAMS_PADDED 141312
+#define SHMM_SURR_MODEL_BYTES (4 * SHMM_SURR_PARAMS_PADDED + 4 * 128 + 2 * SHMM_SURR_PARAMS_PADDED)
+
+/* Features of domains [first, first + count), which must share one patch size
+ * n (8 <= n <= 256): d_features[count][33] FP32, row i for domain first + i,
+ * from the face velocities d_vx, d_vy and the bases d_K_base [n_domains][3].
+ * In-house FP32 FFT; bin sums in a fixed order. */
+int shmm_patch_features(shmm_ctx *ctx, int64_t first, int64_t count, const float *d_vx,
+                        const float *d_vy, const double *d_K_base, float *d_features, void *stream);
+
+/* Refresh the bfloat16 copy of a model's parameters from its FP32 params. */
+int shmm_surrogate_refresh(shmm_ctx *ctx, void *d_model, void *stream);
+
+/* One training step of one model at batch B: forward, loss
+ * mean_b |K_hat - K_true|_F^2 / |K_true|_F^2 (written to d_loss[0], FP64),
+ * backward, and an Adam step (beta 0.9 / 0.999, eps 1e-8, step t >= 1 for the
+ * bias correction, learning rate lr) on the FP32 params; refreshes the bf16
+ * copy.  d_adam holds m then v, 2 * SHMM_SURR_PARAMS_PADDED floats (zero at
+ * t = 1).  d_x [B][33], d_K_base and d_K_true [B][3].  d_grad (optional,
+ * SHMM_SURR_PARAMS floats) receives the gradient of this step. */
+int shmm_surrogate_train_step(shmm_ctx *ctx, void *d_model, float *d_adam, const float *d_x,
+                              const double *d_K_base, const double *d_K_true, int64_t B, float lr,
+                              int32_t t, double *d_loss, float *d_grad, void *stream);
+
+/* Ensemble inference with the fallback gate: E members at d_models; the
+ * estimate is the member mean; a patch is flagged (d_flags[b] = 1) when a
+ * feature lies outside [d_lo, d_hi] (33 floats each, the training range) or
+ * the largest member deviation from the mean exceeds tau in relative
+ * Frobenius norm.  d_K_out [B][3]; d_spread [B] and d_K_members [E][B][3]
+ * optional. */
+int shmm_surrogate_infer(shmm_ctx *ctx, const void *d_models, int32_t E, const float *d_x,
+                         const double *d_K_base, int64_t B, const float *d_lo, const float *d_hi,
+                         double tau, double *d_K_out, uint8_t *d_flags, double *d_spread,
+                         double *d_K_members, void *stream);
+
+/* Plain-solve fallback for the flagged domains of [first, first + count)
+ * (d_flags[i] for domain first + i): zero their correctors, run the planned
+ * local solves and write their effective diffusivity into d_K_out
+ * [n_domains][3] (overwriting the surrogate's), setting SHMM_DOM_FALLBACK in
+ * d_status.  Reads the flags back to the host (synchronises the stream). */
+int shmm_fallback_solve(shmm_ctx *ctx, int64_t first, int64_t count, const uint8_t *d_flags,
+                        const float *d_vx, const float *d_vy, const float *d_f1, const float *d_f2,
+                        const double *d_K_base, float *d_w, double *d_K_out, int32_t *d_status,
+                        void *stream);
 
 #ifdef __cplusplus
 }

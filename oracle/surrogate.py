@@ -51,14 +51,14 @@ def patch_features(vx: np.ndarray, vy: np.ndarray, n: int, N: int, K_base) -> np
     ex = np.abs(np.fft.fft2(vx)) ** 2
     ey = np.abs(np.fft.fft2(vy)) ** 2
     e = (ex + ey) / float(n) ** 4 * (n / N) ** 2     # (L / 2 pi)^2 with L = n 2 pi / N
-    k = np.fft.fftfreq(n, 1.0 / n)
+    k = np.fft.fftfreq(n, 1.0 / n).astype(np.int64)
     K1, K2 = np.meshgrid(k, k, indexing="xy")
-    q = np.sqrt(K1 ** 2 + K2 ** 2)
-    edges = bin_edges()
+    # 2^(b/8) <= q < 2^((b+1)/8)  <=>  2^b <= (q^2)^4 < 2^(b+1): decided in integers
+    m = (K1 * K1 + K2 * K2) ** 4
+    bins = np.array([int(v).bit_length() - 1 for v in m.reshape(-1)]).reshape(n, n)
     E = np.zeros(N_BINS)
     for b in range(N_BINS):
-        sel = (q >= edges[b]) & (q < edges[b + 1])
-        E[b] = float(np.sum(e[sel]))
+        E[b] = float(np.sum(e[(m > 0) & (bins == b)]))
     floor = 1e-8 * float(np.sum(E)) + 1e-30
     out = np.zeros(N_IN)
     for b in range(N_BINS):

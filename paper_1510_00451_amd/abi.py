@@ -22,7 +22,12 @@ MAX_LEVELS = 8
 EXPORTS = ["shmm_ctx_create", "shmm_ctx_destroy", "shmm_build_levels", "shmm_ctx_set_problem",
            "shmm_ctx_table", "shmm_band_tags", "shmm_plan_steps", "shmm_band_filter",
            "shmm_local_solve_batch", "shmm_effective_diffusivity", "shmm_level_chain",
-           "shmm_macro_step", "shmm_ctx_tune"]
+           "shmm_macro_step", "shmm_ctx_tune", "shmm_patch_features", "shmm_surrogate_refresh",
+           "shmm_surrogate_train_step", "shmm_surrogate_infer", "shmm_fallback_solve"]
+
+SURR_BINS, SURR_IN, SURR_WIDTH, SURR_OUT = 32, 33, 256, 3
+SURR_PARAMS, SURR_PARAMS_PADDED = 141059, 141312
+SURR_MODEL_BYTES = 4 * SURR_PARAMS_PADDED + 4 * 128 + 2 * SURR_PARAMS_PADDED
 
 
 class ShmmError(RuntimeError):
@@ -70,6 +75,11 @@ def lib() -> ctypes.CDLL:
             "shmm_level_chain": [P, i64, i64, i32, P, P, P, P, P, P, P, P],
             "shmm_macro_step": [P, i32, P, P, P, i32, f64, i32, P, i32, P],
             "shmm_ctx_tune": [P, i32, i32],
+            "shmm_patch_features": [P, i64, i64, P, P, P, P, P],
+            "shmm_surrogate_refresh": [P, P, P],
+            "shmm_surrogate_train_step": [P, P, P, P, P, P, i64, ctypes.c_float, i32, P, P, P],
+            "shmm_surrogate_infer": [P, P, i32, P, P, i64, P, P, f64, P, P, P, P, P],
+            "shmm_fallback_solve": [P, i64, i64, P, P, P, P, P, P, P, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -203,6 +213,30 @@ class Context:
 
     def solve_variants(self, n: int) -> int:
         return self.shmm_ctx_tune(0, n)
+
+    def shmm_patch_features(self, first, count, d_vx, d_vy, d_K_base, d_features, stream=0):
+        check(lib().shmm_patch_features(self.h, first, count, d_vx, d_vy, d_K_base, d_features, stream),
+              "shmm_patch_features")
+
+    def shmm_surrogate_refresh(self, d_model, stream=0):
+        check(lib().shmm_surrogate_refresh(self.h, d_model, stream), "shmm_surrogate_refresh")
+
+    def shmm_surrogate_train_step(self, d_model, d_adam, d_x, d_K_base, d_K_true, B, lr, t, d_loss,
+                                  d_grad=0, stream=0):
+        check(lib().shmm_surrogate_train_step(self.h, d_model, d_adam, d_x, d_K_base, d_K_true, int(B),
+                                              float(lr), int(t), d_loss, d_grad or None, stream),
+              "shmm_surrogate_train_step")
+
+    def shmm_surrogate_infer(self, d_models, E, d_x, d_K_base, B, d_lo, d_hi, tau, d_K_out, d_flags,
+                             d_spread=0, d_K_members=0, stream=0):
+        check(lib().shmm_surrogate_infer(self.h, d_models, int(E), d_x, d_K_base, int(B), d_lo, d_hi,
+                                         float(tau), d_K_out, d_flags, d_spread or None,
+                                         d_K_members or None, stream), "shmm_surrogate_infer")
+
+    def shmm_fallback_solve(self, first, count, d_flags, d_vx, d_vy, d_f1, d_f2, d_K_base, d_w, d_K_out,
+                            d_status=0, stream=0):
+        check(lib().shmm_fallback_solve(self.h, first, count, d_flags, d_vx, d_vy, d_f1, d_f2, d_K_base,
+                                        d_w, d_K_out, d_status or None, stream), "shmm_fallback_solve")
 
     def shmm_macro_step(self, N, d_vx, d_vy, d_K, K_is_field, dt, nsteps, d_u, dtype, stream=0):
         check(lib().shmm_macro_step(self.h, N, d_vx or None, d_vy or None, d_K, int(K_is_field),

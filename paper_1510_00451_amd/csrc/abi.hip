@@ -119,6 +119,23 @@ double band_speed_bound(const shmm_problem &P, int level) {
     return s;
 }
 
+// Psi_b = sum over the level's diagonal band of |psi_hat(k)|, k2-major.
+double band_amplitude_sum(const shmm_problem &P, int level) {
+    const int K = P.kmax, span = 2 * K + 1;
+    double s = 0.0;
+    for (int b = 0; b < span; ++b)
+        for (int a = 0; a < span; ++a) {
+            const int k1 = a - K, k2 = b - K;
+            if (k1 == 0 && k2 == 0) continue;
+            const int l = band_level(k1, k2, P.thresh, P.n_levels);
+            if (l != level || band_part(k1, k2, l, P.thresh, P.n_levels) != SHMM_DIAG) continue;
+            const int64_t idx = (int64_t)b * span + a;
+            const double re = P.psi_hat[2 * idx], im = P.psi_hat[2 * idx + 1];
+            s = s + sqrt(re * re + im * im);
+        }
+    return s;
+}
+
 // Largest |k1|, |k2| carrying a nonzero coefficient in the level's diagonal band.
 void band_extent(const shmm_problem &P, int level, int *kb1, int *kb2) {
     const int K = P.kmax, span = 2 * K + 1;
@@ -155,12 +172,15 @@ int band_periodic(const shmm_problem &P, int level, int n, int N) {
 }
 
 // Step plan (see shmm.h).  The expression order is part of the contract.
-int plan_one(const shmm_domain &d, const double *K, double Vb, double dt_frac, double delta,
-             double *dt_out, int64_t *nsteps_out) {
+// rho_A = (V_b + s)/h with s = 2 Psi_b / h for a band that is not periodic on
+// the patch: the faces across the wrapped seam carry the jump of psi.
+int plan_one(const shmm_domain &d, const double *K, double Vb, double psi_sum, int periodic,
+             double dt_frac, double delta, double *dt_out, int64_t *nsteps_out) {
     const double K11 = K[0], K12 = K[1], K22 = K[2];
     const double h = d.h;
     const double rho_d = (4.0 * K11 + 4.0 * K22 + 2.0 * fabs(K12)) / (h * h);
-    const double rho_a = Vb / h;
+    const double seam = periodic ? 0.0 : 2.0 * psi_sum / h;
+    const double rho_a = (Vb + seam) / h;
     const double dt_lim = 1.0 / (rho_d / 2.785 + rho_a / 2.828);
     const double lam = 0.5 * (K11 + K22) - sqrt(0.25 * (K11 - K22) * (K11 - K22) + K12 * K12);
     if (!(lam > 0.0)) return SHMM_ENOTSPD;
@@ -216,6 +236,8 @@ struct shmm_ctx {
     int32_t *d_origins = nullptr;
     int32_t *d_child_start = nullptr, *d_child_idx = nullptr;
     std::vector<std::vector<double>> vb;     // [inst][level]
+    std::vector<std::vector<double>> psum;   // [inst][level]
+    std::vector<std::vector<int>> periodic;  // [inst][level]
     std::vector<std::vector<int>> empty;     // [inst][level]: diagonal band without coefficients
     std::map<std::pair<int64_t, int64_t>, RangeLists> lists;
     std::map<int, int> solve_variant;          // patch size n -> kernel variant
@@ -239,6 +261,8 @@ struct shmm_ctx {
         for (auto &kv : lists)
             for (auto *p : kv.second.d_lists) (void)hipFree(p);
         lists.clear();
+        for (auto &kv : seqs) (void)hipFree(kv.second);
+        seqs.clear();
     }
 
     void release() {
@@ -254,6 +278,43 @@ struct shmm_ctx {
         d_table = nullptr;
         d_origins = nullptr;
         d_child_start = d_child_idx = nullptr;
+    }
+
+    // device list first, first + 1, ..., first + count - 1 (cached)
+    std::map<std::pair<int64_t, int64_t>, int32_t *> seqs;
+    int seq_list(int64_t first, int64_t count, int32_t **out) {
+        auto key = std::make_pair(first, count);
+        auto it = seqs.find(key);
+        if (it == seqs.end()) {
+            std::vector<int32_t> v(count);
+            for (int64_t i = 0; i < count; ++i) v[i] = (int32_t)(first + i);
+            int32_t *p = nullptr;
+            int rc = upload(&p, v.data(), v.size());
+            if (rc) return rc;
+            it = seqs.emplace(key, p).first;
+        }
+        *out = it->second;
+        return SHMM_OK;
+    }
+
+    // a device list valid until the next call (synchronous upload)
+    int32_t *tmp = nullptr;
+    size_t tmp_len = 0;
+    int temp_list(const std::vector<int32_t> &v, int32_t **out) {
+        if (v.size() > tmp_len) {
+            if (tmp) {
+                SHMM_HIP_CHECK(hipDeviceSynchronize());
+                SHMM_HIP_CHECK(hipFree(tmp));
+            }
+            tmp = nullptr;
+            tmp_len = 0;
+            SHMM_HIP_CHECK(hipMalloc((void **)&tmp, v.size() * sizeof(int32_t)));
+            tmp_len = v.size();
+        }
+        SHMM_HIP_CHECK(hipDeviceSynchronize());   // earlier launches may still read the old list
+        SHMM_HIP_CHECK(hipMemcpy(tmp, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        *out = tmp;
+        return SHMM_OK;
     }
 
     int range_lists(int64_t first, int64_t count, RangeLists **out) {
@@ -312,6 +373,7 @@ int shmm_ctx_destroy(shmm_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     ctx->release();
     if (ctx->work) (void)hipFree(ctx->work);
+    if (ctx->tmp) (void)hipFree(ctx->tmp);
     delete ctx;
     return SHMM_OK;
 }
@@ -345,6 +407,8 @@ int shmm_ctx_set_problem(shmm_ctx *ctx, const shmm_problem *p, int32_t n_inst) {
     ctx->geo.assign(n_inst, {});
     ctx->inst.assign(n_inst, InstDev());
     ctx->vb.assign(n_inst, {});
+    ctx->psum.assign(n_inst, {});
+    ctx->periodic.assign(n_inst, {});
     ctx->empty.assign(n_inst, {});
     for (int32_t q = 0; q < n_inst; ++q) {
         shmm_problem &P = ctx->probs[q];
@@ -375,6 +439,8 @@ int shmm_ctx_set_problem(shmm_ctx *ctx, const shmm_problem *p, int32_t n_inst) {
         for (int l = 0; l < SHMM_MAX_LEVELS; ++l) I.thresh[l] = l + 1 < L ? P.thresh[l] : 0;
         for (int l = 0; l < L; ++l) {
             ctx->vb[q].push_back(band_speed_bound(P, l));
+            ctx->psum[q].push_back(band_amplitude_sum(P, l));
+            ctx->periodic[q].push_back(band_periodic(P, l, P.n_cells[l], P.n_global[l]));
             int kb1 = 0, kb2 = 0;
             band_extent(P, l, &kb1, &kb2);
             ctx->empty[q].push_back(kb1 == 0 && kb2 == 0 ? 1 : 0);
@@ -458,7 +524,8 @@ int shmm_plan_steps(shmm_ctx *ctx, int64_t first, int64_t count, const double *K
         const shmm_problem &P = ctx->probs[D.instance];
         double dt = 0.0;
         int64_t ns = 0;
-        rc = plan_one(D, K_base + 3 * d, ctx->vb[D.instance][D.level], P.dt_frac, P.delta, &dt, &ns);
+        rc = plan_one(D, K_base + 3 * d, ctx->vb[D.instance][D.level], ctx->psum[D.instance][D.level],
+                      ctx->periodic[D.instance][D.level], P.dt_frac, P.delta, &dt, &ns);
         if (rc) return rc;
         if (ctx->empty[D.instance][D.level]) {
             // zero forcing: the corrector stays zero, nothing to integrate
@@ -573,6 +640,111 @@ int shmm_macro_step(shmm_ctx *ctx, int32_t N, const void *d_vx, const void *d_vy
     if ((rc = ctx->ensure_work(macro_workspace(N, dtype)))) return rc;
     return launch_macro(N, d_vx, d_vy, d_K, K_is_field, dt, nsteps, d_u, dtype, ctx->work,
                         (hipStream_t)stream);
+}
+
+int shmm_patch_features(shmm_ctx *ctx, int64_t first, int64_t count, const float *d_vx,
+                        const float *d_vy, const double *d_K_base, float *d_features, void *stream) {
+    if (!range_ok(ctx, first, count) || !d_vx || !d_vy || !d_K_base || !d_features) return SHMM_EINVAL;
+    if (count == 0) return SHMM_OK;
+    const int n = ctx->table[first].n;
+    for (int64_t d = first; d < first + count; ++d)
+        if (ctx->table[d].n != n) return SHMM_EINVAL;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    int32_t *list = nullptr;
+    if ((rc = ctx->seq_list(first, count, &list))) return rc;
+    if ((rc = ctx->ensure_work(surrogate_feature_workspace(n, count)))) return rc;
+    return launch_patch_features(ctx->d_table, list, (int32_t)count, n, d_vx, d_vy, d_K_base, d_features,
+                                 ctx->work, (hipStream_t)stream);
+}
+
+int shmm_surrogate_refresh(shmm_ctx *ctx, void *d_model, void *stream) {
+    if (!ctx || !d_model) return SHMM_EINVAL;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    return surrogate_refresh_bf16(d_model, (hipStream_t)stream);
+}
+
+int shmm_surrogate_train_step(shmm_ctx *ctx, void *d_model, float *d_adam, const float *d_x,
+                              const double *d_K_base, const double *d_K_true, int64_t B, float lr,
+                              int32_t t, double *d_loss, float *d_grad, void *stream) {
+    if (!ctx || !d_model || !d_adam || !d_x || !d_K_base || !d_K_true || !d_loss || B <= 0 || t < 1)
+        return SHMM_EINVAL;
+    if (B > (1 << 24)) return SHMM_ERANGE;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    if ((rc = ctx->ensure_work(surrogate_net_workspace(B)))) return rc;
+    return surrogate_train_step(d_model, d_adam, d_x, d_K_base, d_K_true, B, lr, t, d_loss, d_grad, ctx->work,
+                                (hipStream_t)stream);
+}
+
+int shmm_surrogate_infer(shmm_ctx *ctx, const void *d_models, int32_t E, const float *d_x,
+                         const double *d_K_base, int64_t B, const float *d_lo, const float *d_hi,
+                         double tau, double *d_K_out, uint8_t *d_flags, double *d_spread,
+                         double *d_K_members, void *stream) {
+    if (!ctx || !d_models || E < 1 || !d_x || !d_K_base || B <= 0 || !d_lo || !d_hi || !d_K_out || !d_flags)
+        return SHMM_EINVAL;
+    if (B > (1 << 24)) return SHMM_ERANGE;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    const size_t net = surrogate_net_workspace(B);
+    const size_t km = d_K_members ? 0 : (size_t)E * B * 3 * sizeof(double);
+    if ((rc = ctx->ensure_work(net + km))) return rc;
+    double *Km = d_K_members ? d_K_members : (double *)((char *)ctx->work + net);
+    return surrogate_infer(d_models, E, d_x, d_K_base, B, d_lo, d_hi, tau, d_K_out, d_flags, d_spread, Km,
+                           ctx->work, (hipStream_t)stream);
+}
+
+int shmm_fallback_solve(shmm_ctx *ctx, int64_t first, int64_t count, const uint8_t *d_flags,
+                        const float *d_vx, const float *d_vy, const float *d_f1, const float *d_f2,
+                        const double *d_K_base, float *d_w, double *d_K_out, int32_t *d_status,
+                        void *stream) {
+    if (!range_ok(ctx, first, count) || !d_flags || !d_vx || !d_vy || !d_f1 || !d_f2 || !d_K_base || !d_w ||
+        !d_K_out)
+        return SHMM_EINVAL;
+    if (count == 0) return SHMM_OK;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<uint8_t> flags(count);
+    SHMM_HIP_CHECK(hipMemcpyAsync(flags.data(), d_flags, count, hipMemcpyDeviceToHost, s));
+    SHMM_HIP_CHECK(hipStreamSynchronize(s));
+    std::map<int, std::vector<int32_t>> byn;
+    for (int64_t i = 0; i < count; ++i) {
+        if (!flags[i]) continue;
+        const shmm_domain &D = ctx->table[first + i];
+        if (D.dt < 0.0) return SHMM_EINVAL;   // never planned
+        byn[D.n].push_back((int32_t)(first + i));
+    }
+    for (auto &kv : byn) {
+        const int n = kv.first;
+        std::vector<int32_t> &ids = kv.second;
+        int32_t max_steps = 0;
+        for (int32_t d : ids) {
+            const shmm_domain &D = ctx->table[d];
+            max_steps = std::max(max_steps, D.nsteps);
+            SHMM_HIP_CHECK(hipMemsetAsync(d_w + D.offset, 0, (size_t)n * n * sizeof(float), s));
+            SHMM_HIP_CHECK(hipMemsetAsync(d_w + ctx->cells + D.offset, 0, (size_t)n * n * sizeof(float), s));
+        }
+        int32_t *dl = nullptr;
+        if ((rc = ctx->temp_list(ids, &dl))) return rc;
+        const int64_t cells = (int64_t)ids.size() * n * n;
+        const size_t need = local_solve_workspace(n, cells);
+        if (need && (rc = ctx->ensure_work(need))) return rc;
+        const auto it = ctx->solve_variant.find(n);
+        const int variant = it == ctx->solve_variant.end() ? default_solve_variant(n) : it->second;
+        rc = launch_local_solve(ctx->d_table, dl, (int32_t)ids.size(), n, max_steps, d_vx, d_vy, d_f1, d_f2,
+                                d_K_base, d_w, ctx->cells, 0, 2147483647, cells, ctx->work, variant, s);
+        if (rc) return rc;
+        rc = launch_effective_diffusivity_list(ctx->d_table, dl, (int64_t)ids.size(), d_f1, d_f2, d_w,
+                                               ctx->cells, d_K_base, d_K_out, d_status, s);
+        if (rc) return rc;
+        if (d_status) {
+            rc = launch_mark_status(d_status, dl, (int64_t)ids.size(), SHMM_DOM_FALLBACK, s);
+            if (rc) return rc;
+        }
+    }
+    return SHMM_OK;
 }
 
 }  // extern "C"

@@ -20,9 +20,9 @@ __global__ __launch_bounds__(kRedThreads) void k_moments(
     const shmm_domain *__restrict__ dom, int64_t first, const float *__restrict__ f1,
     const float *__restrict__ f2, const float *__restrict__ w, int64_t cells_total,
     const double *__restrict__ Kb, double *__restrict__ K_out, double *__restrict__ K_energy,
-    double *__restrict__ mass, int32_t *__restrict__ status) {
+    double *__restrict__ mass, int32_t *__restrict__ status, const int32_t *__restrict__ list) {
     __shared__ double part[kRedThreads / 64][kRedVals];
-    const int64_t d = first + blockIdx.x;
+    const int64_t d = list ? (int64_t)list[blockIdx.x] : first + blockIdx.x;
     const shmm_domain D = dom[d];
     const int n = D.n, mask = n - 1, cells = n * n;
     const int64_t o = D.offset;
@@ -187,7 +187,19 @@ __global__ void k_chain(const shmm_domain *__restrict__ dom, const InstDev *__re
     }
 }
 
+__global__ void k_mark(int32_t *status, const int32_t *list, int64_t count, int32_t bits) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) status[list[t]] |= bits;
+}
+
 }  // namespace
+
+int launch_mark_status(int32_t *status, const int32_t *list, int64_t count, int32_t bits, hipStream_t s) {
+    if (count <= 0) return SHMM_OK;
+    hipLaunchKernelGGL(k_mark, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, status, list, count, bits);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
 
 int launch_effective_diffusivity(const shmm_domain *d_dom, int64_t first, int64_t count,
                                  const float *f1, const float *f2, const float *w,
@@ -195,7 +207,17 @@ int launch_effective_diffusivity(const shmm_domain *d_dom, int64_t first, int64_
                                  double *K_energy, double *mass, int32_t *status, hipStream_t s) {
     if (count <= 0) return SHMM_OK;
     hipLaunchKernelGGL(k_moments, dim3((unsigned)count), dim3(kRedThreads), 0, s, d_dom, first, f1, f2,
-                       w, cells_total, Kb, K_out, K_energy, mass, status);
+                       w, cells_total, Kb, K_out, K_energy, mass, status, (const int32_t *)nullptr);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
+
+int launch_effective_diffusivity_list(const shmm_domain *d_dom, const int32_t *d_list, int64_t count,
+                                      const float *f1, const float *f2, const float *w, int64_t cells_total,
+                                      const double *Kb, double *K_out, int32_t *status, hipStream_t s) {
+    if (count <= 0) return SHMM_OK;
+    hipLaunchKernelGGL(k_moments, dim3((unsigned)count), dim3(kRedThreads), 0, s, d_dom, (int64_t)0, f1, f2, w,
+                       cells_total, Kb, K_out, (double *)nullptr, (double *)nullptr, status, d_list);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
 }

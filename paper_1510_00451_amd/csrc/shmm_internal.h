@@ -73,6 +73,9 @@ bool local_solve_resident(int n);
 int local_solve_variants(int n);
 size_t local_solve_workspace(int n, int64_t list_cells);
 
+int launch_effective_diffusivity_list(const shmm_domain *d_dom, const int32_t *d_list, int64_t count,
+                                      const float *f1, const float *f2, const float *w, int64_t cells_total,
+                                      const double *Kb, double *K_out, int32_t *status, hipStream_t s);
 int launch_effective_diffusivity(const shmm_domain *d_dom, int64_t first, int64_t count,
                                  const float *f1, const float *f2, const float *w,
                                  int64_t cells_total, const double *Kb, double *K_out,
@@ -82,6 +85,21 @@ int launch_level_chain(const shmm_domain *d_dom, const InstDev *d_inst, const in
                        const int32_t *d_child_idx, int64_t first, int64_t count, int32_t mode,
                        const double *lines, double *K_in, double *K_off, double *K_base,
                        const double *K_solve, double *R, int32_t *status, hipStream_t s);
+
+size_t surrogate_feature_workspace(int n, int64_t nlist);
+int launch_patch_features(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n,
+                          const float *vx, const float *vy, const double *Kb, float *features, void *work,
+                          hipStream_t s);
+size_t surrogate_net_workspace(int64_t B);
+int surrogate_train_step(void *model, float *adam, const float *x, const double *Kb, const double *Kt,
+                         int64_t B, float lr, int32_t t, double *loss, float *grad_out, void *work,
+                         hipStream_t s);
+int surrogate_refresh_bf16(void *model, hipStream_t s);
+int surrogate_infer(const void *models, int32_t E, const float *x, const double *Kb, int64_t B,
+                    const float *lo, const float *hi, double tau, double *K_out, uint8_t *flags,
+                    double *spread, double *K_members, void *work, hipStream_t s);
+
+int launch_mark_status(int32_t *status, const int32_t *list, int64_t count, int32_t bits, hipStream_t s);
 
 int launch_macro(int32_t N, const void *vx, const void *vy, const double *K, int32_t K_is_field,
                  double dt, int32_t nsteps, void *u, int32_t dtype, void *work, hipStream_t s);

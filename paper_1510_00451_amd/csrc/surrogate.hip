@@ -1,0 +1,582 @@
+// Learned surrogate of the local solve (not part of the paper's method):
+// patch spectrum features, a 33 -> 256 -> 256 -> 256 -> 3 GELU network on the
+// matrix cores (BF16 operands, FP32 accumulation), its training step (forward,
+// relative Frobenius loss on the Cholesky head, backward, Adam on FP32 master
+// weights) and ensemble inference with a fallback gate.
+#include <math.h>
+
+#include "band_core.h"
+#include "shmm_internal.h"
+
+namespace shmm {
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {   // round to nearest, ties to even
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)(u >> 16);   // Inf / NaN
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_grad(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// ------------------------------------------------------------------ features
+
+struct BlockSync {
+    __device__ void operator()() const { __syncthreads(); }
+};
+
+constexpr int kFeatRows = 8;   // rows (pass A) or columns (pass B) per workgroup
+
+// Pass A: FFT along x of Z = vx + i vy for kFeatRows rows of one patch.
+__global__ __launch_bounds__(256) void k_feat_rows(const shmm_domain *dom, const int32_t *list, int n,
+                                                   const float *vx, const float *vy, c32 *work) {
+    extern __shared__ c32 lds[];
+    const int li = blockIdx.y;
+    const shmm_domain D = dom[list[li]];
+    const int r0 = blockIdx.x * kFeatRows;
+    c32 *a = lds, *b = lds + kFeatRows * n;
+    for (int t = threadIdx.x; t < kFeatRows * n; t += blockDim.x) {
+        const int r = t / n, i = t - r * n;
+        const int64_t c = D.offset + (int64_t)(r0 + r) * n + i;
+        a[t] = c32{vx[c], vy[c]};
+    }
+    __syncthreads();
+    // kFeatRows independent transforms: give each a slice of the threads
+    const int per = blockDim.x / kFeatRows, row = threadIdx.x / per, tid = threadIdx.x - row * per;
+    c32 *res = fft_inverse(a + row * n, b + row * n, n, tid, per, BlockSync{});
+    // every row took the same number of passes, so res sits in the same buffer for all
+    c32 *out = work + ((int64_t)li * n + r0) * n;
+    for (int t = tid; t < n; t += per) out[(int64_t)row * n + t] = res[t];
+}
+
+// Pass B: FFT along y of kFeatRows columns, |Z^|^2, partial bin sums.
+__global__ __launch_bounds__(256) void k_feat_cols(const shmm_domain *dom, const int32_t *list, int n,
+                                                   const c32 *work, float *partial) {
+    extern __shared__ c32 lds[];
+    const int li = blockIdx.y;
+    const int N = dom[list[li]].N;
+    const int c0 = blockIdx.x * kFeatRows;
+    c32 *a = lds, *b = lds + kFeatRows * n;
+    float *e = (float *)(b + kFeatRows * n);
+    const c32 *src = work + (int64_t)li * n * n;
+    for (int t = threadIdx.x; t < kFeatRows * n; t += blockDim.x) {
+        const int col = t / n, j = t - col * n;
+        a[t] = src[(int64_t)j * n + c0 + col];
+    }
+    __syncthreads();
+    const int per = blockDim.x / kFeatRows, col = threadIdx.x / per, tid = threadIdx.x - col * per;
+    c32 *res = fft_inverse(a + col * n, b + col * n, n, tid, per, BlockSync{});
+    const float scale = (float)((double)n / (double)N * (double)n / (double)N / ((double)n * n * n * n));
+    for (int t = tid; t < n; t += per) {
+        const c32 z = res[t];
+        e[col * n + t] = (z.x * z.x + z.y * z.y) * scale;
+    }
+    __syncthreads();
+    // Thread b sums bin b over this workgroup's entries in a fixed order.  The
+    // bin of |k| = q is b with 2^(b/8) <= q < 2^((b+1)/8), i.e. the position of
+    // the leading bit of (k1^2 + k2^2)^4, decided exactly in integers.
+    if (threadIdx.x < SHMM_SURR_BINS) {
+        const int bin = threadIdx.x;
+        float s = 0.0f;
+        for (int col2 = 0; col2 < kFeatRows; ++col2) {
+            int k1 = c0 + col2;
+            k1 = k1 <= n / 2 ? k1 : k1 - n;
+            for (int j = 0; j < n; ++j) {
+                const int k2 = j <= n / 2 ? j : j - n;   // both signs of the Nyquist row give the same q
+                const uint64_t q2 = (uint64_t)(k1 * k1 + k2 * k2);
+                const uint64_t m = q2 * q2 * q2 * q2;
+                if (m == 0 || m >= (1ull << SHMM_SURR_BINS)) continue;
+                if (63 - __builtin_clzll(m) == bin) s += e[col2 * n + j];
+            }
+        }
+        partial[((int64_t)li * gridDim.x + blockIdx.x) * SHMM_SURR_BINS + bin] = s;
+    }
+}
+
+__global__ void k_feat_final(const shmm_domain *dom, const int32_t *list, int nlist, int parts,
+                             const float *partial, const double *Kb, float *features) {
+    const int li = blockIdx.x * blockDim.x + threadIdx.x;
+    if (li >= nlist) return;
+    const int64_t d = list[li];
+    float E[SHMM_SURR_BINS];
+    float tot = 0.0f;
+    for (int bin = 0; bin < SHMM_SURR_BINS; ++bin) {
+        float s = 0.0f;
+        for (int p = 0; p < parts; ++p) s += partial[((int64_t)li * parts + p) * SHMM_SURR_BINS + bin];
+        E[bin] = s;
+        tot += s;
+    }
+    const float floor = 1e-8f * tot + 1e-30f;
+    float *f = features + (int64_t)li * SHMM_SURR_IN;
+    for (int bin = 0; bin < SHMM_SURR_BINS; ++bin) f[bin] = logf(E[bin] + floor);
+    const double det = Kb[3 * d] * Kb[3 * d + 2] - Kb[3 * d + 1] * Kb[3 * d + 1];
+    f[SHMM_SURR_BINS] = (float)(0.5 * log(det));
+}
+
+// ------------------------------------------------------------------ GEMM
+
+enum { EPI_F32 = 0, EPI_BIAS_F32 = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };
+
+struct GemmArgs {
+    int M, N, K;
+    const uint16_t *A;
+    int64_t sam, sak;
+    const uint16_t *B;
+    int64_t sbk, sbn;
+    int epi;
+    const float *bias;     // [N]
+    float *outf;           // FP32 output (pre-activation, gradient, or result)
+    int64_t ldo;
+    uint16_t *outh;        // BF16 output (activation or gradient), may be null
+    int64_t ldh;
+    const float *z;        // saved pre-activations for EPI_GELU_GRAD
+    int64_t ldz;
+};
+
+constexpr int TM = 64, TN = 64, TK = 32, PADK = 8;
+
+// C[M][N] = A[M][K] B[K][N]: BF16 operands from arbitrary strides, FP32
+// accumulation on v_mfma_f32_16x16x16bf16_1k.  64 x 64 tile per workgroup,
+// four wavefronts of 32 x 32 (2 x 2 matrix-core tiles).  Operand layout of the
+// 16x16x16 instruction: lane l holds A[l % 16][4 (l / 16) + i] and
+// B[4 (l / 16) + i][l % 16], i < 4, and receives D[4 (l / 16) + i][l % 16].
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+    __shared__ uint16_t As[TM][TK + PADK];
+    __shared__ uint16_t Bt[TN][TK + PADK];   // B stored transposed: k contiguous
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    f32x4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < g.K; k0 += TK) {
+        for (int t = threadIdx.x; t < TM * TK; t += blockDim.x) {
+            const int m = t / TK, k = t - m * TK;
+            const int gm = m0 + m, gk = k0 + k;
+            As[m][k] = (gm < g.M && gk < g.K) ? g.A[gm * g.sam + gk * g.sak] : (uint16_t)0;
+        }
+        for (int t = threadIdx.x; t < TN * TK; t += blockDim.x) {
+            const int nn = t / TK, k = t - nn * TK;
+            const int gn = n0 + nn, gk = k0 + k;
+            Bt[nn][k] = (gn < g.N && gk < g.K) ? g.B[gk * g.sbk + gn * g.sbn] : (uint16_t)0;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < TK; kk += 16) {
+            const int kq = kk + 4 * (lane >> 4);
+            bf16x4 a[2], b[2];
+            for (int i = 0; i < 2; ++i) {
+                const uint16_t *pa = &As[wm * 32 + i * 16 + (lane & 15)][kq];
+                a[i] = bf16x4{(short)pa[0], (short)pa[1], (short)pa[2], (short)pa[3]};
+                const uint16_t *pb = &Bt[wn * 32 + i * 16 + (lane & 15)][kq];
+                b[i] = bf16x4{(short)pb[0], (short)pb[1], (short)pb[2], (short)pb[3]};
+            }
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+                const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (row >= g.M || col >= g.N) continue;
+                float v = acc[i][j][r];
+                if (g.epi == EPI_BIAS_F32 || g.epi == EPI_BIAS_GELU) v += g.bias[col];
+                if (g.epi == EPI_GELU_GRAD) v *= gelu_grad(g.z[row * g.ldz + col]);
+                if (g.outf) g.outf[row * g.ldo + col] = v;
+                if (g.outh) g.outh[row * g.ldh + col] = to_bf16(g.epi == EPI_BIAS_GELU ? gelu(v) : v);
+            }
+}
+
+int gemm(const GemmArgs &g, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0) return SHMM_OK;
+    hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)((g.N + TN - 1) / TN), (unsigned)((g.M + TM - 1) / TM)),
+                       dim3(256), 0, s, g);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
+
+// ------------------------------------------------------------------ network pieces
+
+struct Layout {
+    int64_t W[4], b[4];
+    int in[4], out[4];
+};
+
+Layout layout() {
+    Layout L;
+    const int dims[5] = {SHMM_SURR_IN, SHMM_SURR_WIDTH, SHMM_SURR_WIDTH, SHMM_SURR_WIDTH, SHMM_SURR_OUT};
+    int64_t off = 0;
+    for (int l = 0; l < 4; ++l) {
+        L.in[l] = dims[l];
+        L.out[l] = dims[l + 1];
+        L.W[l] = off;
+        off += (int64_t)dims[l] * dims[l + 1];
+        L.b[l] = off;
+        off += dims[l + 1];
+    }
+    return L;
+}
+
+__global__ void k_standardize(const float *x, int64_t B, const float *mu, const float *sigma, uint16_t *xh) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= B * SHMM_SURR_IN) return;
+    const int c = (int)(t % SHMM_SURR_IN);
+    xh[t] = to_bf16((x[t] - mu[c]) / sigma[c]);
+}
+
+// Cholesky head K = sqrt(det K_b) L L^T; optional loss and output gradient.
+__global__ void k_head(const float *o, const double *Kb, int64_t B, double *K_out, const double *K_true,
+                       float *go, double *loss_part) {
+    __shared__ double red[256];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double ls = 0.0;
+    if (t < B) {
+        const double s = sqrt(Kb[3 * t] * Kb[3 * t + 2] - Kb[3 * t + 1] * Kb[3 * t + 1]);
+        const double l11 = exp((double)o[3 * t]), l21 = o[3 * t + 1], l22 = exp((double)o[3 * t + 2]);
+        const double k11 = s * l11 * l11, k12 = s * l11 * l21, k22 = s * (l21 * l21 + l22 * l22);
+        if (K_out) {
+            K_out[3 * t] = k11;
+            K_out[3 * t + 1] = k12;
+            K_out[3 * t + 2] = k22;
+        }
+        if (K_true) {
+            const double t11 = K_true[3 * t], t12 = K_true[3 * t + 1], t22 = K_true[3 * t + 2];
+            const double d11 = k11 - t11, d12 = k12 - t12, d22 = k22 - t22;
+            const double nrm = t11 * t11 + 2.0 * t12 * t12 + t22 * t22;
+            ls = (d11 * d11 + 2.0 * d12 * d12 + d22 * d22) / nrm;
+            const double g11 = 2.0 * d11 / nrm / (double)B, g12 = 4.0 * d12 / nrm / (double)B,
+                         g22 = 2.0 * d22 / nrm / (double)B;
+            go[3 * t] = (float)(g11 * 2.0 * s * l11 * l11 + g12 * s * l11 * l21);
+            go[3 * t + 1] = (float)(g12 * s * l11 + g22 * 2.0 * s * l21);
+            go[3 * t + 2] = (float)(g22 * 2.0 * s * l22 * l22);
+        }
+    }
+    if (loss_part) {
+        red[threadIdx.x] = ls;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
+    }
+}
+
+__global__ void k_to_bf16(const float *src, uint16_t *dst, int64_t count) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) dst[t] = to_bf16(src[t]);
+}
+
+// column sums of dz [B][n] into the bias gradient (fixed order per column)
+__global__ void k_colsum(const float *dz, int64_t B, int n, float *out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    float s = 0.0f;
+    for (int64_t r = 0; r < B; ++r) s += dz[r * n + c];
+    out[c] = s;
+}
+
+__global__ void k_loss_total(const double *part, int parts, int64_t B, double *loss) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int p = 0; p < parts; ++p) s += part[p];
+        *loss = s / (double)B;
+    }
+}
+
+// Adam (Kingma & Ba) with bias correction on the FP32 masters; refreshes BF16 copies.
+__global__ void k_adam(float *p, float *m, float *v, const float *g, int64_t count, float lr, float c1,
+                       float c2, uint16_t *ph) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const float gt = g[t];
+    const float mt = 0.9f * m[t] + 0.1f * gt;
+    const float vt = 0.999f * v[t] + 0.001f * gt * gt;
+    m[t] = mt;
+    v[t] = vt;
+    const float pt = p[t] - lr * (mt / c1) / (sqrtf(vt / c2) + 1e-8f);
+    p[t] = pt;
+    ph[t] = to_bf16(pt);
+}
+
+// Ensemble mean, relative spread and the fallback flag.
+__global__ void k_gate(const double *Km, int E, int64_t B, const float *x, const float *lo, const float *hi,
+                       double tau, double *K_out, uint8_t *flag, double *spread_out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= B) return;
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int e = 0; e < E; ++e)
+        for (int q = 0; q < 3; ++q) m[q] += Km[((int64_t)e * B + t) * 3 + q];
+    for (int q = 0; q < 3; ++q) m[q] /= (double)E;
+    const double fm = sqrt(m[0] * m[0] + 2.0 * m[1] * m[1] + m[2] * m[2]);
+    double sp = 0.0;
+    for (int e = 0; e < E; ++e) {
+        const double *k = Km + ((int64_t)e * B + t) * 3;
+        const double a = k[0] - m[0], b = k[1] - m[1], c = k[2] - m[2];
+        const double f = sqrt(a * a + 2.0 * b * b + c * c) / fm;
+        sp = f > sp ? f : sp;
+    }
+    bool out = false;
+    for (int c = 0; c < SHMM_SURR_IN; ++c) {
+        const float v = x[t * SHMM_SURR_IN + c];
+        if (!(v >= lo[c] && v <= hi[c])) out = true;
+    }
+    for (int q = 0; q < 3; ++q) K_out[3 * t + q] = m[q];
+    flag[t] = (uint8_t)((sp > tau || out || !(fm > 0.0)) ? 1 : 0);
+    if (spread_out) spread_out[t] = sp;
+}
+
+}  // namespace
+
+size_t surrogate_feature_workspace(int n, int64_t nlist) {
+    const size_t fft = (size_t)nlist * n * n * sizeof(c32);
+    const size_t part = (size_t)nlist * (n / kFeatRows) * SHMM_SURR_BINS * sizeof(float);
+    return fft + part;
+}
+
+int launch_patch_features(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n,
+                          const float *vx, const float *vy, const double *Kb, float *features, void *work,
+                          hipStream_t s) {
+    if (nlist <= 0) return SHMM_OK;
+    if (n < kFeatRows || n > 256) return SHMM_ERANGE;
+    c32 *fw = (c32 *)work;
+    float *part = (float *)((char *)work + (size_t)nlist * n * n * sizeof(c32));
+    const int parts = n / kFeatRows;
+    const dim3 grid((unsigned)parts, (unsigned)nlist);
+    hipLaunchKernelGGL(k_feat_rows, grid, dim3(256), 2 * kFeatRows * n * sizeof(c32), s, d_dom, d_list, n, vx,
+                       vy, fw);
+    SHMM_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_feat_cols, grid, dim3(256), 2 * kFeatRows * n * sizeof(c32) + kFeatRows * n * sizeof(float),
+                       s, d_dom, d_list, n, (const c32 *)fw, part);
+    SHMM_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_feat_final, dim3((unsigned)((nlist + 63) / 64)), dim3(64), 0, s, d_dom, d_list, nlist,
+                       parts, (const float *)part, Kb, features);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
+
+// Workspace of one forward/backward at batch B (bytes), laid out by `carve`.
+struct NetWork {
+    uint16_t *h[4];      // bf16 activations: h[0] = standardised input [B][33], h[1..3] [B][256]
+    float *z[3];         // pre-activations of the hidden layers [B][256]
+    float *o;            // outputs [B][3]
+    float *go;           // output gradient [B][3]
+    float *dz;           // FP32 gradient of the current layer [B][256]
+    uint16_t *dzh;       // its bf16 copy
+    float *dz2;          // second buffer for the next layer's gradient
+    double *loss_part;   // [ceil(B / 256)]
+    float *grad;         // [SHMM_SURR_PARAMS_PADDED]
+};
+
+static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+size_t surrogate_net_workspace(int64_t B) {
+    size_t s = 0;
+    s += align256((size_t)B * SHMM_SURR_IN * 2);
+    for (int l = 1; l < 4; ++l) s += align256((size_t)B * SHMM_SURR_WIDTH * 2);
+    for (int l = 0; l < 3; ++l) s += align256((size_t)B * SHMM_SURR_WIDTH * 4);
+    s += 2 * align256((size_t)B * 3 * 4);
+    s += 2 * align256((size_t)B * SHMM_SURR_WIDTH * 4) + align256((size_t)B * SHMM_SURR_WIDTH * 2);
+    s += align256((size_t)((B + 255) / 256) * 8);
+    s += align256((size_t)SHMM_SURR_PARAMS_PADDED * 4);
+    return s;
+}
+
+static NetWork carve(void *work, int64_t B) {
+    char *p = (char *)work;
+    NetWork w;
+    auto take = [&](size_t bytes) {
+        char *r = p;
+        p += align256(bytes);
+        return (void *)r;
+    };
+    w.h[0] = (uint16_t *)take((size_t)B * SHMM_SURR_IN * 2);
+    for (int l = 1; l < 4; ++l) w.h[l] = (uint16_t *)take((size_t)B * SHMM_SURR_WIDTH * 2);
+    for (int l = 0; l < 3; ++l) w.z[l] = (float *)take((size_t)B * SHMM_SURR_WIDTH * 4);
+    w.o = (float *)take((size_t)B * 3 * 4);
+    w.go = (float *)take((size_t)B * 3 * 4);
+    w.dz = (float *)take((size_t)B * SHMM_SURR_WIDTH * 4);
+    w.dz2 = (float *)take((size_t)B * SHMM_SURR_WIDTH * 4);
+    w.dzh = (uint16_t *)take((size_t)B * SHMM_SURR_WIDTH * 2);
+    w.loss_part = (double *)take((size_t)((B + 255) / 256) * 8);
+    w.grad = (float *)take((size_t)SHMM_SURR_PARAMS_PADDED * 4);
+    return w;
+}
+
+// member pointers inside one model block
+struct Model {
+    float *p;          // FP32 parameters
+    float *mu, *sigma; // standardisation
+    uint16_t *ph;      // bf16 parameters
+};
+
+static Model model_at(void *base) {
+    Model m;
+    m.p = (float *)base;
+    m.mu = m.p + SHMM_SURR_PARAMS_PADDED;
+    m.sigma = m.mu + 64;
+    m.ph = (uint16_t *)(m.mu + 128);
+    return m;
+}
+
+static int net_forward(const Model &m, const float *x, int64_t B, const NetWork &w, hipStream_t s) {
+    const Layout L = layout();
+    const int64_t nin = B * SHMM_SURR_IN;
+    hipLaunchKernelGGL(k_standardize, dim3((unsigned)((nin + 255) / 256)), dim3(256), 0, s, x, B, m.mu,
+                       m.sigma, w.h[0]);
+    SHMM_HIP_CHECK(hipGetLastError());
+    int rc;
+    for (int l = 0; l < 4; ++l) {
+        GemmArgs g;
+        g.M = (int)B;
+        g.N = L.out[l];
+        g.K = L.in[l];
+        g.A = w.h[l];
+        g.sam = L.in[l];
+        g.sak = 1;
+        g.B = m.ph + L.W[l];
+        g.sbk = 1;
+        g.sbn = L.in[l];
+        g.bias = m.p + L.b[l];
+        g.z = nullptr;
+        g.ldz = 0;
+        if (l < 3) {
+            g.epi = EPI_BIAS_GELU;
+            g.outf = w.z[l];
+            g.ldo = L.out[l];
+            g.outh = w.h[l + 1];
+            g.ldh = L.out[l];
+        } else {
+            g.epi = EPI_BIAS_F32;
+            g.outf = w.o;
+            g.ldo = 3;
+            g.outh = nullptr;
+            g.ldh = 0;
+        }
+        if ((rc = gemm(g, s))) return rc;
+    }
+    return SHMM_OK;
+}
+
+int surrogate_train_step(void *model, float *adam, const float *x, const double *Kb, const double *Kt,
+                         int64_t B, float lr, int32_t t, double *loss, float *grad_out, void *work,
+                         hipStream_t s) {
+    const Layout L = layout();
+    const Model m = model_at(model);
+    const NetWork w = carve(work, B);
+    int rc = net_forward(m, x, B, w, s);
+    if (rc) return rc;
+    const unsigned hb = (unsigned)((B + 255) / 256);
+    hipLaunchKernelGGL(k_head, dim3(hb), dim3(256), 0, s, (const float *)w.o, Kb, B, (double *)nullptr, Kt, w.go,
+                       w.loss_part);
+    SHMM_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, s, (const double *)w.loss_part, (int)hb, B, loss);
+    SHMM_HIP_CHECK(hipGetLastError());
+    // backward: dz of layer 3 is the output gradient
+    const float *dz = w.go;
+    float *next = w.dz;
+    for (int l = 3; l >= 0; --l) {
+        const int n_out = L.out[l], n_in = L.in[l];
+        const int64_t cnt = B * n_out;
+        hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, dz, w.dzh, cnt);
+        SHMM_HIP_CHECK(hipGetLastError());
+        // dW_l = dz^T h_l   ([out][B] x [B][in])
+        GemmArgs g;
+        g.M = n_out;
+        g.N = n_in;
+        g.K = (int)B;
+        g.A = w.dzh;
+        g.sam = 1;
+        g.sak = n_out;
+        g.B = w.h[l];
+        g.sbk = n_in;
+        g.sbn = 1;
+        g.epi = EPI_F32;
+        g.bias = nullptr;
+        g.outf = w.grad + L.W[l];
+        g.ldo = n_in;
+        g.outh = nullptr;
+        g.ldh = 0;
+        g.z = nullptr;
+        g.ldz = 0;
+        if ((rc = gemm(g, s))) return rc;
+        hipLaunchKernelGGL(k_colsum, dim3((unsigned)((n_out + 63) / 64)), dim3(64), 0, s, dz, B, n_out,
+                           w.grad + L.b[l]);
+        SHMM_HIP_CHECK(hipGetLastError());
+        if (l == 0) break;
+        // dz_{l-1} = (dz W_l) * gelu'(z_{l-1})   ([B][out] x [out][in])
+        GemmArgs h;
+        h.M = (int)B;
+        h.N = n_in;
+        h.K = n_out;
+        h.A = w.dzh;
+        h.sam = n_out;
+        h.sak = 1;
+        h.B = m.ph + L.W[l];
+        h.sbk = n_in;
+        h.sbn = 1;
+        h.epi = EPI_GELU_GRAD;
+        h.bias = nullptr;
+        h.outf = next;
+        h.ldo = n_in;
+        h.outh = nullptr;
+        h.ldh = 0;
+        h.z = w.z[l - 1];
+        h.ldz = n_in;
+        if ((rc = gemm(h, s))) return rc;
+        dz = next;
+        next = (next == w.dz) ? w.dz2 : w.dz;
+    }
+    const float c1 = 1.0f - powf(0.9f, (float)t), c2 = 1.0f - powf(0.999f, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((SHMM_SURR_PARAMS + 255) / 256)), dim3(256), 0, s, m.p, adam,
+                       adam + SHMM_SURR_PARAMS_PADDED, (const float *)w.grad, (int64_t)SHMM_SURR_PARAMS, lr, c1,
+                       c2, m.ph);
+    SHMM_HIP_CHECK(hipGetLastError());
+    if (grad_out)
+        SHMM_HIP_CHECK(hipMemcpyAsync(grad_out, w.grad, SHMM_SURR_PARAMS * sizeof(float),
+                                      hipMemcpyDeviceToDevice, s));
+    return SHMM_OK;
+}
+
+int surrogate_refresh_bf16(void *model, hipStream_t s) {
+    const Model m = model_at(model);
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((SHMM_SURR_PARAMS + 255) / 256)), dim3(256), 0, s,
+                       (const float *)m.p, m.ph, (int64_t)SHMM_SURR_PARAMS);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
+
+int surrogate_infer(const void *models, int32_t E, const float *x, const double *Kb, int64_t B,
+                    const float *lo, const float *hi, double tau, double *K_out, uint8_t *flags,
+                    double *spread, double *K_members, void *work, hipStream_t s) {
+    const NetWork w = carve(work, B);
+    double *Km = K_members;
+    int rc;
+    for (int e = 0; e < E; ++e) {
+        const Model m = model_at((char *)models + (size_t)e * SHMM_SURR_MODEL_BYTES);
+        if ((rc = net_forward(m, x, B, w, s))) return rc;
+        hipLaunchKernelGGL(k_head, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, (const float *)w.o, Kb, B,
+                           Km + (size_t)e * B * 3, (const double *)nullptr, (float *)nullptr, (double *)nullptr);
+        SHMM_HIP_CHECK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_gate, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, (const double *)Km, E, B, x, lo,
+                       hi, tau, K_out, flags, spread);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
+
+}  // namespace shmm

@@ -59,9 +59,12 @@ def test_band_tags_bit_exact(torch):
     H.close()
 
 
-def test_step_plan_bit_exact(torch):
-    p = flowgen.config_four_level_cellular(n=32, lattice=2)
-    say("case step plan")
+@pytest.mark.parametrize("name,make", [
+    ("four-level", lambda: flowgen.config_four_level_cellular(n=32, lattice=2)),
+    ("continuous", lambda: flowgen.config_continuous(seed=3, radius=40, n=16, lattice=2, levels=3))])
+def test_step_plan_bit_exact(torch, name, make):
+    p = make()
+    say("case step plan", name)
     H = hier(p, keep_psi=False)
     rng = np.random.default_rng(1)
     nd = H.nd
@@ -73,8 +76,11 @@ def test_step_plan_bit_exact(torch):
     lv, pt = oracle.band_split(p.kmax, p.thresh)
     for d in range(nd):
         D = table[d]
-        Vb = oracle.band_speed_bound(p.psi_hat, p.kmax, oracle.band_mask(lv, pt, int(D["level"]), DIAG))
-        dt, ns = oracle.plan_steps(int(D["n"]), float(D["h"]), Kb[d], Vb, p.dt_frac, p.delta)
+        m = oracle.band_mask(lv, pt, int(D["level"]), DIAG)
+        Vb = oracle.band_speed_bound(p.psi_hat, p.kmax, m)
+        Ps = oracle.band_amplitude_sum(p.psi_hat, p.kmax, m)
+        per = oracle.band_periodic_on_patch(p.psi_hat, p.kmax, m, int(D["n"]), int(D["N"]))
+        dt, ns = oracle.plan_steps(int(D["n"]), float(D["h"]), Kb[d], Vb, p.dt_frac, p.delta, Ps, per)
         assert int(D["nsteps"]) == ns and float(D["dt"]) == dt, d
     H.close()
 

@@ -1,0 +1,241 @@
+"""Parity of the surrogate kernels (features, BF16 matrix-core network, training
+step, gate, fallback) with the FP64 oracle.
+
+Tolerances: features 1e-4 absolute (logs of FP32 energies, relative error
+~1e-6).  Network outputs: the GPU evaluates GELU in FP32 and rounds hidden
+activations to bfloat16, the oracle does the same roundings from FP64 values,
+so a rounding decision can flip where the two differ (about one element in
+1e5); one flipped activation moves K by at most a few 1e-4 relative, hence
+2e-3.  Gradients: FP32 accumulation over the batch versus FP64 plus the same
+flips: 1e-2 relative L2 per layer.  Loss: 1e-4 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import flowgen
+import oracle
+from oracle import DIAG
+from oracle import surrogate as OS
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def _patches(n, lattice=2, seed=3, amp=0.4):
+    p = flowgen.config_continuous(seed=seed, radius=max(2, n // 8), p=-1.5, kappa=0.05, n=n,
+                                  lattice=lattice, levels=1)
+    p.psi_hat *= amp
+    p.n_global = [n * lattice]
+    return p
+
+
+@pytest.mark.parametrize("n", [32, 128])
+def test_patch_features_parity(torch, n):
+    from paper_1510_00451_amd.hierarchy import Hierarchy
+    p = _patches(n)
+    say("case features n=%d" % n)
+    H = Hierarchy(p)
+    H.band_filter()
+    rng = np.random.default_rng(n)
+    Kb = np.stack([rng.uniform(0.01, 0.1, H.nd), rng.uniform(-0.003, 0.003, H.nd),
+                   rng.uniform(0.01, 0.1, H.nd)], 1)
+    H.K_base.copy_(torch.from_numpy(Kb))
+    feats = torch.zeros(H.nd, 33, dtype=torch.float32, device="cuda")
+    H.ctx.shmm_patch_features(0, H.nd, H.vx.data_ptr(), H.vy.data_ptr(), H.K_base.data_ptr(),
+                              feats.data_ptr(), H.stream())
+    torch.cuda.synchronize()
+    got = feats.cpu().numpy()
+    lv, pt = oracle.band_split(p.kmax, p.thresh)
+    mask = oracle.band_mask(lv, pt, 0, DIAG)
+    for d in range(H.nd):
+        D = H.table[d]
+        psi = oracle.synth_patch(p.psi_hat, p.kmax, mask, int(D["N"]), int(D["I0"]), int(D["J0"]), n)
+        vx, vy, _, _ = oracle.staggered(psi, float(D["h"]))
+        ref = OS.patch_features(vx, vy, n, int(D["N"]), Kb[d])
+        assert np.max(np.abs(got[d] - ref)) <= 1e-4, (d, np.abs(got[d] - ref).max())
+    H.close()
+
+
+def _random_member(seed, rng):
+    net = OS.init_net(seed)
+    for l in range(4):
+        net.b[l] = rng.standard_normal(net.b[l].shape) * 0.05
+    net.mu = rng.standard_normal(33)
+    net.sigma = rng.uniform(0.5, 2.0, 33)
+    return net
+
+
+def _pack(torch, nets):
+    from paper_1510_00451_amd import surrogate as GS
+    host = np.concatenate([GS.pack_params(n.W, n.b, n.mu, n.sigma) for n in nets])
+    return torch.from_numpy(host).to("cuda")
+
+
+def _to32(net):
+    """The oracle side of a model stored as FP32 parameters on the device."""
+    n = net.copy()
+    n.W = [w.astype(np.float32).astype(np.float64) for w in n.W]
+    n.b = [v.astype(np.float32).astype(np.float64) for v in n.b]
+    n.mu = n.mu.astype(np.float32).astype(np.float64)
+    n.sigma = n.sigma.astype(np.float32).astype(np.float64)
+    return n
+
+
+def test_inference_and_gate_parity(torch):
+    from paper_1510_00451_amd import abi
+    rng = np.random.default_rng(7)
+    nets = [_to32(_random_member(s, rng)) for s in (11, 12)]
+    B = 200                                  # not a multiple of the 64-row tile
+    x = rng.standard_normal((B, 33)).astype(np.float32).astype(np.float64)
+    Kb = np.stack([rng.uniform(0.01, 0.1, B), rng.uniform(-0.003, 0.003, B), rng.uniform(0.01, 0.1, B)], 1)
+    lo = np.full(33, -3.5, np.float32)
+    hi = np.full(33, 3.5, np.float32)
+    say("case inference")
+    ctx = abi.Context(0)
+    models = _pack(torch, nets)
+    s = torch.cuda.current_stream().cuda_stream
+    for e in range(2):
+        ctx.shmm_surrogate_refresh(models.data_ptr() + e * abi.SURR_MODEL_BYTES, s)
+    dx = torch.tensor(x, dtype=torch.float32, device="cuda")
+    dKb = torch.tensor(Kb, dtype=torch.float64, device="cuda")
+    K = torch.empty(B, 3, dtype=torch.float64, device="cuda")
+    flags = torch.empty(B, dtype=torch.uint8, device="cuda")
+    spread = torch.empty(B, dtype=torch.float64, device="cuda")
+    Km = torch.empty(2, B, 3, dtype=torch.float64, device="cuda")
+    dlo = torch.tensor(lo, device="cuda")
+    dhi = torch.tensor(hi, device="cuda")
+    ref_members = np.stack([OS.head(OS.forward(n, x, bf16_mode=True)[0], Kb) for n in nets])
+    tau = float(np.median(OS.ensemble_gate(ref_members, x, lo, hi, 1.0)[2]))   # about half flagged
+    ctx.shmm_surrogate_infer(models.data_ptr(), 2, dx.data_ptr(), dKb.data_ptr(), B, dlo.data_ptr(),
+                             dhi.data_ptr(), tau, K.data_ptr(), flags.data_ptr(), spread.data_ptr(),
+                             Km.data_ptr(), s)
+    torch.cuda.synchronize()
+    got_members = Km.cpu().numpy()
+    rel = np.abs(got_members - ref_members).max(axis=2) / np.abs(ref_members).max(axis=2)
+    assert rel.max() <= 2e-3, rel.max()
+    Kref, fref, sref = OS.ensemble_gate(ref_members, x, lo.astype(np.float64), hi.astype(np.float64), tau)
+    np.testing.assert_allclose(K.cpu().numpy(), Kref, rtol=2e-3)
+    g = flags.cpu().numpy().astype(bool)
+    near = np.abs(sref - tau) <= 5e-3 * tau
+    assert np.array_equal(g[~near], fref[~near])
+    assert 0 < g.sum() < B                   # both outcomes occur in this case
+    ctx.close()
+
+
+def test_train_step_parity(torch):
+    from paper_1510_00451_amd import abi
+    rng = np.random.default_rng(5)
+    net = _to32(_random_member(21, rng))
+    B = 96
+    x = rng.standard_normal((B, 33)).astype(np.float32).astype(np.float64)
+    Kb = np.stack([rng.uniform(0.01, 0.1, B), rng.uniform(-0.003, 0.003, B), rng.uniform(0.01, 0.1, B)], 1)
+    Kt = Kb * rng.uniform(1.0, 2.5, (B, 1))
+    say("case train step")
+    ctx = abi.Context(0)
+    model = _pack(torch, [net])
+    s = torch.cuda.current_stream().cuda_stream
+    ctx.shmm_surrogate_refresh(model.data_ptr(), s)
+    adam = torch.zeros(2 * abi.SURR_PARAMS_PADDED, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    grad = torch.zeros(abi.SURR_PARAMS, dtype=torch.float32, device="cuda")
+    dx = torch.tensor(x, dtype=torch.float32, device="cuda")
+    dKb = torch.tensor(Kb, device="cuda")
+    dKt = torch.tensor(Kt, device="cuda")
+    lr = 1e-3
+    ctx.shmm_surrogate_train_step(model.data_ptr(), adam.data_ptr(), dx.data_ptr(), dKb.data_ptr(),
+                                  dKt.data_ptr(), B, lr, 1, loss.data_ptr(), grad.data_ptr(), s)
+    torch.cuda.synchronize()
+    o, cache = OS.forward(net, x, bf16_mode=True)
+    l_ref, go = OS.loss_and_grad_o(o, Kb, Kt)
+    gW, gb = OS.backward(net, cache, go, bf16_mode=True)
+    assert abs(loss.item() - l_ref) <= 1e-4 * l_ref
+    g = grad.cpu().numpy().astype(np.float64)
+    off = 0
+    for l in range(4):
+        for ref in (gW[l].reshape(-1), gb[l]):
+            got = g[off:off + ref.size]
+            off += ref.size
+            assert np.linalg.norm(got - ref) <= 1e-2 * np.linalg.norm(ref), (l, ref.size)
+    # Adam step from zero moments: p - lr g / (|g| + eps) elementwise
+    from paper_1510_00451_amd import surrogate as GS
+    W1, b1, _, _ = GS.unpack_params(model.cpu().numpy())
+    flat_new = np.concatenate([np.concatenate([w.reshape(-1), v]) for w, v in zip(W1, b1)])
+    flat_old = np.concatenate([np.concatenate([w.reshape(-1), v]) for w, v in zip(net.W, net.b)])
+    gref = np.concatenate([np.concatenate([gW[l].reshape(-1), gb[l]]) for l in range(4)])
+    big = np.abs(gref) > 1e-3 * np.abs(gref).max()
+    expect = flat_old - lr * gref / (np.abs(gref) + 1e-8)
+    assert np.max(np.abs(flat_new - expect)[big]) <= 1e-6
+    ctx.close()
+
+
+def test_fallback_equals_plain_solve(torch):
+    from paper_1510_00451_amd.hierarchy import Hierarchy
+    p = _patches(32, lattice=4)
+    say("case fallback")
+    H = Hierarchy(p, keep_psi=False)
+    H.band_filter()
+    Kb = np.tile([0.05, 0.0, 0.05], (H.nd, 1))
+    H.K_base.copy_(torch.from_numpy(Kb))
+    H.ctx.shmm_plan_steps(0, H.nd, Kb)
+    s = H.stream()
+    H.w.zero_()
+    H.ctx.shmm_local_solve_batch(0, H.nd, H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(),
+                                 H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(), 0, 2 ** 31 - 1, 0, s)
+    H.ctx.shmm_effective_diffusivity(0, H.nd, H.f1.data_ptr(), H.f2.data_ptr(), H.w.data_ptr(),
+                                     H.K_base.data_ptr(), H.K_solve.data_ptr(), 0, 0, 0, s)
+    torch.cuda.synchronize()
+    plain = H.K_solve.cpu().numpy().copy()
+    flags = torch.zeros(H.nd, dtype=torch.uint8, device="cuda")
+    flags[::3] = 1
+    Kout = torch.full((H.nd, 3), -1.0, dtype=torch.float64, device="cuda")
+    H.status.zero_()
+    H.w.fill_(7.0)                           # the fallback must clear the correctors itself
+    H.ctx.shmm_fallback_solve(0, H.nd, flags.data_ptr(), H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(),
+                              H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(), Kout.data_ptr(),
+                              H.status.data_ptr(), s)
+    torch.cuda.synchronize()
+    got = Kout.cpu().numpy()
+    f = flags.cpu().numpy().astype(bool)
+    assert np.array_equal(got[f], plain[f])
+    assert np.all(got[~f] == -1.0)
+    st = H.status.cpu().numpy()
+    assert np.all((st[f] & 8) == 8) and np.all(st[~f] == 0)
+    H.close()
+
+
+def test_training_reduces_loss(torch):
+    """A few hundred steps on a smooth synthetic target fall well below the
+    initial loss (the kernels learn, not only match one step)."""
+    from paper_1510_00451_amd import abi
+    from paper_1510_00451_amd import surrogate as GS
+    rng = np.random.default_rng(9)
+    S = 2048
+    x = rng.standard_normal((S, 33))
+    Kb = np.tile([0.02, 0.0, 0.02], (S, 1))
+    enh = 1.0 + 0.5 * np.tanh(x[:, 0]) + 0.2 * x[:, 1] ** 2
+    Kt = Kb * enh[:, None]
+    say("case training")
+    ctx = abi.Context(0)
+    ens = GS.Ensemble(ctx, 1, np.zeros(33), np.ones(33), seed0=3)
+    data = GS.Dataset(torch.tensor(x, dtype=torch.float32, device="cuda"), torch.tensor(Kb, device="cuda"),
+                      torch.tensor(Kt, device="cuda"))
+    hist = GS.train(ens, data, steps=300, batch=256, lr0=3e-3, log=lambda *a: None)
+    K, flags, spread = GS.infer(ens, data.x, data.Kb, torch.full((33,), -1e9, device="cuda"),
+                                torch.full((33,), 1e9, device="cuda"), 1.0)
+    torch.cuda.synchronize()
+    err = np.abs(K.cpu().numpy()[:, 0] - Kt[:, 0]) / Kt[:, 0]
+    assert np.median(err) < 0.02, np.median(err)
+    ctx.close()
