@@ -58,8 +58,8 @@ def cpu_baseline(steps_sample: int = 2000, domains_sample: int = 32):
     f1 = np.concatenate([f[3].ravel() for f in fields])
     f2 = np.concatenate([f[4].ravel() for f in fields])
     Kb = np.tile([p.kappa, 0.0, p.kappa], (len(doms), 1))
-    Vb = oracle.band_speed_bound(p.psi_hat, p.kmax, oracle.band_mask(lv, pt, 3, oracle.DIAG))
-    dt, _ = oracle.plan_steps(128, doms[0].h, Kb[0], Vb, p.dt_frac, p.delta)
+    vmax = max(oracle.advection_bound(f[1], f[2]) for f in fields)
+    dt, _ = oracle.plan_steps(128, doms[0].h, Kb[0], vmax, p.dt_frac, p.delta)
     t0 = time.perf_counter()
     oracle.local_solve_batch([d.n for d in doms], [d.h for d in doms], vx, vy, f1, f2, Kb,
                              [dt] * len(doms), [steps_sample] * len(doms))

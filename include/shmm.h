@@ -146,17 +146,20 @@ int shmm_band_tags(shmm_ctx *ctx, int32_t inst, int8_t *d_tags, void *stream);
 /* Step plan of the local solves of domains [first, first + count) (HMM step 2):
  * dt = T/nsteps with T = ln(1/delta) / (lambda_min(K_b) 4 sin^2(pi/n) / h^2)
  * and nsteps = ceil(T / (dt_frac / (rho_D/2.785 + rho_A/2.828))),
- * rho_D = (4 K11 + 4 K22 + 2|K12|)/h^2, rho_A = (V_b + s)/h, V_b = sum over the
- * level's diagonal band of |psi_hat(k)| (|k1| + |k2|); s = 0 when the band is
- * periodic on the patch (k n / N integral for all its modes), otherwise
- * s = 2 Psi_b / h with Psi_b = sum of |psi_hat(k)| over the band (the faces
- * across the wrapped seam of the patch carry the jump of psi).  A patch whose diagonal
- * band holds no coefficient has zero forcing, so its corrector stays zero: it
- * gets nsteps = 0, dt = 0 and the local solve leaves it untouched.  K_base is
- * host [n_domains][3] indexed by global domain.  Host arithmetic, bit-exact;
- * updates the context's table on host and device (synchronous).
- * Errors: SHMM_ENOTSPD if a base is not positive definite. */
-int shmm_plan_steps(shmm_ctx *ctx, int64_t first, int64_t count, const double *K_base);
+ * rho_D = (4 K11 + 4 K22 + 2|K12|)/h^2 and rho_A = vmax_d / h, where vmax_d is
+ * max over the patch's cells of (|vx_W| + |vx_E| + |vy_S| + |vy_N|) / 2: the
+ * centred advection with discretely divergence-free faces is skew-symmetric,
+ * so this Gershgorin value bounds its spectral radius (seam faces of
+ * non-periodic patches included).  vmax is host [n_domains] (global index) or
+ * NULL to use the values the band filter computed for the range.  A patch whose
+ * diagonal band holds no coefficient has zero forcing, so its corrector stays
+ * zero: it gets nsteps = 0, dt = 0 and the local solve leaves it untouched.
+ * K_base is host [n_domains][3].  Host arithmetic in a fixed expression order
+ * (bit-exact for given inputs); updates the context's table on host and device
+ * (synchronous).  Errors: SHMM_ENOTSPD if a base is not positive definite;
+ * SHMM_EINVAL if vmax is NULL and the band filter has not run on the range. */
+int shmm_plan_steps(shmm_ctx *ctx, int64_t first, int64_t count, const double *K_base,
+                    const double *vmax);
 
 /* Band filter of domains [first, first + count) (Section 3.1), which must be
  * whole (instance, level) groups.  For each domain writes, in FP32 at the

@@ -200,49 +200,18 @@ def domain_table(probs) -> List[Domain]:
     return out
 
 
-def band_speed_bound(psi_hat: np.ndarray, kmax: int, mask: np.ndarray) -> float:
-    """V_b = sum over the band of |psi_hat(k)| (|k1| + |k2|), in k2-major order.
+def advection_bound(vx: np.ndarray, vy: np.ndarray) -> float:
+    """max over cells of (|vx_W| + |vx_E| + |vy_S| + |vy_N|) / 2.
 
-    An a-priori bound on |vx| + |vy| of the band's velocity v = (-d2 psi, d1 psi)
-    (Section 2.1).  Used only for the step size.
-    """
-    s = 0.0
-    span = 2 * kmax + 1
-    flat = psi_hat.reshape(-1)
-    for idx in np.flatnonzero(mask.reshape(-1)):
-        b, a = divmod(int(idx), span)
-        re, im = float(flat[idx].real), float(flat[idx].imag)
-        s = s + math.sqrt(re * re + im * im) * float(abs(a - kmax) + abs(b - kmax))
-    return s
+    The centred flux-form advection operator with discretely divergence-free
+    face velocities is skew-symmetric with zero diagonal, so by Gershgorin its
+    spectral radius is at most this value divided by h."""
+    s = (np.abs(vx) + np.abs(np.roll(vx, -1, axis=1)) + np.abs(vy) + np.abs(np.roll(vy, -1, axis=0)))
+    return float(np.max(s)) * 0.5
 
 
-def band_amplitude_sum(psi_hat: np.ndarray, kmax: int, mask: np.ndarray) -> float:
-    """Psi_b = sum over the band of |psi_hat(k)|, in k2-major order: a bound on
-    the band's max |psi|, hence on half the jump of its values across a patch."""
-    s = 0.0
-    flat = psi_hat.reshape(-1)
-    for idx in np.flatnonzero(mask.reshape(-1)):
-        re, im = float(flat[idx].real), float(flat[idx].imag)
-        s = s + math.sqrt(re * re + im * im)
-    return s
-
-
-def band_periodic_on_patch(psi_hat: np.ndarray, kmax: int, mask: np.ndarray, n: int, N: int) -> bool:
-    """True when every band mode with a coefficient has k n / N integral in both
-    directions, i.e. the band is periodic on an n-cell patch of the level grid."""
-    span = 2 * kmax + 1
-    flat = psi_hat.reshape(-1)
-    for idx in np.flatnonzero(mask.reshape(-1)):
-        if flat[idx] == 0:
-            continue
-        b, a = divmod(int(idx), span)
-        if ((a - kmax) * n) % N != 0 or ((b - kmax) * n) % N != 0:
-            return False
-    return True
-
-
-def plan_steps(n: int, h: float, K: Sequence[float], Vb: float, dt_frac: float,
-               delta: float, psi_sum: float = 0.0, periodic: bool = True) -> Tuple[float, int]:
+def plan_steps(n: int, h: float, K: Sequence[float], vmax: float, dt_frac: float,
+               delta: float) -> Tuple[float, int]:
     """Step size and step count of one local solve (HMM step 2, Section 2.2).
 
     The paper evolves to a quasi-stationary state without fixing the time.
@@ -252,16 +221,13 @@ def plan_steps(n: int, h: float, K: Sequence[float], Vb: float, dt_frac: float,
     5-point Laplacian, whose smallest nonzero eigenvalue is 4 sin^2(pi/n)/h^2).
     The RK4 step is dt_frac times 1/(rho_D/2.785 + rho_A/2.828), where 2.785 and
     2.828 bound RK4's real and imaginary stability intervals,
-    rho_D = (4 K11 + 4 K22 + 2|K12|)/h^2 and rho_A = (V_b + s)/h, with s = 0 for a
-    band periodic on the patch and s = 2 Psi_b / h otherwise: the faces across
-    the wrapped seam of a non-periodic patch carry the jump of psi over the
-    patch, at most 2 max|psi| <= 2 Psi_b, divided by h.
+    rho_D = (4 K11 + 4 K22 + 2|K12|)/h^2 bounds the 9-point diffusion and
+    rho_A = vmax/h (see advection_bound) the skew advection operator.
     Every operation is spelled out so the result is reproducible bit for bit.
     """
     K11, K12, K22 = float(K[0]), float(K[1]), float(K[2])
     rho_d = (4.0 * K11 + 4.0 * K22 + 2.0 * abs(K12)) / (h * h)
-    seam = 0.0 if periodic else 2.0 * psi_sum / h
-    rho_a = (Vb + seam) / h
+    rho_a = vmax / h
     dt_lim = 1.0 / (rho_d / 2.785 + rho_a / 2.828)
     lam = 0.5 * (K11 + K22) - math.sqrt(0.25 * (K11 - K22) * (K11 - K22) + K12 * K12)
     if not lam > 0.0:
@@ -503,9 +469,6 @@ def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = N
     dt = np.zeros(nd)
     nsteps = np.zeros(nd, np.int64)
     lines = np.zeros(sum(2 * d.n for d in doms))
-    vb_cache: Dict[Tuple[int, int], float] = {}
-    psum_cache: Dict[Tuple[int, int], float] = {}
-    periodic_band: Dict[Tuple[int, int], bool] = {}
     empty_band: Dict[Tuple[int, int], bool] = {}
     for i, d in enumerate(doms):
         p = probs[d.instance]
@@ -515,11 +478,8 @@ def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = N
         lines[d.line_offset + d.n:d.line_offset + 2 * d.n] = line_energies(
             p.psi_hat, p.kmax, band_mask(lv, pt, d.level, OFF21), d.N, d.J0, d.n, 1)
         key = (d.instance, d.level)
-        if key not in vb_cache:
+        if key not in empty_band:
             dm = band_mask(lv, pt, d.level, DIAG)
-            vb_cache[key] = band_speed_bound(p.psi_hat, p.kmax, dm)
-            psum_cache[key] = band_amplitude_sum(p.psi_hat, p.kmax, dm)
-            periodic_band[key] = band_periodic_on_patch(p.psi_hat, p.kmax, dm, d.n, d.N)
             empty_band[key] = not np.any((dm != 0) & (p.psi_hat != 0))
 
     def s12(i):
@@ -551,8 +511,10 @@ def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = N
     maxL = max(L_of)
     for lev in range(maxL - 1, -1, -1):
         idx = [i for i, d in enumerate(doms) if d.level == lev]
+        # fields of this level (one batch)
+        fields = [level_fields(probs[doms[i].instance], *splits[doms[i].instance], doms[i]) for i in idx]
         # bases of this level
-        for i in idx:
+        for t, i in enumerate(idx):
             d = doms[i]
             if lev == L_of[d.instance] - 1:
                 K_base[i] = K_in[i]
@@ -562,13 +524,11 @@ def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = N
                 K_base[i] = K_star - K_off[i] + K_in[i]
             p = probs[d.instance]
             key = (d.instance, lev)
-            dt[i], nsteps[i] = plan_steps(d.n, d.h, K_base[i], vb_cache[key], p.dt_frac, p.delta,
-                                          psum_cache[key], periodic_band[key])
+            vmax = advection_bound(fields[t][1], fields[t][2])
+            dt[i], nsteps[i] = plan_steps(d.n, d.h, K_base[i], vmax, p.dt_frac, p.delta)
             if empty_band[(d.instance, lev)]:
                 # zero forcing: the corrector stays zero, nothing is integrated
                 dt[i], nsteps[i] = 0.0, 0
-        # fields and solves of this level (one batch)
-        fields = [level_fields(probs[doms[i].instance], *splits[doms[i].instance], doms[i]) for i in idx]
         vx = np.concatenate([f[1].reshape(-1) for f in fields])
         vy = np.concatenate([f[2].reshape(-1) for f in fields])
         f1 = np.concatenate([f[3].reshape(-1) for f in fields])

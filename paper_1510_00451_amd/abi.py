@@ -68,7 +68,7 @@ def lib() -> ctypes.CDLL:
             "shmm_ctx_set_problem": [P, P, i32],
             "shmm_ctx_table": [P, P, P, P, P, P, P],
             "shmm_band_tags": [P, i32, P, P],
-            "shmm_plan_steps": [P, i64, i64, P],
+            "shmm_plan_steps": [P, i64, i64, P, P],
             "shmm_band_filter": [P, i64, i64, P, P, P, P, P, P, P],
             "shmm_local_solve_batch": [P, i64, i64, P, P, P, P, P, P, i32, i32, P, P],
             "shmm_effective_diffusivity": [P, i64, i64, P, P, P, P, P, P, P, P, P],
@@ -178,9 +178,12 @@ class Context:
     def shmm_band_tags(self, inst: int, d_tags: int, stream: int = 0) -> None:
         check(lib().shmm_band_tags(self.h, inst, d_tags, stream), "shmm_band_tags")
 
-    def shmm_plan_steps(self, first: int, count: int, K_base_host: np.ndarray) -> None:
+    def shmm_plan_steps(self, first: int, count: int, K_base_host: np.ndarray,
+                        vmax_host: "np.ndarray | None" = None) -> None:
         K = np.ascontiguousarray(K_base_host, np.float64)
-        check(lib().shmm_plan_steps(self.h, first, count, K.ctypes.data), "shmm_plan_steps")
+        V = None if vmax_host is None else np.ascontiguousarray(vmax_host, np.float64)
+        check(lib().shmm_plan_steps(self.h, first, count, K.ctypes.data,
+                                    None if V is None else V.ctypes.data), "shmm_plan_steps")
 
     def shmm_band_filter(self, first, count, d_psi, d_vx, d_vy, d_f1, d_f2, d_lines, stream=0):
         check(lib().shmm_band_filter(self.h, first, count, d_psi or None, d_vx, d_vy, d_f1, d_f2,

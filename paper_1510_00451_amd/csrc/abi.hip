@@ -102,45 +102,14 @@ void build_table(const shmm_problem *p, int32_t n_inst, std::vector<shmm_domain>
     }
 }
 
-// V_b = sum over the level's diagonal band of |psi_hat(k)| (|k1| + |k2|), k2-major.
-double band_speed_bound(const shmm_problem &P, int level) {
-    const int K = P.kmax, span = 2 * K + 1;
-    double s = 0.0;
-    for (int b = 0; b < span; ++b)
-        for (int a = 0; a < span; ++a) {
-            const int k1 = a - K, k2 = b - K;
-            if (k1 == 0 && k2 == 0) continue;
-            const int l = band_level(k1, k2, P.thresh, P.n_levels);
-            if (l != level || band_part(k1, k2, l, P.thresh, P.n_levels) != SHMM_DIAG) continue;
-            const int64_t idx = (int64_t)b * span + a;
-            const double re = P.psi_hat[2 * idx], im = P.psi_hat[2 * idx + 1];
-            s = s + sqrt(re * re + im * im) * (double)(abs(k1) + abs(k2));
-        }
-    return s;
-}
-
-// Psi_b = sum over the level's diagonal band of |psi_hat(k)|, k2-major.
-double band_amplitude_sum(const shmm_problem &P, int level) {
-    const int K = P.kmax, span = 2 * K + 1;
-    double s = 0.0;
-    for (int b = 0; b < span; ++b)
-        for (int a = 0; a < span; ++a) {
-            const int k1 = a - K, k2 = b - K;
-            if (k1 == 0 && k2 == 0) continue;
-            const int l = band_level(k1, k2, P.thresh, P.n_levels);
-            if (l != level || band_part(k1, k2, l, P.thresh, P.n_levels) != SHMM_DIAG) continue;
-            const int64_t idx = (int64_t)b * span + a;
-            const double re = P.psi_hat[2 * idx], im = P.psi_hat[2 * idx + 1];
-            s = s + sqrt(re * re + im * im);
-        }
-    return s;
-}
-
-// Largest |k1|, |k2| carrying a nonzero coefficient in the level's diagonal band.
-void band_extent(const shmm_problem &P, int level, int *kb1, int *kb2) {
+// One scan of a level's diagonal band: the largest |k1|, |k2| carrying a
+// coefficient, and whether every such mode is periodic on an n-cell patch of
+// the level grid (k n / N integral in both directions).
+void band_stats(const shmm_problem &P, int level, int n, int N, int *kb1, int *kb2, int *periodic) {
     const int K = P.kmax, span = 2 * K + 1;
     *kb1 = 0;
     *kb2 = 0;
+    *periodic = 1;
     for (int b = 0; b < span; ++b)
         for (int a = 0; a < span; ++a) {
             const int k1 = a - K, k2 = b - K;
@@ -151,36 +120,18 @@ void band_extent(const shmm_problem &P, int level, int *kb1, int *kb2) {
             if (l != level || band_part(k1, k2, l, P.thresh, P.n_levels) != SHMM_DIAG) continue;
             *kb1 = std::max(*kb1, abs(k1));
             *kb2 = std::max(*kb2, abs(k2));
+            if (((int64_t)k1 * n) % N != 0 || ((int64_t)k2 * n) % N != 0) *periodic = 0;
         }
-}
-
-// True when every mode of the level's diagonal band is periodic on the patch
-// (k n / N integral in both directions).
-int band_periodic(const shmm_problem &P, int level, int n, int N) {
-    const int K = P.kmax, span = 2 * K + 1;
-    for (int b = 0; b < span; ++b)
-        for (int a = 0; a < span; ++a) {
-            const int k1 = a - K, k2 = b - K;
-            if (k1 == 0 && k2 == 0) continue;
-            const int64_t idx = (int64_t)b * span + a;
-            if (P.psi_hat[2 * idx] == 0.0 && P.psi_hat[2 * idx + 1] == 0.0) continue;
-            const int l = band_level(k1, k2, P.thresh, P.n_levels);
-            if (l != level || band_part(k1, k2, l, P.thresh, P.n_levels) != SHMM_DIAG) continue;
-            if (((int64_t)k1 * n) % N != 0 || ((int64_t)k2 * n) % N != 0) return 0;
-        }
-    return 1;
 }
 
 // Step plan (see shmm.h).  The expression order is part of the contract.
-// rho_A = (V_b + s)/h with s = 2 Psi_b / h for a band that is not periodic on
-// the patch: the faces across the wrapped seam carry the jump of psi.
-int plan_one(const shmm_domain &d, const double *K, double Vb, double psi_sum, int periodic,
-             double dt_frac, double delta, double *dt_out, int64_t *nsteps_out) {
+// rho_A = vmax / h: the Gershgorin bound of the skew advection operator.
+int plan_one(const shmm_domain &d, const double *K, double vmax, double dt_frac, double delta,
+             double *dt_out, int64_t *nsteps_out) {
     const double K11 = K[0], K12 = K[1], K22 = K[2];
     const double h = d.h;
     const double rho_d = (4.0 * K11 + 4.0 * K22 + 2.0 * fabs(K12)) / (h * h);
-    const double seam = periodic ? 0.0 : 2.0 * psi_sum / h;
-    const double rho_a = (Vb + seam) / h;
+    const double rho_a = vmax / h;
     const double dt_lim = 1.0 / (rho_d / 2.785 + rho_a / 2.828);
     const double lam = 0.5 * (K11 + K22) - sqrt(0.25 * (K11 - K22) * (K11 - K22) + K12 * K12);
     if (!(lam > 0.0)) return SHMM_ENOTSPD;
@@ -235,9 +186,7 @@ struct shmm_ctx {
     std::vector<Group> groups;
     int32_t *d_origins = nullptr;
     int32_t *d_child_start = nullptr, *d_child_idx = nullptr;
-    std::vector<std::vector<double>> vb;     // [inst][level]
-    std::vector<std::vector<double>> psum;   // [inst][level]
-    std::vector<std::vector<int>> periodic;  // [inst][level]
+    double *d_vmax = nullptr;                // [nd] advection bound of each patch (band filter)
     std::vector<std::vector<int>> empty;     // [inst][level]: diagonal band without coefficients
     std::map<std::pair<int64_t, int64_t>, RangeLists> lists;
     std::map<int, int> solve_variant;          // patch size n -> kernel variant
@@ -274,6 +223,8 @@ struct shmm_ctx {
         if (d_origins) (void)hipFree(d_origins);
         if (d_child_start) (void)hipFree(d_child_start);
         if (d_child_idx) (void)hipFree(d_child_idx);
+        if (d_vmax) (void)hipFree(d_vmax);
+        d_vmax = nullptr;
         d_inst = nullptr;
         d_table = nullptr;
         d_origins = nullptr;
@@ -406,9 +357,6 @@ int shmm_ctx_set_problem(shmm_ctx *ctx, const shmm_problem *p, int32_t n_inst) {
     ctx->psi.assign(n_inst, {});
     ctx->geo.assign(n_inst, {});
     ctx->inst.assign(n_inst, InstDev());
-    ctx->vb.assign(n_inst, {});
-    ctx->psum.assign(n_inst, {});
-    ctx->periodic.assign(n_inst, {});
     ctx->empty.assign(n_inst, {});
     for (int32_t q = 0; q < n_inst; ++q) {
         shmm_problem &P = ctx->probs[q];
@@ -437,18 +385,15 @@ int shmm_ctx_set_problem(shmm_ctx *ctx, const shmm_problem *p, int32_t n_inst) {
         I.kmax = P.kmax;
         I.L = L;
         for (int l = 0; l < SHMM_MAX_LEVELS; ++l) I.thresh[l] = l + 1 < L ? P.thresh[l] : 0;
-        for (int l = 0; l < L; ++l) {
-            ctx->vb[q].push_back(band_speed_bound(P, l));
-            ctx->psum[q].push_back(band_amplitude_sum(P, l));
-            ctx->periodic[q].push_back(band_periodic(P, l, P.n_cells[l], P.n_global[l]));
-            int kb1 = 0, kb2 = 0;
-            band_extent(P, l, &kb1, &kb2);
-            ctx->empty[q].push_back(kb1 == 0 && kb2 == 0 ? 1 : 0);
-        }
+        for (int l = 0; l < L; ++l) ctx->empty[q].push_back(0);
     }
     if ((rc = upload(&ctx->d_inst, ctx->inst.data(), ctx->inst.size()))) return rc;
     build_table(ctx->probs.data(), n_inst, ctx->table, ctx->cells, ctx->lines, ctx->phase_first);
     if ((rc = upload(&ctx->d_table, ctx->table.data(), ctx->table.size()))) return rc;
+    {
+        std::vector<double> zero(ctx->table.size() ? ctx->table.size() : 1, -1.0);
+        if ((rc = upload(&ctx->d_vmax, zero.data(), zero.size()))) return rc;
+    }
     // groups (instance, level) and the band extents; lattice origins per group
     ctx->groups.clear();
     std::vector<int32_t> origins;
@@ -463,8 +408,8 @@ int shmm_ctx_set_problem(shmm_ctx *ctx, const shmm_problem *p, int32_t n_inst) {
         g.N = D.N;
         g.M = ctx->probs[D.instance].lattice[D.level];
         g.count = (int64_t)g.M * g.M;
-        band_extent(ctx->probs[D.instance], D.level, &g.kb1, &g.kb2);
-        g.periodic = band_periodic(ctx->probs[D.instance], D.level, g.n, g.N);
+        band_stats(ctx->probs[D.instance], D.level, g.n, g.N, &g.kb1, &g.kb2, &g.periodic);
+        ctx->empty[D.instance][D.level] = (g.kb1 == 0 && g.kb2 == 0) ? 1 : 0;
         g.cell_first = D.offset;
         if (2 * std::max(g.kb1, g.kb2) + 1 > g.N) return SHMM_ERANGE;
         g.d_I0 = (const int32_t *)(intptr_t)origins.size();   // fixed up after upload
@@ -515,17 +460,29 @@ int shmm_band_tags(shmm_ctx *ctx, int32_t inst, int8_t *d_tags, void *stream) {
     return launch_band_tags(ctx->inst[inst], d_tags, (hipStream_t)stream);
 }
 
-int shmm_plan_steps(shmm_ctx *ctx, int64_t first, int64_t count, const double *K_base) {
+int shmm_plan_steps(shmm_ctx *ctx, int64_t first, int64_t count, const double *K_base,
+                    const double *vmax) {
     if (!range_ok(ctx, first, count) || !K_base) return SHMM_EINVAL;
     int rc = set_device(ctx);
     if (rc) return rc;
+    std::vector<double> vm;
+    if (!vmax) {   // the band filter's per-patch bounds
+        vm.assign(ctx->table.size(), -1.0);
+        if (count > 0) {
+            SHMM_HIP_CHECK(hipDeviceSynchronize());
+            SHMM_HIP_CHECK(hipMemcpy(vm.data() + first, ctx->d_vmax + first, count * sizeof(double),
+                                     hipMemcpyDeviceToHost));
+        }
+        vmax = vm.data();
+    }
     for (int64_t d = first; d < first + count; ++d) {
         shmm_domain &D = ctx->table[d];
         const shmm_problem &P = ctx->probs[D.instance];
         double dt = 0.0;
         int64_t ns = 0;
-        rc = plan_one(D, K_base + 3 * d, ctx->vb[D.instance][D.level], ctx->psum[D.instance][D.level],
-                      ctx->periodic[D.instance][D.level], P.dt_frac, P.delta, &dt, &ns);
+        const bool empty = ctx->empty[D.instance][D.level] != 0;
+        if (!empty && !(vmax[d] >= 0.0)) return SHMM_EINVAL;   // band filter not run on this range
+        rc = plan_one(D, K_base + 3 * d, empty ? 0.0 : vmax[d], P.dt_frac, P.delta, &dt, &ns);
         if (rc) return rc;
         if (ctx->empty[D.instance][D.level]) {
             // zero forcing: the corrector stays zero, nothing to integrate
@@ -554,7 +511,7 @@ int shmm_band_filter(shmm_ctx *ctx, int64_t first, int64_t count, float *d_psi, 
         const size_t need = band_filter_workspace(g);
         if ((rc = ctx->ensure_work(need))) return rc;
         rc = launch_band_filter(ctx->inst[g.inst], g, ctx->d_table, d_psi, d_vx, d_vy, d_f1, d_f2,
-                                d_lines, ctx->work, ctx->work_bytes, (hipStream_t)stream);
+                                d_lines, ctx->d_vmax, ctx->work, ctx->work_bytes, (hipStream_t)stream);
         if (rc) return rc;
         covered += g.count;
     }

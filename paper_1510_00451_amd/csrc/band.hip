@@ -66,6 +66,30 @@ __global__ void k_seam(const shmm_domain *dom, int64_t first, int n, const float
     vy[o + (int64_t)i * n + (n - 1)] = (P[(int64_t)i * n] - P[(int64_t)i * n + (n - 1)]) * ih;
 }
 
+// Gershgorin bound of the advection operator of each patch:
+// max over cells of (|vx_W| + |vx_E| + |vy_S| + |vy_N|) / 2.
+__global__ __launch_bounds__(256) void k_vmax(const shmm_domain *dom, int64_t first, int n, const float *vx,
+                                              const float *vy, double *vmax) {
+    __shared__ float red[256];
+    const int64_t d = first + blockIdx.x;
+    const int64_t o = dom[d].offset;
+    const int mask = n - 1;
+    float m = 0.0f;
+    for (int c = threadIdx.x; c < n * n; c += blockDim.x) {
+        const int j = c / n, i = c - j * n;
+        const float s = fabsf(vx[o + c]) + fabsf(vx[o + (int64_t)j * n + ((i + 1) & mask)]) + fabsf(vy[o + c]) +
+                        fabsf(vy[o + (int64_t)((j + 1) & mask) * n + i]);
+        m = fmaxf(m, s);
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) vmax[d] = 0.5 * (double)red[0];
+}
+
 __global__ void k_line_energy(BandParams p) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int per_dir = p.M * p.n;
@@ -111,7 +135,7 @@ size_t band_filter_workspace(const Group &g) {
 
 int launch_band_filter(const InstDev &inst, const Group &g, const shmm_domain *d_dom, float *d_psi,
                        float *d_vx, float *d_vy, float *d_f1, float *d_f2, double *d_lines,
-                       void *work, size_t work_bytes, hipStream_t s) {
+                       double *d_vmax, void *work, size_t work_bytes, hipStream_t s) {
     BandParams p;
     fill_params(p, inst, g);
     if (p.P1 > 4096 || p.P2 > 4096 || p.P1 > g.N || p.P2 > g.N) return SHMM_ERANGE;
@@ -149,6 +173,9 @@ int launch_band_filter(const InstDev &inst, const Group &g, const shmm_domain *d
     const int cells = g.n * g.n;
     hipLaunchKernelGGL(k_forcing, dim3((unsigned)((cells + 255) / 256), (unsigned)g.count), dim3(256),
                        0, s, d_dom, g.first, g.n, d_vx, d_vy, d_f1, d_f2);
+    SHMM_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_vmax, dim3((unsigned)g.count), dim3(256), 0, s, d_dom, g.first, g.n, (const float *)d_vx,
+                       (const float *)d_vy, d_vmax);
     SHMM_HIP_CHECK(hipGetLastError());
     const int lines = 2 * g.M * g.n;
     hipLaunchKernelGGL(k_line_energy, dim3((unsigned)((lines + 63) / 64)), dim3(64), 0, s, p);

@@ -71,16 +71,12 @@ def test_step_plan_bit_exact(torch, name, make):
     A = rng.uniform(0.5, 2.0, (nd, 2, 2))
     K = np.einsum("dij,dkj->dik", A, A) * 1e-2
     Kb = np.stack([K[:, 0, 0], K[:, 0, 1], K[:, 1, 1]], 1)
-    H.ctx.shmm_plan_steps(0, nd, Kb)
+    vmax = rng.uniform(0.1, 5.0, nd)          # the same advection bounds on both sides
+    H.ctx.shmm_plan_steps(0, nd, Kb, vmax)
     table, _, _, _ = H.ctx.shmm_ctx_table()
-    lv, pt = oracle.band_split(p.kmax, p.thresh)
     for d in range(nd):
         D = table[d]
-        m = oracle.band_mask(lv, pt, int(D["level"]), DIAG)
-        Vb = oracle.band_speed_bound(p.psi_hat, p.kmax, m)
-        Ps = oracle.band_amplitude_sum(p.psi_hat, p.kmax, m)
-        per = oracle.band_periodic_on_patch(p.psi_hat, p.kmax, m, int(D["n"]), int(D["N"]))
-        dt, ns = oracle.plan_steps(int(D["n"]), float(D["h"]), Kb[d], Vb, p.dt_frac, p.delta, Ps, per)
+        dt, ns = oracle.plan_steps(int(D["n"]), float(D["h"]), Kb[d], vmax[d], p.dt_frac, p.delta)
         assert int(D["nsteps"]) == ns and float(D["dt"]) == dt, d
     H.close()
 
@@ -101,6 +97,9 @@ def test_band_filter_parity(torch, name, make):
     H = hier(p)
     H.band_filter()
     torch.cuda.synchronize()
+    # per-patch advection bounds agree with the oracle's from its own fields (FP32 vs FP64 faces)
+    H.ctx.shmm_plan_steps(0, H.nd, np.tile([1.0, 0.0, 1.0], (H.nd, 1)))
+    planned = H.ctx.shmm_ctx_table()[0]["nsteps"].copy()
     psi, vx, vy = H.psi.cpu().numpy(), H.vx.cpu().numpy(), H.vy.cpu().numpy()
     f1, f2, lines = H.f1.cpu().numpy(), H.f2.cpu().numpy(), H.lines.cpu().numpy()
     lv, pt = oracle.band_split(p.kmax, p.thresh)
@@ -110,6 +109,11 @@ def test_band_filter_parity(torch, name, make):
         ref = oracle.synth_patch(p.psi_hat, p.kmax, oracle.band_mask(lv, pt, lev, DIAG), int(D["N"]),
                                  int(D["I0"]), int(D["J0"]), n)
         rvx, rvy, rf1, rf2 = oracle.staggered(ref, float(D["h"]))
+        ns_ref = 0
+        if np.any(ref != 0):
+            ns_ref = oracle.plan_steps(n, float(D["h"]), [1.0, 0.0, 1.0], oracle.advection_bound(rvx, rvy),
+                                       p.dt_frac, p.delta)[1]
+        assert abs(int(planned[d]) - ns_ref) <= 1, (name, d, int(planned[d]), ns_ref)
         sc = max(np.abs(ref).max(), 1e-300)
         vs = max(np.abs(rvx).max(), np.abs(rvy).max(), 1e-300)
         sl = slice(o, o + n * n)

@@ -212,7 +212,7 @@ def _generic_patch(n, seed=1, amp=0.6):
     lv, pt = oracle.band_split(p.kmax, p.thresh)
     psi = oracle.synth_patch(amp * p.psi_hat, p.kmax, (lv >= 0).astype(np.int8), n, 0, 0, n)
     h = 2 * np.pi / n
-    return psi, h, amp * oracle.band_speed_bound(p.psi_hat, p.kmax, (lv >= 0).astype(np.int8))
+    return psi, h, oracle.advection_bound(*oracle.staggered(psi, h)[:2])
 
 
 def _rk4_K(psi, h, Kb, Vb, delta):
