@@ -71,12 +71,109 @@ def cpu_baseline(steps_sample: int = 2000, domains_sample: int = 32):
                       f"(both correctors, FP64), {el:.1f} s"}
 
 
+def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members: int = 4):
+    """Learned surrogate against the plain local solve.
+
+    Labels: plain-path solves of the finest-level patches of flows from the
+    uneven-batch generator (seeds 100000+, n = 128, 16 x 16 patches, isotropic
+    base).  Training: the rescaling symmetry (two extra copies), an ensemble of
+    `members` networks, Adam at batch 4096.  The spread threshold is calibrated
+    on a held-out tenth of the labels.  Evaluation: finest-level patches of
+    continuous-spectrum flows (seeds 200000+), timed in both forms from the band
+    filter on, with the inputs resident."""
+    import torch
+    import flowgen
+    from paper_1510_00451_amd import abi
+    from paper_1510_00451_amd import surrogate as GS
+    t0 = time.perf_counter()
+    batches = [[flowgen.config_batched_instance(100000 + i + j, n=128, lattice=16) for j in range(4)]
+               for i in range(0, flows_train, 4)]
+    data = GS.labelled_set(batches, log=log)
+    t_label = time.perf_counter() - t0
+    held, train = GS.split(data, 0.1, seed=0)
+    rng = np.random.default_rng(1)
+    train = GS.Dataset.concat([train] + [train.rescaled(rng.uniform(-1.5, 1.5, train.x.shape[0]))
+                                         for _ in range(2)])
+    ctx = abi.Context(0)
+    mu = train.x.double().mean(0).cpu().numpy()
+    sg = train.x.double().std(0).cpu().numpy() + 1e-6
+    ens = GS.Ensemble(ctx, members, mu, sg, seed0=11)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = GS.train(ens, train, steps=steps, batch=4096, lr0=1e-3, seed=5, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    lo, hi = GS.gate_range(train, 0.1)
+    tau = GS.calibrate_tau(ens, held, lo, hi)
+    log(f"surrogate: {data.x.shape[0]} labels in {t_label:.1f} s, trained in {t_train:.1f} s, tau {tau}")
+
+    # all evaluation flows in one phase: the fallback solves of every flagged
+    # patch then share one launch, as they would in a stream of patches
+    ph = GS.IsotropicPhase([flowgen.config_continuous(seed=200000 + i) for i in range(flows_eval)])
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    ph.prepare()
+    Kp = ph.plain()
+    torch.cuda.synchronize()
+    b = time.perf_counter()
+    ph.prepare()
+    Ks = ph.surrogate(ens, lo, hi, tau)
+    torch.cuda.synchronize()
+    c = time.perf_counter()
+    t_plain, t_surr = b - a, c - b
+    act = ph.active
+    n_est = int(act.sum())
+    errs = [GS.relative_frobenius(Ks.cpu().numpy()[act], Kp.cpu().numpy()[act])]
+    flagged = [ph.flags.cpu().numpy()[act].astype(bool)]
+    ph.close()
+    err = np.concatenate(errs)
+    fl = np.concatenate(flagged)
+    ctx.close()
+    return {
+        "estimates_per_s": round(n_est / t_surr, 1),
+        "plain_estimates_per_s": round(n_est / t_plain, 1),
+        "speedup": round(t_plain / t_surr, 2),
+        "err_vs_plain": {"mean": float(err.mean()), "p99": float(np.quantile(err, 0.99)),
+                         "max": float(err.max()), "frac_over_1pct": float(np.mean(err > 0.01))},
+        "fallback_frac": float(fl.mean()),
+        "tau": tau,
+        "eval": f"{flows_eval} continuous-spectrum flows (kappa 1e-3, 1<=|k|<=512, |psi_k|~|k|^-7/3) x "
+                f"256 finest-level 128^2 patches, isotropic base; {n_est} estimates",
+        "train": {"labels": int(data.x.shape[0]), "flows": flows_train, "label_s": round(t_label, 1),
+                  "train_s": round(t_train, 2), "steps": steps, "batch": 4096, "members": members,
+                  "final_loss": hist[-1] if hist else None},
+    }
+
+
+def continuous_leg():
+    """One full pass over the five-level continuous-spectrum flow (256 patches
+    of 128^2 per level): a second throughput figure at full occupancy."""
+    import torch
+    import flowgen
+    from paper_1510_00451_amd.hierarchy import Hierarchy
+    H = Hierarchy([flowgen.config_continuous(seed=0)], keep_psi=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H.run()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res = H.result()
+    H.close()
+    return {"workload": "continuous-5level-256x128 (kappa 1e-3, 1<=|k|<=512)",
+            "gpoint_steps_per_s": round(res.point_steps / el / 1e9, 3),
+            "kappa_eff_estimates_per_s": round(len(res.R) / el, 2), "pass_s": round(el, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-flows", type=int, default=64)
+    ap.add_argument("--surrogate-eval-flows", type=int, default=8)
+    ap.add_argument("--no-continuous", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
@@ -168,6 +265,12 @@ def main():
                      "launches": len(ms_launch), "avg_launch_ms": round(avg_ms, 3)},
     }
     H.close()
+    if not args.no_continuous:
+        log("continuous-spectrum pass ...")
+        out["continuous_5level"] = continuous_leg()
+    if not args.no_surrogate:
+        log("surrogate ...")
+        out["surrogate"] = surrogate_leg(args.surrogate_flows, args.surrogate_eval_flows)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline()

@@ -229,17 +229,22 @@ def config_continuous(seed: int = 0, radius: int = 512, p: float = -7.0 / 3.0,
                    name=f"continuous-{levels}level-{lattice * lattice}x{n}")
 
 
-def config_batched_instance(seed: int) -> Problem:
-    """One instance of the uneven batch: draws kappa, L, slope, n, then phases."""
+def config_batched_instance(seed: int, n: Optional[int] = None, lattice: int = 4) -> Problem:
+    """One instance of the uneven batch: draws kappa, L, slope, n, then phases.
+
+    ``n`` and ``lattice`` override the drawn patch size and the 4 x 4 lattice
+    (the draws themselves are unchanged), e.g. for surrogate training data at a
+    fixed resolution with more patches per flow."""
     u = [uniform01(seed, 0x7F000000 + i) for i in range(4)]
     kappa = 10.0 ** (-3.0 + 2.0 * u[0])
     L = 2 + min(3, int(u[1] * 4))
     s = -3.0 + (3.0 - 5.0 / 3.0) * u[2]
     p = (s - 3.0) / 2.0
-    n = [32, 64, 128, 256][min(3, int(u[3] * 4))]
+    n_drawn = [32, 64, 128, 256][min(3, int(u[3] * 4))]
+    n = n_drawn if n is None else n
     radius = 2 * 4 ** (L - 1)
     ph = random_power_spectrum_fast(seed, radius, p)
     return Problem(kappa=kappa, kmax=radius, psi_hat=ph,
                    thresh=[4 ** l for l in range(1, L)], n_cells=[n] * L,
-                   n_global=[n * 4 ** l for l in range(L)], lattice=[4] * L,
+                   n_global=[n * 4 ** l for l in range(L)], lattice=[lattice] * L,
                    dt_frac=0.5, delta=1e-6, name=f"batched-{seed}")

@@ -244,14 +244,19 @@ int shmm_macro_step(shmm_ctx *ctx, int32_t N, const void *d_vx, const void *d_vy
 
 /* ---------------------------------------------------------------------------
  * Learned surrogate of the local solve (not part of the paper's method).
- * A patch is described by 33 features: 32 log-spaced radial bins (edges
- * 2^(b/8), b = 0..32, of the patch-relative wavenumber |k| L / 2 pi) of the
- * velocity energy spectrum of the patch samples (treated as periodic, scaled
- * by (L / 2 pi)^2), feature_b = log(E_b + 1e-8 sum_b E_b + 1e-30), and
+ * A patch is described by 33 features.  Features 0..31 are log band energies
+ * of the velocity spectrum of the patch samples (treated as periodic, DFT
+ * normalised by 1/n^2, scaled by (L / 2 pi)^2) over the base: feature 8c + b
+ * is log((E_cb + 1e-8 E_tot + 1e-30) / det K_b), where E_cb sums channel c
+ * over the modes k
+ * (patch-relative integers) with 2^b <= k1^2 + k2^2 < 2^(b+1), b = 0..7; the
+ * channels are |Vx|^2, |Vy|^2, |Vx + Vy|^2 / 2 and |Vx - Vy|^2 / 2, and E_tot
+ * is the sum of channels 0 and 1 over the bins.  Feature 32 is
  * log sqrt(det K_b).  A 33 -> 256 -> 256 -> 256 -> 3 GELU network maps the
- * standardised features to o, and K = sqrt(det K_b) L L^T with
- * L = [[e^o1, 0], [o2, e^o3]].  Matrix products run on the matrix cores with
- * BF16 operands and FP32 accumulation.
+ * standardised features to o, and K = K_b + sqrt(det K_b) L L^T with
+ * L = [[e^o1, 0], [o2, e^o3]] (the enhancement K - K_b is positive
+ * semi-definite).  Matrix products run on the matrix cores with BF16 operands
+ * and FP32 accumulation.
  *
  * One ensemble member ("model") is SHMM_SURR_MODEL_BYTES of device memory:
  *   float    params[SHMM_SURR_PARAMS_PADDED]  W1 b1 W2 b2 W3 b3 W4 b4, W_l row-major [out][in]

@@ -3,19 +3,31 @@ ONLY (see the package docstring).
 
 The paper has no surrogate; these definitions are this project's readings:
 
-* Features of a patch (33): the patch velocity spectrum binned into 32
-  log-spaced radial bins of the patch-relative wavenumber q = |k| (units of
-  2 pi / L, L the patch side), edges 2^(b/8) for b = 0..32 (q in [1, 16)),
-  E_b = sum over the bin of |vx^(k)|^2 + |vy^(k)|^2 with the patch samples
-  treated as periodic and normalised so that sum_k = mean(vx^2 + vy^2), times
-  (L / 2 pi)^2 so the features carry stream-function units (K / kappa is
-  invariant under rescaling space); feature_b = log(E_b + 1e-8 E_tot + 1e-30)
-  with E_tot the sum of the 32 bins (the floor sits far above the rounding
-  noise of an FP32 transform, about 1e-12 E_tot, so empty bins read the same in
-  FP32 and FP64).  Feature 32 is log sqrt(det K_b) of the base diffusivity.
+* Features of a patch (33): band energies of the patch velocity spectrum in 4
+  channels x 8 radial bins.  With the patch samples treated as periodic and
+  the DFT normalised so that sum_k |vx^(k)|^2 = mean(vx^2), the channels of a
+  mode k are |vx^|^2, |vy^|^2, |vx^ + vy^|^2 / 2 and |vx^ - vy^|^2 / 2 (the
+  last two carry the cross spectrum, which decides the sign of K12); bin b
+  holds the patch-relative integer wavenumbers with 2^b <= k1^2 + k2^2 <
+  2^(b+1), b = 0..7, so q = |k| in [1, 16) in half-octaves.  Energies are
+  scaled by (L / 2 pi)^2 (L the patch side) so the features carry
+  stream-function units (K / kappa is invariant under rescaling space).
+  feature_{8c+b} = log((E_cb + 1e-8 E_tot + 1e-30) / det K_b), E_tot the sum
+  of channels 0 and 1 over the bins (the floor sits far above the rounding
+  noise of an FP32 transform, about 1e-12 E_tot, so empty bins read the same
+  in FP32 and FP64).  Dividing by det K_b makes these 32 features squared
+  Peclet numbers: for an isotropic base the local problem is invariant under
+  scaling velocity and diffusivity together (K scales with them), so K / kappa
+  depends on them alone.  Feature 32 is log sqrt(det K_b).  At small
+  Peclet number K - K_b is, to first order, a sum over modes of these channel
+  energies divided by q^2 and kappa, so the directional channels give the
+  network the anisotropy that radial energies alone cannot.
 * Network: 33 -> 256 -> 256 -> 256 -> 3 with exact (erf) GELU; inputs are
   standardised with stored means and scales.  Head: L = [[e^o1, 0], [o2, e^o3]],
-  K = sqrt(det K_b) L L^T.
+  K = K_b + sqrt(det K_b) L L^T: the enhancement K - K_b is positive
+  semi-definite (the local solve only adds diffusivity), and its logarithmic
+  parametrisation keeps small enhancements at the same relative precision as
+  large ones.
 * Loss: mean over the batch of |K_hat - K|_F^2 / |K|_F^2 (Frobenius norm of the
   full 2x2 tensor).
 * Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 master weights.
@@ -40,31 +52,47 @@ LAYERS = [(N_IN, WIDTH), (WIDTH, WIDTH), (WIDTH, WIDTH), (WIDTH, N_OUT)]
 
 # ---------------------------------------------------------------- features
 
-def bin_edges() -> np.ndarray:
-    return np.array([2.0 ** (b / 8.0) for b in range(N_BINS + 1)])
+N_CHANNELS = 4
+N_RADIAL = 8
+
+
+def bin_of(k1: int, k2: int) -> int:
+    """Radial bin of the integer wavenumber (k1, k2), or -1 outside q^2 in [1, 256)."""
+    q2 = k1 * k1 + k2 * k2
+    return q2.bit_length() - 1 if 1 <= q2 < 256 else -1
+
+
+def channel_energies(vx: np.ndarray, vy: np.ndarray, n: int, N: int) -> np.ndarray:
+    """E[c][b]: channel c summed over radial bin b (see the module docstring)."""
+    vx = np.asarray(vx, np.float64).reshape(n, n)
+    vy = np.asarray(vy, np.float64).reshape(n, n)
+    X = np.fft.fft2(vx) / float(n * n)
+    Y = np.fft.fft2(vy) / float(n * n)
+    s = (n / N) ** 2                                  # (L / 2 pi)^2 with L = n 2 pi / N
+    chans = [np.abs(X) ** 2, np.abs(Y) ** 2, np.abs(X + Y) ** 2 / 2, np.abs(X - Y) ** 2 / 2]
+    k = np.fft.fftfreq(n, 1.0 / n).astype(np.int64)
+    E = np.zeros((N_CHANNELS, N_RADIAL))
+    for j in range(n):               # row: k2 = k[j]
+        for i in range(n):           # column: k1 = k[i]
+            b = bin_of(int(k[i]), int(k[j]))
+            if b < 0:
+                continue
+            for c in range(N_CHANNELS):
+                E[c, b] += chans[c][j, i] * s
+    return E
 
 
 def patch_features(vx: np.ndarray, vy: np.ndarray, n: int, N: int, K_base) -> np.ndarray:
     """33 features of one n x n patch (velocities [y][x]) with spacing 2 pi / N."""
-    vx = np.asarray(vx, np.float64).reshape(n, n)
-    vy = np.asarray(vy, np.float64).reshape(n, n)
-    ex = np.abs(np.fft.fft2(vx)) ** 2
-    ey = np.abs(np.fft.fft2(vy)) ** 2
-    e = (ex + ey) / float(n) ** 4 * (n / N) ** 2     # (L / 2 pi)^2 with L = n 2 pi / N
-    k = np.fft.fftfreq(n, 1.0 / n).astype(np.int64)
-    K1, K2 = np.meshgrid(k, k, indexing="xy")
-    # 2^(b/8) <= q < 2^((b+1)/8)  <=>  2^b <= (q^2)^4 < 2^(b+1): decided in integers
-    m = (K1 * K1 + K2 * K2) ** 4
-    bins = np.array([int(v).bit_length() - 1 for v in m.reshape(-1)]).reshape(n, n)
-    E = np.zeros(N_BINS)
-    for b in range(N_BINS):
-        E[b] = float(np.sum(e[(m > 0) & (bins == b)]))
-    floor = 1e-8 * float(np.sum(E)) + 1e-30
-    out = np.zeros(N_IN)
-    for b in range(N_BINS):
-        out[b] = math.log(E[b] + floor)
+    E = channel_energies(vx, vy, n, N)
+    floor = 1e-8 * float(np.sum(E[0]) + np.sum(E[1])) + 1e-30
     K11, K12, K22 = [float(v) for v in K_base]
-    out[N_BINS] = 0.5 * math.log(K11 * K22 - K12 * K12)
+    logdet = math.log(K11 * K22 - K12 * K12)
+    out = np.zeros(N_IN)
+    for c in range(N_CHANNELS):
+        for b in range(N_RADIAL):
+            out[N_RADIAL * c + b] = math.log(E[c, b] + floor) - logdet
+    out[N_BINS] = 0.5 * logdet
     return out
 
 
@@ -106,6 +134,9 @@ class Net:
         return Net([w.copy() for w in self.W], [v.copy() for v in self.b], self.mu.copy(), self.sigma.copy())
 
 
+INIT_LOG_ENHANCEMENT = -2.0     # initial o1 = o3: K - K_b starts near e^-4 sqrt(det K_b) I
+
+
 def init_net(seed: int) -> Net:
     """He-uniform weights from a seeded generator (an input, not method arithmetic)."""
     rng = np.random.default_rng(seed)
@@ -115,6 +146,7 @@ def init_net(seed: int) -> Net:
         W.append(rng.uniform(-lim, lim, (fo, fi)))
         b.append(np.zeros(fo))
     W[-1] *= 0.1
+    b[-1][0] = b[-1][2] = INIT_LOG_ENHANCEMENT
     return Net(W, b)
 
 
@@ -137,12 +169,12 @@ def forward(net: Net, x: np.ndarray, bf16_mode: bool = False):
 
 
 def head(o: np.ndarray, K_base: np.ndarray) -> np.ndarray:
-    """Cholesky head: K = sqrt(det K_b) L L^T, L = [[e^o1, 0], [o2, e^o3]]; returns [B][3]."""
+    """Cholesky head: K = K_b + sqrt(det K_b) L L^T, L = [[e^o1, 0], [o2, e^o3]]; returns [B][3]."""
     o = np.atleast_2d(o)
     Kb = np.atleast_2d(K_base)
     s = np.sqrt(Kb[:, 0] * Kb[:, 2] - Kb[:, 1] ** 2)
     l11, l21, l22 = np.exp(o[:, 0]), o[:, 1], np.exp(o[:, 2])
-    return np.stack([s * l11 * l11, s * l11 * l21, s * (l21 * l21 + l22 * l22)], 1)
+    return Kb + np.stack([s * l11 * l11, s * l11 * l21, s * (l21 * l21 + l22 * l22)], 1)
 
 
 def loss_and_grad_o(o: np.ndarray, K_base: np.ndarray, K_true: np.ndarray):
@@ -159,7 +191,7 @@ def loss_and_grad_o(o: np.ndarray, K_base: np.ndarray, K_true: np.ndarray):
     loss = float(np.mean((d[:, 0] ** 2 + 2 * d[:, 1] ** 2 + d[:, 2] ** 2) / nrm))
     # dloss/dK_hat components (the off-diagonal appears twice in the norm)
     g = np.stack([2 * d[:, 0], 4 * d[:, 1], 2 * d[:, 2]], 1) / nrm[:, None] / B
-    # K11 = s l11^2, K12 = s l11 l21, K22 = s (l21^2 + l22^2)
+    # K11 = Kb11 + s l11^2, K12 = Kb12 + s l11 l21, K22 = Kb22 + s (l21^2 + l22^2)
     go = np.zeros_like(o)
     go[:, 0] = (g[:, 0] * 2 * s * l11 * l11 + g[:, 1] * s * l11 * l21)     # dl11/do1 = l11
     go[:, 1] = g[:, 1] * s * l11 + g[:, 2] * 2 * s * l21

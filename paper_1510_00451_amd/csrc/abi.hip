@@ -677,14 +677,10 @@ int shmm_fallback_solve(shmm_ctx *ctx, int64_t first, int64_t count, const uint8
         const int n = kv.first;
         std::vector<int32_t> &ids = kv.second;
         int32_t max_steps = 0;
-        for (int32_t d : ids) {
-            const shmm_domain &D = ctx->table[d];
-            max_steps = std::max(max_steps, D.nsteps);
-            SHMM_HIP_CHECK(hipMemsetAsync(d_w + D.offset, 0, (size_t)n * n * sizeof(float), s));
-            SHMM_HIP_CHECK(hipMemsetAsync(d_w + ctx->cells + D.offset, 0, (size_t)n * n * sizeof(float), s));
-        }
+        for (int32_t d : ids) max_steps = std::max(max_steps, ctx->table[d].nsteps);
         int32_t *dl = nullptr;
         if ((rc = ctx->temp_list(ids, &dl))) return rc;
+        if ((rc = launch_zero_fields(ctx->d_table, dl, (int32_t)ids.size(), n, d_w, ctx->cells, s))) return rc;
         const int64_t cells = (int64_t)ids.size() * n * n;
         const size_t need = local_solve_workspace(n, cells);
         if (need && (rc = ctx->ensure_work(need))) return rc;

@@ -72,6 +72,8 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
 bool local_solve_resident(int n);
 int local_solve_variants(int n);
 size_t local_solve_workspace(int n, int64_t list_cells);
+int launch_zero_fields(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n, float *d_w,
+                       int64_t cells, hipStream_t s);
 
 int launch_effective_diffusivity_list(const shmm_domain *d_dom, const int32_t *d_list, int64_t count,
                                       const float *f1, const float *f2, const float *w, int64_t cells_total,

@@ -16,6 +16,8 @@
 // increments, so FP32 does not stall near the quasi-stationary state) and its
 // face coefficients in registers.  HBM is touched only to load the patch and
 // to store the final state.
+#include <algorithm>
+
 #include "shmm_internal.h"
 
 namespace shmm {
@@ -449,6 +451,28 @@ int launch_resident(const shmm_domain *d_dom, const int32_t *d_list, int32_t nli
 bool local_solve_resident(int n) { return n == 8 || n == 16 || n == 32 || n == 64 || n == 128; }
 
 int local_solve_variants(int n) { return (n == 64 || n == 128) ? 3 : 1; }
+
+namespace {
+// Zero both corrector fields of the listed domains (one workgroup row per domain).
+__global__ __launch_bounds__(256) void k_zero_fields(const shmm_domain *dom, const int32_t *list, int n, float *w,
+                                                     int64_t cells) {
+    const int64_t o = dom[list[blockIdx.y]].offset;
+    const int64_t nn = (int64_t)n * n;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nn; c += (int64_t)gridDim.x * blockDim.x) {
+        w[o + c] = 0.0f;
+        w[cells + o + c] = 0.0f;
+    }
+}
+}  // namespace
+
+int launch_zero_fields(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n, float *d_w,
+                       int64_t cells, hipStream_t s) {
+    if (nlist <= 0) return SHMM_OK;
+    const unsigned bx = (unsigned)std::min<int64_t>(16, ((int64_t)n * n + 255) / 256);
+    hipLaunchKernelGGL(k_zero_fields, dim3(bx, (unsigned)nlist), dim3(256), 0, s, d_dom, d_list, n, d_w, cells);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
 
 size_t local_solve_workspace(int n, int64_t list_cells) {
     if (local_solve_resident(n)) return 0;

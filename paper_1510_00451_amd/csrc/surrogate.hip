@@ -1,7 +1,7 @@
 // Learned surrogate of the local solve (not part of the paper's method):
 // patch spectrum features, a 33 -> 256 -> 256 -> 256 -> 3 GELU network on the
 // matrix cores (BF16 operands, FP32 accumulation), its training step (forward,
-// relative Frobenius loss on the Cholesky head, backward, Adam on FP32 master
+// relative Frobenius loss on a Cholesky head for K - K_b, backward, Adam on FP32 master
 // weights) and ensemble inference with a fallback gate.
 #include <math.h>
 
@@ -60,16 +60,14 @@ __global__ __launch_bounds__(256) void k_feat_rows(const shmm_domain *dom, const
     for (int t = tid; t < n; t += per) out[(int64_t)row * n + t] = res[t];
 }
 
-// Pass B: FFT along y of kFeatRows columns, |Z^|^2, partial bin sums.
-__global__ __launch_bounds__(256) void k_feat_cols(const shmm_domain *dom, const int32_t *list, int n,
-                                                   const c32 *work, float *partial) {
+// Pass B: FFT along y of kFeatRows columns; the spectrum A(k) of Z overwrites
+// the pass-A rows in place (each workgroup owns its columns).
+__global__ __launch_bounds__(256) void k_feat_cols(int n, c32 *work) {
     extern __shared__ c32 lds[];
     const int li = blockIdx.y;
-    const int N = dom[list[li]].N;
     const int c0 = blockIdx.x * kFeatRows;
     c32 *a = lds, *b = lds + kFeatRows * n;
-    float *e = (float *)(b + kFeatRows * n);
-    const c32 *src = work + (int64_t)li * n * n;
+    c32 *src = work + (int64_t)li * n * n;
     for (int t = threadIdx.x; t < kFeatRows * n; t += blockDim.x) {
         const int col = t / n, j = t - col * n;
         a[t] = src[(int64_t)j * n + c0 + col];
@@ -77,51 +75,60 @@ __global__ __launch_bounds__(256) void k_feat_cols(const shmm_domain *dom, const
     __syncthreads();
     const int per = blockDim.x / kFeatRows, col = threadIdx.x / per, tid = threadIdx.x - col * per;
     c32 *res = fft_inverse(a + col * n, b + col * n, n, tid, per, BlockSync{});
-    const float scale = (float)((double)n / (double)N * (double)n / (double)N / ((double)n * n * n * n));
-    for (int t = tid; t < n; t += per) {
-        const c32 z = res[t];
-        e[col * n + t] = (z.x * z.x + z.y * z.y) * scale;
-    }
-    __syncthreads();
-    // Thread b sums bin b over this workgroup's entries in a fixed order.  The
-    // bin of |k| = q is b with 2^(b/8) <= q < 2^((b+1)/8), i.e. the position of
-    // the leading bit of (k1^2 + k2^2)^4, decided exactly in integers.
-    if (threadIdx.x < SHMM_SURR_BINS) {
-        const int bin = threadIdx.x;
-        float s = 0.0f;
-        for (int col2 = 0; col2 < kFeatRows; ++col2) {
-            int k1 = c0 + col2;
-            k1 = k1 <= n / 2 ? k1 : k1 - n;
-            for (int j = 0; j < n; ++j) {
-                const int k2 = j <= n / 2 ? j : j - n;   // both signs of the Nyquist row give the same q
-                const uint64_t q2 = (uint64_t)(k1 * k1 + k2 * k2);
-                const uint64_t m = q2 * q2 * q2 * q2;
-                if (m == 0 || m >= (1ull << SHMM_SURR_BINS)) continue;
-                if (63 - __builtin_clzll(m) == bin) s += e[col2 * n + j];
-            }
-        }
-        partial[((int64_t)li * gridDim.x + blockIdx.x) * SHMM_SURR_BINS + bin] = s;
-    }
+    for (int t = tid; t < n; t += per) src[(int64_t)t * n + c0 + col] = res[t];
 }
 
-__global__ void k_feat_final(const shmm_domain *dom, const int32_t *list, int nlist, int parts,
-                             const float *partial, const double *Kb, float *features) {
-    const int li = blockIdx.x * blockDim.x + threadIdx.x;
-    if (li >= nlist) return;
+constexpr int kFeatWin = 31;   // |k1|, |k2| <= 15 holds every mode with q^2 < 256
+
+// One workgroup per patch.  With A(k) = Vx(k) + i Vy(k) (Vx, Vy the transforms
+// of the real fields), Vx(k) = (A(k) + conj A(-k))/2 and Vy(k) = (A(k) -
+// conj A(-k))/(2i).  Channel energies per mode: |Vx|^2, |Vy|^2, |Vx+Vy|^2/2,
+// |Vx-Vy|^2/2; radial bin b = floor(log2(k1^2 + k2^2)), 0 <= b < 8.  Bin sums
+// run in a fixed mode order; the features are their logarithms over det K_b.
+__global__ __launch_bounds__(256) void k_feat_bins(const shmm_domain *dom, const int32_t *list, int n,
+                                                   const c32 *work, const double *Kb, float *features) {
+    __shared__ float ch[4][kFeatWin * kFeatWin];
+    __shared__ int8_t bin[kFeatWin * kFeatWin];
+    __shared__ float E[SHMM_SURR_BINS];
+    const int li = blockIdx.x;
     const int64_t d = list[li];
-    float E[SHMM_SURR_BINS];
-    float tot = 0.0f;
-    for (int bin = 0; bin < SHMM_SURR_BINS; ++bin) {
-        float s = 0.0f;
-        for (int p = 0; p < parts; ++p) s += partial[((int64_t)li * parts + p) * SHMM_SURR_BINS + bin];
-        E[bin] = s;
-        tot += s;
+    const int N = dom[d].N;
+    const int klo = -min(15, n / 2), khi = min(15, n / 2 - 1);
+    const int w = khi - klo + 1, modes = w * w;
+    const c32 *A = work + (int64_t)li * n * n;
+    const float scale = (float)((double)n / (double)N * (double)n / (double)N / ((double)n * n * n * n));
+    for (int m = threadIdx.x; m < modes; m += blockDim.x) {
+        const int k2 = klo + m / w, k1 = klo + m % w;
+        const int q2 = k1 * k1 + k2 * k2;
+        bin[m] = (int8_t)((q2 >= 1 && q2 < 256) ? 31 - __builtin_clz((unsigned)q2) : -1);
+        const c32 p = A[(int64_t)(k2 & (n - 1)) * n + (k1 & (n - 1))];
+        const c32 r = A[(int64_t)((-k2) & (n - 1)) * n + ((-k1) & (n - 1))];
+        // Vx = (p + conj r)/2, Vy = (p - conj r)/(2i)
+        const float vxr = 0.5f * (p.x + r.x), vxi = 0.5f * (p.y - r.y);
+        const float vyr = 0.5f * (p.y + r.y), vyi = -0.5f * (p.x - r.x);
+        const float pr = vxr + vyr, pi = vxi + vyi, mr = vxr - vyr, mi = vxi - vyi;
+        ch[0][m] = (vxr * vxr + vxi * vxi) * scale;
+        ch[1][m] = (vyr * vyr + vyi * vyi) * scale;
+        ch[2][m] = 0.5f * (pr * pr + pi * pi) * scale;
+        ch[3][m] = 0.5f * (mr * mr + mi * mi) * scale;
     }
-    const float floor = 1e-8f * tot + 1e-30f;
-    float *f = features + (int64_t)li * SHMM_SURR_IN;
-    for (int bin = 0; bin < SHMM_SURR_BINS; ++bin) f[bin] = logf(E[bin] + floor);
-    const double det = Kb[3 * d] * Kb[3 * d + 2] - Kb[3 * d + 1] * Kb[3 * d + 1];
-    f[SHMM_SURR_BINS] = (float)(0.5 * log(det));
+    __syncthreads();
+    if (threadIdx.x < SHMM_SURR_BINS) {
+        const int c = threadIdx.x / 8, b = threadIdx.x % 8;
+        float sum = 0.0f;
+        for (int m = 0; m < modes; ++m)
+            if (bin[m] == b) sum += ch[c][m];
+        E[threadIdx.x] = sum;
+    }
+    __syncthreads();
+    const double logdet = log(Kb[3 * d] * Kb[3 * d + 2] - Kb[3 * d + 1] * Kb[3 * d + 1]);
+    if (threadIdx.x < SHMM_SURR_BINS) {
+        float tot = 0.0f;
+        for (int i = 0; i < 16; ++i) tot += E[i];
+        const float floor = 1e-8f * tot + 1e-30f;
+        features[(int64_t)li * SHMM_SURR_IN + threadIdx.x] = logf(E[threadIdx.x] + floor) - (float)logdet;
+    }
+    if (threadIdx.x == SHMM_SURR_BINS) features[(int64_t)li * SHMM_SURR_IN + SHMM_SURR_BINS] = (float)(0.5 * logdet);
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -142,6 +149,8 @@ struct GemmArgs {
     int64_t ldh;
     const float *z;        // saved pre-activations for EPI_GELU_GRAD
     int64_t ldz;
+    float *partial;        // split K: [gridDim.z][M][N] raw sums (EPI_F32 only), or null
+    int kchunk;            // K per slice when split
 };
 
 constexpr int TM = 64, TN = 64, TK = 32, PADK = 8;
@@ -157,19 +166,21 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
     const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave >> 1, wn = wave & 1;
+    const int kbeg = g.partial ? blockIdx.z * g.kchunk : 0;
+    const int kend = g.partial ? min(g.K, kbeg + g.kchunk) : g.K;
     f32x4 acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < g.K; k0 += TK) {
+    for (int k0 = kbeg; k0 < kend; k0 += TK) {
         for (int t = threadIdx.x; t < TM * TK; t += blockDim.x) {
             const int m = t / TK, k = t - m * TK;
             const int gm = m0 + m, gk = k0 + k;
-            As[m][k] = (gm < g.M && gk < g.K) ? g.A[gm * g.sam + gk * g.sak] : (uint16_t)0;
+            As[m][k] = (gm < g.M && gk < kend) ? g.A[gm * g.sam + gk * g.sak] : (uint16_t)0;
         }
         for (int t = threadIdx.x; t < TN * TK; t += blockDim.x) {
             const int nn = t / TK, k = t - nn * TK;
             const int gn = n0 + nn, gk = k0 + k;
-            Bt[nn][k] = (gn < g.N && gk < g.K) ? g.B[gk * g.sbk + gn * g.sbn] : (uint16_t)0;
+            Bt[nn][k] = (gn < g.N && gk < kend) ? g.B[gk * g.sbk + gn * g.sbn] : (uint16_t)0;
         }
         __syncthreads();
         for (int kk = 0; kk < TK; kk += 16) {
@@ -194,6 +205,10 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
                 const int col = n0 + wn * 32 + j * 16 + (lane & 15);
                 if (row >= g.M || col >= g.N) continue;
                 float v = acc[i][j][r];
+                if (g.partial) {
+                    g.partial[((int64_t)blockIdx.z * g.M + row) * g.N + col] = v;
+                    continue;
+                }
                 if (g.epi == EPI_BIAS_F32 || g.epi == EPI_BIAS_GELU) v += g.bias[col];
                 if (g.epi == EPI_GELU_GRAD) v *= gelu_grad(g.z[row * g.ldz + col]);
                 if (g.outf) g.outf[row * g.ldo + col] = v;
@@ -201,10 +216,38 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
             }
 }
 
-int gemm(const GemmArgs &g, hipStream_t s) {
+// out[r][c] = sum over the slices z = 0, 1, ... of partial[z][r][c], in that order.
+__global__ void k_splitk_sum(const float *partial, int slices, int M, int N, float *out, int64_t ldo) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)M * N) return;
+    const int row = (int)(t / N), col = (int)(t - (int64_t)row * N);
+    float v = 0.0f;
+    for (int z = 0; z < slices; ++z) v += partial[(int64_t)z * M * N + t];
+    out[row * ldo + col] = v;
+}
+
+constexpr int kSplitSlices = 16;   // K slices of the weight-gradient products
+
+int gemm(GemmArgs g, hipStream_t s, float *split_work = nullptr) {
     if (g.M <= 0 || g.N <= 0) return SHMM_OK;
-    hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)((g.N + TN - 1) / TN), (unsigned)((g.M + TM - 1) / TM)),
-                       dim3(256), 0, s, g);
+    const dim3 tiles((unsigned)((g.N + TN - 1) / TN), (unsigned)((g.M + TM - 1) / TM));
+    // few output tiles over a long K (weight gradients: K = batch): split K
+    // into slices, then add the slices in a fixed order
+    if (split_work && g.epi == EPI_F32 && tiles.x * tiles.y < 64 && g.K >= 4 * TK * kSplitSlices) {
+        g.kchunk = (g.K / kSplitSlices + TK - 1) / TK * TK;
+        const int slices = (g.K + g.kchunk - 1) / g.kchunk;
+        g.partial = split_work;
+        hipLaunchKernelGGL(k_gemm_bf16, dim3(tiles.x, tiles.y, (unsigned)slices), dim3(256), 0, s, g);
+        SHMM_HIP_CHECK(hipGetLastError());
+        const int64_t cnt = (int64_t)g.M * g.N;
+        hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
+                           (const float *)split_work, slices, g.M, g.N, g.outf, g.ldo);
+        SHMM_HIP_CHECK(hipGetLastError());
+        return SHMM_OK;
+    }
+    g.partial = nullptr;
+    g.kchunk = 0;
+    hipLaunchKernelGGL(k_gemm_bf16, tiles, dim3(256), 0, s, g);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
 }
@@ -238,7 +281,8 @@ __global__ void k_standardize(const float *x, int64_t B, const float *mu, const 
     xh[t] = to_bf16((x[t] - mu[c]) / sigma[c]);
 }
 
-// Cholesky head K = sqrt(det K_b) L L^T; optional loss and output gradient.
+// Head K = K_b + sqrt(det K_b) L L^T (the enhancement K - K_b is positive
+// semi-definite); optional loss and output gradient.
 __global__ void k_head(const float *o, const double *Kb, int64_t B, double *K_out, const double *K_true,
                        float *go, double *loss_part) {
     __shared__ double red[256];
@@ -247,7 +291,8 @@ __global__ void k_head(const float *o, const double *Kb, int64_t B, double *K_ou
     if (t < B) {
         const double s = sqrt(Kb[3 * t] * Kb[3 * t + 2] - Kb[3 * t + 1] * Kb[3 * t + 1]);
         const double l11 = exp((double)o[3 * t]), l21 = o[3 * t + 1], l22 = exp((double)o[3 * t + 2]);
-        const double k11 = s * l11 * l11, k12 = s * l11 * l21, k22 = s * (l21 * l21 + l22 * l22);
+        const double k11 = Kb[3 * t] + s * l11 * l11, k12 = Kb[3 * t + 1] + s * l11 * l21,
+                     k22 = Kb[3 * t + 2] + s * (l21 * l21 + l22 * l22);
         if (K_out) {
             K_out[3 * t] = k11;
             K_out[3 * t + 1] = k12;
@@ -281,13 +326,33 @@ __global__ void k_to_bf16(const float *src, uint16_t *dst, int64_t count) {
     if (t < count) dst[t] = to_bf16(src[t]);
 }
 
-// column sums of dz [B][n] into the bias gradient (fixed order per column)
-__global__ void k_colsum(const float *dz, int64_t B, int n, float *out) {
+constexpr int kColSlices = 16;
+
+// Column sums of dz [B][n] (the bias gradient) in a fixed order: workgroup
+// (x, z) sums 64 columns over row slice z, four row lanes then lane 0..3 in
+// order; k_colsum_final adds the slices in order.
+__global__ __launch_bounds__(256) void k_colsum_part(const float *dz, int64_t B, int n, float *part) {
+    __shared__ float red[4][64];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63), lane = threadIdx.x >> 6;
+    const int64_t chunk = (B + kColSlices - 1) / kColSlices;
+    const int64_t r0 = blockIdx.y * chunk, r1 = min(B, r0 + chunk);
+    float v = 0.0f;
+    if (c < n)
+        for (int64_t r = r0 + lane; r < r1; r += 4) v += dz[r * n + c];
+    red[lane][threadIdx.x & 63] = v;
+    __syncthreads();
+    if (lane == 0 && c < n) {
+        const int i = threadIdx.x & 63;
+        part[(int64_t)blockIdx.y * n + c] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
+    }
+}
+
+__global__ void k_colsum_final(const float *part, int n, float *out) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
-    float s = 0.0f;
-    for (int64_t r = 0; r < B; ++r) s += dz[r * n + c];
-    out[c] = s;
+    float v = 0.0f;
+    for (int z = 0; z < kColSlices; ++z) v += part[(int64_t)z * n + c];
+    out[c] = v;
 }
 
 __global__ void k_loss_total(const double *part, int parts, int64_t B, double *loss) {
@@ -342,11 +407,7 @@ __global__ void k_gate(const double *Km, int E, int64_t B, const float *x, const
 
 }  // namespace
 
-size_t surrogate_feature_workspace(int n, int64_t nlist) {
-    const size_t fft = (size_t)nlist * n * n * sizeof(c32);
-    const size_t part = (size_t)nlist * (n / kFeatRows) * SHMM_SURR_BINS * sizeof(float);
-    return fft + part;
-}
+size_t surrogate_feature_workspace(int n, int64_t nlist) { return (size_t)nlist * n * n * sizeof(c32); }
 
 int launch_patch_features(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n,
                           const float *vx, const float *vy, const double *Kb, float *features, void *work,
@@ -354,17 +415,14 @@ int launch_patch_features(const shmm_domain *d_dom, const int32_t *d_list, int32
     if (nlist <= 0) return SHMM_OK;
     if (n < kFeatRows || n > 256) return SHMM_ERANGE;
     c32 *fw = (c32 *)work;
-    float *part = (float *)((char *)work + (size_t)nlist * n * n * sizeof(c32));
-    const int parts = n / kFeatRows;
-    const dim3 grid((unsigned)parts, (unsigned)nlist);
+    const dim3 grid((unsigned)(n / kFeatRows), (unsigned)nlist);
     hipLaunchKernelGGL(k_feat_rows, grid, dim3(256), 2 * kFeatRows * n * sizeof(c32), s, d_dom, d_list, n, vx,
                        vy, fw);
     SHMM_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(k_feat_cols, grid, dim3(256), 2 * kFeatRows * n * sizeof(c32) + kFeatRows * n * sizeof(float),
-                       s, d_dom, d_list, n, (const c32 *)fw, part);
+    hipLaunchKernelGGL(k_feat_cols, grid, dim3(256), 2 * kFeatRows * n * sizeof(c32), s, n, fw);
     SHMM_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(k_feat_final, dim3((unsigned)((nlist + 63) / 64)), dim3(64), 0, s, d_dom, d_list, nlist,
-                       parts, (const float *)part, Kb, features);
+    hipLaunchKernelGGL(k_feat_bins, dim3((unsigned)nlist), dim3(256), 0, s, d_dom, d_list, n, (const c32 *)fw, Kb,
+                       features);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
 }
@@ -380,6 +438,8 @@ struct NetWork {
     float *dz2;          // second buffer for the next layer's gradient
     double *loss_part;   // [ceil(B / 256)]
     float *grad;         // [SHMM_SURR_PARAMS_PADDED]
+    float *split;        // split-K slices [kSplitSlices][256][256]
+    float *colpart;      // column-sum slices [kColSlices][256]
 };
 
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
@@ -393,6 +453,8 @@ size_t surrogate_net_workspace(int64_t B) {
     s += 2 * align256((size_t)B * SHMM_SURR_WIDTH * 4) + align256((size_t)B * SHMM_SURR_WIDTH * 2);
     s += align256((size_t)((B + 255) / 256) * 8);
     s += align256((size_t)SHMM_SURR_PARAMS_PADDED * 4);
+    s += align256((size_t)kSplitSlices * SHMM_SURR_WIDTH * SHMM_SURR_WIDTH * 4);
+    s += align256((size_t)kColSlices * SHMM_SURR_WIDTH * 4);
     return s;
 }
 
@@ -414,6 +476,8 @@ static NetWork carve(void *work, int64_t B) {
     w.dzh = (uint16_t *)take((size_t)B * SHMM_SURR_WIDTH * 2);
     w.loss_part = (double *)take((size_t)((B + 255) / 256) * 8);
     w.grad = (float *)take((size_t)SHMM_SURR_PARAMS_PADDED * 4);
+    w.split = (float *)take((size_t)kSplitSlices * SHMM_SURR_WIDTH * SHMM_SURR_WIDTH * 4);
+    w.colpart = (float *)take((size_t)kColSlices * SHMM_SURR_WIDTH * 4);
     return w;
 }
 
@@ -513,9 +577,12 @@ int surrogate_train_step(void *model, float *adam, const float *x, const double 
         g.ldh = 0;
         g.z = nullptr;
         g.ldz = 0;
-        if ((rc = gemm(g, s))) return rc;
-        hipLaunchKernelGGL(k_colsum, dim3((unsigned)((n_out + 63) / 64)), dim3(64), 0, s, dz, B, n_out,
-                           w.grad + L.b[l]);
+        if ((rc = gemm(g, s, w.split))) return rc;
+        hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)((n_out + 63) / 64), (unsigned)kColSlices), dim3(256), 0,
+                           s, dz, B, n_out, w.colpart);
+        SHMM_HIP_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, s,
+                           (const float *)w.colpart, n_out, w.grad + L.b[l]);
         SHMM_HIP_CHECK(hipGetLastError());
         if (l == 0) break;
         // dz_{l-1} = (dz W_l) * gelu'(z_{l-1})   ([B][out] x [out][in])

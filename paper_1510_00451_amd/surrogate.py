@@ -15,6 +15,11 @@ import numpy as np
 
 from . import abi
 
+
+def _torch():
+    import torch
+    return torch
+
 PARAM_FLOATS = abi.SURR_MODEL_BYTES // 4
 LAYERS = [(abi.SURR_IN, abi.SURR_WIDTH), (abi.SURR_WIDTH, abi.SURR_WIDTH),
           (abi.SURR_WIDTH, abi.SURR_WIDTH), (abi.SURR_WIDTH, abi.SURR_OUT)]
@@ -50,7 +55,9 @@ def unpack_params(block: np.ndarray):
 
 
 def init_params(seed: int):
-    """He-uniform initial weights from a seeded generator (zero biases, small last layer)."""
+    """He-uniform initial weights from a seeded generator: zero hidden biases, a
+    small last layer whose biases start the enhancement K - K_b near
+    e^-4 sqrt(det K_b) I."""
     rng = np.random.default_rng(seed)
     W, b = [], []
     for fi, fo in LAYERS:
@@ -58,6 +65,7 @@ def init_params(seed: int):
         W.append(rng.uniform(-lim, lim, (fo, fi)))
         b.append(np.zeros(fo))
     W[-1] *= 0.1
+    b[-1][0] = b[-1][2] = -2.0
     return W, b
 
 
@@ -91,10 +99,28 @@ class Dataset:
     Kb: "object"       # torch float64 [S][3]
     K: "object"        # torch float64 [S][3]
 
+    def rescaled(self, log10_c):
+        """The same local problems with velocity and diffusivity scaled by
+        c = 10^log10_c (one factor per sample, host array [S]): the corrector
+        is unchanged, so K and K_b scale by c, the 32 band features (squared
+        Peclet numbers) are unchanged and feature 32 shifts by ln c."""
+        torch = _torch()
+        c = torch.from_numpy(10.0 ** np.asarray(log10_c, np.float64)).to(self.K.device)
+        x = self.x.clone()
+        x[:, abi.SURR_BINS] += torch.log(c).to(torch.float32)
+        return Dataset(x, self.Kb * c[:, None], self.K * c[:, None])
+
+    @staticmethod
+    def concat(parts):
+        torch = _torch()
+        return Dataset(torch.cat([p.x for p in parts]), torch.cat([p.Kb for p in parts]),
+                       torch.cat([p.K for p in parts]))
+
 
 def train(ens: Ensemble, data: Dataset, steps: int, batch: int, lr0: float = 1e-3, seed: int = 0,
           log=None) -> List[float]:
-    """Adam with a cosine learning-rate schedule; each member draws its own batch order."""
+    """Adam with a linear warm-up over the first 5% of the steps, then a cosine
+    decay; each member draws its own batch order."""
     torch = ens.torch
     S = data.x.shape[0]
     rng = np.random.default_rng(seed)
@@ -103,10 +129,15 @@ def train(ens: Ensemble, data: Dataset, steps: int, batch: int, lr0: float = 1e-
     kb = torch.empty(batch, 3, dtype=torch.float64, device="cuda")
     kt = torch.empty(batch, 3, dtype=torch.float64, device="cuda")
     history = []
+    chunk = 64
     for it in range(steps):
-        lr = 0.5 * lr0 * (1.0 + math.cos(math.pi * it / steps))
+        warm = max(1, steps // 20)
+        lr = lr0 * (it + 1) / warm if it < warm else \
+            0.5 * lr0 * (1.0 + math.cos(math.pi * (it - warm) / max(1, steps - warm)))
+        if it % chunk == 0:     # batch indices of the next steps, one upload
+            draws = torch.from_numpy(rng.integers(0, S, (min(chunk, steps - it), ens.E, batch))).to("cuda")
         for e in range(ens.E):
-            idx = torch.from_numpy(rng.integers(0, S, batch)).to("cuda")
+            idx = draws[it % chunk, e]
             torch.index_select(data.x, 0, idx, out=xb)
             torch.index_select(data.Kb, 0, idx, out=kb)
             torch.index_select(data.K, 0, idx, out=kt)
@@ -121,7 +152,8 @@ def train(ens: Ensemble, data: Dataset, steps: int, batch: int, lr0: float = 1e-
 
 
 def infer(ens: Ensemble, x, Kb, lo, hi, tau: float):
-    """(K_mean [B][3], flags [B] uint8, spread [B]) on the device."""
+    """(K_mean [B][3], flags [B] uint8, spread [B]) on the device (tau may be
+    huge to gate on the feature range alone)."""
     torch = ens.torch
     B = x.shape[0]
     K = torch.empty(B, 3, dtype=torch.float64, device="cuda")
@@ -131,3 +163,160 @@ def infer(ens: Ensemble, x, Kb, lo, hi, tau: float):
                                  hi.data_ptr(), tau, K.data_ptr(), flags.data_ptr(), spread.data_ptr(), 0,
                                  torch.cuda.current_stream().cuda_stream)
     return K, flags, spread
+
+
+class IsotropicPhase:
+    """One phase of a batch of flows (default: the finest level of each), every
+    patch on the isotropic base kappa I of its flow: the setting in which the
+    surrogate replaces the local solve.
+
+    The constructor only allocates.  ``prepare()`` runs the band filter of the
+    phase and plans its steps; then either ``plain()`` (the local solves of
+    every patch: labels, or the plain form) or ``surrogate(...)`` (features,
+    ensemble inference, plain-solve fallback of the flagged patches) gives
+    K [count][3] on the device.  Patches whose diagonal band holds no
+    coefficient are inactive: their result is the base exactly and neither form
+    spends solver steps on them.
+    """
+
+    def __init__(self, problems, phase: int = 0, device: int = 0):
+        from .hierarchy import Hierarchy
+        torch = _torch()
+        self.torch = torch
+        H = Hierarchy(problems, device)
+        self.H = H
+        self.first = int(H.phase[phase])
+        self.count = int(H.phase[phase + 1] - H.phase[phase])
+        sl = slice(self.first, self.first + self.count)
+        kap = np.array([H.problems[i].kappa for i in H.table["instance"][sl]])
+        H.host_K[sl] = np.stack([kap, np.zeros_like(kap), kap], 1)
+        H.K_base[sl] = torch.from_numpy(H.host_K[sl]).to(H.device)
+        self.n = H.table["n"][sl].copy()
+        self.x = torch.zeros(self.count, abi.SURR_IN, dtype=torch.float32, device=H.device)
+        self.K = torch.zeros(H.nd, 3, dtype=torch.float64, device=H.device)
+        self.flags = torch.zeros(self.count, dtype=torch.uint8, device=H.device)
+        self.spread = torch.zeros(self.count, dtype=torch.float64, device=H.device)
+        self.nsteps = None
+
+    def prepare(self) -> None:
+        """Band filter of the phase and its step plan (synchronises: the plan is host work)."""
+        H = self.H
+        H.status[self.first:self.first + self.count].zero_()
+        H.ctx.shmm_band_filter(self.first, self.count, 0, H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(),
+                               H.f2.data_ptr(), H.lines.data_ptr(), H.stream())
+        H.ctx.shmm_plan_steps(self.first, self.count, H.host_K)
+        table = H.ctx.shmm_ctx_table()[0]
+        self.nsteps = table["nsteps"][self.first:self.first + self.count].copy()
+        self.active = self.nsteps > 0
+        self.point_steps = int(np.sum(self.n.astype(np.int64) ** 2 * self.nsteps))
+
+    def features(self) -> None:
+        """Features of every patch of the phase (runs of equal n, one call each)."""
+        H = self.H
+        s = H.stream()
+        i = 0
+        while i < self.count:
+            j = i
+            while j < self.count and self.n[j] == self.n[i]:
+                j += 1
+            H.ctx.shmm_patch_features(self.first + i, j - i, H.vx.data_ptr(), H.vy.data_ptr(),
+                                      H.K_base.data_ptr(), self.x[i:].data_ptr(), s)
+            i = j
+
+    def K_base(self):
+        return self.H.K_base[self.first:self.first + self.count]
+
+    def plain(self):
+        """Plain local solves and estimator of every patch; returns K [count][3] (device)."""
+        H = self.H
+        s = H.stream()
+        a, b = H.cell_range(self.first, self.count)
+        H.w.view(2, H.cells)[:, a:b].zero_()
+        H.ctx.shmm_local_solve_batch(self.first, self.count, H.vx.data_ptr(), H.vy.data_ptr(),
+                                     H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(),
+                                     0, 2 ** 31 - 1, H.status.data_ptr(), s)
+        H.ctx.shmm_effective_diffusivity(self.first, self.count, H.f1.data_ptr(), H.f2.data_ptr(),
+                                         H.w.data_ptr(), H.K_base.data_ptr(), H.K_solve.data_ptr(), 0, 0,
+                                         H.status.data_ptr(), s)
+        return H.K_solve[self.first:self.first + self.count]
+
+    def surrogate(self, ens: "Ensemble", lo, hi, tau: float):
+        """Surrogate-with-fallback form: features, ensemble estimate and gate,
+        plain solves of the flagged patches; returns K [count][3] (device).
+        Synchronises once (the fallback reads the flags)."""
+        H = self.H
+        s = H.stream()
+        self.features()
+        sl = self.K[self.first:self.first + self.count]
+        H.ctx.shmm_surrogate_infer(ens.buf.data_ptr(), ens.E, self.x.data_ptr(), self.K_base().data_ptr(),
+                                   self.count, lo.data_ptr(), hi.data_ptr(), tau, sl.data_ptr(),
+                                   self.flags.data_ptr(), self.spread.data_ptr(), 0, s)
+        H.ctx.shmm_fallback_solve(self.first, self.count, self.flags.data_ptr(), H.vx.data_ptr(),
+                                  H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(),
+                                  H.w.data_ptr(), self.K.data_ptr(), H.status.data_ptr(), s)
+        return sl
+
+    def close(self):
+        self.H.close()
+
+
+def relative_frobenius(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """|A - B|_F / |B|_F of symmetric 2x2 tensors stored as {K11, K12, K22}."""
+    d = A - B
+    return np.sqrt((d[:, 0] ** 2 + 2 * d[:, 1] ** 2 + d[:, 2] ** 2) /
+                   (B[:, 0] ** 2 + 2 * B[:, 1] ** 2 + B[:, 2] ** 2))
+
+
+def labelled_set(problem_batches, log=None) -> Dataset:
+    """Features and plain-path labels of the finest-level patches of each batch
+    of flows (isotropic base kappa I), active patches only."""
+    torch = _torch()
+    xs, kbs, ks = [], [], []
+    for i, probs in enumerate(problem_batches):
+        ph = IsotropicPhase(probs)
+        ph.prepare()
+        ph.features()
+        K = ph.plain()
+        act = torch.from_numpy(np.flatnonzero(ph.active)).to(ph.x.device)
+        xs.append(ph.x.index_select(0, act))
+        kbs.append(ph.K_base().index_select(0, act))
+        ks.append(K.index_select(0, act))
+        torch.cuda.synchronize()
+        ph.close()
+        if log is not None:
+            log(f"labels: batch {i}, {sum(len(x) for x in xs)} patches")
+    return Dataset(torch.cat(xs), torch.cat(kbs), torch.cat(ks))
+
+
+def split(data: Dataset, frac: float, seed: int):
+    """(held-out, rest) by a seeded permutation."""
+    torch = _torch()
+    S = data.x.shape[0]
+    perm = torch.from_numpy(np.random.default_rng(seed).permutation(S)).to(data.x.device)
+    k = int(S * frac)
+    pick = lambda idx: Dataset(data.x[idx], data.Kb[idx], data.K[idx])
+    return pick(perm[:k]), pick(perm[k:])
+
+
+def gate_range(data: Dataset, margin: float = 0.1):
+    """Per-feature training range widened by `margin` of its width (device float32)."""
+    lo = data.x.min(0).values
+    hi = data.x.max(0).values
+    w = hi - lo
+    return lo - margin * w, hi + margin * w
+
+
+def calibrate_tau(ens: Ensemble, held: Dataset, lo, hi, target: float = 0.01, quantile: float = 0.99,
+                  grid=(5e-4, 1e-3, 2e-3, 3e-3, 5e-3, 7.5e-3, 1e-2, 1.5e-2, 2e-2, 3e-2)):
+    """Largest ensemble-spread threshold whose accepted held-out estimates keep
+    the `quantile` of the relative Frobenius error within `target`."""
+    K, flags, spread = infer(ens, held.x, held.Kb, lo, hi, 1e300)
+    err = relative_frobenius(K.cpu().numpy(), held.K.cpu().numpy())
+    spread = spread.cpu().numpy()
+    out_of_range = flags.cpu().numpy().astype(bool)
+    best = grid[0]
+    for tau in grid:
+        acc = (spread <= tau) & ~out_of_range
+        if acc.any() and np.quantile(err[acc], quantile) <= target:
+            best = tau
+    return best

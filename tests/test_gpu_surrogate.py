@@ -225,7 +225,7 @@ def test_training_reduces_loss(torch):
     S = 2048
     x = rng.standard_normal((S, 33))
     Kb = np.tile([0.02, 0.0, 0.02], (S, 1))
-    enh = 1.0 + 0.5 * np.tanh(x[:, 0]) + 0.2 * x[:, 1] ** 2
+    enh = 1.5 + 0.5 * np.tanh(x[:, 0]) + 0.2 * x[:, 1] ** 2     # K >= K_b, as the head requires
     Kt = Kb * enh[:, None]
     say("case training")
     ctx = abi.Context(0)
@@ -239,3 +239,31 @@ def test_training_reduces_loss(torch):
     err = np.abs(K.cpu().numpy()[:, 0] - Kt[:, 0]) / Kt[:, 0]
     assert np.median(err) < 0.02, np.median(err)
     ctx.close()
+
+
+def test_surrogate_form_gates_and_falls_back(torch):
+    """The surrogate-with-fallback form of a phase: with every patch flagged it
+    returns the plain result bit for bit; with none flagged it returns the
+    ensemble estimate unchanged and runs no solve."""
+    from paper_1510_00451_amd import abi
+    from paper_1510_00451_amd import surrogate as GS
+    p = _patches(32, lattice=4)
+    say("case surrogate form")
+    ph = GS.IsotropicPhase([p])
+    ph.prepare()
+    plain = ph.plain().cpu().numpy().copy()
+    ctx = abi.Context(0)
+    ens = GS.Ensemble(ctx, 2, np.zeros(33), np.ones(33), seed0=4)
+    wide_lo = torch.full((33,), -1e30, dtype=torch.float32, device="cuda")
+    wide_hi = torch.full((33,), 1e30, dtype=torch.float32, device="cuda")
+    K_all = ph.surrogate(ens, wide_lo, wide_hi, -1.0).cpu().numpy().copy()
+    assert ph.flags.cpu().numpy().all()
+    assert np.array_equal(K_all, plain)
+    ph.H.status.zero_()
+    K_none = ph.surrogate(ens, wide_lo, wide_hi, 1e300).cpu().numpy().copy()
+    assert not ph.flags.cpu().numpy().any()
+    K_ref, _, _ = GS.infer(ens, ph.x, ph.K_base(), wide_lo, wide_hi, 1e300)
+    assert np.array_equal(K_none, K_ref.cpu().numpy())
+    assert not (ph.H.status.cpu().numpy() & 8).any()
+    ctx.close()
+    ph.close()

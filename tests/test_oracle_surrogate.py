@@ -10,23 +10,81 @@ import torch
 from oracle import surrogate as S
 
 
-def test_features_single_mode_closed_form():
-    n, N = 32, 128
-    a, b, A = 3, 2, 0.7
+def _mode(n, a, b, A, B, quadrature=False):
     i = np.arange(n)
     I, J = np.meshgrid(i, i, indexing="xy")
-    vx = A * np.cos(2 * np.pi * (a * I + b * J) / n)
-    vy = np.zeros_like(vx)
+    ph = 2 * np.pi * (a * I + b * J) / n
+    vx = A * np.cos(ph)
+    vy = B * (np.sin(ph) if quadrature else np.cos(ph))
+    return vx, vy
+
+
+def test_features_single_mode_closed_form():
+    """One Fourier mode in phase in both components: every channel by hand."""
+    n, N = 32, 128
+    a, b, A, B = 3, 2, 0.7, -0.3
+    vx, vy = _mode(n, a, b, A, B)
     Kb = [0.02, 0.005, 0.03]
     f = S.patch_features(vx, vy, n, N, Kb)
-    q = math.hypot(a, b)
-    edges = S.bin_edges()
-    bq = int(np.searchsorted(edges, q, side="right") - 1)
-    Etot = A * A / 2 * (n / N) ** 2
-    expect = np.full(33, math.log(1e-8 * Etot + 1e-30))
-    expect[bq] = math.log(Etot + 1e-8 * Etot + 1e-30)
-    expect[32] = 0.5 * math.log(0.02 * 0.03 - 0.005 ** 2)
+    bq = int(math.floor(math.log2(a * a + b * b)))          # 13 -> bin 3
+    assert bq == 3
+    s = (n / N) ** 2
+    # cos splits into +-k with amplitude 1/2 each: sum over the pair of |c/2|^2 = c^2/2
+    E = [A * A / 2 * s, B * B / 2 * s, (A + B) ** 2 / 4 * s, (A - B) ** 2 / 4 * s]
+    Etot = E[0] + E[1]
+    fl = 1e-8 * Etot + 1e-30
+    det = 0.02 * 0.03 - 0.005 ** 2
+    expect = np.full(33, math.log(fl / det))
+    for c in range(4):
+        expect[8 * c + bq] = math.log((E[c] + fl) / det)
+    expect[32] = 0.5 * math.log(det)
     np.testing.assert_allclose(f, expect, rtol=1e-12, atol=1e-12)
+
+
+def test_features_scale_invariance():
+    """Scaling velocity by c and the base by c shifts feature 32 by log c and
+    leaves the 32 band features unchanged (squared Peclet numbers)."""
+    rng = np.random.default_rng(8)
+    n, N, c = 32, 64, 7.5
+    vx, vy = rng.standard_normal((n, n)), rng.standard_normal((n, n))
+    Kb = np.array([0.03, -0.004, 0.02])
+    f = S.patch_features(vx, vy, n, N, Kb)
+    g = S.patch_features(c * vx, c * vy, n, N, c * Kb)
+    np.testing.assert_allclose(g[:32], f[:32], rtol=0, atol=1e-12)
+    assert abs(g[32] - f[32] - math.log(c)) <= 1e-12
+
+
+def test_features_quadrature_has_no_cross_spectrum():
+    """vx = A cos, vy = B sin: the +-45 degree channels carry equal energy."""
+    n, N = 32, 32
+    vx, vy = _mode(n, 1, 4, 0.5, 0.8, quadrature=True)
+    E = S.channel_energies(vx, vy, n, N)
+    b = int(math.floor(math.log2(17)))
+    np.testing.assert_allclose(E[2, b], E[3, b], rtol=1e-12)
+    np.testing.assert_allclose(E[2, b], (E[0, b] + E[1, b]) / 2, rtol=1e-12)
+
+
+def test_features_symmetries():
+    """Swapping the components swaps channels 0 and 1; negating vy swaps 2 and 3;
+    channels 2 + 3 equal 0 + 1 in every bin (a random field, several bins)."""
+    rng = np.random.default_rng(5)
+    n, N = 32, 64
+    vx, vy = rng.standard_normal((n, n)), rng.standard_normal((n, n))
+    E = S.channel_energies(vx, vy, n, N)
+    Es = S.channel_energies(vy, vx, n, N)
+    En = S.channel_energies(vx, -vy, n, N)
+    np.testing.assert_allclose(Es[[1, 0, 2, 3]], E, rtol=1e-12)
+    np.testing.assert_allclose(En[[0, 1, 3, 2]], E, rtol=1e-12)
+    np.testing.assert_allclose(E[2] + E[3], E[0] + E[1], rtol=1e-12)
+    # bin populations: sum over bins of a flat spectrum counts the modes with 1 <= q^2 < 256
+    ones = np.zeros((n, n))
+    ones[0, 0] = n * n                    # delta at the origin: flat spectrum |X|^2 = 1
+    Ef = S.channel_energies(ones, np.zeros((n, n)), n, n)
+    k = np.arange(-15, 16)
+    K1, K2 = np.meshgrid(k, k)
+    q2 = K1 ** 2 + K2 ** 2
+    for b in range(8):
+        assert Ef[0, b] == np.sum((q2 >= 2 ** b) & (q2 < 2 ** (b + 1)))
 
 
 def test_bf16_rounding_matches_torch():
@@ -63,7 +121,7 @@ def test_forward_backward_match_torch_autograd():
     Kbt = torch.tensor(Kb)
     s = torch.sqrt(Kbt[:, 0] * Kbt[:, 2] - Kbt[:, 1] ** 2)
     l11, l21, l22 = torch.exp(h[:, 0]), h[:, 1], torch.exp(h[:, 2])
-    Kh = torch.stack([s * l11 * l11, s * l11 * l21, s * (l21 * l21 + l22 * l22)], 1)
+    Kh = Kbt + torch.stack([s * l11 * l11, s * l11 * l21, s * (l21 * l21 + l22 * l22)], 1)
     Ktt = torch.tensor(Kt)
     d = Kh - Ktt
     L = torch.mean((d[:, 0] ** 2 + 2 * d[:, 1] ** 2 + d[:, 2] ** 2)
@@ -76,12 +134,13 @@ def test_forward_backward_match_torch_autograd():
         np.testing.assert_allclose(gb[l], b[l].grad.numpy(), rtol=1e-9, atol=1e-14)
 
 
-def test_head_closed_form_and_spd():
+def test_head_closed_form_and_enhancement_psd():
     Kb = np.array([[0.02, 0.0, 0.08]])
-    np.testing.assert_allclose(S.head(np.zeros((1, 3)), Kb), [[0.04, 0.0, 0.04]], rtol=1e-15)
+    np.testing.assert_allclose(S.head(np.zeros((1, 3)), Kb), [[0.06, 0.0, 0.12]], rtol=1e-15)
     o = np.random.default_rng(2).standard_normal((100, 3))
-    K = S.head(o, np.tile([0.05, 0.01, 0.03], (100, 1)))
-    assert np.all(K[:, 0] > 0) and np.all(K[:, 0] * K[:, 2] - K[:, 1] ** 2 > 0)
+    Kb = np.tile([0.05, 0.01, 0.03], (100, 1))
+    D = S.head(o, Kb) - Kb
+    assert np.all(D[:, 0] > 0) and np.all(D[:, 0] * D[:, 2] - D[:, 1] ** 2 > -1e-15)
 
 
 def test_adam_matches_torch():
