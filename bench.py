@@ -30,6 +30,22 @@ METRIC = "κ_eff estimates/s + Gpoint-steps/s; surrogate vs plain at ≤1% κ_ef
 # and the final update (8 flop): 78 flop; two correctors.
 FLOP_PER_POINT_STEP = 156
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (256 CU, 2.4 GHz)
+# HBM bytes per full-phase launch of k_solve_resident<128, 32> on this
+# workload, from rocprofv3 FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0), the scale
+# factors read off a 1 GiB device copy.  Valid only for the kernel source they
+# were taken on (first 16 hex digits of its SHA-256); otherwise reported null.
+SOLVE_TRAFFIC = {"source_sha256": "6cdfa8b179d4ec15", "bytes_per_launch": (2 * 15765.7 + 14848.0) * 1024}
+
+
+SOLVE_KERNELS_128 = {0: "k_solve_resident<128,32>", 1: "k_solve_rows<128,2,16>", 2: "k_solve_rows<128,2,8>",
+                     3: "k_solve_resident_e<128,32>", 4: "k_solve_resident_e<128,16>"}
+
+
+def solve_traffic():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1510_00451_amd", "csrc", "solve.hip")
+    h = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    return SOLVE_TRAFFIC["bytes_per_launch"] if h == SOLVE_TRAFFIC["source_sha256"] else None
 
 
 def log(*a):
@@ -43,7 +59,7 @@ def workload():
     return [main, shear]
 
 
-def cpu_baseline(steps_sample: int = 2000, domains_sample: int = 32):
+def cpu_baseline(steps_sample: int = 10000, domains_sample: int = 32):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload:
     the finest-level patches of the four-level instance, a fixed number of RK4
     steps each, OpenMP over (patch, corrector)."""
@@ -174,6 +190,8 @@ def main():
     ap.add_argument("--surrogate-flows", type=int, default=64)
     ap.add_argument("--surrogate-eval-flows", type=int, default=8)
     ap.add_argument("--no-continuous", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="copy this many MiB once before the passes (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
@@ -186,6 +204,12 @@ def main():
         log("no HIP device: the benchmark needs an MI355X")
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_probe_mib > 0:
+        src = torch.full((args.copy_probe_mib << 20,), 1, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     probs = workload()
     H = Hierarchy(probs, keep_psi=False)
     log(f"domains {H.nd}, cells {H.cells}, phases {len(H.phase) - 1}")
@@ -259,9 +283,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3),
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-                     "traffic": None,
-                     "kernel": {0: "k_solve_resident<128,32>", 1: "k_solve_rows<128,2,16>",
-                                2: "k_solve_rows<128,2,8>"}[tuned.get(128, {"variant": 2})["variant"]],
+                     "traffic": solve_traffic() if tuned.get(128, {"variant": 0})["variant"] == 0 else None,
+                     "kernel": SOLVE_KERNELS_128[tuned.get(128, {"variant": 0})["variant"]],
                      "launches": len(ms_launch), "avg_launch_ms": round(avg_ms, 3)},
     }
     H.close()

@@ -41,6 +41,10 @@ __device__ inline SolveConsts solve_consts(const shmm_domain &D, const double *K
     return c;
 }
 
+__device__ __forceinline__ float uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 // One RK stage over a thread's strip.  KIND 0: r = dt (L y + f);
 // KIND 1: q = r + cw dt L y; KIND 2: q1 = r + dt/2 L y, w <- w + q1 (compensated).
 template <int NN, int R, int FIELD, int KIND>
@@ -171,6 +175,138 @@ __global__ __launch_bounds__(NN *NN / R) void k_solve_resident(
         solve_body<NN, R, 1>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
     else
         solve_body<NN, R, 0>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
+}
+
+// Resident kernel, coefficient form.  With eE = cxx + aE, eW = cxx - aW,
+// eN = cyy + aN and eS = cyy - aS the dt-scaled operator is
+//   cc w_C + eE w_E + eW w_W + eN w_N + eS w_S + cxy ((w_NE - w_NW) - (w_SE - w_SW)),
+// five products instead of the split advection and diffusion terms.  A thread
+// keeps eE, eW and nb[r] = cyy + (south face of row r) for its strip, so
+// eN of row r is nb[r + 1] and eS is 2 cyy - nb[r]; the forcing is
+// h (eE - eW) (first corrector) or h (eN - eS) (second).  The x-difference of
+// a row, w_E - w_W, is formed once and used by the rows above and below.
+template <int NN, int R, int FIELD, int KIND>
+__device__ __forceinline__ void rk_stage_e(const float *__restrict__ C, int offW, int offE, int offS,
+                                           int offN, float *__restrict__ out, const SolveConsts &k,
+                                           float two_cyy, float cw, float (&eE)[R], float (&eW)[R],
+                                           float (&nb)[R + 1], float (&wv)[R], float (&comp)[R],
+                                           float (&rr)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) asm volatile("" : "+v"(eE[r]), "+v"(eW[r]));
+#pragma unroll
+    for (int r = 0; r <= R; ++r) asm volatile("" : "+v"(nb[r]));
+    const float *Wc = C + offW;
+    const float *Ec = C + offE;
+    float sC = C[offS];
+    float dS = Ec[offS] - Wc[offS];
+    float cW = Wc[0], cC = C[0], cE = Ec[0];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int rn = (r + 1 < R) ? (r + 1) * NN : offN;
+        const float nW = Wc[rn], nC = C[rn], nE = Ec[rn];
+        const float dN = nE - nW;
+        const float eS = two_cyy - nb[r];
+        float t = k.cc * cC;
+        t = fmaf(eE[r], cE, t);
+        t = fmaf(eW[r], cW, t);
+        t = fmaf(nb[r + 1], nC, t);
+        t = fmaf(eS, sC, t);
+        t = fmaf(k.cxy, dN - dS, t);
+        float o;
+        if (KIND == 0) {
+            rr[r] = FIELD == 0 ? fmaf(k.fh, eE[r] - eW[r], t) : fmaf(k.fh, nb[r + 1] - eS, t);
+            o = rr[r];
+        } else if (KIND == 1) {
+            o = fmaf(cw, t, rr[r]);
+        } else {
+            const float q1 = fmaf(0.5f, t, rr[r]);
+            const float yk = q1 - comp[r];
+            const float tk = wv[r] + yk;
+            comp[r] = (tk - wv[r]) - yk;
+            wv[r] = tk;
+            o = tk;
+        }
+        out[r * NN] = o;
+        sC = cC;
+        dS = cE - cW;
+        cW = nW; cC = nC; cE = nE;
+    }
+}
+
+template <int NN, int R, int FIELD>
+__device__ __forceinline__ void solve_body_e(float *__restrict__ buf, const shmm_domain *__restrict__ dom,
+                                             const int32_t *__restrict__ list,
+                                             const float *__restrict__ vx, const float *__restrict__ vy,
+                                             const double *__restrict__ Kb, float *__restrict__ w,
+                                             int64_t cells_total, int32_t step_begin, int32_t steps) {
+    constexpr int MASK = NN - 1;
+    constexpr int PLANE = NN * NN;
+    const int64_t d = list[blockIdx.x >> 1];
+    const shmm_domain D = dom[d];
+    const int64_t s_end64 = (int64_t)step_begin + steps;
+    const int32_t s_end = (int32_t)(s_end64 < D.nsteps ? s_end64 : D.nsteps);
+    if (step_begin >= s_end) return;
+
+    const int tid = threadIdx.x;
+    const int x = tid & MASK;
+    const int y0 = (tid / NN) * R;
+    const int offW = x == 0 ? MASK : -1;
+    const int offE = x == MASK ? -MASK : 1;
+    const int offS = y0 == 0 ? (NN - 1) * NN : -NN;
+    const int offN = y0 + R == NN ? (R - NN) * NN : R * NN;
+    SolveConsts k = solve_consts(D, Kb, d);
+    // the constants are uniform across the workgroup: keep them in scalar registers
+    k.cc = uniform(k.cc);
+    k.cxy = uniform(k.cxy);
+    k.fh = uniform(k.fh);
+    const float two_cyy = uniform(2.0f * k.cyy);
+    const int64_t o = D.offset;
+    const float *vxo = vx + o + y0 * NN + x;
+    const float *vyo = vy + o + y0 * NN + x;
+
+    float eE[R], eW[R], nb[R + 1], wv[R], comp[R], rr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        eE[r] = k.cxx + k.a * vxo[r * NN + offE];
+        eW[r] = k.cxx - k.a * vxo[r * NN];
+        nb[r] = k.cyy + k.a * vyo[r * NN];
+    }
+    nb[R] = k.cyy + k.a * vyo[offN];
+    float *wf = w + (int64_t)FIELD * cells_total + o + y0 * NN + x;
+    float *lo = buf + y0 * NN + x, *hi = lo + PLANE;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        wv[r] = wf[r * NN];
+        comp[r] = 0.0f;
+        rr[r] = 0.0f;
+        lo[r * NN] = wv[r];
+    }
+    __syncthreads();
+    for (int32_t s = step_begin; s < s_end; ++s) {
+        rk_stage_e<NN, R, FIELD, 0>(lo, offW, offE, offS, offN, hi, k, two_cyy, 0.0f, eE, eW, nb, wv, comp, rr);
+        __syncthreads();
+        rk_stage_e<NN, R, FIELD, 1>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.25f, eE, eW, nb, wv, comp, rr);
+        __syncthreads();
+        rk_stage_e<NN, R, FIELD, 1>(lo, offW, offE, offS, offN, hi, k, two_cyy, 1.0f / 3.0f, eE, eW, nb, wv, comp,
+                                    rr);
+        __syncthreads();
+        rk_stage_e<NN, R, FIELD, 2>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.5f, eE, eW, nb, wv, comp, rr);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) wf[r * NN] = wv[r];
+}
+
+template <int NN, int R>
+__global__ __launch_bounds__(NN *NN / R) void k_solve_resident_e(
+    const shmm_domain *__restrict__ dom, const int32_t *__restrict__ list,
+    const float *__restrict__ vx, const float *__restrict__ vy, const double *__restrict__ Kb,
+    float *__restrict__ w, int64_t cells_total, int32_t step_begin, int32_t steps) {
+    __shared__ float buf[2 * NN * NN];
+    if (blockIdx.x & 1)
+        solve_body_e<NN, R, 1>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
+    else
+        solve_body_e<NN, R, 0>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
 }
 
 // Row-resident variant for patches whose row fits one wavefront (n = 64 C):
@@ -446,11 +582,21 @@ int launch_resident(const shmm_domain *d_dom, const int32_t *d_list, int32_t nli
     return SHMM_OK;
 }
 
+template <int NN, int R>
+int launch_resident_e(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, const float *vx,
+                      const float *vy, const double *Kb, float *w, int64_t cells_total,
+                      int32_t step_begin, int32_t steps, hipStream_t s) {
+    hipLaunchKernelGGL((k_solve_resident_e<NN, R>), dim3((unsigned)(2 * nlist)), dim3(NN * NN / R), 0, s,
+                       d_dom, d_list, vx, vy, Kb, w, cells_total, step_begin, steps);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
+
 }  // namespace
 
 bool local_solve_resident(int n) { return n == 8 || n == 16 || n == 32 || n == 64 || n == 128; }
 
-int local_solve_variants(int n) { return (n == 64 || n == 128) ? 3 : 1; }
+int local_solve_variants(int n) { return (n == 64 || n == 128) ? 5 : 1; }
 
 namespace {
 // Zero both corrector fields of the listed domains (one workgroup row per domain).
@@ -488,16 +634,20 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
     (void)f2;   // the forcing is rebuilt from the face velocities in registers
     if (nlist <= 0) return SHMM_OK;
     switch (n) {
-        case 8: return launch_resident<8, 2>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
-        case 16: return launch_resident<16, 4>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
-        case 32: return launch_resident<32, 8>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+        case 8: return launch_resident_e<8, 2>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+        case 16: return launch_resident_e<16, 4>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+        case 32: return launch_resident_e<32, 8>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
         case 64:
             if (variant == 1) return launch_rows<64, 1, 16>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
             if (variant == 2) return launch_rows<64, 1, 8>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            if (variant == 3) return launch_resident_e<64, 16>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            if (variant == 4) return launch_resident_e<64, 8>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
             return launch_resident<64, 16>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
         case 128:
             if (variant == 1) return launch_rows<128, 2, 16>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
             if (variant == 2) return launch_rows<128, 2, 8>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            if (variant == 3) return launch_resident_e<128, 32>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            if (variant == 4) return launch_resident_e<128, 16>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
             return launch_resident<128, 32>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
         default: break;
     }
