@@ -179,6 +179,37 @@ def continuous_leg():
             "kappa_eff_estimates_per_s": round(len(res.R) / el, 2), "pass_s": round(el, 3)}
 
 
+def uneven_leg(instances: int, window: int):
+    """The uneven batch (generator seeds 0.., kappa, levels, slope and patch size
+    drawn per instance; 4 x 4 patches per level, n from 32 to 256 mixed in
+    every phase): one pass with every local solve capped at `window` steps,
+    after tuning the kernels on the first phase."""
+    import torch
+    import flowgen
+    from paper_1510_00451_amd.hierarchy import Hierarchy
+    from paper_1510_00451_amd import autotune
+    H = Hierarchy([flowgen.config_batched_instance(s) for s in range(instances)], keep_psi=False)
+    H.run(steps=1)
+    torch.cuda.synchronize()
+    tuned = autotune.tune_solve(H, phase=0, steps=50, repeats=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H.run(steps=window)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    table = H.ctx.shmm_ctx_table()[0]
+    ns = np.minimum(table["nsteps"].astype(np.int64), window)
+    pts = int(np.sum(table["n"].astype(np.int64) ** 2 * ns))
+    sizes = {int(n): int(np.sum(table["n"] == n)) for n in sorted(set(table["n"].tolist()))}
+    full = int(np.sum(table["n"].astype(np.int64) ** 2 * table["nsteps"].astype(np.int64)))
+    H.close()
+    return {"workload": f"uneven batch, {instances} instances (seeds 0-{instances - 1}), every solve capped "
+                        f"at {window} steps",
+            "gpoint_steps_per_s": round(pts / el / 1e9, 3), "window_s": round(el, 3),
+            "domains_by_n": sizes, "autotune": {str(k): v["variant"] for k, v in tuned.items()},
+            "full_run_point_steps_planned": full}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +220,9 @@ def main():
     ap.add_argument("--surrogate-flows", type=int, default=64)
     ap.add_argument("--surrogate-eval-flows", type=int, default=8)
     ap.add_argument("--no-continuous", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--uneven-instances", type=int, default=256)
+    ap.add_argument("--uneven-window", type=int, default=2000)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="copy this many MiB once before the passes (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -291,6 +325,9 @@ def main():
     if not args.no_continuous:
         log("continuous-spectrum pass ...")
         out["continuous_5level"] = continuous_leg()
+    if not args.no_uneven:
+        log("uneven batch ...")
+        out["uneven_batch"] = uneven_leg(args.uneven_instances, args.uneven_window)
     if not args.no_surrogate:
         log("surrogate ...")
         out["surrogate"] = surrogate_leg(args.surrogate_flows, args.surrogate_eval_flows)

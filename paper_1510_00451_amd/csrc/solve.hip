@@ -500,6 +500,120 @@ int launch_rows(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, 
     return SHMM_OK;
 }
 
+// Overlapped tiles for patches too large for one CU (n = 256): a workgroup
+// advances a TW x TW tile of one corrector by HALO / 4 RK4 steps, computing on
+// the tile plus a HALO-cell ring (each stage consumes one ring of valid
+// cells, so after 4 s stages everything at least 4 s cells inside the region
+// is exact) and writes back the tile.  The state (w and its compensation)
+// lives in list-local workspace planes between launches, ping-ponged so no
+// workgroup overwrites cells another one still reads.  The stage arithmetic
+// is the coefficient-form resident stage; cells on the region's border see
+// clamped neighbours and lie outside the written tile.
+template <int TW, int HALO, int R, int FIELD>
+__device__ __forceinline__ void tiled_body(float *__restrict__ buf, const shmm_domain *__restrict__ dom,
+                                           const int32_t *__restrict__ list, int n,
+                                           const float *__restrict__ vx, const float *__restrict__ vy,
+                                           const double *__restrict__ Kb, const float *__restrict__ w_in,
+                                           const float *__restrict__ c_in, float *__restrict__ w_out,
+                                           float *__restrict__ c_out, int64_t list_cells, int32_t step0,
+                                           int32_t s_cap) {
+    constexpr int W = TW + 2 * HALO;
+    constexpr int PLANE = W * W;
+    const int tiles = n / TW;
+    const int tx = blockIdx.x % tiles, ty = blockIdx.x / tiles;
+    const int li = blockIdx.y >> 1;
+    const int64_t d = list[li];
+    const shmm_domain D = dom[d];
+    const int32_t lim = s_cap < D.nsteps ? s_cap : D.nsteps;
+    const int32_t s_end = step0 + HALO / 4 < lim ? step0 + HALO / 4 : lim;
+    const int mask = n - 1;
+
+    const int tid = threadIdx.x;
+    const int x = tid % W;
+    const int y0 = (tid / W) * R;
+    const int offW = x == 0 ? 0 : -1;
+    const int offE = x == W - 1 ? 0 : 1;
+    const int offS = y0 == 0 ? 0 : -W;
+    const int offN = y0 + R == W ? (R - 1) * W : R * W;
+    SolveConsts k = solve_consts(D, Kb, d);
+    k.cc = uniform(k.cc);
+    k.cxy = uniform(k.cxy);
+    k.fh = uniform(k.fh);
+    const float two_cyy = uniform(2.0f * k.cyy);
+    const int gx = (tx * TW - HALO + x) & mask;
+    const int gxe = (gx + 1) & mask;
+    const int gy0 = ty * TW - HALO + y0;
+    // uniform base pointers and 32-bit offsets inside one patch plane
+    const float *vxp = vx + D.offset, *vyp = vy + D.offset;
+    const int64_t ws = (int64_t)FIELD * list_cells + (int64_t)li * n * n;
+    const float *wp = w_in + ws, *cp = c_in + ws;
+
+    float eE[R], eW[R], nb[R + 1], wv[R], comp[R], rr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = ((gy0 + r) & mask) * n;
+        eE[r] = k.cxx + k.a * vxp[row + gxe];
+        eW[r] = k.cxx - k.a * vxp[row + gx];
+        nb[r] = k.cyy + k.a * vyp[row + gx];
+        wv[r] = wp[row + gx];
+        comp[r] = cp[row + gx];
+        rr[r] = 0.0f;
+    }
+    nb[R] = k.cyy + k.a * vyp[((gy0 + R) & mask) * n + gx];
+    float *lo = buf + y0 * W + x, *hi = lo + PLANE;
+#pragma unroll
+    for (int r = 0; r < R; ++r) lo[r * W] = wv[r];
+    __syncthreads();
+    for (int32_t s = step0; s < s_end; ++s) {
+        rk_stage_e<W, R, FIELD, 0>(lo, offW, offE, offS, offN, hi, k, two_cyy, 0.0f, eE, eW, nb, wv, comp, rr);
+        __syncthreads();
+        rk_stage_e<W, R, FIELD, 1>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.25f, eE, eW, nb, wv, comp, rr);
+        __syncthreads();
+        rk_stage_e<W, R, FIELD, 1>(lo, offW, offE, offS, offN, hi, k, two_cyy, 1.0f / 3.0f, eE, eW, nb, wv, comp,
+                                   rr);
+        __syncthreads();
+        rk_stage_e<W, R, FIELD, 2>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.5f, eE, eW, nb, wv, comp, rr);
+        __syncthreads();
+    }
+    if (x < HALO || x >= HALO + TW) return;
+    float *wo = w_out + ws, *co = c_out + ws;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int yy = y0 + r;
+        if (yy < HALO || yy >= HALO + TW) continue;
+        const int at = ((gy0 + r) & mask) * n + gx;
+        wo[at] = wv[r];
+        co[at] = comp[r];
+    }
+}
+
+template <int TW, int HALO, int R>
+__global__ __launch_bounds__((TW + 2 * HALO) * (TW + 2 * HALO) / R) void k_solve_tiled(
+    const shmm_domain *__restrict__ dom, const int32_t *__restrict__ list, int n,
+    const float *__restrict__ vx, const float *__restrict__ vy, const double *__restrict__ Kb,
+    const float *__restrict__ w_in, const float *__restrict__ c_in, float *__restrict__ w_out,
+    float *__restrict__ c_out, int64_t list_cells, int32_t step0, int32_t s_cap) {
+    __shared__ float buf[2 * (TW + 2 * HALO) * (TW + 2 * HALO)];
+    if (blockIdx.y & 1)
+        tiled_body<TW, HALO, R, 1>(buf, dom, list, n, vx, vy, Kb, w_in, c_in, w_out, c_out, list_cells, step0,
+                                   s_cap);
+    else
+        tiled_body<TW, HALO, R, 0>(buf, dom, list, n, vx, vy, Kb, w_in, c_in, w_out, c_out, list_cells, step0,
+                                   s_cap);
+}
+
+// Copy the list-local state planes back to the correctors.
+__global__ void k_solve_tiled_fini(const shmm_domain *__restrict__ dom, const int32_t *__restrict__ list, int n,
+                                   const float *__restrict__ ycur, float *__restrict__ w, int64_t cells_total,
+                                   int64_t list_cells) {
+    const int li = blockIdx.y >> 1;
+    const int field = blockIdx.y & 1;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n * n) return;
+    const shmm_domain D = dom[list[li]];
+    w[(int64_t)field * cells_total + D.offset + c] = ycur[(int64_t)field * list_cells + (int64_t)li * n * n + c];
+}
+
 // Fallback for patches that do not fit in LDS: one launch per RK stage, state
 // in global memory.  Same arithmetic as the resident kernel.
 __global__ __launch_bounds__(256) void k_solve_stage(
@@ -596,7 +710,7 @@ int launch_resident_e(const shmm_domain *d_dom, const int32_t *d_list, int32_t n
 
 bool local_solve_resident(int n) { return n == 8 || n == 16 || n == 32 || n == 64 || n == 128; }
 
-int local_solve_variants(int n) { return (n == 64 || n == 128) ? 5 : 1; }
+int local_solve_variants(int n) { return (n == 64 || n == 128) ? 5 : n == 256 ? 4 : 1; }
 
 namespace {
 // Zero both corrector fields of the listed domains (one workgroup row per domain).
@@ -651,7 +765,6 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
             return launch_resident<128, 32>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
         default: break;
     }
-    // generic path
     float *ws = (float *)work;
     float *ycur = ws, *ynext = ws + 2 * list_cells, *acc = ws + 4 * list_cells,
           *comp = ws + 6 * list_cells;
@@ -661,6 +774,33 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
     SHMM_HIP_CHECK(hipGetLastError());
     const int64_t s_end64 = (int64_t)step_begin + steps;
     const int32_t s_end = (int32_t)(s_end64 < max_steps ? s_end64 : max_steps);
+    if (n == 256 && variant != 2) {
+        // overlapped tiles: variant 0 advances 2 steps per launch on 64^2
+        // tiles (ring of 8, 640 threads), variant 1 one step (ring of 4),
+        // variant 3 2 steps on 32^2 tiles (288 threads, several per CU)
+        float *cnext = acc;
+        const int tw = variant == 3 ? 32 : 64;
+        const dim3 tg((unsigned)((n / tw) * (n / tw)), (unsigned)(2 * nlist));
+        for (int32_t step = step_begin; step < s_end; step += (variant == 1 ? 1 : 2)) {
+            if (variant == 0)
+                hipLaunchKernelGGL((k_solve_tiled<64, 8, 10>), tg, dim3(640), 0, s, d_dom, d_list, n, vx, vy, Kb,
+                                   (const float *)ycur, (const float *)comp, ynext, cnext, list_cells, step, s_end);
+            else if (variant == 3)
+                hipLaunchKernelGGL((k_solve_tiled<32, 8, 8>), tg, dim3(288), 0, s, d_dom, d_list, n, vx, vy, Kb,
+                                   (const float *)ycur, (const float *)comp, ynext, cnext, list_cells, step, s_end);
+            else
+                hipLaunchKernelGGL((k_solve_tiled<64, 4, 9>), tg, dim3(576), 0, s, d_dom, d_list, n, vx, vy, Kb,
+                                   (const float *)ycur, (const float *)comp, ynext, cnext, list_cells, step, s_end);
+            SHMM_HIP_CHECK(hipGetLastError());
+            std::swap(ycur, ynext);
+            std::swap(comp, cnext);
+        }
+        hipLaunchKernelGGL(k_solve_tiled_fini, grid, dim3(256), 0, s, d_dom, d_list, n, (const float *)ycur, w,
+                           cells_total, list_cells);
+        SHMM_HIP_CHECK(hipGetLastError());
+        return SHMM_OK;
+    }
+    // generic path: one launch per RK stage
     for (int32_t step = step_begin; step < s_end; ++step) {
         for (int st = 0; st < 4; ++st) {
             hipLaunchKernelGGL(k_solve_stage, grid, dim3(256), 0, s, d_dom, d_list, n, vx, vy, Kb, w,

@@ -144,7 +144,8 @@ def _single_level(n, seed, amp, kappa, lattice=2, radius=None):
 @pytest.mark.parametrize("n,steps,variant", [(8, None, 0), (16, None, 0), (32, None, 0),
                                              (64, 400, 0), (64, 400, 1), (64, 400, 2), (64, 400, 3),
                                              (64, 400, 4), (128, 60, 0), (128, 60, 1), (128, 60, 2),
-                                             (128, 60, 3), (128, 60, 4), (256, 12, 0)])
+                                             (128, 60, 3), (128, 60, 4), (256, 12, 0), (256, 12, 1),
+                                             (256, 12, 2), (256, 12, 3)])
 def test_local_solve_and_estimator_parity(torch, n, steps, variant):
     """Band filter + RK4 local solve + FP64 estimator against the oracle's own
     synthesis, solve and estimator, on an anisotropic base (every kernel variant)."""
@@ -187,7 +188,7 @@ def test_local_solve_and_estimator_parity(torch, n, steps, variant):
     H.close()
 
 
-@pytest.mark.parametrize("n", [32, 128])
+@pytest.mark.parametrize("n", [32, 128, 256])
 def test_chunked_solve_matches_single_launch(torch, n):
     p = _single_level(n, seed=9, amp=0.3, kappa=0.05)
     say("case chunked solve")
@@ -253,6 +254,31 @@ def test_hierarchy_parity(torch, name, make):
         assert np.max(np.abs(r.R[d] - Kr)) <= 1e-5 * np.max(np.abs(Kr)), (name, d, r.R[d], Kr)
     if name == "shear-closed-form":
         assert abs(r.K_total[0][2] - 0.2053125) <= 1e-12
+    assert int(H.status.cpu().numpy().max()) == 0
+    H.close()
+
+
+# one instance of the uneven-batch generator per (patch size, level count), levels 2-3
+STRATIFIED_SEEDS = [23, 3, 2, 35, 0, 4, 14, 12]     # n = 32, 32, 64, 64, 128, 128, 256, 256
+
+
+def test_uneven_batch_stratified(torch):
+    """Instances of the uneven-batch generator at their real sizes (4 x 4
+    patches per level, n from 32 to 256, mixed in every phase so each phase
+    launches one kernel per size), a whole pass with every local solve capped
+    at 40 steps on both sides: all level results against the oracle."""
+    probs = [flowgen.config_batched_instance(s) for s in STRATIFIED_SEEDS]
+    assert sorted(set(p.n_cells[0] for p in probs)) == [32, 64, 128, 256]
+    say("case uneven batch stratified")
+    H = hier(probs, keep_psi=False)
+    H.run(steps=40)
+    r = H.result()
+    ref = oracle.run_hierarchy(probs, steps_override=40)
+    assert np.array_equal(r.nsteps == 0, ref.nsteps == 0)
+    assert np.all(np.abs(r.nsteps.astype(np.int64) - ref.nsteps.astype(np.int64)) <= 1)
+    for d in range(H.nd):
+        Kr = ref.R[d]
+        assert np.max(np.abs(r.R[d] - Kr)) <= 1e-5 * np.max(np.abs(Kr)), (d, r.R[d], Kr)
     assert int(H.status.cpu().numpy().max()) == 0
     H.close()
 
