@@ -171,8 +171,12 @@ struct RangeLists {
     std::vector<int64_t> cells;        // cells per list
 };
 
+constexpr int kSideStreams = 3;   // patch sizes of one range solved concurrently
+
 struct shmm_ctx {
     int device = 0;
+    hipStream_t side[kSideStreams] = {};   // default priority
+    hipEvent_t ev_fork = nullptr, ev_join[kSideStreams] = {};
     std::vector<shmm_problem> probs;
     std::vector<std::vector<double>> psi;
     std::vector<std::vector<int32_t>> geo;   // thresh | n_cells | n_global | lattice per instance
@@ -326,6 +330,11 @@ int shmm_ctx_destroy(shmm_ctx *ctx) {
     ctx->release();
     if (ctx->work) (void)hipFree(ctx->work);
     if (ctx->tmp) (void)hipFree(ctx->tmp);
+    for (int i = 0; i < kSideStreams; ++i) {
+        if (ctx->side[i]) (void)hipStreamDestroy(ctx->side[i]);
+        if (ctx->ev_join[i]) (void)hipEventDestroy(ctx->ev_join[i]);
+    }
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     delete ctx;
     return SHMM_OK;
 }
@@ -509,7 +518,7 @@ int shmm_band_filter(shmm_ctx *ctx, int64_t first, int64_t count, float *d_psi, 
     for (const Group &g : ctx->groups) {
         if (g.first + g.count <= first || g.first >= first + count) continue;
         if (g.first < first || g.first + g.count > first + count) return SHMM_EINVAL;
-        const size_t need = band_filter_workspace(g);
+        const size_t need = band_filter_workspace(ctx->inst[g.inst], g);
         if ((rc = ctx->ensure_work(need))) return rc;
         rc = launch_band_filter(ctx->inst[g.inst], g, ctx->d_table, d_psi, d_vx, d_vy, d_f1, d_f2,
                                 d_lines, ctx->d_vmax, ctx->work, ctx->work_bytes, (hipStream_t)stream);
@@ -533,19 +542,55 @@ int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const fl
         if (ctx->table[d].nsteps < 0 || ctx->table[d].dt < 0.0) return SHMM_EINVAL;   // unplanned
     RangeLists *rl = nullptr;
     if ((rc = ctx->range_lists(first, count, &rl))) return rc;
-    for (size_t q = 0; q < rl->ns.size(); ++q) {
+    const size_t groups = rl->ns.size();
+    // Patch sizes of the range run concurrently: the group that needs the
+    // workspace (at most one size does) and the first group go on the
+    // caller's stream, the others on side streams forked from and joined back
+    // into it with events.
+    size_t need = 0;
+    for (size_t q = 0; q < groups; ++q) need = std::max(need, local_solve_workspace(rl->ns[q], rl->cells[q]));
+    if (need && (rc = ctx->ensure_work(need))) return rc;
+    int n_work = 0;
+    for (size_t q = 0; q < groups; ++q) n_work += local_solve_workspace(rl->ns[q], rl->cells[q]) ? 1 : 0;
+    const bool concurrent = groups > 1 && n_work <= 1;
+    hipStream_t main_s = (hipStream_t)stream;
+    bool used[kSideStreams] = {};
+    if (concurrent) {
+        if (!ctx->ev_fork) {
+            SHMM_HIP_CHECK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+            for (int i = 0; i < kSideStreams; ++i) {
+                SHMM_HIP_CHECK(hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking));
+                SHMM_HIP_CHECK(hipEventCreateWithFlags(&ctx->ev_join[i], hipEventDisableTiming));
+            }
+        }
+        SHMM_HIP_CHECK(hipEventRecord(ctx->ev_fork, main_s));
+    }
+    int next_side = 0;
+    for (size_t q = 0; q < groups; ++q) {
         int32_t max_steps = 0;
         for (int64_t d = first; d < first + count; ++d)
             if (ctx->table[d].n == rl->ns[q]) max_steps = std::max(max_steps, ctx->table[d].nsteps);
-        const size_t need = local_solve_workspace(rl->ns[q], rl->cells[q]);
-        if (need && (rc = ctx->ensure_work(need))) return rc;
         const auto it = ctx->solve_variant.find(rl->ns[q]);
         const int variant = it == ctx->solve_variant.end() ? default_solve_variant(rl->ns[q]) : it->second;
+        hipStream_t s = main_s;
+        const bool on_main = !concurrent || local_solve_workspace(rl->ns[q], rl->cells[q]) ||
+                             (n_work == 0 && q == 0);
+        if (!on_main) {
+            const int i = next_side++ % kSideStreams;
+            s = ctx->side[i];
+            if (!used[i]) SHMM_HIP_CHECK(hipStreamWaitEvent(s, ctx->ev_fork, 0));
+            used[i] = true;
+        }
         rc = launch_local_solve(ctx->d_table, rl->d_lists[q], rl->counts[q], rl->ns[q], max_steps,
                                 d_vx, d_vy, d_f1, d_f2, d_K_base, d_w, ctx->cells, step_begin, steps,
-                                rl->cells[q], ctx->work, variant, (hipStream_t)stream);
+                                rl->cells[q], ctx->work, variant, s);
         if (rc) return rc;
     }
+    for (int i = 0; i < kSideStreams; ++i)
+        if (used[i]) {
+            SHMM_HIP_CHECK(hipEventRecord(ctx->ev_join[i], ctx->side[i]));
+            SHMM_HIP_CHECK(hipStreamWaitEvent(main_s, ctx->ev_join[i], 0));
+        }
     return SHMM_OK;
 }
 

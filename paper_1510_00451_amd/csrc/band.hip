@@ -90,12 +90,29 @@ __global__ __launch_bounds__(256) void k_vmax(const shmm_domain *dom, int64_t fi
     if (threadIdx.x == 0) vmax[d] = 0.5 * (double)red[0];
 }
 
-__global__ void k_line_energy(BandParams p) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// One thread per (outer wavenumber, line): neighbouring lanes take
+// neighbouring lines of the same outer wavenumber, so they read the same
+// coefficients.  part[kidx][line].
+__global__ void k_line_rows(BandParams p, int cnt, double *part) {
+    const int lines = 2 * p.M * p.n;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)cnt * lines) return;
+    const int kidx = (int)(t / lines), line = (int)(t - (int64_t)kidx * lines);
     const int per_dir = p.M * p.n;
-    if (t >= 2 * per_dir) return;
-    const int dir = t / per_dir, r = t - dir * per_dir;
-    line_energy_one(p, dir, r / p.n, r % p.n);
+    const int dir = line / per_dir, r = line - dir * per_dir;
+    part[t] = line_row_energy(p, dir, r / p.n, r % p.n, kidx);
+}
+
+// Per line: the outer contributions added in increasing k_o (fixed order).
+__global__ void k_line_sum(BandParams p, int cnt, const double *part) {
+    const int lines = 2 * p.M * p.n;
+    const int line = blockIdx.x * blockDim.x + threadIdx.x;
+    if (line >= lines) return;
+    double total = 0.0;
+    for (int kidx = 0; kidx < cnt; ++kidx) total += part[(int64_t)kidx * lines + line];
+    const int per_dir = p.M * p.n;
+    const int dir = line / per_dir, r = line - dir * per_dir;
+    line_store(p, dir, r / p.n, r % p.n, total);
 }
 
 int next_pow2(int v) {
@@ -128,9 +145,14 @@ static void fill_params(BandParams &p, const InstDev &inst, const Group &g) {
     p.first = g.first;
 }
 
-size_t band_filter_workspace(const Group &g) {
-    // G[3][kb1 + 1][M n], then psi of the group's cells when the caller wants none
+static size_t line_part_offset(const Group &g) {
     return (size_t)3 * (g.kb1 + 1) * g.M * g.n * sizeof(c32) + (size_t)g.count * g.n * g.n * sizeof(float);
+}
+
+size_t band_filter_workspace(const InstDev &inst, const Group &g) {
+    // G[3][kb1 + 1][M n], psi of the group's cells when the caller wants none,
+    // then the line-energy contributions [outer wavenumbers][2 M n] (FP64)
+    return line_part_offset(g) + (size_t)line_outer_count(inst, g.level) * 2 * g.M * g.n * sizeof(double);
 }
 
 int launch_band_filter(const InstDev &inst, const Group &g, const shmm_domain *d_dom, float *d_psi,
@@ -139,7 +161,7 @@ int launch_band_filter(const InstDev &inst, const Group &g, const shmm_domain *d
     BandParams p;
     fill_params(p, inst, g);
     if (p.P1 > 4096 || p.P2 > 4096 || p.P1 > g.N || p.P2 > g.N) return SHMM_ERANGE;
-    if (work_bytes < band_filter_workspace(g)) return SHMM_ENOMEM;
+    if (work_bytes < band_filter_workspace(inst, g)) return SHMM_ENOMEM;
     p.dom = d_dom;
     p.I0 = g.d_I0;
     p.J0 = g.d_J0;
@@ -178,7 +200,15 @@ int launch_band_filter(const InstDev &inst, const Group &g, const shmm_domain *d
                        (const float *)d_vy, d_vmax);
     SHMM_HIP_CHECK(hipGetLastError());
     const int lines = 2 * g.M * g.n;
-    hipLaunchKernelGGL(k_line_energy, dim3((unsigned)((lines + 63) / 64)), dim3(64), 0, s, p);
+    const int cnt = line_outer_count(inst, g.level);
+    double *part = (double *)((char *)work + line_part_offset(g));
+    if (cnt > 0) {
+        const int64_t rows = (int64_t)cnt * lines;
+        hipLaunchKernelGGL(k_line_rows, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, p, cnt, part);
+        SHMM_HIP_CHECK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_line_sum, dim3((unsigned)((lines + 255) / 256)), dim3(256), 0, s, p, cnt,
+                       (const double *)part);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
 }

@@ -204,53 +204,70 @@ __host__ __device__ void band_pass2_block(const BandParams &p, int blk, c32 *a, 
     }
 }
 
-// Line energy of one line (Algorithm 1 with eq:shearhomoY / eq:shearhomoX, by
-// Parseval): dir 0 = column x1 = pi (2 (I0[q] + i) + 1) / N of the off-12 band
-// (inner index k1, outer k2); dir 1 = row of the off-21 band (inner k2, outer k1).
-// Written to every domain of the group that contains the line.
-__host__ __device__ inline void line_energy_one(const BandParams &p, int dir, int q, int i) {
-    const int L = p.inst.L, lev = p.level, kmax = p.inst.kmax;
-    double total = 0.0;
-    if (lev < L - 1) {
-        const int in_lo = lev == 0 ? 0 : p.inst.thresh[lev - 1] + 1;
-        const int in_hi = p.inst.thresh[lev] < kmax ? p.inst.thresh[lev] : kmax;
-        const int out_lo = p.inst.thresh[lev] + 1;
-        const int span = 2 * kmax + 1;
-        const int64_t twoI1 = 2 * (int64_t)((dir == 0 ? p.I0[q] : p.J0[q]) + i) + 1;
-        const int64_t twoN = 2 * (int64_t)p.N;
-        int64_t rs = twoI1 % twoN;
-        double ss, sc;
-        sincospi_f64((double)rs / (double)p.N, &ss, &sc);   // e^{i x}
-        int64_t r0 = ((-(int64_t)in_hi) * twoI1) % twoN;
-        if (r0 < 0) r0 += twoN;
-        double s0, c0;
-        sincospi_f64((double)r0 / (double)p.N, &s0, &c0);   // e^{-i in_hi x}
-        for (int ko = -kmax; ko <= kmax && in_lo <= in_hi; ++ko) {
-            const int ako = ko < 0 ? -ko : ko;
-            if (ako < out_lo) continue;
-            double sr = 0.0, si = 0.0;
-            double er = c0, ei = s0;
-            for (int ki = -in_hi; ki <= in_hi; ++ki) {
-                const int aki = ki < 0 ? -ki : ki;
-                if (aki >= in_lo) {
-                    const int k1 = dir == 0 ? ki : ko, k2 = dir == 0 ? ko : ki;
-                    const int64_t idx = (int64_t)(k2 + kmax) * span + (k1 + kmax);
-                    const double pr = p.inst.psi_hat[2 * idx], pi = p.inst.psi_hat[2 * idx + 1];
-                    sr += pr * er - pi * ei;
-                    si += pr * ei + pi * er;
-                }
-                const double nr = er * sc - ei * ss, ni = er * ss + ei * sc;
-                er = nr;
-                ei = ni;
-            }
-            total += sr * sr + si * si;
+// Number of outer wavenumbers of a level's off-diagonal bands: |k_o| in
+// (a_l, kmax] on both signs (0 at the last level).
+__host__ __device__ inline int line_outer_count(const InstDev &inst, int lev) {
+    if (lev >= inst.L - 1) return 0;
+    const int out_lo = inst.thresh[lev] + 1;
+    return inst.kmax >= out_lo ? 2 * (inst.kmax - out_lo + 1) : 0;
+}
+
+// Contribution of one outer wavenumber to the energy of one line (Algorithm 1
+// with eq:shearhomoY / eq:shearhomoX, by Parseval): |sum over the inner
+// wavenumbers of psi_hat e^{i k_in x}|^2.  dir 0 = column x1 = pi (2 (I0[q] +
+// i) + 1) / N of the off-12 band (inner index k1, outer k2); dir 1 = row of the
+// off-21 band (inner k2, outer k1).  kidx enumerates the outer wavenumbers in
+// increasing order (-kmax .. -out_lo, then out_lo .. kmax).
+__host__ __device__ inline double line_row_energy(const BandParams &p, int dir, int q, int i, int kidx) {
+    const int lev = p.level, kmax = p.inst.kmax;
+    const int in_lo = lev == 0 ? 0 : p.inst.thresh[lev - 1] + 1;
+    const int in_hi = p.inst.thresh[lev] < kmax ? p.inst.thresh[lev] : kmax;
+    const int out_lo = p.inst.thresh[lev] + 1;
+    if (in_lo > in_hi) return 0.0;
+    const int half = kmax - out_lo + 1;
+    const int ko = kidx < half ? -kmax + kidx : out_lo + (kidx - half);
+    const int span = 2 * kmax + 1;
+    const int64_t twoI1 = 2 * (int64_t)((dir == 0 ? p.I0[q] : p.J0[q]) + i) + 1;
+    const int64_t twoN = 2 * (int64_t)p.N;
+    const int64_t rs = twoI1 % twoN;
+    double ss, sc;
+    sincospi_f64((double)rs / (double)p.N, &ss, &sc);   // e^{i x}
+    int64_t r0 = ((-(int64_t)in_hi) * twoI1) % twoN;
+    if (r0 < 0) r0 += twoN;
+    double er, ei;
+    sincospi_f64((double)r0 / (double)p.N, &ei, &er);   // e^{-i in_hi x}
+    double sr = 0.0, si = 0.0;
+    for (int ki = -in_hi; ki <= in_hi; ++ki) {
+        const int aki = ki < 0 ? -ki : ki;
+        if (aki >= in_lo) {
+            const int k1 = dir == 0 ? ki : ko, k2 = dir == 0 ? ko : ki;
+            const int64_t idx = (int64_t)(k2 + kmax) * span + (k1 + kmax);
+            const double pr = p.inst.psi_hat[2 * idx], pi = p.inst.psi_hat[2 * idx + 1];
+            sr += pr * er - pi * ei;
+            si += pr * ei + pi * er;
         }
+        const double nr = er * sc - ei * ss, ni = er * ss + ei * sc;
+        er = nr;
+        ei = ni;
     }
+    return sr * sr + si * si;
+}
+
+// Write the energy of one line to every domain of the group that contains it.
+__host__ __device__ inline void line_store(const BandParams &p, int dir, int q, int i, double total) {
     for (int o = 0; o < p.M; ++o) {
         const int64_t local = dir == 0 ? (int64_t)o * p.M + q : (int64_t)q * p.M + o;
         const shmm_domain &d = p.dom[p.first + local];
         p.lines[d.line_offset + (dir == 0 ? 0 : p.n) + i] = total;
     }
+}
+
+// Energy of one line: the outer contributions added in increasing k_o.
+__host__ __device__ inline void line_energy_one(const BandParams &p, int dir, int q, int i) {
+    double total = 0.0;
+    const int cnt = line_outer_count(p.inst, p.level);
+    for (int kidx = 0; kidx < cnt; ++kidx) total += line_row_energy(p, dir, q, i, kidx);
+    line_store(p, dir, q, i, total);
 }
 
 }  // namespace shmm
