@@ -283,6 +283,50 @@ def test_uneven_batch_stratified(torch):
     H.close()
 
 
+def test_solve_batch_replays_from_a_captured_graph(torch):
+    """A chunk of local solves over a phase with two patch sizes (64^2
+    resident, 256^2 overlapped tiles; the sizes run on forked streams),
+    captured once into a graph and replayed three times, with eager work and
+    synchronisations between the replays: every replay equals the eager
+    result bit for bit."""
+    probs = [flowgen.config_batched_instance(2), flowgen.config_batched_instance(14)]
+    assert sorted(p.n_cells[0] for p in probs) == [64, 256]
+    say("case graph replay")
+    H = hier(probs, keep_psi=False)
+    H.band_filter()
+    first, count = int(H.phase[0]), int(H.phase[1] - H.phase[0])
+    kap = np.array([probs[i].kappa for i in H.table["instance"]])
+    Kb = np.stack([kap, np.zeros_like(kap), kap], 1)
+    H.K_base.copy_(torch.from_numpy(Kb))
+    H.ctx.shmm_plan_steps(0, H.nd, Kb)
+    args = (H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(),
+            H.w.data_ptr())
+
+    def chunk(stream):
+        H.ctx.shmm_local_solve_batch(first, count, *args, 0, 20, 0, stream)
+
+    H.w.zero_()
+    chunk(H.stream())                      # eager: also sizes the workspace and the launch lists
+    torch.cuda.synchronize()
+    eager = H.w.cpu().numpy().copy()
+    assert np.abs(eager).max() > 0
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.graph(g, stream=side):
+        chunk(torch.cuda.current_stream().cuda_stream)
+    for rep in range(3):
+        H.w.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(H.w.cpu().numpy(), eager), rep
+        H.w.fill_(1.0)                      # eager work between replays
+        chunk(H.stream())
+        torch.cuda.synchronize()
+    del g
+    H.close()
+
+
 def test_pass_is_deterministic(torch):
     p = flowgen.config_four_level_cellular(n=16, lattice=2)
     say("case determinism")
