@@ -185,16 +185,22 @@ __global__ __launch_bounds__(NN *NN / R) void k_solve_resident(
 // eN of row r is nb[r + 1] and eS is 2 cyy - nb[r]; the forcing is
 // h (eE - eW) (first corrector) or h (eN - eS) (second).  The x-difference of
 // a row, w_E - w_W, is formed once and used by the rows above and below.
-template <int NN, int R, int FIELD, int KIND>
+// OPAQUE: hide the coefficients from loop-invariant motion, so that derived
+// values are recomputed each stage instead of hoisted into R more registers
+// each.  Needed at n = 128, where hoisting spills; smaller patches are faster
+// with the derived values hoisted.
+template <int NN, int R, int FIELD, int KIND, bool OPAQUE>
 __device__ __forceinline__ void rk_stage_e(const float *__restrict__ C, int offW, int offE, int offS,
                                            int offN, float *__restrict__ out, const SolveConsts &k,
                                            float two_cyy, float cw, float (&eE)[R], float (&eW)[R],
                                            float (&nb)[R + 1], float (&wv)[R], float (&comp)[R],
                                            float (&rr)[R]) {
+    if (OPAQUE) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) asm volatile("" : "+v"(eE[r]), "+v"(eW[r]));
+        for (int r = 0; r < R; ++r) asm volatile("" : "+v"(eE[r]), "+v"(eW[r]));
 #pragma unroll
-    for (int r = 0; r <= R; ++r) asm volatile("" : "+v"(nb[r]));
+        for (int r = 0; r <= R; ++r) asm volatile("" : "+v"(nb[r]));
+    }
     const float *Wc = C + offW;
     const float *Ec = C + offE;
     float sC = C[offS];
@@ -283,14 +289,14 @@ __device__ __forceinline__ void solve_body_e(float *__restrict__ buf, const shmm
     }
     __syncthreads();
     for (int32_t s = step_begin; s < s_end; ++s) {
-        rk_stage_e<NN, R, FIELD, 0>(lo, offW, offE, offS, offN, hi, k, two_cyy, 0.0f, eE, eW, nb, wv, comp, rr);
+        rk_stage_e<NN, R, FIELD, 0, (NN >= 128)>(lo, offW, offE, offS, offN, hi, k, two_cyy, 0.0f, eE, eW, nb, wv, comp, rr);
         __syncthreads();
-        rk_stage_e<NN, R, FIELD, 1>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.25f, eE, eW, nb, wv, comp, rr);
+        rk_stage_e<NN, R, FIELD, 1, (NN >= 128)>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.25f, eE, eW, nb, wv, comp, rr);
         __syncthreads();
-        rk_stage_e<NN, R, FIELD, 1>(lo, offW, offE, offS, offN, hi, k, two_cyy, 1.0f / 3.0f, eE, eW, nb, wv, comp,
+        rk_stage_e<NN, R, FIELD, 1, (NN >= 128)>(lo, offW, offE, offS, offN, hi, k, two_cyy, 1.0f / 3.0f, eE, eW, nb, wv, comp,
                                     rr);
         __syncthreads();
-        rk_stage_e<NN, R, FIELD, 2>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.5f, eE, eW, nb, wv, comp, rr);
+        rk_stage_e<NN, R, FIELD, 2, (NN >= 128)>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.5f, eE, eW, nb, wv, comp, rr);
         __syncthreads();
     }
 #pragma unroll
@@ -565,14 +571,14 @@ __device__ __forceinline__ void tiled_body(float *__restrict__ buf, const shmm_d
     for (int r = 0; r < R; ++r) lo[r * W] = wv[r];
     __syncthreads();
     for (int32_t s = step0; s < s_end; ++s) {
-        rk_stage_e<W, R, FIELD, 0>(lo, offW, offE, offS, offN, hi, k, two_cyy, 0.0f, eE, eW, nb, wv, comp, rr);
+        rk_stage_e<W, R, FIELD, 0, false>(lo, offW, offE, offS, offN, hi, k, two_cyy, 0.0f, eE, eW, nb, wv, comp, rr);
         __syncthreads();
-        rk_stage_e<W, R, FIELD, 1>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.25f, eE, eW, nb, wv, comp, rr);
+        rk_stage_e<W, R, FIELD, 1, false>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.25f, eE, eW, nb, wv, comp, rr);
         __syncthreads();
-        rk_stage_e<W, R, FIELD, 1>(lo, offW, offE, offS, offN, hi, k, two_cyy, 1.0f / 3.0f, eE, eW, nb, wv, comp,
+        rk_stage_e<W, R, FIELD, 1, false>(lo, offW, offE, offS, offN, hi, k, two_cyy, 1.0f / 3.0f, eE, eW, nb, wv, comp,
                                    rr);
         __syncthreads();
-        rk_stage_e<W, R, FIELD, 2>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.5f, eE, eW, nb, wv, comp, rr);
+        rk_stage_e<W, R, FIELD, 2, false>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.5f, eE, eW, nb, wv, comp, rr);
         __syncthreads();
     }
     if (x < HALO || x >= HALO + TW) return;
