@@ -122,7 +122,7 @@ int shmm_ctx_destroy(shmm_ctx *ctx);
  * the sizes; then with out holding *n_domains entries.  Errors: SHMM_EINVAL
  * for malformed geometry (n not a power of two, patch origin off the level
  * grid, lattice not refining its parent's, band edges not increasing,
- * kappa <= 0). */
+ * kappa <= 0, dt_frac outside (0, 1], delta outside (0, 1)). */
 int shmm_build_levels(const shmm_problem *p, int32_t n_inst, shmm_domain *out,
                       int64_t *n_domains, int64_t *n_cells_total, int64_t *n_lines_total);
 
@@ -237,7 +237,8 @@ int shmm_ctx_tune(shmm_ctx *ctx, int32_t key, int32_t value);
  * velocities (may both be NULL: pure diffusion); d_K is [N*N][3] at cell
  * centres (face value = mean of the two cells) if K_is_field, else [1][3].
  * dtype 64: d_vx, d_vy, d_u are double; dtype 32: float (K stays double).
- * Errors: SHMM_EINVAL for N < 4 or a dtype other than 32/64. */
+ * Errors: SHMM_EINVAL for N < 4 or not a power of two, a dtype other than
+ * 32/64, or nsteps < 0 (nsteps = 0 is a no-op). */
 int shmm_macro_step(shmm_ctx *ctx, int32_t N, const void *d_vx, const void *d_vy,
                     const double *d_K, int32_t K_is_field, double dt, int32_t nsteps, void *d_u,
                     int32_t dtype, void *stream);
@@ -298,7 +299,7 @@ int shmm_surrogate_train_step(shmm_ctx *ctx, void *d_model, float *d_adam, const
  * feature lies outside [d_lo, d_hi] (33 floats each, the training range) or
  * the largest member deviation from the mean exceeds tau in relative
  * Frobenius norm.  d_K_out [B][3]; d_spread [B] and d_K_members [E][B][3]
- * optional. */
+ * optional.  B = 0 is a no-op; B above 2^24 is SHMM_ERANGE. */
 int shmm_surrogate_infer(shmm_ctx *ctx, const void *d_models, int32_t E, const float *d_x,
                          const double *d_K_base, int64_t B, const float *d_lo, const float *d_hi,
                          double tau, double *d_K_out, uint8_t *d_flags, double *d_spread,

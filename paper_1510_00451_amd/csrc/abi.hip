@@ -29,6 +29,7 @@ int validate(const shmm_problem *p, int32_t n_inst) {
         const int L = P.n_levels;
         if (L < 1 || L > SHMM_MAX_LEVELS) return SHMM_EINVAL;
         if (!(P.kappa > 0.0) || P.kmax < 0) return SHMM_EINVAL;
+        if (!(P.dt_frac > 0.0 && P.dt_frac <= 1.0) || !(P.delta > 0.0 && P.delta < 1.0)) return SHMM_EINVAL;
         if (!P.n_cells || !P.n_global || !P.lattice || (L > 1 && !P.thresh)) return SHMM_EINVAL;
         for (int l = 0; l + 1 < L - 1; ++l)
             if (!(P.thresh[l + 1] > P.thresh[l])) return SHMM_EINVAL;
@@ -685,9 +686,10 @@ int shmm_surrogate_infer(shmm_ctx *ctx, const void *d_models, int32_t E, const f
                          const double *d_K_base, int64_t B, const float *d_lo, const float *d_hi,
                          double tau, double *d_K_out, uint8_t *d_flags, double *d_spread,
                          double *d_K_members, void *stream) {
-    if (!ctx || !d_models || E < 1 || !d_x || !d_K_base || B <= 0 || !d_lo || !d_hi || !d_K_out || !d_flags)
+    if (!ctx || !d_models || E < 1 || !d_x || !d_K_base || B < 0 || !d_lo || !d_hi || !d_K_out || !d_flags)
         return SHMM_EINVAL;
     if (B > (1 << 24)) return SHMM_ERANGE;
+    if (B == 0) return SHMM_OK;
     int rc = set_device(ctx);
     if (rc) return rc;
     const size_t net = surrogate_net_workspace(B);

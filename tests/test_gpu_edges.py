@@ -1,0 +1,140 @@
+"""Edge cases of the C ABI on the GPU: empty ranges and batches are no-ops,
+invalid arguments return their error codes, and nothing is written on error."""
+import numpy as np
+import pytest
+
+import flowgen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def _hier():
+    from paper_1510_00451_amd.hierarchy import Hierarchy
+    p = flowgen.config_four_level_cellular(n=16, lattice=2)
+    return Hierarchy(p, keep_psi=False)
+
+
+def test_empty_ranges_are_no_ops(torch):
+    from paper_1510_00451_amd import abi
+    from paper_1510_00451_amd import surrogate as GS
+    say("case empty ranges")
+    H = _hier()
+    c, s = H.ctx, H.stream()
+    for buf in (H.vx, H.vy, H.f1, H.f2, H.w):
+        buf.fill_(3.0)
+    H.K_base.fill_(0.5)
+    H.K_solve.fill_(-2.0)
+    c.shmm_band_filter(0, 0, 0, H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(),
+                       H.lines.data_ptr(), s)
+    c.shmm_plan_steps(0, 0, np.zeros((H.nd, 3)))
+    c.shmm_local_solve_batch(0, 0, H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(),
+                             H.K_base.data_ptr(), H.w.data_ptr(), 0, 10, 0, s)
+    c.shmm_effective_diffusivity(0, 0, H.f1.data_ptr(), H.f2.data_ptr(), H.w.data_ptr(), H.K_base.data_ptr(),
+                                 H.K_solve.data_ptr(), 0, 0, 0, s)
+    for mode in (0, 1, 2):
+        c.shmm_level_chain(0, 0, mode, H.lines.data_ptr(), H.K_in.data_ptr(), H.K_off.data_ptr(),
+                           H.K_base.data_ptr(), H.K_solve.data_ptr(), H.R.data_ptr(), 0, s)
+    x = torch.zeros(1, 33, dtype=torch.float32, device="cuda")
+    c.shmm_patch_features(0, 0, H.vx.data_ptr(), H.vy.data_ptr(), H.K_base.data_ptr(), x.data_ptr(), s)
+    ens = GS.Ensemble(c, 1, np.zeros(33), np.ones(33))
+    K = torch.full((1, 3), -1.0, dtype=torch.float64, device="cuda")
+    flags = torch.full((1,), 7, dtype=torch.uint8, device="cuda")
+    lo = torch.zeros(33, dtype=torch.float32, device="cuda")
+    c.shmm_surrogate_infer(ens.buf.data_ptr(), 1, x.data_ptr(), H.K_base.data_ptr(), 0, lo.data_ptr(),
+                           lo.data_ptr(), 0.1, K.data_ptr(), flags.data_ptr(), 0, 0, s)
+    c.shmm_fallback_solve(0, 0, flags.data_ptr(), H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(),
+                          H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(), K.data_ptr(), 0, s)
+    u = torch.full((16 * 16,), 2.0, dtype=torch.float64, device="cuda")
+    Kc = torch.tensor([[0.1, 0.0, 0.1]], dtype=torch.float64, device="cuda")
+    c.shmm_macro_step(16, 0, 0, Kc.data_ptr(), 0, 0.01, 0, u.data_ptr(), 64, s)
+    torch.cuda.synchronize()
+    for buf in (H.vx, H.vy, H.f1, H.f2, H.w):
+        assert bool((buf == 3.0).all())
+    assert bool((H.K_solve == -2.0).all())
+    assert bool((K == -1.0).all()) and int(flags[0]) == 7
+    assert bool((u == 2.0).all())
+    H.close()
+
+
+def test_invalid_arguments_return_error_codes(torch):
+    from paper_1510_00451_amd import abi
+    say("case invalid arguments")
+    H = _hier()
+    c, s = H.ctx, H.stream()
+    nd = H.nd
+    args = (H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(),
+            H.w.data_ptr())
+
+    def code(fn):
+        with pytest.raises(abi.ShmmError) as e:
+            fn()
+        return e.value.code
+
+    # ranges outside the table
+    assert code(lambda: c.shmm_local_solve_batch(nd - 1, 2, *args, 0, 1, 0, s)) == abi.SHMM_EINVAL
+    assert code(lambda: c.shmm_local_solve_batch(-1, 1, *args, 0, 1, 0, s)) == abi.SHMM_EINVAL
+    # negative step counts; solving before any plan
+    assert code(lambda: c.shmm_local_solve_batch(0, nd, *args, 0, -1, 0, s)) == abi.SHMM_EINVAL
+    assert code(lambda: c.shmm_local_solve_batch(0, nd, *args, 0, 10, 0, s)) == abi.SHMM_EINVAL
+    # a band filter range that cuts a group of patches
+    assert code(lambda: c.shmm_band_filter(0, 1, 0, H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(),
+                                           H.f2.data_ptr(), H.lines.data_ptr(), s)) == abi.SHMM_EINVAL
+    # planning before the band filter has produced the advection bounds
+    Kb = np.tile([0.02, 0.0, 0.02], (nd, 1))
+    assert code(lambda: c.shmm_plan_steps(0, nd, Kb)) == abi.SHMM_EINVAL
+    H.band_filter()
+    # a base that is not positive definite, and a non-finite advection bound
+    bad = Kb.copy()
+    bad[0] = [0.02, 0.05, 0.02]
+    assert code(lambda: c.shmm_plan_steps(0, nd, bad)) == abi.SHMM_ENOTSPD
+    vmax = np.ones(nd)
+    vmax[1] = np.nan
+    assert code(lambda: c.shmm_plan_steps(0, nd, Kb, vmax)) == abi.SHMM_EINVAL
+    # macro grid that is not a power of two, unknown dtype, negative step count
+    u = torch.zeros(12 * 12, dtype=torch.float64, device="cuda")
+    Kc = torch.tensor([[0.1, 0.0, 0.1]], dtype=torch.float64, device="cuda")
+    assert code(lambda: c.shmm_macro_step(12, 0, 0, Kc.data_ptr(), 0, 0.01, 1, u.data_ptr(), 64, s)) \
+        == abi.SHMM_EINVAL
+    assert code(lambda: c.shmm_macro_step(16, 0, 0, Kc.data_ptr(), 0, 0.01, 1, u.data_ptr(), 16, s)) \
+        == abi.SHMM_EINVAL
+    assert code(lambda: c.shmm_macro_step(16, 0, 0, Kc.data_ptr(), 0, 0.01, -1, u.data_ptr(), 64, s)) \
+        == abi.SHMM_EINVAL
+    # unknown tuning key or variant
+    with pytest.raises(abi.ShmmError):
+        c.shmm_ctx_tune(128, 99)
+    torch.cuda.synchronize()
+    H.close()
+
+
+def test_problem_validation(torch):
+    from paper_1510_00451_amd import abi
+    say("case problem validation")
+    good = flowgen.config_four_level_cellular(n=16, lattice=2)
+    ctx = abi.Context(0)
+    for field, value in (("kappa", 0.0), ("kappa", -1.0), ("dt_frac", 0.0), ("delta", 1.5)):
+        p = flowgen.config_four_level_cellular(n=16, lattice=2)
+        setattr(p, field, value)
+        with pytest.raises(abi.ShmmError) as e:
+            ctx.shmm_ctx_set_problem(p)
+        assert e.value.code == abi.SHMM_EINVAL, field
+    p = flowgen.config_four_level_cellular(n=16, lattice=2)
+    p.n_cells = [16, 16, 24, 16]                  # not a power of two
+    with pytest.raises(abi.ShmmError):
+        ctx.shmm_ctx_set_problem(p)
+    p = flowgen.config_four_level_cellular(n=16, lattice=2)
+    p.thresh = [8, 2, 32]                         # not increasing
+    with pytest.raises(abi.ShmmError):
+        ctx.shmm_ctx_set_problem(p)
+    ctx.shmm_ctx_set_problem(good)               # the context is still usable
+    ctx.close()
