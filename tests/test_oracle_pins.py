@@ -434,3 +434,79 @@ def test_domain_table_geometry():
         bad = flowgen.config_four_level_cellular(n=32, lattice=4)
         bad.lattice = [3, 4, 4, 4]
         oracle.domain_table(bad)
+
+
+# ---------------------------------------------------------------- step plan
+
+def _dense(vx, vy, K, h, n):
+    """The discrete operator u -> div(v u + K grad u) as a dense matrix, column by column."""
+    A = np.zeros((n * n, n * n))
+    for c in range(n * n):
+        e = np.zeros(n * n)
+        e[c] = 1.0
+        A[:, c] = oracle.operator(vx, vy, K, None, e.reshape(n, n), h).ravel()
+    return A
+
+
+def _random_flow(n, seed, amp):
+    rng = np.random.default_rng(seed)
+    h = 2 * np.pi / n
+    psi = np.zeros((n, n))
+    x = np.arange(n) * h
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    for _ in range(4):
+        k1, k2 = rng.integers(-3, 4, 2)
+        psi += amp * rng.standard_normal() * np.cos(k1 * X + k2 * Y + rng.uniform(0, 2 * np.pi))
+    return oracle.staggered(psi, h)[:2] + (h,)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_advection_bound_bounds_the_spectrum(seed):
+    """The eigenvalues of the discrete advection operator (zero diffusion) are
+    imaginary and no larger than advection_bound / h; a uniform flow reaches it."""
+    n = 8
+    vx, vy, h = _random_flow(n, seed, 1.0)
+    ev = np.linalg.eigvals(_dense(vx, vy, [0.0, 0.0, 0.0], h, n))
+    bound = oracle.advection_bound(vx, vy) / h
+    assert np.max(np.abs(ev.real)) <= 1e-10 * bound
+    assert np.max(np.abs(ev)) <= bound * (1 + 1e-12)
+    V = 0.7
+    ev = np.linalg.eigvals(_dense(np.full((n, n), V), np.zeros((n, n)), [0.0, 0.0, 0.0], h, n))
+    assert abs(np.max(np.abs(ev)) - oracle.advection_bound(np.full((n, n), V), np.zeros((n, n))) / h) \
+        <= 1e-12 * V / h
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_step_plan_is_stable_and_decays_by_delta(seed):
+    """For random flows and random SPD bases, independently of the plan's
+    formula: (i) every eigenvalue of the discrete operator times dt lies in the
+    classic RK4 stability region (|1 + z + z^2/2 + z^3/6 + z^4/24| <= 1); (ii)
+    the slowest decaying non-constant mode has decayed by delta or more at
+    T = nsteps dt."""
+    rng = np.random.default_rng(100 + seed)
+    n = 8
+    vx, vy, h = _random_flow(n, seed, 0.3 + 3.0 * rng.uniform())
+    a, b = rng.uniform(0.02, 0.3, 2)
+    c = rng.uniform(-0.9, 0.9) * np.sqrt(a * b)
+    K = [a, c, b]
+    delta = 1e-6
+    dt, ns = oracle.plan_steps(n, h, K, oracle.advection_bound(vx, vy), 0.9, delta)
+    ev = np.linalg.eigvals(_dense(vx, vy, K, h, n))
+    z = dt * ev
+    R = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    assert np.max(np.abs(R)) <= 1 + 1e-12
+    decay = np.sort(-ev.real)
+    assert abs(decay[0]) <= 1e-10 * np.max(np.abs(ev))       # the constant mode
+    assert np.exp(-decay[1] * dt * ns) <= delta * (1 + 1e-9)
+
+
+def test_step_plan_decay_is_tight_for_pure_diffusion():
+    """Without flow and with an isotropic base the slowest mode decays at
+    exactly the plan's bound, so the planned time brings it to delta, no less."""
+    n, kap, delta = 8, 0.07, 1e-6
+    h = 2 * np.pi / n
+    z = np.zeros((n, n))
+    dt, ns = oracle.plan_steps(n, h, [kap, 0.0, kap], oracle.advection_bound(z, z), 0.5, delta)
+    ev = np.linalg.eigvals(_dense(z, z, [kap, 0.0, kap], h, n))
+    slow = np.sort(-ev.real)[1]
+    assert abs(np.exp(-slow * dt * ns) / delta - 1) <= 1e-9
