@@ -37,7 +37,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (256 CU, 2
 SOLVE_TRAFFIC = {"source_sha256": "d4ba548b571a213d", "variant": 3,
                  "bytes_per_launch": (2 * 19429.6 + 25474.9) * 1024}
 SOLVE_KERNELS_128 = {0: "k_solve_resident<128,32>", 1: "k_solve_rows<128,2,16>", 2: "k_solve_rows<128,2,8>",
-                     3: "k_solve_resident_e<128,32>", 4: "k_solve_resident_e<128,16>"}
+                     3: "k_solve_resident_e<128,32>", 4: "k_solve_resident_e<128,16>",
+                     5: "k_solve_resident_e<128,32,8>", 6: "k_solve_resident_e<128,32,16>"}
 
 
 def solve_traffic():

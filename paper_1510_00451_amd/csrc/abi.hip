@@ -300,7 +300,7 @@ struct shmm_ctx {
 // Kernel variant per patch size when no tuning result was set: the
 // LDS-staged kernel in coefficient form (the fastest in the measurements on
 // MI355X; sizes below 64 have no other variant).
-static int default_solve_variant(int n) { return (n == 64 || n == 128) ? 3 : 0; }
+static int default_solve_variant(int n) { return n == 64 ? 3 : n == 128 ? 5 : 0; }
 
 static int set_device(shmm_ctx *ctx) {
     SHMM_HIP_CHECK(hipSetDevice(ctx->device));

@@ -189,12 +189,15 @@ __global__ __launch_bounds__(NN *NN / R) void k_solve_resident(
 // values are recomputed each stage instead of hoisted into R more registers
 // each.  Needed at n = 128, where hoisting spills; smaller patches are faster
 // with the derived values hoisted.
-template <int NN, int R, int FIELD, int KIND, bool OPAQUE>
+// CL: the compensation of the first CL rows of the strip lives in LDS
+// (cl[r * cstride]) instead of registers, to relieve register pressure.
+template <int NN, int R, int FIELD, int KIND, bool OPAQUE, int CL = 0>
 __device__ __forceinline__ void rk_stage_e(const float *__restrict__ C, int offW, int offE, int offS,
                                            int offN, float *__restrict__ out, const SolveConsts &k,
                                            float two_cyy, float cw, float (&eE)[R], float (&eW)[R],
                                            float (&nb)[R + 1], float (&wv)[R], float (&comp)[R],
-                                           float (&rr)[R]) {
+                                           float (&rr)[R], float *__restrict__ cl = nullptr,
+                                           int cstride = 0) {
     if (OPAQUE) {
 #pragma unroll
         for (int r = 0; r < R; ++r) asm volatile("" : "+v"(eE[r]), "+v"(eW[r]));
@@ -226,9 +229,14 @@ __device__ __forceinline__ void rk_stage_e(const float *__restrict__ C, int offW
             o = fmaf(cw, t, rr[r]);
         } else {
             const float q1 = fmaf(0.5f, t, rr[r]);
-            const float yk = q1 - comp[r];
+            const float cp = r < CL ? cl[r * cstride] : comp[r];
+            const float yk = q1 - cp;
             const float tk = wv[r] + yk;
-            comp[r] = (tk - wv[r]) - yk;
+            const float cn = (tk - wv[r]) - yk;
+            if (r < CL)
+                cl[r * cstride] = cn;
+            else
+                comp[r] = cn;
             wv[r] = tk;
             o = tk;
         }
@@ -239,7 +247,7 @@ __device__ __forceinline__ void rk_stage_e(const float *__restrict__ C, int offW
     }
 }
 
-template <int NN, int R, int FIELD>
+template <int NN, int R, int FIELD, int CL>
 __device__ __forceinline__ void solve_body_e(float *__restrict__ buf, const shmm_domain *__restrict__ dom,
                                              const int32_t *__restrict__ list,
                                              const float *__restrict__ vx, const float *__restrict__ vy,
@@ -280,39 +288,46 @@ __device__ __forceinline__ void solve_body_e(float *__restrict__ buf, const shmm
     nb[R] = k.cyy + k.a * vyo[offN];
     float *wf = w + (int64_t)FIELD * cells_total + o + y0 * NN + x;
     float *lo = buf + y0 * NN + x, *hi = lo + PLANE;
+    constexpr int T = NN * NN / R;
+    float *cl = buf + 2 * PLANE + tid;   // CL rows of compensation, stride T
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         wv[r] = wf[r * NN];
         comp[r] = 0.0f;
         rr[r] = 0.0f;
         lo[r * NN] = wv[r];
+        if (r < CL) cl[r * T] = 0.0f;
     }
     __syncthreads();
+    constexpr bool OP = NN >= 128;
     for (int32_t s = step_begin; s < s_end; ++s) {
-        rk_stage_e<NN, R, FIELD, 0, (NN >= 128)>(lo, offW, offE, offS, offN, hi, k, two_cyy, 0.0f, eE, eW, nb, wv, comp, rr);
+        rk_stage_e<NN, R, FIELD, 0, OP, CL>(lo, offW, offE, offS, offN, hi, k, two_cyy, 0.0f, eE, eW, nb, wv, comp,
+                                            rr, cl, T);
         __syncthreads();
-        rk_stage_e<NN, R, FIELD, 1, (NN >= 128)>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.25f, eE, eW, nb, wv, comp, rr);
+        rk_stage_e<NN, R, FIELD, 1, OP, CL>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.25f, eE, eW, nb, wv, comp,
+                                            rr, cl, T);
         __syncthreads();
-        rk_stage_e<NN, R, FIELD, 1, (NN >= 128)>(lo, offW, offE, offS, offN, hi, k, two_cyy, 1.0f / 3.0f, eE, eW, nb, wv, comp,
-                                    rr);
+        rk_stage_e<NN, R, FIELD, 1, OP, CL>(lo, offW, offE, offS, offN, hi, k, two_cyy, 1.0f / 3.0f, eE, eW, nb, wv,
+                                            comp, rr, cl, T);
         __syncthreads();
-        rk_stage_e<NN, R, FIELD, 2, (NN >= 128)>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.5f, eE, eW, nb, wv, comp, rr);
+        rk_stage_e<NN, R, FIELD, 2, OP, CL>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.5f, eE, eW, nb, wv, comp,
+                                            rr, cl, T);
         __syncthreads();
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) wf[r * NN] = wv[r];
 }
 
-template <int NN, int R>
+template <int NN, int R, int CL = 0>
 __global__ __launch_bounds__(NN *NN / R) void k_solve_resident_e(
     const shmm_domain *__restrict__ dom, const int32_t *__restrict__ list,
     const float *__restrict__ vx, const float *__restrict__ vy, const double *__restrict__ Kb,
     float *__restrict__ w, int64_t cells_total, int32_t step_begin, int32_t steps) {
-    __shared__ float buf[2 * NN * NN];
+    __shared__ float buf[2 * NN * NN + CL * (NN * NN / R)];
     if (blockIdx.x & 1)
-        solve_body_e<NN, R, 1>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
+        solve_body_e<NN, R, 1, CL>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
     else
-        solve_body_e<NN, R, 0>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
+        solve_body_e<NN, R, 0, CL>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
 }
 
 // Row-resident variant for patches whose row fits one wavefront (n = 64 C):
@@ -702,11 +717,11 @@ int launch_resident(const shmm_domain *d_dom, const int32_t *d_list, int32_t nli
     return SHMM_OK;
 }
 
-template <int NN, int R>
+template <int NN, int R, int CL = 0>
 int launch_resident_e(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, const float *vx,
                       const float *vy, const double *Kb, float *w, int64_t cells_total,
                       int32_t step_begin, int32_t steps, hipStream_t s) {
-    hipLaunchKernelGGL((k_solve_resident_e<NN, R>), dim3((unsigned)(2 * nlist)), dim3(NN * NN / R), 0, s,
+    hipLaunchKernelGGL((k_solve_resident_e<NN, R, CL>), dim3((unsigned)(2 * nlist)), dim3(NN * NN / R), 0, s,
                        d_dom, d_list, vx, vy, Kb, w, cells_total, step_begin, steps);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
@@ -716,7 +731,7 @@ int launch_resident_e(const shmm_domain *d_dom, const int32_t *d_list, int32_t n
 
 bool local_solve_resident(int n) { return n == 8 || n == 16 || n == 32 || n == 64 || n == 128; }
 
-int local_solve_variants(int n) { return (n == 64 || n == 128) ? 5 : n == 256 ? 4 : 1; }
+int local_solve_variants(int n) { return n == 64 ? 5 : n == 128 ? 7 : n == 256 ? 4 : 1; }
 
 namespace {
 // Zero both corrector fields of the listed domains (one workgroup row per domain).
@@ -768,6 +783,8 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
             if (variant == 2) return launch_rows<128, 2, 8>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
             if (variant == 3) return launch_resident_e<128, 32>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
             if (variant == 4) return launch_resident_e<128, 16>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            if (variant == 5) return launch_resident_e<128, 32, 8>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            if (variant == 6) return launch_resident_e<128, 32, 16>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
             return launch_resident<128, 32>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
         default: break;
     }

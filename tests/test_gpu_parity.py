@@ -144,7 +144,8 @@ def _single_level(n, seed, amp, kappa, lattice=2, radius=None):
 @pytest.mark.parametrize("n,steps,variant", [(8, None, 0), (16, None, 0), (32, None, 0),
                                              (64, 400, 0), (64, 400, 1), (64, 400, 2), (64, 400, 3),
                                              (64, 400, 4), (128, 60, 0), (128, 60, 1), (128, 60, 2),
-                                             (128, 60, 3), (128, 60, 4), (256, 12, 0), (256, 12, 1),
+                                             (128, 60, 3), (128, 60, 4), (128, 60, 5), (128, 60, 6),
+                                             (256, 12, 0), (256, 12, 1),
                                              (256, 12, 2), (256, 12, 3)])
 def test_local_solve_and_estimator_parity(torch, n, steps, variant):
     """Band filter + RK4 local solve + FP64 estimator against the oracle's own
