@@ -30,12 +30,12 @@ METRIC = "κ_eff estimates/s + Gpoint-steps/s; surrogate vs plain at ≤1% κ_ef
 # and the final update (8 flop): 78 flop; two correctors.
 FLOP_PER_POINT_STEP = 156
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (256 CU, 2.4 GHz)
-# HBM bytes per full-phase launch of k_solve_resident_e<128, 32> on this
+# HBM bytes per full-phase launch of k_solve_resident_e<128, 32, 8> on this
 # workload, from rocprofv3 FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0), the scale
 # factors read off a 1 GiB device copy.  Valid only for the kernel source they
 # were taken on (first 16 hex digits of its SHA-256); otherwise reported null.
-SOLVE_TRAFFIC = {"source_sha256": "d4ba548b571a213d", "variant": 3,
-                 "bytes_per_launch": (2 * 19429.6 + 25474.9) * 1024}
+SOLVE_TRAFFIC = {"source_sha256": "fda87b5633ab9c6a", "variant": 5,
+                 "bytes_per_launch": (2 * 18586.2 + 20992.0) * 1024}
 SOLVE_KERNELS_128 = {0: "k_solve_resident<128,32>", 1: "k_solve_rows<128,2,16>", 2: "k_solve_rows<128,2,8>",
                      3: "k_solve_resident_e<128,32>", 4: "k_solve_resident_e<128,16>",
                      5: "k_solve_resident_e<128,32,8>", 6: "k_solve_resident_e<128,32,16>"}
@@ -317,7 +317,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3),
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-                     "traffic": solve_traffic() if tuned.get(128, {"variant": 3})["variant"] == SOLVE_TRAFFIC["variant"]
+                     "traffic": solve_traffic() if tuned.get(128, {"variant": 5})["variant"] == SOLVE_TRAFFIC["variant"]
                      else None,
                      "kernel": SOLVE_KERNELS_128[tuned.get(128, {"variant": 0})["variant"]],
                      "launches": len(ms_launch), "avg_launch_ms": round(avg_ms, 3)},
