@@ -228,8 +228,8 @@ def main():
                     help="copy this many MiB once before the passes (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        log("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
-            "(patches are independent; see the sharding note in DESIGN.md). Use --gpus 1.")
+        log("bench.py measures one GPU only: the hot path runs on a single MI355X; patches are "
+            "independent, so more GPUs would each take a share of the centres. Use --gpus 1.")
         sys.exit(2)
 
     import torch

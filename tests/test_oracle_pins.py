@@ -171,7 +171,7 @@ def test_local_solve_discrete_taylor_identity(Kb):
     assert abs(K[0] - Kb[0]) <= 1e-12 and abs(K[1] - Kb[1]) <= 1e-12
 
 
-def test_taylor_dispersion_north_star_value():
+def test_taylor_dispersion_shear_value():
     """v = (0, sin 16 x), kappa = 1e-2: K_yy = kappa + V^2/(2 kappa k^2) = 0.2053125.
     On a 64-cell grid the node samples of cos^2 average to exactly 1/2."""
     K, K22, _ = _shear_patch(64, -1.0 / 16, 16, [1e-2, 0.0, 1e-2])
