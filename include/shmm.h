@@ -215,7 +215,13 @@ int shmm_effective_diffusivity(shmm_ctx *ctx, int64_t first, int64_t count, cons
  *   mode 2 (result):   finest level: R = K_solve; otherwise
  *          R = K_solve + S12(K_base) + S21(K_base) - 2 K_base (the additive
  *          rule of Algorithm 2 applied to the final step of Algorithm 3).
- * Run mode 0 phase by phase from the coarsest, modes 1-2 from the finest. */
+ *   mode 3 (macro):    R = S12(K_base) + S21(K_base) - K_base (K_base at the
+ *          finest level): the level's effective diffusivity without its own
+ *          diagonal band, for a macro grid that resolves that band as its
+ *          advecting velocity (eq:homo with v_M; HMM step 4).  Pass a separate
+ *          buffer as d_R to keep the level results.
+ * Run mode 0 phase by phase from the coarsest, modes 1-2 from the finest;
+ * mode 3 after mode 1 on the range. */
 int shmm_level_chain(shmm_ctx *ctx, int64_t first, int64_t count, int32_t mode,
                      const double *d_lines, double *d_K_in, double *d_K_off, double *d_K_base,
                      const double *d_K_solve, double *d_R, int32_t *d_status, void *stream);

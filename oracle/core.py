@@ -436,6 +436,17 @@ class HierarchyResult:
         return np.array([self.R[i] for i, d in enumerate(self.domains) if d.level == 0])
 
 
+def macro_diffusivity(res: HierarchyResult, i: int) -> np.ndarray:
+    """Diffusivity for a macro grid that resolves domain i's own diagonal band
+    as its advecting velocity (eq:homo with v_M, HMM step 4): the level's
+    result without that band's local solve, i.e. Algorithm 2's closed form on
+    the level's base, S12(K_base) + S21(K_base) - K_base."""
+    d = res.domains[i]
+    s12 = res.lines[d.line_offset:d.line_offset + d.n]
+    s21 = res.lines[d.line_offset + d.n:d.line_offset + 2 * d.n]
+    return sum_offdiag(res.K_base[i], s12, s21)
+
+
 def level_fields(p, level_arr, part_arr, d: Domain):
     """Diagonal-band psi, face velocities and forcings of one domain."""
     mask = band_mask(level_arr, part_arr, d.level, DIAG)

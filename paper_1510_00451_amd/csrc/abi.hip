@@ -611,7 +611,7 @@ int shmm_effective_diffusivity(shmm_ctx *ctx, int64_t first, int64_t count, cons
 int shmm_level_chain(shmm_ctx *ctx, int64_t first, int64_t count, int32_t mode,
                      const double *d_lines, double *d_K_in, double *d_K_off, double *d_K_base,
                      const double *d_K_solve, double *d_R, int32_t *d_status, void *stream) {
-    if (!range_ok(ctx, first, count) || mode < 0 || mode > 2 || !d_lines || !d_K_in || !d_K_off)
+    if (!range_ok(ctx, first, count) || mode < 0 || mode > 3 || !d_lines || !d_K_in || !d_K_off)
         return SHMM_EINVAL;
     if (mode >= 1 && (!d_K_base || !d_R)) return SHMM_EINVAL;
     if (mode == 2 && !d_K_solve) return SHMM_EINVAL;

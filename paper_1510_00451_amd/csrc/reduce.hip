@@ -175,6 +175,16 @@ __global__ void k_chain(const shmm_domain *__restrict__ dom, const InstDev *__re
             if (status) status[d] |= SHMM_DOM_NOT_SPD;
         }
         for (int q = 0; q < 3; ++q) K_base[3 * d + q] = kb[q];
+    } else if (mode == 3) {
+        // macro diffusivity: the level without its own diagonal band
+        const double *kn = K_base + 3 * d;
+        if (finest) {
+            for (int q = 0; q < 3; ++q) R[3 * d + q] = kn[q];
+            return;
+        }
+        offdiag(kn, s12, D.n, 0, a);
+        offdiag(kn, s21, D.n, 1, b);
+        for (int q = 0; q < 3; ++q) R[3 * d + q] = a[q] + b[q] - kn[q];
     } else {
         if (finest) {
             for (int q = 0; q < 3; ++q) R[3 * d + q] = K_solve[3 * d + q];

@@ -15,7 +15,7 @@ import numpy as np
 
 from . import abi
 
-MODE_TOPDOWN, MODE_BASE, MODE_RESULT = 0, 1, 2
+MODE_TOPDOWN, MODE_BASE, MODE_RESULT, MODE_MACRO = 0, 1, 2, 3
 
 
 def _torch():

@@ -510,3 +510,18 @@ def test_step_plan_decay_is_tight_for_pure_diffusion():
     ev = np.linalg.eigvals(_dense(z, z, [kap, 0.0, kap], h, n))
     slow = np.sort(-ev.real)[1]
     assert abs(np.exp(-slow * dt * ns) / delta - 1) <= 1e-9
+
+
+def test_macro_diffusivity_of_a_resolved_shear_is_the_taylor_value():
+    """v = (0, sin 16x) with band edge 8: the mode lies in level 0's off-21
+    band, which a macro grid does not resolve, so the macro diffusivity is the
+    closed-form shear value K_yy = kappa + V^2/(2 kappa k^2) = 0.2053125 with
+    K_xx = kappa; and the additive rule R = K_solve + macro - K_base holds."""
+    p = flowgen.config_shear(k=16, V=1.0, kappa=1e-2, n=32, levels=2, thresh=[8])
+    r = oracle.run_hierarchy(p)
+    for i, d in enumerate(r.domains):
+        if d.level != 0:
+            continue
+        Km = oracle.macro_diffusivity(r, i)
+        assert abs(Km[2] - 0.2053125) <= 1e-14 and abs(Km[0] - 0.01) <= 1e-16 and abs(Km[1]) <= 1e-16
+        np.testing.assert_allclose(r.R[i], r.K_solve[i] + Km - r.K_base[i], rtol=1e-14, atol=1e-16)
