@@ -9,13 +9,19 @@
 // (centred flux-form advection with div v = 0 dropped from the centre term;
 // K11 dxx + K22 dyy + 2 K12 dxdy diffusion), advanced by classic RK4.
 //
-// Resident kernel: one workgroup per (domain, corrector) holds the whole
-// patch.  The RK stage input is double-buffered in LDS (one barrier per
-// stage); every thread owns a column strip of R cells and keeps their state,
-// the RK accumulator, a compensation term (Kahan summation of the step
-// increments, so FP32 does not stall near the quasi-stationary state) and its
-// face coefficients in registers.  HBM is touched only to load the patch and
-// to store the final state.
+// Kernels, by patch size (variants are chosen per size through the tuner):
+// * resident (n <= 128): one workgroup per (domain, corrector) holds the whole
+//   patch.  The RK stage input is double-buffered in LDS (one barrier per
+//   stage); every thread owns a column strip of R cells and keeps their state,
+//   the RK accumulator, a compensation term (Kahan summation of the step
+//   increments, so FP32 does not stall near the quasi-stationary state) and
+//   its face coefficients in registers.  HBM is touched only to load the
+//   patch and to store the final state.  Two arithmetic forms: the split form
+//   above (k_solve_resident) and the coefficient form (k_solve_resident_e,
+//   the default), plus a row-per-wavefront variant (k_solve_rows).
+// * overlapped tiles (n = 256, k_solve_tiled): a few steps per launch on a
+//   tile plus a ring of redundant cells, state in workspace between launches.
+// * per-stage launches (k_solve_stage): any other size.
 #include <algorithm>
 
 #include "shmm_internal.h"
@@ -635,8 +641,9 @@ __global__ void k_solve_tiled_fini(const shmm_domain *__restrict__ dom, const in
     w[(int64_t)field * cells_total + D.offset + c] = ycur[(int64_t)field * list_cells + (int64_t)li * n * n + c];
 }
 
-// Fallback for patches that do not fit in LDS: one launch per RK stage, state
-// in global memory.  Same arithmetic as the resident kernel.
+// Fallback for other patch sizes: one launch per RK stage, state in global
+// memory, classic RK4 stage by stage (k1..k4 accumulated) with the same
+// operator and the same compensated update.
 __global__ __launch_bounds__(256) void k_solve_stage(
     const shmm_domain *__restrict__ dom, const int32_t *__restrict__ list, int n,
     const float *__restrict__ vx, const float *__restrict__ vy, const double *__restrict__ Kb,
