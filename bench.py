@@ -120,8 +120,9 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     lo, hi = GS.gate_range(train, 0.1)
-    tau = GS.calibrate_tau(ens, held, lo, hi)
-    log(f"surrogate: {data.x.shape[0]} labels in {t_label:.1f} s, trained in {t_train:.1f} s, tau {tau}")
+    tau, emax, held_acc = GS.calibrate_gate(ens, held, lo, hi)
+    log(f"surrogate: {data.x.shape[0]} labels in {t_label:.1f} s, trained in {t_train:.1f} s, "
+        f"tau {tau}, emax {emax}, held-out accepted {held_acc:.3f}")
 
     # all evaluation flows in one phase: the fallback solves of every flagged
     # patch then share one launch, as they would in a stream of patches
@@ -133,7 +134,7 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
     torch.cuda.synchronize()
     b = time.perf_counter()
     ph.prepare()
-    Ks = ph.surrogate(ens, lo, hi, tau)
+    Ks = ph.surrogate(ens, lo, hi, tau, emax)
     torch.cuda.synchronize()
     c = time.perf_counter()
     t_plain, t_surr = b - a, c - b
@@ -152,7 +153,7 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
         "err_vs_plain": {"mean": float(err.mean()), "p99": float(np.quantile(err, 0.99)),
                          "max": float(err.max()), "frac_over_1pct": float(np.mean(err > 0.01))},
         "fallback_frac": float(fl.mean()),
-        "tau": tau,
+        "tau": tau, "emax": emax if math.isfinite(emax) else None, "held_out_accepted": round(held_acc, 4),
         "eval": f"{flows_eval} continuous-spectrum flows (kappa 1e-3, 1<=|k|<=512, |psi_k|~|k|^-7/3) x "
                 f"256 finest-level 128^2 patches, isotropic base; {n_est} estimates",
         "train": {"labels": int(data.x.shape[0]), "flows": flows_train, "label_s": round(t_label, 1),
@@ -219,7 +220,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-flows", type=int, default=64)
-    ap.add_argument("--surrogate-eval-flows", type=int, default=8)
+    ap.add_argument("--surrogate-eval-flows", type=int, default=32)
     ap.add_argument("--no-continuous", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--uneven-instances", type=int, default=256)

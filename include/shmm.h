@@ -302,13 +302,16 @@ int shmm_surrogate_train_step(shmm_ctx *ctx, void *d_model, float *d_adam, const
 
 /* Ensemble inference with the fallback gate: E members at d_models; the
  * estimate is the member mean; a patch is flagged (d_flags[b] = 1) when a
- * feature lies outside [d_lo, d_hi] (33 floats each, the training range) or
+ * feature lies outside [d_lo, d_hi] (33 floats each, the training range), when
  * the largest member deviation from the mean exceeds tau in relative
- * Frobenius norm.  d_K_out [B][3]; d_spread [B] and d_K_members [E][B][3]
- * optional.  B = 0 is a no-op; B above 2^24 is SHMM_ERANGE. */
+ * Frobenius norm, or when the predicted enhancement |K - K_b|_F / |K_b|_F
+ * exceeds emax (the regime where the network was not shown accurate; pass
+ * infinity to disable).  d_K_base [B][3]; d_K_out [B][3]; d_spread [B] and
+ * d_K_members [E][B][3] optional.  B = 0 is a no-op; B above 2^24 is
+ * SHMM_ERANGE. */
 int shmm_surrogate_infer(shmm_ctx *ctx, const void *d_models, int32_t E, const float *d_x,
                          const double *d_K_base, int64_t B, const float *d_lo, const float *d_hi,
-                         double tau, double *d_K_out, uint8_t *d_flags, double *d_spread,
+                         double tau, double emax, double *d_K_out, uint8_t *d_flags, double *d_spread,
                          double *d_K_members, void *stream);
 
 /* Plain-solve fallback for the flagged domains of [first, first + count)

@@ -22,6 +22,10 @@ The paper has no surrogate; these definitions are this project's readings:
   Peclet number K - K_b is, to first order, a sum over modes of these channel
   energies divided by q^2 and kappa, so the directional channels give the
   network the anisotropy that radial energies alone cannot.
+* Gate: a patch falls back to the plain solve when a feature leaves the
+  training range, when the ensemble disagrees (spread > tau), or when the
+  predicted enhancement is beyond emax (the regime where the network was not
+  shown accurate).
 * Network: 33 -> 256 -> 256 -> 256 -> 3 with exact (erf) GELU; inputs are
   standardised with stored means and scales.  Head: L = [[e^o1, 0], [o2, e^o3]],
   K = K_b + sqrt(det K_b) L L^T: the enhancement K - K_b is positive
@@ -250,15 +254,20 @@ def cosine_lr(step: int, total: int, lr0: float) -> float:
 # ---------------------------------------------------------------- gate
 
 def ensemble_gate(K_members: np.ndarray, features: np.ndarray, lo: np.ndarray, hi: np.ndarray,
-                  tau: float):
+                  tau: float, K_base: Optional[np.ndarray] = None, emax: float = math.inf):
     """Mean prediction and fallback flag of an ensemble.
 
     K_members [E][B][3].  Flag a patch when any feature lies outside [lo, hi]
-    (the training range) or when the largest member deviation from the mean,
-    in Frobenius norm relative to the mean, exceeds tau."""
+    (the training range), when the largest member deviation from the mean,
+    in Frobenius norm relative to the mean, exceeds tau, or when the predicted
+    enhancement |K_mean - K_base| / |K_base| (Frobenius) exceeds emax."""
     Km = K_members.mean(axis=0)
     d = K_members - Km[None]
     fro = lambda a: np.sqrt(a[..., 0] ** 2 + 2 * a[..., 1] ** 2 + a[..., 2] ** 2)
     spread = fro(d).max(axis=0) / fro(Km)
     out = np.any((features < lo) | (features > hi), axis=1)
-    return Km, (spread > tau) | out, spread
+    flag = (spread > tau) | out
+    if K_base is not None:
+        Kb = np.atleast_2d(K_base)
+        flag |= ~(fro(Km - Kb) / fro(Kb) <= emax)
+    return Km, flag, spread

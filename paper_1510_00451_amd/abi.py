@@ -78,7 +78,7 @@ def lib() -> ctypes.CDLL:
             "shmm_patch_features": [P, i64, i64, P, P, P, P, P],
             "shmm_surrogate_refresh": [P, P, P],
             "shmm_surrogate_train_step": [P, P, P, P, P, P, i64, ctypes.c_float, i32, P, P, P],
-            "shmm_surrogate_infer": [P, P, i32, P, P, i64, P, P, f64, P, P, P, P, P],
+            "shmm_surrogate_infer": [P, P, i32, P, P, i64, P, P, f64, f64, P, P, P, P, P],
             "shmm_fallback_solve": [P, i64, i64, P, P, P, P, P, P, P, P, P, P],
         }
         for name, args in sig.items():
@@ -230,10 +230,10 @@ class Context:
                                               float(lr), int(t), d_loss, d_grad or None, stream),
               "shmm_surrogate_train_step")
 
-    def shmm_surrogate_infer(self, d_models, E, d_x, d_K_base, B, d_lo, d_hi, tau, d_K_out, d_flags,
+    def shmm_surrogate_infer(self, d_models, E, d_x, d_K_base, B, d_lo, d_hi, tau, emax, d_K_out, d_flags,
                              d_spread=0, d_K_members=0, stream=0):
         check(lib().shmm_surrogate_infer(self.h, d_models, int(E), d_x, d_K_base, int(B), d_lo, d_hi,
-                                         float(tau), d_K_out, d_flags, d_spread or None,
+                                         float(tau), float(emax), d_K_out, d_flags, d_spread or None,
                                          d_K_members or None, stream), "shmm_surrogate_infer")
 
     def shmm_fallback_solve(self, first, count, d_flags, d_vx, d_vy, d_f1, d_f2, d_K_base, d_w, d_K_out,

@@ -684,7 +684,7 @@ int shmm_surrogate_train_step(shmm_ctx *ctx, void *d_model, float *d_adam, const
 
 int shmm_surrogate_infer(shmm_ctx *ctx, const void *d_models, int32_t E, const float *d_x,
                          const double *d_K_base, int64_t B, const float *d_lo, const float *d_hi,
-                         double tau, double *d_K_out, uint8_t *d_flags, double *d_spread,
+                         double tau, double emax, double *d_K_out, uint8_t *d_flags, double *d_spread,
                          double *d_K_members, void *stream) {
     if (!ctx || !d_models || E < 1 || !d_x || !d_K_base || B < 0 || !d_lo || !d_hi || !d_K_out || !d_flags)
         return SHMM_EINVAL;
@@ -696,7 +696,7 @@ int shmm_surrogate_infer(shmm_ctx *ctx, const void *d_models, int32_t E, const f
     const size_t km = d_K_members ? 0 : (size_t)E * B * 3 * sizeof(double);
     if ((rc = ctx->ensure_work(net + km))) return rc;
     double *Km = d_K_members ? d_K_members : (double *)((char *)ctx->work + net);
-    return surrogate_infer(d_models, E, d_x, d_K_base, B, d_lo, d_hi, tau, d_K_out, d_flags, d_spread, Km,
+    return surrogate_infer(d_models, E, d_x, d_K_base, B, d_lo, d_hi, tau, emax, d_K_out, d_flags, d_spread, Km,
                            ctx->work, (hipStream_t)stream);
 }
 

@@ -98,7 +98,7 @@ int surrogate_train_step(void *model, float *adam, const float *x, const double 
                          hipStream_t s);
 int surrogate_refresh_bf16(void *model, hipStream_t s);
 int surrogate_infer(const void *models, int32_t E, const float *x, const double *Kb, int64_t B,
-                    const float *lo, const float *hi, double tau, double *K_out, uint8_t *flags,
+                    const float *lo, const float *hi, double tau, double emax, double *K_out, uint8_t *flags,
                     double *spread, double *K_members, void *work, hipStream_t s);
 
 int launch_mark_status(int32_t *status, const int32_t *list, int64_t count, int32_t bits, hipStream_t s);

@@ -379,8 +379,13 @@ __global__ void k_adam(float *p, float *m, float *v, const float *g, int64_t cou
 }
 
 // Ensemble mean, relative spread and the fallback flag.
-__global__ void k_gate(const double *Km, int E, int64_t B, const float *x, const float *lo, const float *hi,
-                       double tau, double *K_out, uint8_t *flag, double *spread_out) {
+// Ensemble mean, spread and gate.  A patch is flagged when a feature lies
+// outside [lo, hi], when the largest member deviation from the mean exceeds
+// tau (relative Frobenius), or when the predicted enhancement
+// |K_mean - K_b|_F / |K_b|_F exceeds emax.
+__global__ void k_gate(const double *Km, int E, int64_t B, const float *x, const double *Kb, const float *lo,
+                       const float *hi, double tau, double emax, double *K_out, uint8_t *flag,
+                       double *spread_out) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= B) return;
     double m[3] = {0.0, 0.0, 0.0};
@@ -400,8 +405,12 @@ __global__ void k_gate(const double *Km, int E, int64_t B, const float *x, const
         const float v = x[t * SHMM_SURR_IN + c];
         if (!(v >= lo[c] && v <= hi[c])) out = true;
     }
+    const double *kb = Kb + 3 * t;
+    const double d0 = m[0] - kb[0], d1 = m[1] - kb[1], d2 = m[2] - kb[2];
+    const double enh = sqrt(d0 * d0 + 2.0 * d1 * d1 + d2 * d2) /
+                       sqrt(kb[0] * kb[0] + 2.0 * kb[1] * kb[1] + kb[2] * kb[2]);
     for (int q = 0; q < 3; ++q) K_out[3 * t + q] = m[q];
-    flag[t] = (uint8_t)((sp > tau || out || !(fm > 0.0)) ? 1 : 0);
+    flag[t] = (uint8_t)((sp > tau || out || !(fm > 0.0) || !(enh <= emax)) ? 1 : 0);
     if (spread_out) spread_out[t] = sp;
 }
 
@@ -628,7 +637,7 @@ int surrogate_refresh_bf16(void *model, hipStream_t s) {
 }
 
 int surrogate_infer(const void *models, int32_t E, const float *x, const double *Kb, int64_t B,
-                    const float *lo, const float *hi, double tau, double *K_out, uint8_t *flags,
+                    const float *lo, const float *hi, double tau, double emax, double *K_out, uint8_t *flags,
                     double *spread, double *K_members, void *work, hipStream_t s) {
     const NetWork w = carve(work, B);
     double *Km = K_members;
@@ -640,8 +649,8 @@ int surrogate_infer(const void *models, int32_t E, const float *x, const double 
                            Km + (size_t)e * B * 3, (const double *)nullptr, (float *)nullptr, (double *)nullptr);
         SHMM_HIP_CHECK(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_gate, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, (const double *)Km, E, B, x, lo,
-                       hi, tau, K_out, flags, spread);
+    hipLaunchKernelGGL(k_gate, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, (const double *)Km, E, B, x, Kb,
+                       lo, hi, tau, emax, K_out, flags, spread);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
 }

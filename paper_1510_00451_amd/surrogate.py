@@ -151,16 +151,16 @@ def train(ens: Ensemble, data: Dataset, steps: int, batch: int, lr0: float = 1e-
     return history
 
 
-def infer(ens: Ensemble, x, Kb, lo, hi, tau: float):
-    """(K_mean [B][3], flags [B] uint8, spread [B]) on the device (tau may be
-    huge to gate on the feature range alone)."""
+def infer(ens: Ensemble, x, Kb, lo, hi, tau: float, emax: float = math.inf):
+    """(K_mean [B][3], flags [B] uint8, spread [B]) on the device (tau and emax
+    may be infinite to gate on the feature range alone)."""
     torch = ens.torch
     B = x.shape[0]
     K = torch.empty(B, 3, dtype=torch.float64, device="cuda")
     flags = torch.empty(B, dtype=torch.uint8, device="cuda")
     spread = torch.empty(B, dtype=torch.float64, device="cuda")
     ens.ctx.shmm_surrogate_infer(ens.buf.data_ptr(), ens.E, x.data_ptr(), Kb.data_ptr(), B, lo.data_ptr(),
-                                 hi.data_ptr(), tau, K.data_ptr(), flags.data_ptr(), spread.data_ptr(), 0,
+                                 hi.data_ptr(), tau, emax, K.data_ptr(), flags.data_ptr(), spread.data_ptr(), 0,
                                  torch.cuda.current_stream().cuda_stream)
     return K, flags, spread
 
@@ -240,7 +240,7 @@ class IsotropicPhase:
                                          H.status.data_ptr(), s)
         return H.K_solve[self.first:self.first + self.count]
 
-    def surrogate(self, ens: "Ensemble", lo, hi, tau: float):
+    def surrogate(self, ens: "Ensemble", lo, hi, tau: float, emax: float = math.inf):
         """Surrogate-with-fallback form: features, ensemble estimate and gate,
         plain solves of the flagged patches; returns K [count][3] (device).
         Synchronises once (the fallback reads the flags)."""
@@ -249,7 +249,7 @@ class IsotropicPhase:
         self.features()
         sl = self.K[self.first:self.first + self.count]
         H.ctx.shmm_surrogate_infer(ens.buf.data_ptr(), ens.E, self.x.data_ptr(), self.K_base().data_ptr(),
-                                   self.count, lo.data_ptr(), hi.data_ptr(), tau, sl.data_ptr(),
+                                   self.count, lo.data_ptr(), hi.data_ptr(), tau, emax, sl.data_ptr(),
                                    self.flags.data_ptr(), self.spread.data_ptr(), 0, s)
         H.ctx.shmm_fallback_solve(self.first, self.count, self.flags.data_ptr(), H.vx.data_ptr(),
                                   H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(),
@@ -306,17 +306,27 @@ def gate_range(data: Dataset, margin: float = 0.1):
     return lo - margin * w, hi + margin * w
 
 
-def calibrate_tau(ens: Ensemble, held: Dataset, lo, hi, target: float = 0.01, quantile: float = 0.99,
-                  grid=(5e-4, 1e-3, 2e-3, 3e-3, 5e-3, 7.5e-3, 1e-2, 1.5e-2, 2e-2, 3e-2)):
-    """Largest ensemble-spread threshold whose accepted held-out estimates keep
-    the `quantile` of the relative Frobenius error within `target`."""
-    K, flags, spread = infer(ens, held.x, held.Kb, lo, hi, 1e300)
-    err = relative_frobenius(K.cpu().numpy(), held.K.cpu().numpy())
+def calibrate_gate(ens: Ensemble, held: Dataset, lo, hi, target: float = 0.01, quantile: float = 0.99,
+                   taus=(5e-4, 1e-3, 1.5e-3, 2e-3, 2.5e-3, 3e-3, 4e-3, 5e-3, 6e-3, 7.5e-3, 1e-2, 1.5e-2,
+                         2e-2, 3e-2),
+                   emaxes=(0.01, 0.02, 0.05, 0.1, 0.2, 0.5, 1.0, 2.0, 5.0, math.inf)):
+    """Spread threshold tau and enhancement limit emax of the gate: the pair
+    that accepts the most held-out patches while the `quantile` of their
+    relative Frobenius error stays within `target`.  Ties go to the larger
+    thresholds.  Returns (tau, emax, accepted fraction)."""
+    K, flags, spread = infer(ens, held.x, held.Kb, lo, hi, math.inf, math.inf)
+    Kn, Kt, Kb = K.cpu().numpy(), held.K.cpu().numpy(), held.Kb.cpu().numpy()
+    err = relative_frobenius(Kn, Kt)
+    enh = relative_frobenius(Kn, Kb)
     spread = spread.cpu().numpy()
-    out_of_range = flags.cpu().numpy().astype(bool)
-    best = grid[0]
-    for tau in grid:
-        acc = (spread <= tau) & ~out_of_range
-        if acc.any() and np.quantile(err[acc], quantile) <= target:
-            best = tau
+    inside = ~flags.cpu().numpy().astype(bool)
+    best = (taus[0], emaxes[0], -1.0)
+    for tau in taus:
+        for emax in emaxes:
+            acc = inside & (spread <= tau) & (enh <= emax)
+            if not acc.any() or np.quantile(err[acc], quantile) > target:
+                continue
+            frac = float(acc.mean())
+            if frac >= best[2]:
+                best = (tau, emax, frac)
     return best

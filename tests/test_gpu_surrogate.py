@@ -119,17 +119,22 @@ def test_inference_and_gate_parity(torch):
     dhi = torch.tensor(hi, device="cuda")
     ref_members = np.stack([OS.head(OS.forward(n, x, bf16_mode=True)[0], Kb) for n in nets])
     tau = float(np.median(OS.ensemble_gate(ref_members, x, lo, hi, 1.0)[2]))   # about half flagged
+    mean = ref_members.mean(axis=0)
+    fro = lambda a: np.sqrt(a[:, 0] ** 2 + 2 * a[:, 1] ** 2 + a[:, 2] ** 2)
+    enh = fro(mean - Kb) / fro(Kb)
+    emax = float(np.quantile(enh, 0.8))     # a fifth more flagged by the enhancement limit
     ctx.shmm_surrogate_infer(models.data_ptr(), 2, dx.data_ptr(), dKb.data_ptr(), B, dlo.data_ptr(),
-                             dhi.data_ptr(), tau, K.data_ptr(), flags.data_ptr(), spread.data_ptr(),
+                             dhi.data_ptr(), tau, emax, K.data_ptr(), flags.data_ptr(), spread.data_ptr(),
                              Km.data_ptr(), s)
     torch.cuda.synchronize()
     got_members = Km.cpu().numpy()
     rel = np.abs(got_members - ref_members).max(axis=2) / np.abs(ref_members).max(axis=2)
     assert rel.max() <= 2e-3, rel.max()
-    Kref, fref, sref = OS.ensemble_gate(ref_members, x, lo.astype(np.float64), hi.astype(np.float64), tau)
+    Kref, fref, sref = OS.ensemble_gate(ref_members, x, lo.astype(np.float64), hi.astype(np.float64), tau,
+                                        Kb, emax)
     np.testing.assert_allclose(K.cpu().numpy(), Kref, rtol=2e-3)
     g = flags.cpu().numpy().astype(bool)
-    near = np.abs(sref - tau) <= 5e-3 * tau
+    near = (np.abs(sref - tau) <= 5e-3 * tau) | (np.abs(enh - emax) <= 5e-3 * emax)
     assert np.array_equal(g[~near], fref[~near])
     assert 0 < g.sum() < B                   # both outcomes occur in this case
     ctx.close()
@@ -260,9 +265,9 @@ def test_surrogate_form_gates_and_falls_back(torch):
     assert ph.flags.cpu().numpy().all()
     assert np.array_equal(K_all, plain)
     ph.H.status.zero_()
-    K_none = ph.surrogate(ens, wide_lo, wide_hi, 1e300).cpu().numpy().copy()
+    K_none = ph.surrogate(ens, wide_lo, wide_hi, 1e300, 1e300).cpu().numpy().copy()
     assert not ph.flags.cpu().numpy().any()
-    K_ref, _, _ = GS.infer(ens, ph.x, ph.K_base(), wide_lo, wide_hi, 1e300)
+    K_ref, _, _ = GS.infer(ens, ph.x, ph.K_base(), wide_lo, wide_hi, 1e300, 1e300)
     assert np.array_equal(K_none, K_ref.cpu().numpy())
     assert not (ph.H.status.cpu().numpy() & 8).any()
     ctx.close()

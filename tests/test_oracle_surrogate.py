@@ -169,3 +169,14 @@ def test_gate_flags():
     assert list(flag) == [False, True] and spread[1] > 0.005
     K, flag, spread = S.ensemble_gate(Km, f2, np.zeros(2), np.ones(2), 0.05)
     assert list(flag) == [False, False]
+
+
+def test_gate_flags_large_enhancement():
+    """The enhancement limit: |K - K_b| / |K_b| above emax falls back."""
+    Kb = np.array([[1.0, 0.0, 1.0], [1.0, 0.0, 1.0]])
+    Km = np.array([[[1.05, 0.0, 1.05], [1.5, 0.0, 1.5]]] * 2)      # enhancements 0.05 and 0.5
+    f = np.full((2, 2), 0.5)
+    _, flag, _ = S.ensemble_gate(Km, f, np.zeros(2), np.ones(2), 0.01, Kb, 0.1)
+    assert list(flag) == [False, True]
+    _, flag, _ = S.ensemble_gate(Km, f, np.zeros(2), np.ones(2), 0.01, Kb, 1.0)
+    assert list(flag) == [False, False]
