@@ -87,7 +87,7 @@ def cpu_baseline(steps_sample: int = 10000, domains_sample: int = 32):
                       f"(both correctors, FP64), {el:.1f} s"}
 
 
-def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members: int = 4):
+def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members: int = 4, lattice: int = 16):
     """Learned surrogate against the plain local solve.
 
     Labels: plain-path solves of the finest-level patches of flows from the
@@ -102,8 +102,9 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
     from paper_1510_00451_amd import abi
     from paper_1510_00451_amd import surrogate as GS
     t0 = time.perf_counter()
-    batches = [[flowgen.config_batched_instance(100000 + i + j, n=128, lattice=16) for j in range(4)]
-               for i in range(0, flows_train, 4)]
+    per = max(1, 1024 // (lattice * lattice))          # about 1024 finest patches per batch
+    batches = ([flowgen.config_batched_instance(100000 + i + j, n=128, lattice=lattice)
+                for j in range(min(per, flows_train - i))] for i in range(0, flows_train, per))
     data = GS.labelled_set(batches, log=log)
     t_label = time.perf_counter() - t0
     held, train = GS.split(data, 0.1, seed=0)
@@ -156,7 +157,8 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
         "tau": tau, "emax": emax if math.isfinite(emax) else None, "held_out_accepted": round(held_acc, 4),
         "eval": f"{flows_eval} continuous-spectrum flows (kappa 1e-3, 1<=|k|<=512, |psi_k|~|k|^-7/3) x "
                 f"256 finest-level 128^2 patches, isotropic base; {n_est} estimates",
-        "train": {"labels": int(data.x.shape[0]), "flows": flows_train, "label_s": round(t_label, 1),
+        "train": {"labels": int(data.x.shape[0]), "flows": flows_train, "patches_per_flow": lattice * lattice,
+                  "label_s": round(t_label, 1),
                   "train_s": round(t_train, 2), "steps": steps, "batch": 4096, "members": members,
                   "final_loss": hist[-1] if hist else None},
     }
@@ -221,6 +223,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-flows", type=int, default=64)
     ap.add_argument("--surrogate-eval-flows", type=int, default=32)
+    ap.add_argument("--surrogate-steps", type=int, default=1500)
+    ap.add_argument("--surrogate-lattice", type=int, default=16)
     ap.add_argument("--no-continuous", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--uneven-instances", type=int, default=256)
@@ -332,7 +336,8 @@ def main():
         out["uneven_batch"] = uneven_leg(args.uneven_instances, args.uneven_window)
     if not args.no_surrogate:
         log("surrogate ...")
-        out["surrogate"] = surrogate_leg(args.surrogate_flows, args.surrogate_eval_flows)
+        out["surrogate"] = surrogate_leg(args.surrogate_flows, args.surrogate_eval_flows,
+                                         steps=args.surrogate_steps, lattice=args.surrogate_lattice)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline()
