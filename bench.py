@@ -120,6 +120,8 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
     hist = GS.train(ens, train, steps=steps, batch=4096, lr0=1e-3, seed=5, log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
+    member_losses = ens.prune(held)
+    log(f"surrogate: held-out member losses {member_losses}, {ens.E} kept")
     lo, hi = GS.gate_range(train, 0.1)
     tau, emax, held_acc = GS.calibrate_gate(ens, held, lo, hi)
     log(f"surrogate: {data.x.shape[0]} labels in {t_label:.1f} s, trained in {t_train:.1f} s, "
@@ -160,6 +162,7 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
         "train": {"labels": int(data.x.shape[0]), "flows": flows_train, "patches_per_flow": lattice * lattice,
                   "label_s": round(t_label, 1),
                   "train_s": round(t_train, 2), "steps": steps, "batch": 4096, "members": members,
+                  "members_kept": ens.E, "held_out_member_losses": [round(float(v), 6) for v in member_losses],
                   "final_loss": hist[-1] if hist else None},
     }
 

@@ -89,6 +89,35 @@ class Ensemble:
     def model_ptr(self, e: int) -> int:
         return self.buf.data_ptr() + e * abi.SURR_MODEL_BYTES
 
+    def member_losses(self, data: "Dataset") -> np.ndarray:
+        """Mean relative squared Frobenius error of every member on `data`."""
+        torch = self.torch
+        B = data.x.shape[0]
+        K = torch.empty(B, 3, dtype=torch.float64, device="cuda")
+        flags = torch.empty(B, dtype=torch.uint8, device="cuda")
+        Km = torch.empty(self.E, B, 3, dtype=torch.float64, device="cuda")
+        hi = torch.full((abi.SURR_IN,), math.inf, dtype=torch.float32, device="cuda")
+        lo = -hi
+        self.ctx.shmm_surrogate_infer(self.buf.data_ptr(), self.E, data.x.data_ptr(), data.Kb.data_ptr(), B,
+                                      lo.data_ptr(), hi.data_ptr(), math.inf, math.inf, K.data_ptr(),
+                                      flags.data_ptr(), 0, Km.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        Kt = data.K.cpu().numpy()
+        return np.array([float(np.mean(relative_frobenius(m, Kt) ** 2)) for m in Km.cpu().numpy()])
+
+    def prune(self, data: "Dataset", factor: float = 3.0) -> np.ndarray:
+        """Drop members whose loss on `data` exceeds `factor` times the best
+        member's (a member that failed to train would otherwise dominate the
+        ensemble spread).  Returns the losses of all members before pruning."""
+        losses = self.member_losses(data)
+        keep = [e for e in range(self.E) if losses[e] <= factor * losses.min()]
+        if len(keep) < self.E:
+            words = abi.SURR_MODEL_BYTES // 4
+            self.buf = self.torch.cat([self.buf[e * words:(e + 1) * words] for e in keep]).contiguous()
+            self.adam = self.adam[keep].contiguous()
+            self.loss = self.loss[keep].contiguous()
+            self.E = len(keep)
+        return losses
+
     def member_host(self, e: int) -> np.ndarray:
         return self.buf[e * (PARAM_FLOATS):(e + 1) * PARAM_FLOATS].cpu().numpy()
 

@@ -272,3 +272,30 @@ def test_surrogate_form_gates_and_falls_back(torch):
     assert not (ph.H.status.cpu().numpy() & 8).any()
     ctx.close()
     ph.close()
+
+
+def test_ensemble_prune_drops_a_member_that_failed(torch):
+    """Pruning keeps members within a factor of the best held-out loss: a member
+    with untrained weights is dropped, and the kept blocks are the originals."""
+    from paper_1510_00451_amd import abi
+    from paper_1510_00451_amd import surrogate as GS
+    rng = np.random.default_rng(12)
+    S = 1024
+    x = rng.standard_normal((S, 33))
+    Kb = np.tile([0.02, 0.0, 0.02], (S, 1))
+    Kt = Kb * (1.5 + 0.5 * np.tanh(x[:, :1]))
+    say("case prune")
+    ctx = abi.Context(0)
+    ens = GS.Ensemble(ctx, 3, np.zeros(33), np.ones(33), seed0=5)
+    data = GS.Dataset(torch.tensor(x, dtype=torch.float32, device="cuda"), torch.tensor(Kb, device="cuda"),
+                      torch.tensor(Kt, device="cuda"))
+    GS.train(ens, data, steps=200, batch=256, lr0=3e-3)
+    words = abi.SURR_MODEL_BYTES // 4
+    fresh = GS.Ensemble(ctx, 1, np.zeros(33), np.ones(33), seed0=99)
+    ens.buf[words:2 * words] = fresh.buf        # member 1 reverts to untrained weights
+    keep0, keep2 = ens.buf[:words].clone(), ens.buf[2 * words:].clone()
+    losses = ens.prune(data)
+    assert losses[1] > 3 * min(losses[0], losses[2])
+    assert ens.E == 2
+    assert torch.equal(ens.buf[:words], keep0) and torch.equal(ens.buf[words:], keep2)
+    ctx.close()
