@@ -93,8 +93,9 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
     Labels: plain-path solves of the finest-level patches of flows from the
     uneven-batch generator (seeds 100000+, n = 128, 16 x 16 patches, isotropic
     base).  Training: the rescaling symmetry (two extra copies), an ensemble of
-    `members` networks, Adam at batch 4096.  The spread threshold is calibrated
-    on a held-out tenth of the labels.  Evaluation: finest-level patches of
+    `members` networks, Adam at batch 4096 on gradients clipped to norm 1.
+    Members that failed to train are dropped and the gate (spread threshold,
+    enhancement limit) is calibrated on a held-out tenth of the labels.  Evaluation: finest-level patches of
     continuous-spectrum flows (seeds 200000+), timed in both forms from the band
     filter on, with the inputs resident."""
     import torch
@@ -117,7 +118,7 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
     ens = GS.Ensemble(ctx, members, mu, sg, seed0=11)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    hist = GS.train(ens, train, steps=steps, batch=4096, lr0=1e-3, seed=5, log=log)
+    hist = GS.train(ens, train, steps=steps, batch=4096, lr0=1e-3, seed=5, log=log, clip=1.0)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     member_losses = ens.prune(held)
@@ -161,7 +162,7 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
                 f"256 finest-level 128^2 patches, isotropic base; {n_est} estimates",
         "train": {"labels": int(data.x.shape[0]), "flows": flows_train, "patches_per_flow": lattice * lattice,
                   "label_s": round(t_label, 1),
-                  "train_s": round(t_train, 2), "steps": steps, "batch": 4096, "members": members,
+                  "train_s": round(t_train, 2), "steps": steps, "batch": 4096, "clip": 1.0, "members": members,
                   "members_kept": ens.E, "held_out_member_losses": [round(float(v), 6) for v in member_losses],
                   "final_loss": hist[-1] if hist else None},
     }

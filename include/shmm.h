@@ -291,14 +291,16 @@ int shmm_surrogate_refresh(shmm_ctx *ctx, void *d_model, void *stream);
 
 /* One training step of one model at batch B: forward, loss
  * mean_b |K_hat - K_true|_F^2 / |K_true|_F^2 (written to d_loss[0], FP64),
- * backward, and an Adam step (beta 0.9 / 0.999, eps 1e-8, step t >= 1 for the
- * bias correction, learning rate lr) on the FP32 params; refreshes the bf16
- * copy.  d_adam holds m then v, 2 * SHMM_SURR_PARAMS_PADDED floats (zero at
- * t = 1).  d_x [B][33], d_K_base and d_K_true [B][3].  d_grad (optional,
- * SHMM_SURR_PARAMS floats) receives the gradient of this step. */
+ * backward, the global gradient norm (written to d_loss[1]; the gradient is
+ * scaled by min(1, clip / norm) when clip > 0), and an Adam step (beta 0.9 /
+ * 0.999, eps 1e-8, step t >= 1 for the bias correction, learning rate lr) on
+ * the FP32 params; refreshes the bf16 copy.  d_adam holds m then v,
+ * 2 * SHMM_SURR_PARAMS_PADDED floats (zero at t = 1).  d_x [B][33], d_K_base
+ * and d_K_true [B][3], d_loss [2].  d_grad (optional, SHMM_SURR_PARAMS floats)
+ * receives the gradient of this step before clipping. */
 int shmm_surrogate_train_step(shmm_ctx *ctx, void *d_model, float *d_adam, const float *d_x,
                               const double *d_K_base, const double *d_K_true, int64_t B, float lr,
-                              int32_t t, double *d_loss, float *d_grad, void *stream);
+                              float clip, int32_t t, double *d_loss, float *d_grad, void *stream);
 
 /* Ensemble inference with the fallback gate: E members at d_models; the
  * estimate is the member mean; a patch is flagged (d_flags[b] = 1) when a

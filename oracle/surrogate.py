@@ -230,8 +230,14 @@ class Adam:
     m: Optional[List[np.ndarray]] = None
     v: Optional[List[np.ndarray]] = None
 
-    def step(self, params: List[np.ndarray], grads: List[np.ndarray], lr: Optional[float] = None):
-        """One Adam update with bias correction (Kingma & Ba), in place."""
+    def step(self, params: List[np.ndarray], grads: List[np.ndarray], lr: Optional[float] = None,
+             clip: Optional[float] = None):
+        """One Adam update with bias correction (Kingma & Ba), in place, on the
+        gradients scaled to global norm at most `clip` when given."""
+        if clip is not None and clip > 0:
+            norm = math.sqrt(sum(float(np.sum(g * g)) for g in grads))
+            if norm > clip:
+                grads = [g * (clip / norm) for g in grads]
         if self.m is None:
             self.m = [np.zeros_like(p) for p in params]
             self.v = [np.zeros_like(p) for p in params]

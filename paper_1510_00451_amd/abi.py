@@ -77,7 +77,7 @@ def lib() -> ctypes.CDLL:
             "shmm_ctx_tune": [P, i32, i32],
             "shmm_patch_features": [P, i64, i64, P, P, P, P, P],
             "shmm_surrogate_refresh": [P, P, P],
-            "shmm_surrogate_train_step": [P, P, P, P, P, P, i64, ctypes.c_float, i32, P, P, P],
+            "shmm_surrogate_train_step": [P, P, P, P, P, P, i64, ctypes.c_float, ctypes.c_float, i32, P, P, P],
             "shmm_surrogate_infer": [P, P, i32, P, P, i64, P, P, f64, f64, P, P, P, P, P],
             "shmm_fallback_solve": [P, i64, i64, P, P, P, P, P, P, P, P, P, P],
         }
@@ -224,10 +224,10 @@ class Context:
     def shmm_surrogate_refresh(self, d_model, stream=0):
         check(lib().shmm_surrogate_refresh(self.h, d_model, stream), "shmm_surrogate_refresh")
 
-    def shmm_surrogate_train_step(self, d_model, d_adam, d_x, d_K_base, d_K_true, B, lr, t, d_loss,
+    def shmm_surrogate_train_step(self, d_model, d_adam, d_x, d_K_base, d_K_true, B, lr, clip, t, d_loss,
                                   d_grad=0, stream=0):
         check(lib().shmm_surrogate_train_step(self.h, d_model, d_adam, d_x, d_K_base, d_K_true, int(B),
-                                              float(lr), int(t), d_loss, d_grad or None, stream),
+                                              float(lr), float(clip), int(t), d_loss, d_grad or None, stream),
               "shmm_surrogate_train_step")
 
     def shmm_surrogate_infer(self, d_models, E, d_x, d_K_base, B, d_lo, d_hi, tau, emax, d_K_out, d_flags,

@@ -671,15 +671,15 @@ int shmm_surrogate_refresh(shmm_ctx *ctx, void *d_model, void *stream) {
 
 int shmm_surrogate_train_step(shmm_ctx *ctx, void *d_model, float *d_adam, const float *d_x,
                               const double *d_K_base, const double *d_K_true, int64_t B, float lr,
-                              int32_t t, double *d_loss, float *d_grad, void *stream) {
+                              float clip, int32_t t, double *d_loss, float *d_grad, void *stream) {
     if (!ctx || !d_model || !d_adam || !d_x || !d_K_base || !d_K_true || !d_loss || B <= 0 || t < 1)
         return SHMM_EINVAL;
     if (B > (1 << 24)) return SHMM_ERANGE;
     int rc = set_device(ctx);
     if (rc) return rc;
     if ((rc = ctx->ensure_work(surrogate_net_workspace(B)))) return rc;
-    return surrogate_train_step(d_model, d_adam, d_x, d_K_base, d_K_true, B, lr, t, d_loss, d_grad, ctx->work,
-                                (hipStream_t)stream);
+    return surrogate_train_step(d_model, d_adam, d_x, d_K_base, d_K_true, B, lr, clip, t, d_loss, d_grad,
+                                ctx->work, (hipStream_t)stream);
 }
 
 int shmm_surrogate_infer(shmm_ctx *ctx, const void *d_models, int32_t E, const float *d_x,

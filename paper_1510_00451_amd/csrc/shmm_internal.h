@@ -94,7 +94,7 @@ int launch_patch_features(const shmm_domain *d_dom, const int32_t *d_list, int32
                           hipStream_t s);
 size_t surrogate_net_workspace(int64_t B);
 int surrogate_train_step(void *model, float *adam, const float *x, const double *Kb, const double *Kt,
-                         int64_t B, float lr, int32_t t, double *loss, float *grad_out, void *work,
+                         int64_t B, float lr, float clip, int32_t t, double *loss, float *grad_out, void *work,
                          hipStream_t s);
 int surrogate_refresh_bf16(void *model, hipStream_t s);
 int surrogate_infer(const void *models, int32_t E, const float *x, const double *Kb, int64_t B,

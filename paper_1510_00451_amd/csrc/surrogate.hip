@@ -363,12 +363,43 @@ __global__ void k_loss_total(const double *part, int parts, int64_t B, double *l
     }
 }
 
-// Adam (Kingma & Ba) with bias correction on the FP32 masters; refreshes BF16 copies.
-__global__ void k_adam(float *p, float *m, float *v, const float *g, int64_t count, float lr, float c1,
-                       float c2, uint16_t *ph) {
+constexpr int kNormParts = 128;
+
+// Global gradient norm, fixed order: workgroup b sums the squares of entries
+// b, b + 128 * 256 ... per thread, then a tree; k_norm_final adds the parts
+// in order (FP64), writes the norm to loss[1] and the clipping scale
+// min(1, clip / norm) (1 when clip <= 0).
+__global__ __launch_bounds__(256) void k_sqsum(const float *g, int64_t count, float *part) {
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        s += g[i] * g[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_norm_final(const float *part, int parts, float clip, double *loss, float *scale) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < parts; ++i) s += (double)part[i];
+    const double norm = sqrt(s);
+    loss[1] = norm;
+    *scale = (clip > 0.0f && norm > (double)clip) ? (float)((double)clip / norm) : 1.0f;
+}
+
+// Adam (Kingma & Ba) with bias correction on the FP32 masters, on the
+// gradient times the clipping scale; refreshes BF16 copies.
+__global__ void k_adam(float *p, float *m, float *v, const float *g, const float *scale, int64_t count, float lr,
+                       float c1, float c2, uint16_t *ph) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= count) return;
-    const float gt = g[t];
+    const float gt = g[t] * scale[0];
     const float mt = 0.9f * m[t] + 0.1f * gt;
     const float vt = 0.999f * v[t] + 0.001f * gt * gt;
     m[t] = mt;
@@ -449,6 +480,7 @@ struct NetWork {
     float *grad;         // [SHMM_SURR_PARAMS_PADDED]
     float *split;        // split-K slices [kSplitSlices][256][256]
     float *colpart;      // column-sum slices [kColSlices][256]
+    float *gpart;        // gradient-norm parts [kNormParts], then the clipping scale
 };
 
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
@@ -464,6 +496,7 @@ size_t surrogate_net_workspace(int64_t B) {
     s += align256((size_t)SHMM_SURR_PARAMS_PADDED * 4);
     s += align256((size_t)kSplitSlices * SHMM_SURR_WIDTH * SHMM_SURR_WIDTH * 4);
     s += align256((size_t)kColSlices * SHMM_SURR_WIDTH * 4);
+    s += align256((size_t)(kNormParts + 1) * 4);
     return s;
 }
 
@@ -487,6 +520,7 @@ static NetWork carve(void *work, int64_t B) {
     w.grad = (float *)take((size_t)SHMM_SURR_PARAMS_PADDED * 4);
     w.split = (float *)take((size_t)kSplitSlices * SHMM_SURR_WIDTH * SHMM_SURR_WIDTH * 4);
     w.colpart = (float *)take((size_t)kColSlices * SHMM_SURR_WIDTH * 4);
+    w.gpart = (float *)take((size_t)(kNormParts + 1) * 4);
     return w;
 }
 
@@ -546,7 +580,7 @@ static int net_forward(const Model &m, const float *x, int64_t B, const NetWork 
 }
 
 int surrogate_train_step(void *model, float *adam, const float *x, const double *Kb, const double *Kt,
-                         int64_t B, float lr, int32_t t, double *loss, float *grad_out, void *work,
+                         int64_t B, float lr, float clip, int32_t t, double *loss, float *grad_out, void *work,
                          hipStream_t s) {
     const Layout L = layout();
     const Model m = model_at(model);
@@ -617,10 +651,16 @@ int surrogate_train_step(void *model, float *adam, const float *x, const double 
         dz = next;
         next = (next == w.dz) ? w.dz2 : w.dz;
     }
+    hipLaunchKernelGGL(k_sqsum, dim3(kNormParts), dim3(256), 0, s, (const float *)w.grad, (int64_t)SHMM_SURR_PARAMS,
+                       w.gpart);
+    SHMM_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, s, (const float *)w.gpart, kNormParts, clip, loss,
+                       w.gpart + kNormParts);
+    SHMM_HIP_CHECK(hipGetLastError());
     const float c1 = 1.0f - powf(0.9f, (float)t), c2 = 1.0f - powf(0.999f, (float)t);
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((SHMM_SURR_PARAMS + 255) / 256)), dim3(256), 0, s, m.p, adam,
-                       adam + SHMM_SURR_PARAMS_PADDED, (const float *)w.grad, (int64_t)SHMM_SURR_PARAMS, lr, c1,
-                       c2, m.ph);
+                       adam + SHMM_SURR_PARAMS_PADDED, (const float *)w.grad, (const float *)(w.gpart + kNormParts),
+                       (int64_t)SHMM_SURR_PARAMS, lr, c1, c2, m.ph);
     SHMM_HIP_CHECK(hipGetLastError());
     if (grad_out)
         SHMM_HIP_CHECK(hipMemcpyAsync(grad_out, w.grad, SHMM_SURR_PARAMS * sizeof(float),

@@ -80,7 +80,7 @@ class Ensemble:
         host = np.concatenate([pack_params(*init_params(seed0 + e), mu, sigma) for e in range(E)])
         self.buf = torch.from_numpy(host).to("cuda")
         self.adam = torch.zeros(E, 2 * abi.SURR_PARAMS_PADDED, dtype=torch.float32, device="cuda")
-        self.loss = torch.zeros(E, dtype=torch.float64, device="cuda")
+        self.loss = torch.zeros(E, 2, dtype=torch.float64, device="cuda")   # loss, gradient norm
         self.step = 0
         s = torch.cuda.current_stream().cuda_stream
         for e in range(E):
@@ -147,9 +147,10 @@ class Dataset:
 
 
 def train(ens: Ensemble, data: Dataset, steps: int, batch: int, lr0: float = 1e-3, seed: int = 0,
-          log=None) -> List[float]:
+          log=None, clip: float = 0.0) -> List[float]:
     """Adam with a linear warm-up over the first 5% of the steps, then a cosine
-    decay; each member draws its own batch order."""
+    decay, on gradients clipped to global norm `clip` (0: no clipping); each
+    member draws its own batch order."""
     torch = ens.torch
     S = data.x.shape[0]
     rng = np.random.default_rng(seed)
@@ -171,12 +172,12 @@ def train(ens: Ensemble, data: Dataset, steps: int, batch: int, lr0: float = 1e-
             torch.index_select(data.Kb, 0, idx, out=kb)
             torch.index_select(data.K, 0, idx, out=kt)
             ens.ctx.shmm_surrogate_train_step(ens.model_ptr(e), ens.adam[e].data_ptr(), xb.data_ptr(),
-                                              kb.data_ptr(), kt.data_ptr(), batch, lr, it + 1,
-                                              ens.loss[e:e + 1].data_ptr(), 0, s)
+                                              kb.data_ptr(), kt.data_ptr(), batch, lr, clip, it + 1,
+                                              ens.loss[e].data_ptr(), 0, s)
         if log is not None and (it % max(1, steps // 10) == 0 or it == steps - 1):
             l = ens.loss.cpu().numpy()
-            history.append(float(l.mean()))
-            log(f"surrogate step {it}: loss {l}")
+            history.append(float(l[:, 0].mean()))
+            log(f"surrogate step {it}: loss {l[:, 0]} gradient norm {l[:, 1]}")
     return history
 
 

@@ -154,19 +154,19 @@ def test_train_step_parity(torch):
     s = torch.cuda.current_stream().cuda_stream
     ctx.shmm_surrogate_refresh(model.data_ptr(), s)
     adam = torch.zeros(2 * abi.SURR_PARAMS_PADDED, dtype=torch.float32, device="cuda")
-    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    loss = torch.zeros(2, dtype=torch.float64, device="cuda")
     grad = torch.zeros(abi.SURR_PARAMS, dtype=torch.float32, device="cuda")
     dx = torch.tensor(x, dtype=torch.float32, device="cuda")
     dKb = torch.tensor(Kb, device="cuda")
     dKt = torch.tensor(Kt, device="cuda")
     lr = 1e-3
     ctx.shmm_surrogate_train_step(model.data_ptr(), adam.data_ptr(), dx.data_ptr(), dKb.data_ptr(),
-                                  dKt.data_ptr(), B, lr, 1, loss.data_ptr(), grad.data_ptr(), s)
+                                  dKt.data_ptr(), B, lr, 0.0, 1, loss.data_ptr(), grad.data_ptr(), s)
     torch.cuda.synchronize()
     o, cache = OS.forward(net, x, bf16_mode=True)
     l_ref, go = OS.loss_and_grad_o(o, Kb, Kt)
     gW, gb = OS.backward(net, cache, go, bf16_mode=True)
-    assert abs(loss.item() - l_ref) <= 1e-4 * l_ref
+    assert abs(loss.cpu().numpy()[0] - l_ref) <= 1e-4 * l_ref
     g = grad.cpu().numpy().astype(np.float64)
     off = 0
     for l in range(4):
@@ -183,6 +183,33 @@ def test_train_step_parity(torch):
     big = np.abs(gref) > 1e-3 * np.abs(gref).max()
     expect = flat_old - lr * gref / (np.abs(gref) + 1e-8)
     assert np.max(np.abs(flat_new - expect)[big]) <= 1e-6
+    assert abs(loss.cpu().numpy()[1] - np.linalg.norm(gref)) <= 1e-2 * np.linalg.norm(gref)
+    # second step with clipping active: the oracle's Adam from the device's
+    # moments and parameters, on its own gradient at those parameters
+    net2 = net.copy()
+    net2.W, net2.b = [w.copy() for w in W1], [v.copy() for v in b1]
+    mv = adam.cpu().numpy().astype(np.float64)
+    P = abi.SURR_PARAMS_PADDED
+    o2, cache2 = OS.forward(net2, x, bf16_mode=True)
+    _, go2 = OS.loss_and_grad_o(o2, Kb, Kt)
+    gW2, gb2 = OS.backward(net2, cache2, go2, bf16_mode=True)
+    g2 = np.concatenate([np.concatenate([gW2[l].reshape(-1), gb2[l]]) for l in range(4)])
+    clip = 0.3 * float(np.linalg.norm(g2))
+    ctx.shmm_surrogate_train_step(model.data_ptr(), adam.data_ptr(), dx.data_ptr(), dKb.data_ptr(),
+                                  dKt.data_ptr(), B, lr, clip, 2, loss.data_ptr(), 0, s)
+    torch.cuda.synchronize()
+    ad = OS.Adam(lr=lr)
+    ad.t = 1
+    ad.m = [mv[:abi.SURR_PARAMS].copy()]
+    ad.v = [mv[P:P + abi.SURR_PARAMS].copy()]
+    p2 = [flat_new.copy()]
+    ad.step(p2, [g2], clip=clip)
+    W3, b3, _, _ = GS.unpack_params(model.cpu().numpy())
+    flat3 = np.concatenate([np.concatenate([w.reshape(-1), v]) for w, v in zip(W3, b3)])
+    moved = np.abs(p2[0] - flat_new) > 0.3 * lr
+    assert moved.sum() > 1000
+    assert np.max(np.abs(flat3 - p2[0])[moved]) <= 0.05 * lr
+    assert abs(loss.cpu().numpy()[1] - np.linalg.norm(g2)) <= 1e-2 * np.linalg.norm(g2)
     ctx.close()
 
 
@@ -237,7 +264,7 @@ def test_training_reduces_loss(torch):
     ens = GS.Ensemble(ctx, 1, np.zeros(33), np.ones(33), seed0=3)
     data = GS.Dataset(torch.tensor(x, dtype=torch.float32, device="cuda"), torch.tensor(Kb, device="cuda"),
                       torch.tensor(Kt, device="cuda"))
-    hist = GS.train(ens, data, steps=300, batch=256, lr0=3e-3, log=lambda *a: None)
+    hist = GS.train(ens, data, steps=300, batch=256, lr0=3e-3, log=lambda *a: None, clip=1.0)
     K, flags, spread = GS.infer(ens, data.x, data.Kb, torch.full((33,), -1e9, device="cuda"),
                                 torch.full((33,), 1e9, device="cuda"), 1.0)
     torch.cuda.synchronize()

@@ -180,3 +180,22 @@ def test_gate_flags_large_enhancement():
     assert list(flag) == [False, True]
     _, flag, _ = S.ensemble_gate(Km, f, np.zeros(2), np.ones(2), 0.01, Kb, 1.0)
     assert list(flag) == [False, False]
+
+
+def test_adam_clipping_matches_torch():
+    """Global-norm clipping before Adam equals torch's clip_grad_norm_ + Adam
+    (torch adds 1e-6 to the norm, hence the tolerance)."""
+    rng = np.random.default_rng(6)
+    p = [rng.standard_normal((5, 3)), rng.standard_normal(4)]
+    pt = [torch.tensor(a.copy(), requires_grad=True) for a in p]
+    opt = torch.optim.Adam(pt, lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    ad = S.Adam(lr=1e-2)
+    for it in range(5):
+        g = [rng.standard_normal(a.shape) * (10.0 if it % 2 else 0.1) for a in p]
+        ad.step(p, g, clip=1.0)
+        for t, gg in zip(pt, g):
+            t.grad = torch.tensor(gg)
+        torch.nn.utils.clip_grad_norm_(pt, 1.0)
+        opt.step()
+    for a, t in zip(p, pt):
+        np.testing.assert_allclose(a, t.detach().numpy(), rtol=1e-6, atol=1e-12)
