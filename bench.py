@@ -32,10 +32,11 @@ FLOP_PER_POINT_STEP = 156
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (256 CU, 2.4 GHz)
 # HBM bytes per full-phase launch of k_solve_resident_e<128, 32, 8> on this
 # workload, from rocprofv3 FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0), the scale
-# factors read off a 1 GiB device copy.  Valid only for the kernel source they
-# were taken on (first 16 hex digits of its SHA-256); otherwise reported null.
-SOLVE_TRAFFIC = {"source_sha256": "fda87b5633ab9c6a", "variant": 5,
-                 "bytes_per_launch": (2 * 18586.2 + 20992.0) * 1024}
+# factors read off a 1 GiB device copy.  Valid only for the kernel code they
+# were taken on (first 16 hex digits of the SHA-256 of solve.hip without its
+# comments and blank lines); otherwise reported null.
+SOLVE_TRAFFIC = {"code_sha256": "db7ae9dcee86758f", "variant": 5,
+                 "bytes_per_launch": (2 * 18586.5 + 20992.0) * 1024}
 SOLVE_KERNELS_128 = {0: "k_solve_resident<128,32>", 1: "k_solve_rows<128,2,16>", 2: "k_solve_rows<128,2,8>",
                      3: "k_solve_resident_e<128,32>", 4: "k_solve_resident_e<128,16>",
                      5: "k_solve_resident_e<128,32,8>", 6: "k_solve_resident_e<128,32,16>"}
@@ -44,8 +45,10 @@ SOLVE_KERNELS_128 = {0: "k_solve_resident<128,32>", 1: "k_solve_rows<128,2,16>",
 def solve_traffic():
     import hashlib
     path = os.path.join(ROOT, "paper_1510_00451_amd", "csrc", "solve.hip")
-    h = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
-    return SOLVE_TRAFFIC["bytes_per_launch"] if h == SOLVE_TRAFFIC["source_sha256"] else None
+    lines = open(path).read().split("\n")
+    code = "\n".join(l.split("//")[0].rstrip() for l in lines if l.split("//")[0].strip())
+    h = hashlib.sha256(code.encode()).hexdigest()[:16]
+    return SOLVE_TRAFFIC["bytes_per_launch"] if h == SOLVE_TRAFFIC["code_sha256"] else None
 
 
 def log(*a):
