@@ -525,3 +525,27 @@ def test_macro_diffusivity_of_a_resolved_shear_is_the_taylor_value():
         Km = oracle.macro_diffusivity(r, i)
         assert abs(Km[2] - 0.2053125) <= 1e-14 and abs(Km[0] - 0.01) <= 1e-16 and abs(Km[1]) <= 1e-16
         np.testing.assert_allclose(r.R[i], r.K_solve[i] + Km - r.K_base[i], rtol=1e-14, atol=1e-16)
+
+
+def test_one_level_hierarchy_is_the_direct_cell_problem():
+    """With a single level the band filter is the identity, so the hierarchy's
+    K is the discrete cell problem of the full flow on the whole domain,
+    solved directly (dense LU) from psi sampled at the grid nodes."""
+    n = 8
+    kmax = 3
+    ph = flowgen.random_power_spectrum(seed=4, radius=kmax, p=-2.0, amp=0.15)
+    p = flowgen.Problem(kappa=0.05, kmax=kmax, psi_hat=ph, thresh=[], n_cells=[n], n_global=[n],
+                        lattice=[1], dt_frac=0.5, delta=1e-12, name="one-level")
+    r = oracle.run_hierarchy(p)
+    h = 2 * np.pi / n
+    x = np.arange(n) * h
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    kk = np.arange(-kmax, kmax + 1)
+    psi = np.zeros((n, n))
+    for b, k2 in enumerate(kk):
+        for a, k1 in enumerate(kk):
+            psi += (ph[b, a] * np.exp(1j * (k1 * X + k2 * Y))).real
+    vx, vy, f1, f2 = oracle.staggered(psi, h)
+    K = oracle.cell_problem_dense(vx, vy, f1, f2, [0.05, 0.0, 0.05], h)
+    assert len(r.domains) == 1
+    np.testing.assert_allclose(r.K_total()[0], K, rtol=1e-9, atol=1e-13)
