@@ -19,8 +19,9 @@
 //   patch and to store the final state.  Two arithmetic forms: the split form
 //   above (k_solve_resident) and the coefficient form (k_solve_resident_e,
 //   the default), plus a row-per-wavefront variant (k_solve_rows).
-// * overlapped tiles (n = 256, k_solve_tiled): a few steps per launch on a
-//   tile plus a ring of redundant cells, state in workspace between launches.
+// * overlapped regions (n = 256): a few steps per launch on a square tile
+//   (k_solve_tiled) or a full-width band of rows (k_solve_band) plus a ring
+//   of redundant cells, state in workspace between launches.
 // * per-stage launches (k_solve_stage): any other size.
 #include <algorithm>
 
@@ -535,7 +536,9 @@ int launch_rows(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, 
 // lives in list-local workspace planes between launches, ping-ponged so no
 // workgroup overwrites cells another one still reads.  The stage arithmetic
 // is the coefficient-form resident stage; cells on the region's border see
-// clamped neighbours and lie outside the written tile.
+// clamped neighbours and lie outside the written tile.  A patch whose plan
+// has ended leaves both planes alone: k_solve_tiles_fini picks its last state
+// by the parity of the launches that advanced it.
 template <int TW, int HALO, int R, int FIELD>
 __device__ __forceinline__ void tiled_body(float *__restrict__ buf, const shmm_domain *__restrict__ dom,
                                            const int32_t *__restrict__ list, int n,
@@ -552,6 +555,7 @@ __device__ __forceinline__ void tiled_body(float *__restrict__ buf, const shmm_d
     const int64_t d = list[li];
     const shmm_domain D = dom[d];
     const int32_t lim = s_cap < D.nsteps ? s_cap : D.nsteps;
+    if (step0 >= lim) return;
     const int32_t s_end = step0 + HALO / 4 < lim ? step0 + HALO / 4 : lim;
     const int mask = n - 1;
 
@@ -629,16 +633,170 @@ __global__ __launch_bounds__((TW + 2 * HALO) * (TW + 2 * HALO) / R) void k_solve
                                    s_cap);
 }
 
-// Copy the list-local state planes back to the correctors.
-__global__ void k_solve_tiled_fini(const shmm_domain *__restrict__ dom, const int32_t *__restrict__ list, int n,
-                                   const float *__restrict__ ycur, float *__restrict__ w, int64_t cells_total,
-                                   int64_t list_cells) {
+// Full-width bands (n = 256): the same scheme with a region of whole rows,
+// TH rows of the patch plus a HALO-row ring above and below, so x stays
+// periodic inside the region and only the rows carry redundant work.  NN x
+// (TH + 2 HALO) cells with R-cell column strips, as in the resident kernel
+// (CL rows of compensation in LDS).  When TH does not divide NN the last band
+// is moved up to end at the last row; it then shares rows with the band
+// before it, and both write the same values there (a cell at least HALO rows
+// inside both regions goes through the same operations on the same inputs).
+template <int NN, int TH, int HALO, int R, int CL, int FIELD>
+__device__ __forceinline__ void band_body(float *__restrict__ buf, const shmm_domain *__restrict__ dom,
+                                          const int32_t *__restrict__ list, int li, int band,
+                                          const float *__restrict__ vx, const float *__restrict__ vy,
+                                          const double *__restrict__ Kb, const float *__restrict__ w_in,
+                                          const float *__restrict__ c_in, float *__restrict__ w_out,
+                                          float *__restrict__ c_out, int64_t list_cells, int32_t step0,
+                                          int32_t s_cap) {
+    constexpr int MASK = NN - 1;
+    constexpr int H = TH + 2 * HALO;
+    constexpr int PLANE = NN * H;
+    constexpr int T = PLANE / R;
+    const int64_t d = list[li];
+    const shmm_domain D = dom[d];
+    const int32_t lim = s_cap < D.nsteps ? s_cap : D.nsteps;
+    if (step0 >= lim) return;
+    const int32_t s_end = step0 + HALO / 4 < lim ? step0 + HALO / 4 : lim;
+    const int band_top = band * TH < NN - TH ? band * TH : NN - TH;
+
+    const int tid = threadIdx.x;
+    const int x = tid & MASK;
+    const int y0 = (tid / NN) * R;
+    const int offW = x == 0 ? MASK : -1;
+    const int offE = x == MASK ? -MASK : 1;
+    const int offS = y0 == 0 ? 0 : -NN;
+    const int offN = y0 + R == H ? (R - 1) * NN : R * NN;
+    SolveConsts k = solve_consts(D, Kb, d);
+    k.cc = uniform(k.cc);
+    k.cxy = uniform(k.cxy);
+    k.fh = uniform(k.fh);
+    const float two_cyy = uniform(2.0f * k.cyy);
+    const int xe = (x + 1) & MASK;
+    const int gy0 = band_top - HALO + y0;
+    const float *vxp = vx + D.offset, *vyp = vy + D.offset;
+    const int64_t ws = (int64_t)FIELD * list_cells + (int64_t)li * NN * NN;
+    const float *wp = w_in + ws, *cp = c_in + ws;
+    float *cl = buf + 2 * PLANE + tid;
+
+    float eE[R], eW[R], nb[R + 1], wv[R], comp[R], rr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = ((gy0 + r) & MASK) * NN;
+        eE[r] = k.cxx + k.a * vxp[row + xe];
+        eW[r] = k.cxx - k.a * vxp[row + x];
+        nb[r] = k.cyy + k.a * vyp[row + x];
+        wv[r] = wp[row + x];
+        if (r < CL) {
+            cl[r * T] = cp[row + x];
+            comp[r] = 0.0f;
+        } else {
+            comp[r] = cp[row + x];
+        }
+        rr[r] = 0.0f;
+    }
+    nb[R] = k.cyy + k.a * vyp[((gy0 + R) & MASK) * NN + x];
+    float *lo = buf + y0 * NN + x, *hi = lo + PLANE;
+#pragma unroll
+    for (int r = 0; r < R; ++r) lo[r * NN] = wv[r];
+    __syncthreads();
+    constexpr bool OP = R >= 32;
+    for (int32_t s = step0; s < s_end; ++s) {
+        rk_stage_e<NN, R, FIELD, 0, OP, CL>(lo, offW, offE, offS, offN, hi, k, two_cyy, 0.0f, eE, eW, nb, wv, comp,
+                                            rr, cl, T);
+        __syncthreads();
+        rk_stage_e<NN, R, FIELD, 1, OP, CL>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.25f, eE, eW, nb, wv, comp,
+                                            rr, cl, T);
+        __syncthreads();
+        rk_stage_e<NN, R, FIELD, 1, OP, CL>(lo, offW, offE, offS, offN, hi, k, two_cyy, 1.0f / 3.0f, eE, eW, nb, wv,
+                                            comp, rr, cl, T);
+        __syncthreads();
+        rk_stage_e<NN, R, FIELD, 2, OP, CL>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.5f, eE, eW, nb, wv, comp,
+                                            rr, cl, T);
+        __syncthreads();
+    }
+    // recompute the row addresses here rather than keep R of them live
+    // through the step loop
+    int gy = gy0, xs = x;
+    asm volatile("" : "+v"(gy), "+v"(xs));
+    float *wo = w_out + ws, *co = c_out + ws;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int yy = y0 + r;
+        if (yy < HALO || yy >= HALO + TH) continue;
+        const int at = ((gy + r) & MASK) * NN + xs;
+        wo[at] = wv[r];
+        co[at] = r < CL ? cl[r * T] : comp[r];
+    }
+}
+
+// One-dimensional grid, 2 * bands workgroups per patch (band-major, the two
+// correctors of a band side by side).  xcd_map: workgroup i runs on XCD
+// i mod 8 (round-robin dispatch), so patch 8 q + j takes the slots of XCD j
+// from 2 * bands * q on; a patch's bands and correctors then run together
+// on one XCD and share its L2 for the face velocities and the ring rows.
+// The grid is padded to a multiple of 8 patches; padding slots return.
+template <int NN, int TH>
+constexpr int band_count() { return (NN + TH - 1) / TH; }
+
+template <int NN, int TH, int HALO, int R, int CL>
+__global__ __launch_bounds__(NN *(TH + 2 * HALO) / R) void k_solve_band(
+    const shmm_domain *__restrict__ dom, const int32_t *__restrict__ list, int32_t count, int32_t xcd_map,
+    const float *__restrict__ vx, const float *__restrict__ vy, const double *__restrict__ Kb,
+    const float *__restrict__ w_in, const float *__restrict__ c_in, float *__restrict__ w_out,
+    float *__restrict__ c_out, int64_t list_cells, int32_t step0, int32_t s_cap) {
+    __shared__ float buf[2 * NN * (TH + 2 * HALO) + CL * (NN * (TH + 2 * HALO) / R)];
+    constexpr int PER = 2 * band_count<NN, TH>();
+    const int i = blockIdx.x;
+    int li, k;
+    if (xcd_map) {
+        const int slot = i >> 3;
+        li = (slot / PER) * 8 + (i & 7);
+        k = slot % PER;
+    } else {
+        li = i / PER;
+        k = i % PER;
+    }
+    if (li >= count) return;
+    if (k & 1)
+        band_body<NN, TH, HALO, R, CL, 1>(buf, dom, list, li, k >> 1, vx, vy, Kb, w_in, c_in, w_out, c_out,
+                                          list_cells, step0, s_cap);
+    else
+        band_body<NN, TH, HALO, R, CL, 0>(buf, dom, list, li, k >> 1, vx, vy, Kb, w_in, c_in, w_out, c_out,
+                                          list_cells, step0, s_cap);
+}
+
+template <int NN, int TH, int HALO, int R, int CL>
+int launch_band(const shmm_domain *d_dom, const int32_t *d_list, int32_t cn, const float *vx, const float *vy,
+                const double *Kb, const float *w_in, const float *c_in, float *w_out, float *c_out,
+                int64_t list_cells, int32_t step, int32_t s_end, hipStream_t s) {
+    constexpr int PER = 2 * band_count<NN, TH>();
+    // the XCD mapping once every XCD gets at least 8 patches
+    const int32_t xcd_map = cn >= 64 ? 1 : 0;
+    const int64_t wgs = xcd_map ? (int64_t)PER * 8 * ((cn + 7) / 8) : (int64_t)PER * cn;
+    hipLaunchKernelGGL((k_solve_band<NN, TH, HALO, R, CL>), dim3((unsigned)wgs), dim3(NN * (TH + 2 * HALO) / R), 0,
+                       s, d_dom, d_list, cn, xcd_map, vx, vy, Kb, w_in, c_in, w_out, c_out, list_cells, step, s_end);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
+
+// Copy each patch's last state back to its corrector.  The launches from
+// step_begin advanced a patch ceil((min(s_end, nsteps) - step_begin) / per)
+// times; an even count leaves its state in y0 (the plane the first launch
+// read), an odd count in y1.
+__global__ void k_solve_tiles_fini(const shmm_domain *__restrict__ dom, const int32_t *__restrict__ list, int n,
+                                   const float *__restrict__ y0, const float *__restrict__ y1,
+                                   float *__restrict__ w, int64_t cells_total, int64_t list_cells,
+                                   int32_t step_begin, int32_t s_end, int32_t per) {
     const int li = blockIdx.y >> 1;
     const int field = blockIdx.y & 1;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n * n) return;
     const shmm_domain D = dom[list[li]];
-    w[(int64_t)field * cells_total + D.offset + c] = ycur[(int64_t)field * list_cells + (int64_t)li * n * n + c];
+    const int32_t lim = s_end < D.nsteps ? s_end : D.nsteps;
+    const int32_t launches = lim > step_begin ? (lim - step_begin + per - 1) / per : 0;
+    const float *src = (launches & 1) ? y1 : y0;
+    w[(int64_t)field * cells_total + D.offset + c] = src[(int64_t)field * list_cells + (int64_t)li * n * n + c];
 }
 
 // Fallback for other patch sizes: one launch per RK stage, state in global
@@ -738,7 +896,7 @@ int launch_resident_e(const shmm_domain *d_dom, const int32_t *d_list, int32_t n
 
 bool local_solve_resident(int n) { return n == 8 || n == 16 || n == 32 || n == 64 || n == 128; }
 
-int local_solve_variants(int n) { return n == 64 ? 5 : n == 128 ? 7 : n == 256 ? 4 : 1; }
+int local_solve_variants(int n) { return n == 64 ? 5 : n == 128 ? 7 : n == 256 ? 6 : 1; }
 
 namespace {
 // Zero both corrector fields of the listed domains (one workgroup row per domain).
@@ -755,10 +913,13 @@ __global__ __launch_bounds__(256) void k_zero_fields(const shmm_domain *dom, con
 
 int launch_zero_fields(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n, float *d_w,
                        int64_t cells, hipStream_t s) {
-    if (nlist <= 0) return SHMM_OK;
     const unsigned bx = (unsigned)std::min<int64_t>(16, ((int64_t)n * n + 255) / 256);
-    hipLaunchKernelGGL(k_zero_fields, dim3(bx, (unsigned)nlist), dim3(256), 0, s, d_dom, d_list, n, d_w, cells);
-    SHMM_HIP_CHECK(hipGetLastError());
+    for (int32_t c0 = 0; c0 < nlist; c0 += 65535) {
+        const int32_t cn = std::min<int32_t>(65535, nlist - c0);
+        hipLaunchKernelGGL(k_zero_fields, dim3(bx, (unsigned)cn), dim3(256), 0, s, d_dom, d_list + c0, n, d_w,
+                           cells);
+        SHMM_HIP_CHECK(hipGetLastError());
+    }
     return SHMM_OK;
 }
 
@@ -798,38 +959,67 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
     float *ws = (float *)work;
     float *ycur = ws, *ynext = ws + 2 * list_cells, *acc = ws + 4 * list_cells,
           *comp = ws + 6 * list_cells;
+    const int64_t s_end64 = (int64_t)step_begin + steps;
+    const int32_t s_end = (int32_t)(s_end64 < max_steps ? s_end64 : max_steps);
+    if (n == 256 && variant != 2) {
+        // Overlapped regions, HALO / 4 steps per launch.  Full-width bands:
+        // variant 0 32 rows with 8 above and below (768 threads), 1 the same
+        // with 1024 threads, 3 24 rows with 12 (3 steps per launch), 4 16
+        // rows with 8 (256 threads, two workgroups per CU); 5 square 64^2
+        // tiles with a ring of 8 (640 threads).  Lists split at 16384
+        // patches (grid.y < 65536).
+        const int32_t per = variant == 3 ? 3 : 2;
+        for (int32_t c0 = 0; c0 < nlist; c0 += 16384) {
+            const int32_t cn = std::min<int32_t>(16384, nlist - c0);
+            const int64_t off = (int64_t)c0 * n * n;
+            const int32_t *cl = d_list + c0;
+            float *const y0 = ycur + off, *const y1 = ynext + off;
+            float *yc = y0, *yn = y1, *cc = comp + off, *cx = acc + off;
+            const dim3 cg((unsigned)((n * n + 255) / 256), (unsigned)(2 * cn));
+            hipLaunchKernelGGL(k_solve_stage_init, cg, dim3(256), 0, s, d_dom, cl, n, w, cells_total, y0, cc,
+                               list_cells);
+            SHMM_HIP_CHECK(hipGetLastError());
+            for (int32_t step = step_begin; step < s_end; step += per) {
+                const float *ycc = yc, *ccc = cc;
+                int rc = SHMM_OK;
+                switch (variant) {
+                    case 1:
+                        rc = launch_band<256, 32, 8, 12, 0>(d_dom, cl, cn, vx, vy, Kb, ycc, ccc, yn, cx, list_cells,
+                                                           step, s_end, s);
+                        break;
+                    case 3:
+                        rc = launch_band<256, 24, 12, 16, 0>(d_dom, cl, cn, vx, vy, Kb, ycc, ccc, yn, cx, list_cells,
+                                                             step, s_end, s);
+                        break;
+                    case 4:
+                        rc = launch_band<256, 16, 8, 32, 8>(d_dom, cl, cn, vx, vy, Kb, ycc, ccc, yn, cx, list_cells,
+                                                           step, s_end, s);
+                        break;
+                    case 5:
+                        hipLaunchKernelGGL((k_solve_tiled<64, 8, 10>), dim3(16, (unsigned)(2 * cn)), dim3(640), 0, s,
+                                           d_dom, cl, n, vx, vy, Kb, ycc, ccc, yn, cx, list_cells, step, s_end);
+                        break;
+                    default:
+                        rc = launch_band<256, 32, 8, 16, 0>(d_dom, cl, cn, vx, vy, Kb, ycc, ccc, yn, cx, list_cells,
+                                                           step, s_end, s);
+                        break;
+                }
+                if (rc) return rc;
+                SHMM_HIP_CHECK(hipGetLastError());
+                std::swap(yc, yn);
+                std::swap(cc, cx);
+            }
+            hipLaunchKernelGGL(k_solve_tiles_fini, cg, dim3(256), 0, s, d_dom, cl, n, (const float *)y0,
+                               (const float *)y1, w, cells_total, list_cells, step_begin, s_end, per);
+            SHMM_HIP_CHECK(hipGetLastError());
+        }
+        return SHMM_OK;
+    }
+    if (2 * (int64_t)nlist > 65535) return SHMM_ERANGE;
     const dim3 grid((unsigned)((n * n + 255) / 256), (unsigned)(2 * nlist));
     hipLaunchKernelGGL(k_solve_stage_init, grid, dim3(256), 0, s, d_dom, d_list, n, w, cells_total,
                        ycur, comp, list_cells);
     SHMM_HIP_CHECK(hipGetLastError());
-    const int64_t s_end64 = (int64_t)step_begin + steps;
-    const int32_t s_end = (int32_t)(s_end64 < max_steps ? s_end64 : max_steps);
-    if (n == 256 && variant != 2) {
-        // overlapped tiles: variant 0 advances 2 steps per launch on 64^2
-        // tiles (ring of 8, 640 threads), variant 1 one step (ring of 4),
-        // variant 3 2 steps on 32^2 tiles (288 threads, several per CU)
-        float *cnext = acc;
-        const int tw = variant == 3 ? 32 : 64;
-        const dim3 tg((unsigned)((n / tw) * (n / tw)), (unsigned)(2 * nlist));
-        for (int32_t step = step_begin; step < s_end; step += (variant == 1 ? 1 : 2)) {
-            if (variant == 0)
-                hipLaunchKernelGGL((k_solve_tiled<64, 8, 10>), tg, dim3(640), 0, s, d_dom, d_list, n, vx, vy, Kb,
-                                   (const float *)ycur, (const float *)comp, ynext, cnext, list_cells, step, s_end);
-            else if (variant == 3)
-                hipLaunchKernelGGL((k_solve_tiled<32, 8, 8>), tg, dim3(288), 0, s, d_dom, d_list, n, vx, vy, Kb,
-                                   (const float *)ycur, (const float *)comp, ynext, cnext, list_cells, step, s_end);
-            else
-                hipLaunchKernelGGL((k_solve_tiled<64, 4, 9>), tg, dim3(576), 0, s, d_dom, d_list, n, vx, vy, Kb,
-                                   (const float *)ycur, (const float *)comp, ynext, cnext, list_cells, step, s_end);
-            SHMM_HIP_CHECK(hipGetLastError());
-            std::swap(ycur, ynext);
-            std::swap(comp, cnext);
-        }
-        hipLaunchKernelGGL(k_solve_tiled_fini, grid, dim3(256), 0, s, d_dom, d_list, n, (const float *)ycur, w,
-                           cells_total, list_cells);
-        SHMM_HIP_CHECK(hipGetLastError());
-        return SHMM_OK;
-    }
     // generic path: one launch per RK stage
     for (int32_t step = step_begin; step < s_end; ++step) {
         for (int st = 0; st < 4; ++st) {

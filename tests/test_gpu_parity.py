@@ -146,7 +146,8 @@ def _single_level(n, seed, amp, kappa, lattice=2, radius=None):
                                              (64, 400, 4), (128, 60, 0), (128, 60, 1), (128, 60, 2),
                                              (128, 60, 3), (128, 60, 4), (128, 60, 5), (128, 60, 6),
                                              (256, 12, 0), (256, 12, 1),
-                                             (256, 12, 2), (256, 12, 3)])
+                                             (256, 12, 2), (256, 12, 3), (256, 12, 4),
+                                             (256, 12, 5)])
 def test_local_solve_and_estimator_parity(torch, n, steps, variant):
     """Band filter + RK4 local solve + FP64 estimator against the oracle's own
     synthesis, solve and estimator, on an anisotropic base (every kernel variant)."""
@@ -210,6 +211,58 @@ def test_chunked_solve_matches_single_launch(torch, n):
         H.ctx.shmm_local_solve_batch(0, H.nd, *args, b, 500, 0, H.stream())
     torch.cuda.synchronize()
     assert relerr(H.w.cpu().numpy(), one) <= 1e-6
+    H.close()
+
+
+def test_tile_paths_follow_each_patch_plan(torch):
+    """The 256^2 region paths (full-width bands and square tiles) on 64
+    patches whose plans differ (anisotropy grows with the patch index; delta
+    near 1 keeps the plans to tens of steps): a patch whose plan has ended
+    drops out of the later launches, and its last state is still the one
+    copied back.  All variants agree, and sampled patches match the oracle
+    at their own step counts."""
+    n = 256
+    p = _single_level(n, seed=4, amp=0.3, kappa=0.05, lattice=8)
+    p.delta = 0.998
+    say("case region paths n=256, 64 patches, per-patch plans")
+    H = hier(p, keep_psi=False)
+    H.band_filter()
+    nd = H.nd
+    assert nd == 64
+    ratio = 1.0 + 3.0 * np.arange(nd) / (nd - 1)
+    Kb = np.stack([np.full(nd, 0.05), np.full(nd, 0.004), 0.05 * ratio], axis=1)
+    H.K_base.copy_(torch.from_numpy(Kb))
+    H.ctx.shmm_plan_steps(0, nd, Kb)
+    table = H.ctx.shmm_ctx_table()[0]
+    ns = table["nsteps"].astype(np.int64)
+    assert ns.min() > 0 and ns.max() > ns.min() + 8
+    args = (H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(),
+            H.w.data_ptr())
+    variants = (0, 1, 3, 4, 5)
+    out = {}
+    for v in variants:
+        say("  variant", v)
+        H.ctx.shmm_ctx_tune(n, v)
+        H.w.zero_()
+        H.ctx.shmm_local_solve_batch(0, nd, *args, 0, 2 ** 31 - 1, 0, H.stream())
+        torch.cuda.synchronize()
+        out[v] = H.w.cpu().numpy().copy()
+    for v in variants[1:]:
+        assert relerr(out[v], out[0]) <= 1e-6, v
+    cells = H.cells
+    lv, pt = oracle.band_split(p.kmax, p.thresh)
+    mask = oracle.band_mask(lv, pt, 0, DIAG)
+    for d in (0, 21, 42, 63):
+        D = table[d]
+        psi = oracle.synth_patch(p.psi_hat, p.kmax, mask, int(D["N"]), int(D["I0"]), int(D["J0"]), n)
+        vx, vy, f1, f2 = oracle.staggered(psi, float(D["h"]))
+        wr = oracle.local_solve_batch([n], [float(D["h"])], vx.ravel(), vy.ravel(), f1.ravel(), f2.ravel(),
+                                      Kb[d:d + 1], [float(D["dt"])], [int(D["nsteps"])])
+        o = int(D["offset"])
+        for v in variants:
+            w = out[v].reshape(2, cells)
+            for j in range(2):
+                assert relerr(w[j, o:o + n * n], wr[j]) <= 1e-5, (v, d, j)
     H.close()
 
 
