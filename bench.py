@@ -35,8 +35,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (256 CU, 2
 # factors read off a 1 GiB device copy.  Valid only for the kernel code they
 # were taken on (first 16 hex digits of the SHA-256 of solve.hip without its
 # comments and blank lines); otherwise reported null.
-SOLVE_TRAFFIC = {"code_sha256": "db7ae9dcee86758f", "variant": 5,
-                 "bytes_per_launch": (2 * 18586.5 + 20992.0) * 1024}
+SOLVE_TRAFFIC = {"code_sha256": "20228757dcff080a", "variant": 5,
+                 "bytes_per_launch": (2 * 12631.7 + 8832.0) * 1024}
 SOLVE_KERNELS_128 = {0: "k_solve_resident<128,32>", 1: "k_solve_rows<128,2,16>", 2: "k_solve_rows<128,2,8>",
                      3: "k_solve_resident_e<128,32>", 4: "k_solve_resident_e<128,16>",
                      5: "k_solve_resident_e<128,32,8>", 6: "k_solve_resident_e<128,32,16>"}
@@ -221,6 +221,53 @@ def uneven_leg(instances: int, window: int):
             "full_run_point_steps_planned": full}
 
 
+SOLVE_KERNELS_256 = {0: "k_solve_band<256,32,8,16,0>", 1: "k_solve_band<256,32,8,12,0>", 2: "k_solve_stage",
+                     3: "k_solve_band<256,24,12,16,0>", 4: "k_solve_band<256,16,8,32,8>",
+                     5: "k_solve_tiled<64,8,10>"}
+
+
+def n256_leg(steps: int = 200):
+    """Every kernel variant for 256^2 patches on one phase of 1024 of them (four
+    uneven-batch instances at n = 256 with 16 x 16 patches per level), each
+    run for `steps` RK4 steps and timed with HIP events on the launch stream
+    (best of two)."""
+    import torch
+    import flowgen
+    from paper_1510_00451_amd.hierarchy import Hierarchy
+    H = Hierarchy([flowgen.config_batched_instance(100 + i, n=256, lattice=16) for i in range(4)], keep_psi=False)
+    H.band_filter()
+    H.top_down()
+    H.phase_solve(0, steps=1)
+    torch.cuda.synchronize()
+    first, count = int(H.phase[0]), int(H.phase[1] - H.phase[0])
+    table = H.ctx.shmm_ctx_table()[0]
+    ns = np.minimum(table["nsteps"][first:first + count].astype(np.int64), steps)
+    pts = int(np.sum(table["n"][first:first + count].astype(np.int64) ** 2 * ns))
+    a, b = H.cell_range(first, count)
+    s = H.stream()
+    out = {}
+    for v in range(H.ctx.solve_variants(256)):
+        H.ctx.shmm_ctx_tune(256, v)
+        best = float("inf")
+        for rep in range(2):
+            H.w.view(2, H.cells)[:, a:b].zero_()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            H.ctx.shmm_local_solve_batch(first, count, H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(),
+                                         H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(), 0, steps, 0, s)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        out[SOLVE_KERNELS_256[v]] = round(pts / (best * 1e-3) / 1e9, 1)
+        log(f"n = 256 variant {v}: {out[SOLVE_KERNELS_256[v]]} Gpoint-steps/s")
+    H.close()
+    return {"workload": f"{count} patches of 256^2 (uneven-batch generator, seeds 100-103, n = 256, "
+                        f"16 x 16 patches per level), {steps} steps",
+            "shortest_plan": int(table["nsteps"][first:first + count].min()),
+            "gpoint_steps_per_s": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +283,7 @@ def main():
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--uneven-instances", type=int, default=256)
     ap.add_argument("--uneven-window", type=int, default=2000)
+    ap.add_argument("--no-n256", action="store_true", help="skip the 256^2 kernel-variant leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="copy this many MiB once before the passes (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -341,6 +389,9 @@ def main():
     if not args.no_uneven:
         log("uneven batch ...")
         out["uneven_batch"] = uneven_leg(args.uneven_instances, args.uneven_window)
+    if not args.no_n256:
+        log("256^2 kernel variants ...")
+        out["n256_variants"] = n256_leg()
     if not args.no_surrogate:
         log("surrogate ...")
         out["surrogate"] = surrogate_leg(args.surrogate_flows, args.surrogate_eval_flows,

@@ -321,6 +321,9 @@ __device__ __forceinline__ void solve_body_e(float *__restrict__ buf, const shmm
                                             rr, cl, T);
         __syncthreads();
     }
+    // a fresh base pointer: the row addresses are rebuilt here instead of
+    // being held in registers through the step loop
+    asm volatile("" : "+v"(wf));
 #pragma unroll
     for (int r = 0; r < R; ++r) wf[r * NN] = wv[r];
 }

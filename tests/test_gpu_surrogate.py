@@ -42,7 +42,7 @@ def _patches(n, lattice=2, seed=3, amp=0.4):
     return p
 
 
-@pytest.mark.parametrize("n", [32, 128])
+@pytest.mark.parametrize("n", [32, 64, 128, 256])
 def test_patch_features_parity(torch, n):
     from paper_1510_00451_amd.hierarchy import Hierarchy
     p = _patches(n)
