@@ -185,8 +185,12 @@ int shmm_band_filter(shmm_ctx *ctx, int64_t first, int64_t count, float *d_psi, 
  * d_K_base is [n_domains][3] (global index), d_w is [2][n_cells_total] FP32
  * in/out.  FP32 stencils with a compensated state update.  Requires
  * shmm_plan_steps on the range; patches planned with zero steps are skipped.
- * d_status (may be NULL) gets SHMM_DOM_* bits.
- * Errors: SHMM_EINVAL for a range that was never planned. */
+ * d_status (may be NULL) gets SHMM_DOM_* bits.  Patches with n <= 128 stay
+ * resident in LDS for the whole call; n = 256 advances in overlapped regions
+ * and other sizes stage by stage, both through the context's workspace
+ * (32 B per listed cell, grown on demand).
+ * Errors: SHMM_EINVAL for a range that was never planned; SHMM_ERANGE for
+ * more than 32767 patches of one size outside 8..256 in one call. */
 int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const float *d_vx,
                            const float *d_vy, const float *d_f1, const float *d_f2,
                            const double *d_K_base, float *d_w, int32_t step_begin,
@@ -230,9 +234,18 @@ int shmm_level_chain(shmm_ctx *ctx, int64_t first, int64_t count, int32_t mode,
  * order).  key = a patch size n (power of two): select local-solve kernel
  * variant `value` for patches of that size, 0 <= value < the count returned by
  * key = SHMM_TUNE_SOLVE_VARIANT_COUNT with value = n (a non-negative return).
- * Variants for n = 64 and 128: 0 = whole patch staged in LDS, column strips;
- * 1 = rows per wavefront, 16 rows per thread; 2 = rows per wavefront, 8 rows
- * per thread.  Errors: SHMM_EINVAL for an unknown key or value. */
+ * n = 64: 0 = whole patch in LDS, column strips of 16 (split operator form);
+ *   1, 2 = rows per wavefront, 16 or 8 rows per thread; 3 = whole patch in
+ *   LDS, coefficient form, strips of 16 (default); 4 = the same, strips of 8.
+ * n = 128: 0 = split form, strips of 32; 1, 2 = rows per wavefront (16, 8);
+ *   3, 4 = coefficient form, strips of 32 or 16; 5 = strips of 32 with the
+ *   compensation of 8 strip rows in LDS (default); 6 = the same with 16 rows.
+ * n = 256: 0 = full-width bands of 32 rows with 8-row rings, 768 threads
+ *   (default); 1 = the same at 1024 threads; 2 = one launch per RK stage;
+ *   3 = bands of 24 rows with 12-row rings (3 steps per launch); 4 = bands of
+ *   16 rows, 256 threads; 5 = square 64 x 64 tiles with 8-cell rings.
+ * Other sizes have one variant.
+ * Errors: SHMM_EINVAL for an unknown key or value. */
 #define SHMM_TUNE_SOLVE_VARIANT_COUNT 0
 int shmm_ctx_tune(shmm_ctx *ctx, int32_t key, int32_t value);
 
