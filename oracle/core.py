@@ -50,10 +50,11 @@ def _lib():
         lib.orc_rhs.argtypes = [ctypes.c_int, f64, P, P, P, P, P, P, P, P, P]
         lib.orc_local_solve_batch.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, i64, P]
         lib.orc_macro.argtypes = [ctypes.c_int, f64, P, P, P, ctypes.c_int, f64, i64, P]
+        lib.orc_macro_dirichlet_x.argtypes = [ctypes.c_int, f64, f64, f64, P, P, P, ctypes.c_int, f64, i64, P]
         lib.orc_diffusion.argtypes = [ctypes.c_int, f64, P, P, P]
         lib.orc_operator.argtypes = [ctypes.c_int, f64, P, P, P, P, P, P]
         for name in ("orc_synth_points", "orc_line_energy", "orc_rhs", "orc_local_solve_batch",
-                     "orc_macro", "orc_diffusion", "orc_operator"):
+                     "orc_macro", "orc_macro_dirichlet_x", "orc_diffusion", "orc_operator"):
             getattr(lib, name).restype = None
         _lib_handle = lib
     return _lib_handle
@@ -589,14 +590,21 @@ def macro_plan(N: int, K_cells: np.ndarray, Vb: float, dt_frac: float, T: float)
 
 
 def macro_run(N: int, vx: Optional[np.ndarray], vy: Optional[np.ndarray], K: np.ndarray,
-              u0: np.ndarray, dt: float, nsteps: int) -> np.ndarray:
-    """u_t = div(v_M u + K grad u), periodic N x N, RK4 (FP64)."""
+              u0: np.ndarray, dt: float, nsteps: int,
+              dirichlet_x: Optional[Tuple[float, float]] = None) -> np.ndarray:
+    """u_t = div(v_M u + K grad u) on the N x N grid of [0, 2 pi]^2, RK4 (FP64):
+    periodic, or with u = dirichlet_x[0] on x = 0 and dirichlet_x[1] on
+    x = 2 pi and periodic in y (the boundary conditions of Section 4)."""
     K = _c(K, np.float64).reshape(-1)
     is_field = 1 if K.size > 3 else 0
     u = _c(u0, np.float64).copy()
-    _lib().orc_macro(int(N), 2.0 * math.pi / N, _p(None if vx is None else _c(vx, np.float64)),
-                     _p(None if vy is None else _c(vy, np.float64)), _p(K), is_field,
-                     float(dt), int(nsteps), _p(u))
+    vxp = _p(None if vx is None else _c(vx, np.float64))
+    vyp = _p(None if vy is None else _c(vy, np.float64))
+    if dirichlet_x is None:
+        _lib().orc_macro(int(N), 2.0 * math.pi / N, vxp, vyp, _p(K), is_field, float(dt), int(nsteps), _p(u))
+    else:
+        _lib().orc_macro_dirichlet_x(int(N), 2.0 * math.pi / N, float(dirichlet_x[0]), float(dirichlet_x[1]),
+                                     vxp, vyp, _p(K), is_field, float(dt), int(nsteps), _p(u))
     return u
 
 

@@ -263,6 +263,96 @@ void orc_macro(int N, double h, const double *vx, const double *vy, const double
     free(kx11); free(kx12); free(ky12); free(ky22);
 }
 
+/* ------------------------------------------------------------------------
+ * Macro solver with the boundary conditions of the paper's numerical
+ * examples (Section 4): u = g0 on x = 0 and u = g1 on x = 2 pi (Dirichlet in
+ * x), periodic in y.  Cells i = 0..N-1 sit at x = (i + 1/2) h.
+ *   interior x-faces (1 <= i <= N-1): the periodic flux above, with the face
+ *     diffusivity the mean of the two cells;
+ *   boundary x-faces: the face value is the boundary value, the normal
+ *     derivative is one-sided over h/2, and the tangential derivative is zero
+ *     (u is constant along the boundary):
+ *       Jx(0)  = vx g0 + Kx11 (u[0] - g0) / (h/2)
+ *       Jx(N)  = vx g1 + Kx11 (g1 - u[N-1]) / (h/2)
+ *     with vx of the periodic velocity field at x = 0 and the diffusivity of
+ *     the adjacent cell;
+ *   y-faces: periodic in y; the tangential x-derivative uses ghost values
+ *     u[-1] = 2 g0 - u[0] and u[N] = 2 g1 - u[N-1] (linear through the
+ *     boundary value).
+ * ---------------------------------------------------------------------- */
+static void rhs_dirichlet_x(int N, double h, double g0, double g1, const double *vx, const double *vy,
+                            const double *Kc, int is_field, const double *u, double *out)
+{
+    size_t cells = (size_t)N * N;
+    double *jx = (double *)malloc(sizeof(double) * (size_t)N * (N + 1));   /* faces 0..N of each row */
+    double *jy = (double *)malloc(sizeof(double) * cells);
+#define U(jj, ii) u[(size_t)(jj) * N + (ii)]
+#define KC(c, q) (is_field ? Kc[3 * (c) + (q)] : Kc[(q)])
+    for (int j = 0; j < N; ++j) {
+        int jp = wrap(j + 1, N), jm = wrap(j - 1, N);
+        for (int i = 0; i <= N; ++i) {
+            double J;
+            if (i == 0) {
+                size_t c = (size_t)j * N;
+                J = (vx ? vx[c] * g0 : 0.0) + KC(c, 0) * (U(j, 0) - g0) / (0.5 * h);
+            } else if (i == N) {
+                size_t c = (size_t)j * N + (N - 1);
+                J = (vx ? vx[(size_t)j * N] * g1 : 0.0) + KC(c, 0) * (g1 - U(j, N - 1)) / (0.5 * h);
+            } else {
+                size_t c = (size_t)j * N + i, cl = c - 1;
+                double k11 = 0.5 * (KC(c, 0) + KC(cl, 0)), k12 = 0.5 * (KC(c, 1) + KC(cl, 1));
+                double ul = U(j, i - 1), ur = U(j, i);
+                J = (vx ? vx[c] * 0.5 * (ul + ur) : 0.0) + k11 * (ur - ul) / h
+                  + k12 * (U(jp, i) + U(jp, i - 1) - U(jm, i) - U(jm, i - 1)) / (4.0 * h);
+            }
+            jx[(size_t)j * (N + 1) + i] = J;
+        }
+        for (int i = 0; i < N; ++i) {
+            size_t c = (size_t)j * N + i, cb = (size_t)jm * N + i;
+            double k22 = 0.5 * (KC(c, 2) + KC(cb, 2)), k12 = 0.5 * (KC(c, 1) + KC(cb, 1));
+            double e_t = i + 1 < N ? U(j, i + 1) : 2.0 * g1 - U(j, N - 1);
+            double e_b = i + 1 < N ? U(jm, i + 1) : 2.0 * g1 - U(jm, N - 1);
+            double w_t = i > 0 ? U(j, i - 1) : 2.0 * g0 - U(j, 0);
+            double w_b = i > 0 ? U(jm, i - 1) : 2.0 * g0 - U(jm, 0);
+            double ub = U(jm, i), ut = U(j, i);
+            jy[c] = (vy ? vy[c] * 0.5 * (ub + ut) : 0.0) + k22 * (ut - ub) / h
+                  + k12 * (e_t + e_b - w_t - w_b) / (4.0 * h);
+        }
+    }
+#undef U
+#undef KC
+    for (int j = 0; j < N; ++j)
+        for (int i = 0; i < N; ++i) {
+            size_t c = (size_t)j * N + i;
+            out[c] = (jx[(size_t)j * (N + 1) + i + 1] - jx[(size_t)j * (N + 1) + i]) / h
+                   + (jy[(size_t)wrap(j + 1, N) * N + i] - jy[c]) / h;
+        }
+    free(jx); free(jy);
+}
+
+void orc_macro_dirichlet_x(int N, double h, double g0, double g1, const double *vx, const double *vy,
+                           const double *Kc, int is_field, double dt, int64_t nsteps, double *u)
+{
+    size_t cells = (size_t)N * N;
+    double *k1 = (double *)malloc(sizeof(double) * cells);
+    double *k2 = (double *)malloc(sizeof(double) * cells);
+    double *k3 = (double *)malloc(sizeof(double) * cells);
+    double *k4 = (double *)malloc(sizeof(double) * cells);
+    double *y = (double *)malloc(sizeof(double) * cells);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        rhs_dirichlet_x(N, h, g0, g1, vx, vy, Kc, is_field, u, k1);
+        for (size_t c = 0; c < cells; ++c) y[c] = u[c] + 0.5 * dt * k1[c];
+        rhs_dirichlet_x(N, h, g0, g1, vx, vy, Kc, is_field, y, k2);
+        for (size_t c = 0; c < cells; ++c) y[c] = u[c] + 0.5 * dt * k2[c];
+        rhs_dirichlet_x(N, h, g0, g1, vx, vy, Kc, is_field, y, k3);
+        for (size_t c = 0; c < cells; ++c) y[c] = u[c] + dt * k3[c];
+        rhs_dirichlet_x(N, h, g0, g1, vx, vy, Kc, is_field, y, k4);
+        for (size_t c = 0; c < cells; ++c)
+            u[c] = u[c] + dt / 6.0 * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]);
+    }
+    free(k1); free(k2); free(k3); free(k4); free(y);
+}
+
 /* Diffusion-only operator with constant K (no advection, no forcing). */
 void orc_diffusion(int n, double h, const double *K, const double *u, double *out)
 {

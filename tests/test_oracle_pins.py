@@ -417,6 +417,101 @@ def test_macro_conserves_mass_with_advection_and_field():
     assert abs(u.sum() - u0.sum()) <= 1e-13 * abs(u0.sum())
 
 
+def _heat_series(x, t, K11, terms=4000):
+    """u_t = K11 u_xx on [0, L], u(0) = 1, u(L) = 0, u(x, 0) = 1 for x <= L/2
+    else 0 (the step data of Section 4): the steady line plus the sine series
+    of the initial deviation, whose coefficients are -2 cos(m pi / 2) / (m pi)."""
+    L = 2 * np.pi
+    u = 1 - x / L
+    for m in range(1, terms + 1):
+        b = -2.0 * math.cos(m * math.pi / 2) / (m * math.pi)
+        if b != 0.0:
+            u = u + b * np.sin(m * math.pi * x / L) * math.exp(-K11 * (m * math.pi / L) ** 2 * t)
+    return u
+
+
+def test_macro_dirichlet_step_converges_to_the_heat_series():
+    """Dirichlet in x, periodic in y (Section 4), pure diffusion from the step
+    data: second-order convergence to the closed-form series solution (a
+    boundary flux over the wrong distance would cost an order)."""
+    K = np.array([1.0, 0.0, 1.0])
+    errs = []
+    for N in (32, 64, 128):
+        h = 2 * np.pi / N
+        x = (np.arange(N) + 0.5) * h
+        u0 = np.tile((x <= np.pi).astype(float), (N, 1))
+        dt, ns = oracle.macro_plan(N, K, 0.0, 0.2, 0.5)
+        u = oracle.macro_run(N, None, None, K, u0, dt, ns, dirichlet_x=(1.0, 0.0))
+        assert np.max(np.abs(u - u[0:1])) == 0.0           # stays independent of y
+        errs.append(float(np.max(np.abs(u - _heat_series(x, 0.5, 1.0)[None, :]))))
+    assert errs[2] <= 1e-4
+    for a, b in zip(errs, errs[1:]):
+        assert 3.6 <= a / b <= 4.4, errs
+
+
+def test_macro_dirichlet_linear_profile_is_steady():
+    """The linear profile between the two boundary values is a steady state of
+    the Dirichlet scheme for any constant K (cross term included): every
+    x-face, boundary faces over h/2 included, carries the same flux, and the
+    ghost values continue the line."""
+    N = 16
+    h = 2 * np.pi / N
+    x = (np.arange(N) + 0.5) * h
+    g0, g1 = 1.0, 0.25
+    u0 = np.tile(g0 + (g1 - g0) * x / (2 * np.pi), (N, 1))
+    u = oracle.macro_run(N, None, None, np.array([0.3, 0.12, 0.2]), u0, 0.01, 50, dirichlet_x=(g0, g1))
+    assert np.max(np.abs(u - u0)) <= 1e-13
+
+
+def test_macro_dirichlet_shear_along_the_boundary_does_not_act():
+    """A shear v = (0, V sin kx) carries a field that depends on x alone along
+    its own level lines: with the Dirichlet boundaries the solution is the
+    pure-diffusion one; a constant field stays constant under a divergence-free
+    flow with both boundary values equal to it."""
+    N = 32
+    h = 2 * np.pi / N
+    x = (np.arange(N) + 0.5) * h
+    xf = np.arange(N) * h
+    K = np.array([0.7, 0.0, 0.7])
+    u0 = np.tile((x <= np.pi).astype(float), (N, 1))
+    vy = np.tile(1.5 * np.sin(3 * (xf + 0.5 * h)), (N, 1))   # y-faces sit at x = (i + 1/2) h
+    vx = np.zeros((N, N))
+    dt, ns = oracle.macro_plan(N, K, 3.0, 0.2, 0.4)
+    ref = oracle.macro_run(N, None, None, K, u0, dt, ns, dirichlet_x=(1.0, 0.0))
+    got = oracle.macro_run(N, vx, vy, K, u0, dt, ns, dirichlet_x=(1.0, 0.0))
+    assert np.max(np.abs(got - ref)) <= 1e-13
+    X, Y = np.meshgrid(xf, xf, indexing="xy")
+    wx, wy, _, _ = oracle.staggered(np.sin(X) * np.sin(2 * Y) + 0.3 * np.cos(2 * X + Y), h)
+    c = np.full((N, N), 0.4)
+    cst = oracle.macro_run(N, wx, wy, K, c, dt, ns, dirichlet_x=(0.4, 0.4))
+    assert np.max(np.abs(cst - 0.4)) <= 1e-13
+
+
+def test_macro_dirichlet_uniform_flow_reaches_the_discrete_steady_state():
+    """A uniform flow vx = V with Dirichlet boundaries: the scheme's steady
+    state carries one flux C through every x-face, boundary faces included
+    (face value = boundary value, gradient over h/2).  Marching that relation
+    from x = 0 gives u as an affine function of C and the last face fixes C:
+    an independent 1-D computation the long-time oracle solution must reach."""
+    N, K, V, g0, g1 = 16, 0.8, 0.6, 1.0, 0.2
+    h = 2 * np.pi / N
+
+    def march(C):
+        u = np.zeros(N)
+        u[0] = g0 + (C - V * g0) * h / (2 * K)
+        for i in range(1, N):
+            u[i] = (C - u[i - 1] * (V / 2 - K / h)) / (V / 2 + K / h)
+        return u, V * g1 + K * (g1 - u[N - 1]) / (h / 2) - C
+
+    (_, ra), (_, rb) = march(0.0), march(1.0)
+    u_ss, _ = march(-ra / (rb - ra))
+    Kv = np.array([K, 0.0, K])
+    dt, ns = oracle.macro_plan(N, Kv, 2 * V, 0.4, 120.0)
+    u = oracle.macro_run(N, np.full((N, N), V), np.zeros((N, N)), Kv, np.zeros((N, N)), dt, ns,
+                         dirichlet_x=(g0, g1))
+    assert np.max(np.abs(u - u_ss[None, :])) <= 1e-12
+
+
 # ---------------------------------------------------------------- bookkeeping
 
 def test_domain_table_geometry():
