@@ -221,6 +221,100 @@ def uneven_leg(instances: int, window: int):
             "full_run_point_steps_planned": full}
 
 
+def _macro_dt(vx, vy, K, N, dt_frac, T):
+    """RK4 step for the macro grid: dt_frac of the stability bound of the
+    diffusion (4 K11 + 4 K22 + 2 |K12|) / h^2 and of the advection (Gershgorin
+    bound of the face velocities) / h, rounded so the steps end at T."""
+    h = 2.0 * math.pi / N
+    rho = (4.0 * K[0] + 4.0 * K[2] + 2.0 * abs(K[1])) / h ** 2 / 2.785
+    if vx is not None:
+        ax, ay = np.abs(vx.reshape(N, N)), np.abs(vy.reshape(N, N))
+        vmax = 0.5 * float(np.max(ax + np.roll(ax, -1, axis=1) + ay + np.roll(ay, -1, axis=0)))
+        rho += vmax / h / 2.828
+    steps = max(1, int(math.ceil(T / (dt_frac / rho))))
+    return T / steps, steps
+
+
+def paper_tests_leg(n_k: int = 128, n_dns: int = 512):
+    """The cellular examples of Section 4 (Tests 2 and 3), as printed and with
+    the velocity scaled by 2 pi.  K: two-level SHMM (decomposition factor 5)
+    against the direct cell problem of the full flow, on the wavenumbers
+    divided by 5 (the same homogenized K) at n_k^2.  u: the Section 4
+    problem (step data, u = 1 on x = 0 and 0 on x = 2 pi, y periodic) at
+    t = 0.02 and t = 0.1 of the paper (x 4 pi^2 here): a direct simulation with the full
+    velocity on n_dns^2 (FP32), against the homogenized equation with the
+    SHMM K and with kappa alone (FP64, n_dns / 4), compared with the DNS
+    averaged over y and over 4-cell blocks in x."""
+    import torch
+    import flowgen
+    from paper_1510_00451_amd import abi
+    from paper_1510_00451_amd.hierarchy import Hierarchy
+    T = 0.4 * math.pi ** 2
+    s = torch.cuda.current_stream().cuda_stream
+    out = []
+    for test in (2, 3):
+        for label, scale in (("as printed", 1.0), ("velocity x 2 pi", 2.0 * math.pi)):
+            rec = {"test": test, "scale": label}
+            K = {}
+            for levels in (2, 1):
+                H = Hierarchy(flowgen.config_paper_cellular(test, scale, n=n_k, levels=levels, divide=5),
+                              keep_psi=False)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                H.run()
+                r = H.result()
+                rec[f"{'shmm' if levels == 2 else 'direct'}_s"] = round(time.perf_counter() - t0, 3)
+                K[levels] = r.K_total[0]
+                H.close()
+            rec["K_shmm"] = [round(float(v), 6) for v in K[2]]
+            rec["K_direct"] = [round(float(v), 6) for v in K[1]]
+            rec["rel_gap"] = float(np.max(np.abs(K[2] - K[1])) / K[1][0])
+            # direct simulation with the full velocity (face velocities of the one-band filter),
+            # recorded at t = 0.02 and t = 0.1 of the paper; the homogenized models alongside
+            Hd = Hierarchy(flowgen.config_paper_cellular(test, scale, n=n_dns, levels=1), keep_psi=False)
+            Hd.band_filter()
+            torch.cuda.synchronize()
+            vx, vy = Hd.vx[:n_dns * n_dns].contiguous(), Hd.vy[:n_dns * n_dns].contiguous()
+            kap = [1.0, 0.0, 1.0]
+            dt, ns = _macro_dt(vx.cpu().numpy(), vy.cpu().numpy(), kap, n_dns, 0.5, T / 5)
+            u = torch.tensor(flowgen.paper_step_initial(n_dns), dtype=torch.float32, device="cuda").contiguous()
+            Kd = torch.tensor([kap], dtype=torch.float64, device="cuda")
+            nm, b = n_dns // 4, 4
+            models = {}
+            for name, Km in (("shmm", K[2]), ("molecular", np.array(kap))):
+                dtm, nsm = _macro_dt(None, None, Km, nm, 0.5, T / 5)
+                models[name] = (dtm, nsm, torch.tensor(flowgen.paper_step_initial(nm), dtype=torch.float64,
+                                                       device="cuda").contiguous(),
+                                torch.tensor([list(Km)], dtype=torch.float64, device="cuda"))
+            rec["dns_steps"] = 5 * ns
+            rec["dns_s"] = 0.0
+            for t_paper, reps in ((0.02, 1), (0.1, 4)):
+                t0 = time.perf_counter()
+                Hd.ctx.shmm_macro_step(n_dns, abi.BC_DIRICHLET_X, 1.0, 0.0, vx.data_ptr(), vy.data_ptr(),
+                                       Kd.data_ptr(), 0, dt, reps * ns, u.data_ptr(), 32, s)
+                torch.cuda.synchronize()
+                rec["dns_s"] = round(rec["dns_s"] + time.perf_counter() - t0, 3)
+                ud = u.cpu().numpy().astype(np.float64).reshape(n_dns, n_dns)
+                ubar = ud.mean(axis=0).reshape(nm, b).mean(axis=1)
+                at = {"dns_fluctuation_rms": float(np.sqrt(np.mean((ud - ud.mean(axis=0)[None, :]) ** 2)))}
+                for name, (dtm, nsm, um, Kt) in models.items():
+                    Hd.ctx.shmm_macro_step(nm, abi.BC_DIRICHLET_X, 1.0, 0.0, 0, 0, Kt.data_ptr(), 0, dtm,
+                                           reps * nsm, um.data_ptr(), 64, s)
+                    torch.cuda.synchronize()
+                    prof = um.cpu().numpy().reshape(nm, nm)[nm // 2]
+                    at[f"u_rms_vs_dns_{name}"] = float(np.sqrt(np.mean((prof - ubar) ** 2)))
+                rec[f"t={t_paper}"] = at
+            Hd.close()
+            log(f"paper test {test} ({label}): K gap {rec['rel_gap']:.2e}; u rms vs DNS at t = 0.02 / 0.1: "
+                f"SHMM {rec['t=0.02']['u_rms_vs_dns_shmm']:.2e} / {rec['t=0.1']['u_rms_vs_dns_shmm']:.2e}, "
+                f"kappa alone {rec['t=0.02']['u_rms_vs_dns_molecular']:.2e} / "
+                f"{rec['t=0.1']['u_rms_vs_dns_molecular']:.2e}")
+            out.append(rec)
+    return {"workload": f"Section 4 Tests 2-3: K on wavenumbers / 5 at {n_k}^2; u at t = 0.02 and 0.1 (paper units), "
+                        f"DNS {n_dns}^2 FP32, homogenized models {n_dns // 4}^2 FP64",
+            "cases": out}
+
+
 SOLVE_KERNELS_256 = {0: "k_solve_band<256,32,8,16,0>", 1: "k_solve_band<256,32,8,12,0>", 2: "k_solve_stage",
                      3: "k_solve_band<256,24,12,16,0>", 4: "k_solve_band<256,16,8,32,8>",
                      5: "k_solve_tiled<64,8,10>"}
@@ -284,6 +378,7 @@ def main():
     ap.add_argument("--uneven-instances", type=int, default=256)
     ap.add_argument("--uneven-window", type=int, default=2000)
     ap.add_argument("--no-n256", action="store_true", help="skip the 256^2 kernel-variant leg")
+    ap.add_argument("--no-paper", action="store_true", help="skip the Section 4 examples")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="copy this many MiB once before the passes (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -392,6 +487,9 @@ def main():
     if not args.no_n256:
         log("256^2 kernel variants ...")
         out["n256_variants"] = n256_leg()
+    if not args.no_paper:
+        log("Section 4 examples ...")
+        out["paper_tests"] = paper_tests_leg()
     if not args.no_surrogate:
         log("surrogate ...")
         out["surrogate"] = surrogate_leg(args.surrogate_flows, args.surrogate_eval_flows,

@@ -217,6 +217,48 @@ def config_shear(k: int = 16, V: float = 1.0, kappa: float = 1e-2, n: int = 128,
                    lattice=[1] * levels, dt_frac=0.5, delta=1e-6, name=f"shear-k{k}")
 
 
+def config_paper_cellular(test: int, scale: float = 1.0, n: int = 128, levels: int = 2,
+                          divide: int = 1) -> Problem:
+    """The cellular examples of Section 4 (Tests 2 and 3) on [0, 2 pi]^2.
+
+    The paper's [0,1]^2 with kappa = 1 maps to [0, 2 pi]^2 by x' = 2 pi x,
+    t' = 4 pi^2 t with the same stream function in x' and kappa = 1, so
+    phi_c(a x1, b x2) becomes sin(a x') sin(b y'):
+      test 2: psi = (1/3) (phi_c(5, 5) + phi_c(25, 25));
+      test 3: psi = (1/5) (phi_c(5, 5) + phi_c(5, 45) + phi_c(45, 5) + phi_c(50, 50)),
+    times `scale`.  `divide` divides every wavenumber (5 -> the same
+    homogenized K at a fifth of the resolution: the cell problem of a
+    periodic flow does not depend on the number of periods in the domain).
+    levels = 2: decomposition factor alpha = 5 (band edge 5 / divide), both
+    levels on one whole-domain patch of n^2 cells (the fine modes are periodic
+    on no smaller power-of-two patch); levels = 1: one band, the direct cell
+    problem of the full flow."""
+    if test == 2:
+        modes = [(5, 5, 1.0 / 3.0), (25, 25, 1.0 / 3.0)]
+    elif test == 3:
+        modes = [(5, 5, 0.2), (5, 45, 0.2), (45, 5, 0.2), (50, 50, 0.2)]
+    else:
+        raise ValueError("test must be 2 or 3")
+    if any(a % divide or b % divide for a, b, _ in modes):
+        raise ValueError("divide must divide every wavenumber")
+    modes = [(a // divide, b // divide, amp * scale) for a, b, amp in modes]
+    kmax = max(max(a, b) for a, b, _ in modes)
+    ph = _empty_spectrum(kmax)
+    for a, b, amp in modes:
+        add_cellular(ph, kmax, a, b, amp)
+    thresh = [5 // divide] if levels == 2 else []
+    return Problem(kappa=1.0, kmax=kmax, psi_hat=ph, thresh=thresh, n_cells=[n] * levels,
+                   n_global=[n] * levels, lattice=[1] * levels, dt_frac=0.5, delta=1e-6,
+                   name=f"paper-test{test}-x{scale:.3g}-div{divide}-L{levels}")
+
+
+def paper_step_initial(N: int) -> np.ndarray:
+    """The step data of Section 4 at the N x N cell centres of [0, 2 pi]^2:
+    1 where x <= pi, else 0."""
+    xc = (np.arange(N) + 0.5) * (2.0 * np.pi / N)
+    return np.tile((xc <= np.pi).astype(np.float64), (N, 1))
+
+
 def config_continuous(seed: int = 0, radius: int = 512, p: float = -7.0 / 3.0,
                       kappa: float = 1e-3, n: int = 128, lattice: int = 16,
                       levels: int = 5) -> Problem:

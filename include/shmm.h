@@ -252,15 +252,26 @@ int shmm_ctx_tune(shmm_ctx *ctx, int32_t key, int32_t value);
 /* Macro solver (HMM step 4 on eq:homo with the resolved velocity kept as
  * advection): nsteps classic RK4 steps of
  *   u_t = div(v u + K(x) grad u)
- * on the periodic N x N grid of spacing h = 2 pi / N.  d_vx, d_vy are face
- * velocities (may both be NULL: pure diffusion); d_K is [N*N][3] at cell
- * centres (face value = mean of the two cells) if K_is_field, else [1][3].
- * dtype 64: d_vx, d_vy, d_u are double; dtype 32: float (K stays double).
- * Errors: SHMM_EINVAL for N < 4 or not a power of two, a dtype other than
- * 32/64, or nsteps < 0 (nsteps = 0 is a no-op). */
-int shmm_macro_step(shmm_ctx *ctx, int32_t N, const void *d_vx, const void *d_vy,
-                    const double *d_K, int32_t K_is_field, double dt, int32_t nsteps, void *d_u,
-                    int32_t dtype, void *stream);
+ * on the N x N grid of [0, 2 pi]^2, spacing h = 2 pi / N, cells at
+ * ((i + 1/2) h, (j + 1/2) h).  d_vx, d_vy are face velocities (left x-face,
+ * bottom y-face of each cell; may both be NULL: pure diffusion); d_K is
+ * [N*N][3] at cell centres (face value = mean of the two cells) if
+ * K_is_field, else [1][3].  dtype 64: d_vx, d_vy, d_u are double; dtype 32:
+ * float (K stays double).
+ * bc: SHMM_BC_PERIODIC, or SHMM_BC_DIRICHLET_X (the numerical examples of
+ * Section 4): u = g0 on x = 0 and u = g1 on x = 2 pi, periodic in y.  A
+ * boundary x-face carries the boundary value (advection with the velocity
+ * field's x-face value at x = 0, diffusion K11 of the adjacent cell over the
+ * half cell, no tangential term); y-face cross terms in the first and last
+ * columns use the ghost value 2 g - u.  g0, g1 are ignored when periodic.
+ * Errors: SHMM_EINVAL for N < 4 or not a power of two, an unknown bc, a
+ * non-finite boundary value, a dtype other than 32/64, or nsteps < 0
+ * (nsteps = 0 is a no-op). */
+#define SHMM_BC_PERIODIC 0
+#define SHMM_BC_DIRICHLET_X 1
+int shmm_macro_step(shmm_ctx *ctx, int32_t N, int32_t bc, double g0, double g1, const void *d_vx,
+                    const void *d_vy, const double *d_K, int32_t K_is_field, double dt, int32_t nsteps,
+                    void *d_u, int32_t dtype, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Learned surrogate of the local solve (not part of the paper's method).

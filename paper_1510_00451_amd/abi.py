@@ -25,6 +25,7 @@ EXPORTS = ["shmm_ctx_create", "shmm_ctx_destroy", "shmm_build_levels", "shmm_ctx
            "shmm_macro_step", "shmm_ctx_tune", "shmm_patch_features", "shmm_surrogate_refresh",
            "shmm_surrogate_train_step", "shmm_surrogate_infer", "shmm_fallback_solve"]
 
+BC_PERIODIC, BC_DIRICHLET_X = 0, 1
 SURR_BINS, SURR_IN, SURR_WIDTH, SURR_OUT = 32, 33, 256, 3
 SURR_PARAMS, SURR_PARAMS_PADDED = 141059, 141312
 SURR_MODEL_BYTES = 4 * SURR_PARAMS_PADDED + 4 * 128 + 2 * SURR_PARAMS_PADDED
@@ -73,7 +74,7 @@ def lib() -> ctypes.CDLL:
             "shmm_local_solve_batch": [P, i64, i64, P, P, P, P, P, P, i32, i32, P, P],
             "shmm_effective_diffusivity": [P, i64, i64, P, P, P, P, P, P, P, P, P],
             "shmm_level_chain": [P, i64, i64, i32, P, P, P, P, P, P, P, P],
-            "shmm_macro_step": [P, i32, P, P, P, i32, f64, i32, P, i32, P],
+            "shmm_macro_step": [P, i32, i32, f64, f64, P, P, P, i32, f64, i32, P, i32, P],
             "shmm_ctx_tune": [P, i32, i32],
             "shmm_patch_features": [P, i64, i64, P, P, P, P, P],
             "shmm_surrogate_refresh": [P, P, P],
@@ -241,7 +242,7 @@ class Context:
         check(lib().shmm_fallback_solve(self.h, first, count, d_flags, d_vx, d_vy, d_f1, d_f2, d_K_base,
                                         d_w, d_K_out, d_status or None, stream), "shmm_fallback_solve")
 
-    def shmm_macro_step(self, N, d_vx, d_vy, d_K, K_is_field, dt, nsteps, d_u, dtype, stream=0):
-        check(lib().shmm_macro_step(self.h, N, d_vx or None, d_vy or None, d_K, int(K_is_field),
-                                    float(dt), int(nsteps), d_u, int(dtype), stream),
+    def shmm_macro_step(self, N, bc, g0, g1, d_vx, d_vy, d_K, K_is_field, dt, nsteps, d_u, dtype, stream=0):
+        check(lib().shmm_macro_step(self.h, N, int(bc), float(g0), float(g1), d_vx or None, d_vy or None, d_K,
+                                    int(K_is_field), float(dt), int(nsteps), d_u, int(dtype), stream),
               "shmm_macro_step")

@@ -633,16 +633,18 @@ int shmm_ctx_tune(shmm_ctx *ctx, int32_t key, int32_t value) {
     return SHMM_EINVAL;
 }
 
-int shmm_macro_step(shmm_ctx *ctx, int32_t N, const void *d_vx, const void *d_vy, const double *d_K,
-                    int32_t K_is_field, double dt, int32_t nsteps, void *d_u, int32_t dtype,
-                    void *stream) {
+int shmm_macro_step(shmm_ctx *ctx, int32_t N, int32_t bc, double g0, double g1, const void *d_vx,
+                    const void *d_vy, const double *d_K, int32_t K_is_field, double dt, int32_t nsteps,
+                    void *d_u, int32_t dtype, void *stream) {
     if (!ctx || N < 4 || !pow2(N) || !d_K || !d_u || (dtype != 32 && dtype != 64) || nsteps < 0)
         return SHMM_EINVAL;
+    if (bc != SHMM_BC_PERIODIC && bc != SHMM_BC_DIRICHLET_X) return SHMM_EINVAL;
+    if (bc == SHMM_BC_DIRICHLET_X && !(std::isfinite(g0) && std::isfinite(g1))) return SHMM_EINVAL;
     if ((d_vx == nullptr) != (d_vy == nullptr)) return SHMM_EINVAL;
     int rc = set_device(ctx);
     if (rc) return rc;
     if ((rc = ctx->ensure_work(macro_workspace(N, dtype)))) return rc;
-    return launch_macro(N, d_vx, d_vy, d_K, K_is_field, dt, nsteps, d_u, dtype, ctx->work,
+    return launch_macro(N, bc, g0, g1, d_vx, d_vy, d_K, K_is_field, dt, nsteps, d_u, dtype, ctx->work,
                         (hipStream_t)stream);
 }
 

@@ -103,8 +103,8 @@ int surrogate_infer(const void *models, int32_t E, const float *x, const double 
 
 int launch_mark_status(int32_t *status, const int32_t *list, int64_t count, int32_t bits, hipStream_t s);
 
-int launch_macro(int32_t N, const void *vx, const void *vy, const double *K, int32_t K_is_field,
-                 double dt, int32_t nsteps, void *u, int32_t dtype, void *work, hipStream_t s);
+int launch_macro(int32_t N, int32_t bc, double g0, double g1, const void *vx, const void *vy, const double *K,
+                 int32_t K_is_field, double dt, int32_t nsteps, void *u, int32_t dtype, void *work, hipStream_t s);
 size_t macro_workspace(int32_t N, int32_t dtype);
 
 }  // namespace shmm

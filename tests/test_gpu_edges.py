@@ -57,7 +57,7 @@ def test_empty_ranges_are_no_ops(torch):
                           H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(), K.data_ptr(), 0, s)
     u = torch.full((16 * 16,), 2.0, dtype=torch.float64, device="cuda")
     Kc = torch.tensor([[0.1, 0.0, 0.1]], dtype=torch.float64, device="cuda")
-    c.shmm_macro_step(16, 0, 0, Kc.data_ptr(), 0, 0.01, 0, u.data_ptr(), 64, s)
+    c.shmm_macro_step(16, 0, 0.0, 0.0, 0, 0, Kc.data_ptr(), 0, 0.01, 0, u.data_ptr(), 64, s)
     torch.cuda.synchronize()
     for buf in (H.vx, H.vy, H.f1, H.f2, H.w):
         assert bool((buf == 3.0).all())
@@ -104,12 +104,19 @@ def test_invalid_arguments_return_error_codes(torch):
     # macro grid that is not a power of two, unknown dtype, negative step count
     u = torch.zeros(12 * 12, dtype=torch.float64, device="cuda")
     Kc = torch.tensor([[0.1, 0.0, 0.1]], dtype=torch.float64, device="cuda")
-    assert code(lambda: c.shmm_macro_step(12, 0, 0, Kc.data_ptr(), 0, 0.01, 1, u.data_ptr(), 64, s)) \
+    assert code(lambda: c.shmm_macro_step(12, 0, 0.0, 0.0, 0, 0, Kc.data_ptr(), 0, 0.01, 1, u.data_ptr(), 64, s)) \
         == abi.SHMM_EINVAL
-    assert code(lambda: c.shmm_macro_step(16, 0, 0, Kc.data_ptr(), 0, 0.01, 1, u.data_ptr(), 16, s)) \
+    assert code(lambda: c.shmm_macro_step(16, 0, 0.0, 0.0, 0, 0, Kc.data_ptr(), 0, 0.01, 1, u.data_ptr(), 16, s)) \
         == abi.SHMM_EINVAL
-    assert code(lambda: c.shmm_macro_step(16, 0, 0, Kc.data_ptr(), 0, 0.01, -1, u.data_ptr(), 64, s)) \
+    assert code(lambda: c.shmm_macro_step(16, 0, 0.0, 0.0, 0, 0, Kc.data_ptr(), 0, 0.01, -1, u.data_ptr(), 64, s)) \
         == abi.SHMM_EINVAL
+    # unknown boundary condition, non-finite boundary value (a full-size field,
+    # so that nothing could run out of bounds even if a check were missing)
+    u16 = torch.zeros(16 * 16, dtype=torch.float64, device="cuda")
+    assert code(lambda: c.shmm_macro_step(16, 7, 0.0, 0.0, 0, 0, Kc.data_ptr(), 0, 0.01, 1, u16.data_ptr(), 64,
+                                          s)) == abi.SHMM_EINVAL
+    assert code(lambda: c.shmm_macro_step(16, abi.BC_DIRICHLET_X, float("nan"), 0.0, 0, 0, Kc.data_ptr(), 0, 0.01,
+                                          1, u16.data_ptr(), 64, s)) == abi.SHMM_EINVAL
     # unknown tuning key or variant
     with pytest.raises(abi.ShmmError):
         c.shmm_ctx_tune(128, 99)
