@@ -379,6 +379,7 @@ def main():
     ap.add_argument("--uneven-window", type=int, default=2000)
     ap.add_argument("--no-n256", action="store_true", help="skip the 256^2 kernel-variant leg")
     ap.add_argument("--no-paper", action="store_true", help="skip the Section 4 examples")
+    ap.add_argument("--no-adaptive", action="store_true", help="skip the quasi-stationary-stop passes")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="copy this many MiB once before the passes (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -477,6 +478,25 @@ def main():
                      "kernel": SOLVE_KERNELS_128[tuned.get(128, {"variant": 0})["variant"]],
                      "launches": len(ms_launch), "avg_launch_ms": round(avg_ms, 3)},
     }
+    if not args.no_adaptive:
+        # the same passes with the quasi-stationary stop of HMM step 2
+        H.solve_hook = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            H.run(adaptive=True)
+        torch.cuda.synchronize()
+        el_a = time.perf_counter() - t0
+        ra = H.result()
+        rel = np.max(np.abs(ra.K_total - res.K_total), axis=1) / np.max(np.abs(res.K_total), axis=1)
+        out["adaptive"] = {
+            "kappa_eff_estimates_per_s": round(len(ra.R) * args.steps / el_a, 2),
+            "ms_per_pass": round(el_a * 1e3 / args.steps, 3),
+            "steps_taken_fraction": round(ra.point_steps / res.point_steps, 4),
+            "speedup_vs_planned": round(el / el_a, 2),
+            "max_rel_K_vs_planned": float(rel.max()),
+            "rule": "stop when rms(f) rms(dw) rho/(1-rho) <= delta max|K_b|, chunks of plan/32"}
+        log(f"adaptive: {out['adaptive']}")
     H.close()
     if not args.no_continuous:
         log("continuous-spectrum pass ...")

@@ -196,6 +196,27 @@ int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const fl
                            const double *d_K_base, float *d_w, int32_t step_begin,
                            int32_t steps, int32_t *d_status, void *stream);
 
+/* Local solves with the quasi-stationary stop of HMM step 2 (Section 2.2:
+ * evolve until the time derivative is small).  Advances the range in chunks
+ * of ceil(longest plan / chunks) steps (shmm_local_solve_batch, from step 0;
+ * d_w must hold the initial correctors, normally zero) and after each chunk
+ * measures, per domain in FP64, the change of both correctors over the chunk
+ * and the size of the forcings.  The step operator contracts w - chi (chi
+ * the steady corrector) in the mean square at least by rho = exp(-mu C dt)
+ * per chunk of C steps, mu the Poincare rate of shmm_plan_steps, so every
+ * entry of K - K_b = <f_i w_j> is within rms(f_i) rms(Delta w_j) rho/(1-rho)
+ * of its limit.  A domain stops once that bound is at most tol times the
+ * largest entry of its current K (tol = 0: the instance's delta); its plan is cut to
+ * the steps taken, so shmm_ctx_table reports them.  Domains that never meet
+ * the test run their full plan.  Synchronises the stream after every chunk.
+ * Uses a context buffer of 8 B per cell of the range plus 64 B per domain.
+ * Errors: as shmm_local_solve_batch; SHMM_EINVAL for chunks < 1 or a
+ * negative or non-finite tol. */
+int shmm_local_solve_adaptive(shmm_ctx *ctx, int64_t first, int64_t count, const float *d_vx,
+                              const float *d_vy, const float *d_f1, const float *d_f2,
+                              const double *d_K_base, float *d_w, int32_t chunks, double tol,
+                              int32_t *d_status, void *stream);
+
 /* Effective diffusivity of domains [first, first + count) (the K formula after
  * eq:homo with the corrector as chi; HMM step 3): FP64 moments of FP32 data,
  *   d_K_out   = K_b + sym(<f_i w_j>)                       [n_domains][3]

@@ -328,6 +328,43 @@ def local_solve_batch(n: Sequence[int], h: Sequence[float], vx, vy, f1, f2,
     return w.reshape(2, total)
 
 
+def local_solve_adaptive(n: int, h: float, vx, vy, f1, f2, Kb, dt: float, nsteps: int, delta: float,
+                         chunks: int = 32) -> Tuple[np.ndarray, int]:
+    """HMM step 2 of Section 2.2 run to the quasi-stationary state of one
+    domain: chunks of C = ceil(nsteps / chunks) RK4 steps, stopping after the
+    first chunk at which the change dw_j of each corrector over the chunk
+    bounds the remaining error of K below delta times its largest entry.
+
+    The steady corrector chi attracts w in the mean square at least at the
+    Poincare rate mu of the step plan, so over a chunk the error shrinks by
+    rho = exp(-mu C dt) or more, rms(w - chi) <= rho / (1 - rho) rms(dw), and
+    each entry <f_i w_j> of K - K_b is within rms(f_i) rms(w_j - chi_j) of its
+    limit (Cauchy-Schwarz).  Returns (w [2][n n], steps taken); the plan's
+    nsteps caps the count."""
+    f1 = _c(f1, np.float64).reshape(-1)
+    f2 = _c(f2, np.float64).reshape(-1)
+    Kb = _c(Kb, np.float64).reshape(3)
+    C = max(1, -(-int(nsteps) // int(chunks)))
+    lam = 0.5 * (Kb[0] + Kb[2]) - math.sqrt(0.25 * (Kb[0] - Kb[2]) ** 2 + Kb[1] ** 2)
+    mu = lam * 4.0 * math.sin(math.pi / n) ** 2 / (h * h)
+    rho = math.exp(-mu * C * dt)
+    frms = max(math.sqrt(np.mean(f1 * f1)), math.sqrt(np.mean(f2 * f2)))
+    w = np.zeros((2, n * n))
+    done = 0
+    while done < nsteps:
+        c = min(C, nsteps - done)
+        prev = w
+        w = local_solve_batch([n], [h], vx, vy, f1, f2, Kb[None, :], [dt], [c], w0=prev)
+        done += c
+        if done >= nsteps:
+            break
+        dw = max(math.sqrt(np.mean((w[0] - prev[0]) ** 2)), math.sqrt(np.mean((w[1] - prev[1]) ** 2)))
+        scale = float(np.max(np.abs(estimate(f1, f2, w[0], w[1], Kb))))
+        if rho < 1.0 and frms * dw * rho / (1.0 - rho) <= delta * scale:
+            break
+    return w, done
+
+
 def estimate(f1, f2, w1, w2, Kb) -> np.ndarray:
     """K = K_b + sym(<f_i w_j>) (the paper's K = kappa I + (1/2) int (v x chi + chi x v)
     with chi the corrector, here the time-integrated w)."""

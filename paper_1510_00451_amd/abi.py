@@ -21,7 +21,8 @@ MAX_LEVELS = 8
 
 EXPORTS = ["shmm_ctx_create", "shmm_ctx_destroy", "shmm_build_levels", "shmm_ctx_set_problem",
            "shmm_ctx_table", "shmm_band_tags", "shmm_plan_steps", "shmm_band_filter",
-           "shmm_local_solve_batch", "shmm_effective_diffusivity", "shmm_level_chain",
+           "shmm_local_solve_batch", "shmm_local_solve_adaptive", "shmm_effective_diffusivity",
+           "shmm_level_chain",
            "shmm_macro_step", "shmm_ctx_tune", "shmm_patch_features", "shmm_surrogate_refresh",
            "shmm_surrogate_train_step", "shmm_surrogate_infer", "shmm_fallback_solve"]
 
@@ -72,6 +73,7 @@ def lib() -> ctypes.CDLL:
             "shmm_plan_steps": [P, i64, i64, P, P],
             "shmm_band_filter": [P, i64, i64, P, P, P, P, P, P, P],
             "shmm_local_solve_batch": [P, i64, i64, P, P, P, P, P, P, i32, i32, P, P],
+            "shmm_local_solve_adaptive": [P, i64, i64, P, P, P, P, P, P, i32, f64, P, P],
             "shmm_effective_diffusivity": [P, i64, i64, P, P, P, P, P, P, P, P, P],
             "shmm_level_chain": [P, i64, i64, i32, P, P, P, P, P, P, P, P],
             "shmm_macro_step": [P, i32, i32, f64, f64, P, P, P, i32, f64, i32, P, i32, P],
@@ -195,6 +197,12 @@ class Context:
         check(lib().shmm_local_solve_batch(self.h, first, count, d_vx, d_vy, d_f1, d_f2, d_K_base,
                                            d_w, int(step_begin), int(steps), d_status or None,
                                            stream), "shmm_local_solve_batch")
+
+    def shmm_local_solve_adaptive(self, first, count, d_vx, d_vy, d_f1, d_f2, d_K_base, d_w,
+                                  chunks=32, tol=0.0, d_status=0, stream=0):
+        check(lib().shmm_local_solve_adaptive(self.h, first, count, d_vx, d_vy, d_f1, d_f2, d_K_base, d_w,
+                                              int(chunks), float(tol), d_status or None, stream),
+              "shmm_local_solve_adaptive")
 
     def shmm_effective_diffusivity(self, first, count, d_f1, d_f2, d_w, d_K_base, d_K_out,
                                    d_K_energy=0, d_mass=0, d_status=0, stream=0):

@@ -1,6 +1,8 @@
 // Host side of the C ABI: context, bookkeeping of the domain hierarchy, step
 // planning, and the entry points that enqueue the kernels.
 #include <math.h>
+
+#include <cmath>
 #include <stdio.h>
 #include <string.h>
 
@@ -197,6 +199,21 @@ struct shmm_ctx {
     std::map<int, int> solve_variant;          // patch size n -> kernel variant
     void *work = nullptr;
     size_t work_bytes = 0;
+    void *adapt = nullptr;                      // previous correctors and chunk statistics (adaptive stop)
+    size_t adapt_bytes = 0;
+
+    int ensure_adapt(size_t bytes) {
+        if (bytes <= adapt_bytes) return SHMM_OK;
+        if (adapt) {
+            SHMM_HIP_CHECK(hipDeviceSynchronize());
+            SHMM_HIP_CHECK(hipFree(adapt));
+        }
+        adapt = nullptr;
+        adapt_bytes = 0;
+        SHMM_HIP_CHECK(hipMalloc(&adapt, bytes));
+        adapt_bytes = bytes;
+        return SHMM_OK;
+    }
 
     int ensure_work(size_t bytes) {
         if (bytes <= work_bytes) return SHMM_OK;
@@ -330,6 +347,7 @@ int shmm_ctx_destroy(shmm_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     ctx->release();
     if (ctx->work) (void)hipFree(ctx->work);
+    if (ctx->adapt) (void)hipFree(ctx->adapt);
     if (ctx->tmp) (void)hipFree(ctx->tmp);
     for (int i = 0; i < kSideStreams; ++i) {
         if (ctx->side[i]) (void)hipStreamDestroy(ctx->side[i]);
@@ -592,6 +610,85 @@ int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const fl
             SHMM_HIP_CHECK(hipEventRecord(ctx->ev_join[i], ctx->side[i]));
             SHMM_HIP_CHECK(hipStreamWaitEvent(main_s, ctx->ev_join[i], 0));
         }
+    return SHMM_OK;
+}
+
+int shmm_local_solve_adaptive(shmm_ctx *ctx, int64_t first, int64_t count, const float *d_vx,
+                              const float *d_vy, const float *d_f1, const float *d_f2, const double *d_K_base,
+                              float *d_w, int32_t chunks, double tol, int32_t *d_status, void *stream) {
+    if (!range_ok(ctx, first, count) || !d_vx || !d_vy || !d_f1 || !d_f2 || !d_K_base || !d_w || chunks < 1 ||
+        !(tol >= 0.0) || !std::isfinite(tol))
+        return SHMM_EINVAL;
+    if (count == 0) return SHMM_OK;
+    for (int64_t d = first; d < first + count; ++d)
+        if (ctx->table[d].nsteps < 0 || ctx->table[d].dt < 0.0) return SHMM_EINVAL;   // unplanned
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t longest = 0;
+    for (int64_t d = first; d < first + count; ++d) longest = std::max(longest, ctx->table[d].nsteps);
+    if (longest == 0) return SHMM_OK;
+    const int32_t C = (int32_t)(((int64_t)longest + chunks - 1) / chunks);
+    const shmm_domain &last = ctx->table[first + count - 1];
+    const int64_t base = ctx->table[first].offset;
+    const int64_t rcells = last.offset + (int64_t)last.n * last.n - base;
+    const size_t prev_bytes = (size_t)2 * rcells * sizeof(float);
+    if ((rc = ctx->ensure_adapt(prev_bytes + (size_t)8 * count * sizeof(double)))) return rc;
+    float *w_prev = (float *)ctx->adapt;
+    double *d_stats = (double *)((char *)ctx->adapt + prev_bytes);
+    std::vector<double> Kb(3 * count), stats(8 * count);
+    SHMM_HIP_CHECK(hipMemcpyAsync(Kb.data(), d_K_base + 3 * first, Kb.size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+    for (int j = 0; j < 2; ++j)
+        SHMM_HIP_CHECK(hipMemcpyAsync(w_prev + j * rcells, d_w + j * ctx->cells + base, rcells * sizeof(float),
+                                      hipMemcpyDeviceToDevice, s));
+    SHMM_HIP_CHECK(hipStreamSynchronize(s));
+    for (int32_t s0 = 0; s0 < longest; s0 += C) {
+        if ((rc = shmm_local_solve_batch(ctx, first, count, d_vx, d_vy, d_f1, d_f2, d_K_base, d_w, s0, C, d_status,
+                                         stream)))
+            return rc;
+        if ((rc = launch_chunk_delta(ctx->d_table, first, count, d_f1, d_f2, d_w, ctx->cells, w_prev, rcells, base,
+                                     d_stats, s)))
+            return rc;
+        SHMM_HIP_CHECK(hipMemcpyAsync(stats.data(), d_stats, stats.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        SHMM_HIP_CHECK(hipStreamSynchronize(s));
+        const int64_t done = (int64_t)s0 + C;
+        bool running = false, changed = false;
+        for (int64_t i = 0; i < count; ++i) {
+            shmm_domain &D = ctx->table[first + i];
+            if ((int64_t)D.nsteps <= done) continue;   // finished with this chunk, or never started
+            // The step operator contracts the error w - chi (chi the steady
+            // corrector) at least by rho = exp(-mu C dt) per chunk in the mean
+            // square, mu the Poincare rate of the step plan, so
+            //   rms(w - chi) <= rho / (1 - rho) rms(w - w_prev),
+            // and every entry of K - K_b = <f_i w_j> is then within
+            // rms(f_i) rms(w_j - chi_j) of its limit; compared with the
+            // largest entry of the current K.
+            const double *k = Kb.data() + 3 * i;
+            const double lam = 0.5 * (k[0] + k[2]) - std::sqrt(0.25 * (k[0] - k[2]) * (k[0] - k[2]) + k[1] * k[1]);
+            const double sn = std::sin(M_PI / D.n);
+            const double mu = lam * 4.0 * sn * sn / (D.h * D.h);
+            const double rho = std::exp(-mu * (double)C * D.dt);
+            const double cells = (double)D.n * D.n;
+            const double *st = stats.data() + 8 * i;
+            const double dw = std::sqrt(std::max(st[0], st[1]) / cells), fr = std::sqrt(std::max(st[2], st[3]) / cells);
+            const double bound = fr * dw * rho / (1.0 - rho);
+            const double t = tol > 0.0 ? tol : ctx->probs[D.instance].delta;
+            const double K11 = k[0] + st[4] / cells, K12 = k[1] + 0.5 * (st[5] + st[6]) / cells,
+                         K22 = k[2] + st[7] / cells;
+            const double scale = std::max(std::fabs(K11), std::max(std::fabs(K12), std::fabs(K22)));
+            if (rho < 1.0 && bound <= t * scale) {
+                D.nsteps = (int32_t)done;
+                changed = true;
+            } else {
+                running = true;
+            }
+        }
+        if (changed)
+            SHMM_HIP_CHECK(hipMemcpy(ctx->d_table + first, ctx->table.data() + first, count * sizeof(shmm_domain),
+                                     hipMemcpyHostToDevice));
+        if (!running) break;
+    }
     return SHMM_OK;
 }
 

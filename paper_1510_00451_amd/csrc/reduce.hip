@@ -94,6 +94,55 @@ __global__ __launch_bounds__(kRedThreads) void k_moments(
     }
 }
 
+// Change of both correctors over the last chunk of steps, for the adaptive
+// stop of the local solves: out[8 i + q] for domain first + i holds the sums
+// over its cells of (w_j - w_prev_j)^2 (q = 0, 1), f_j^2 (q = 2, 3) and
+// f_i w_j (q = 4 + 2 (i - 1) + (j - 1)), FP64 in a fixed order; then
+// w_prev <- w.  w_prev covers the range only: [2][prev_cells], cell c of
+// domain d at d.offset - prev_base + c.
+constexpr int kDeltaVals = 8;
+
+__global__ __launch_bounds__(kRedThreads) void k_chunk_delta(
+    const shmm_domain *__restrict__ dom, int64_t first, const float *__restrict__ f1,
+    const float *__restrict__ f2, const float *__restrict__ w, int64_t cells_total, float *__restrict__ w_prev,
+    int64_t prev_cells, int64_t prev_base, double *__restrict__ out) {
+    __shared__ double part[kRedThreads / 64][kDeltaVals];
+    const shmm_domain D = dom[first + blockIdx.x];
+    const int cells = D.n * D.n;
+    const int64_t o = D.offset, po = D.offset - prev_base;
+    double v[kDeltaVals];
+#pragma unroll
+    for (int q = 0; q < kDeltaVals; ++q) v[q] = 0.0;
+    for (int c = threadIdx.x; c < cells; c += kRedThreads) {
+        const float a = w[o + c], b = w[cells_total + o + c];
+        const double da = (double)a - (double)w_prev[po + c];
+        const double db = (double)b - (double)w_prev[prev_cells + po + c];
+        const double g1 = f1[o + c], g2 = f2[o + c];
+        v[0] += da * da;
+        v[1] += db * db;
+        v[2] += g1 * g1;
+        v[3] += g2 * g2;
+        v[4] += g1 * (double)a;
+        v[5] += g1 * (double)b;
+        v[6] += g2 * (double)a;
+        v[7] += g2 * (double)b;
+        w_prev[po + c] = a;
+        w_prev[prev_cells + po + c] = b;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kDeltaVals; ++q) {
+        const double t = wave_sum(v[q]);
+        if (lane == 0) part[wave][q] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < kDeltaVals) {
+        double t = 0.0;
+        for (int wv = 0; wv < kRedThreads / 64; ++wv) t += part[wv][threadIdx.x];
+        out[kDeltaVals * (int64_t)blockIdx.x + threadIdx.x] = t;
+    }
+}
+
 // Algorithm 1: line-wise shear formula (eq:shearhomoY for the columns of the
 // off-12 band, eq:shearhomoX for the rows of the off-21 band), then the
 // harmonic mean across lines; the other diagonal entry and K12 pass through.
@@ -218,6 +267,16 @@ int launch_effective_diffusivity(const shmm_domain *d_dom, int64_t first, int64_
     if (count <= 0) return SHMM_OK;
     hipLaunchKernelGGL(k_moments, dim3((unsigned)count), dim3(kRedThreads), 0, s, d_dom, first, f1, f2,
                        w, cells_total, Kb, K_out, K_energy, mass, status, (const int32_t *)nullptr);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
+
+int launch_chunk_delta(const shmm_domain *d_dom, int64_t first, int64_t count, const float *f1, const float *f2,
+                       const float *w, int64_t cells_total, float *w_prev, int64_t prev_cells, int64_t prev_base,
+                       double *out, hipStream_t s) {
+    if (count <= 0) return SHMM_OK;
+    hipLaunchKernelGGL(k_chunk_delta, dim3((unsigned)count), dim3(kRedThreads), 0, s, d_dom, first, f1, f2, w,
+                       cells_total, w_prev, prev_cells, prev_base, out);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
 }

@@ -72,6 +72,9 @@ class Hierarchy:
         self.level0 = np.flatnonzero(self.table["level"] == 0)
         # optional callable(first, count, launch) wrapped around each solve launch
         self.solve_hook = None
+        # quasi-stationary stop: chunks per plan, tolerance (0: each instance's delta)
+        self.adaptive_chunks = 32
+        self.adaptive_tol = 0.0
 
     # -- pieces -------------------------------------------------------------
     def stream(self) -> int:
@@ -100,7 +103,7 @@ class Hierarchy:
             self.ctx.shmm_level_chain(first, count, MODE_TOPDOWN, self.lines.data_ptr(),
                                       self.K_in.data_ptr(), self.K_off.data_ptr(), stream=s)
 
-    def phase_solve(self, p: int, steps: Optional[int] = None) -> None:
+    def phase_solve(self, p: int, steps: Optional[int] = None, adaptive: bool = False) -> None:
         s = self.stream()
         first, count = int(self.phase[p]), int(self.phase[p + 1] - self.phase[p])
         c = self.ctx
@@ -113,6 +116,13 @@ class Hierarchy:
         a, b = self.cell_range(first, count)
         self.w.view(2, self.cells)[:, a:b].zero_()
         def launch():
+            if adaptive:
+                # quasi-stationary stop (plans cut to the steps taken)
+                c.shmm_local_solve_adaptive(first, count, self.vx.data_ptr(), self.vy.data_ptr(),
+                                            self.f1.data_ptr(), self.f2.data_ptr(), self.K_base.data_ptr(),
+                                            self.w.data_ptr(), self.adaptive_chunks, self.adaptive_tol,
+                                            self.status.data_ptr(), s)
+                return
             c.shmm_local_solve_batch(first, count, self.vx.data_ptr(), self.vy.data_ptr(),
                                      self.f1.data_ptr(), self.f2.data_ptr(), self.K_base.data_ptr(),
                                      self.w.data_ptr(), 0, 2 ** 31 - 1 if steps is None else steps,
@@ -130,13 +140,14 @@ class Hierarchy:
                            self.K_off.data_ptr(), self.K_base.data_ptr(), self.K_solve.data_ptr(),
                            self.R.data_ptr(), self.status.data_ptr(), s)
 
-    def run(self, steps: Optional[int] = None) -> None:
-        """One pass of the hot path (asynchronous apart from the per-phase plan)."""
+    def run(self, steps: Optional[int] = None, adaptive: bool = False) -> None:
+        """One pass of the hot path (asynchronous apart from the per-phase plan;
+        with `adaptive`, the local solves stop at the quasi-stationary test)."""
         self.status.zero_()
         self.band_filter()
         self.top_down()
         for p in range(len(self.phase) - 1):
-            self.phase_solve(p, steps)
+            self.phase_solve(p, steps, adaptive)
 
     # -- results ------------------------------------------------------------
     def result(self) -> PassResult:

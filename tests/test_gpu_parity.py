@@ -266,6 +266,71 @@ def test_tile_paths_follow_each_patch_plan(torch):
     H.close()
 
 
+@pytest.mark.parametrize("n", [32, 64])
+def test_quasi_stationary_stop_parity(torch, n):
+    """The adaptive stop (shmm_local_solve_adaptive): each patch's K matches the
+    oracle's fully planned K within 1e-5; a patch stops at a chunk boundary
+    or runs its whole plan (when FP32 rounding keeps the change over a chunk
+    above what the bound needs), never more than two chunks before the FP64
+    oracle stops under the same rule; the batch takes fewer steps than its
+    plan, and the table reports the steps taken."""
+    p = _single_level(n, seed=n + 1, amp=0.5, kappa=0.05)
+    say("case quasi-stationary stop n=%d" % n)
+    H = hier(p, keep_psi=False)
+    H.band_filter()
+    Kb = np.tile([0.05, 0.01, 0.04], (H.nd, 1))
+    H.K_base.copy_(torch.from_numpy(Kb))
+    H.ctx.shmm_plan_steps(0, H.nd, Kb)
+    planned = H.ctx.shmm_ctx_table()[0]
+    ns_plan = planned["nsteps"].astype(np.int64).copy()
+    dts = planned["dt"].copy()
+    H.w.zero_()
+    H.ctx.shmm_local_solve_adaptive(0, H.nd, H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(),
+                                    H.K_base.data_ptr(), H.w.data_ptr(), 32, 0.0, 0, H.stream())
+    H.ctx.shmm_effective_diffusivity(0, H.nd, H.f1.data_ptr(), H.f2.data_ptr(), H.w.data_ptr(),
+                                     H.K_base.data_ptr(), H.K_solve.data_ptr(), 0, 0, 0, H.stream())
+    torch.cuda.synchronize()
+    table = H.ctx.shmm_ctx_table()[0]
+    taken = table["nsteps"].astype(np.int64)
+    K = H.K_solve.cpu().numpy()
+    lv, pt = oracle.band_split(p.kmax, p.thresh)
+    mask = oracle.band_mask(lv, pt, 0, DIAG)
+    for d in range(H.nd):
+        D = table[d]
+        C = -(-int(ns_plan.max()) // 32)
+        assert taken[d] == ns_plan[d] or (taken[d] < ns_plan[d] and taken[d] % C == 0), (d, taken[d], C)
+        psi = oracle.synth_patch(p.psi_hat, p.kmax, mask, int(D["N"]), int(D["I0"]), int(D["J0"]), n)
+        vx, vy, f1, f2 = oracle.staggered(psi, float(D["h"]))
+        wr = oracle.local_solve_batch([n], [float(D["h"])], vx.ravel(), vy.ravel(), f1.ravel(), f2.ravel(),
+                                      Kb[d:d + 1], [float(dts[d])], [int(ns_plan[d])])
+        Kr = oracle.estimate(f1, f2, wr[0].reshape(n, n), wr[1].reshape(n, n), Kb[d])
+        assert np.max(np.abs(K[d] - Kr)) <= 1e-5 * np.max(np.abs(Kr)), (d, K[d], Kr)
+        _, t_or = oracle.local_solve_adaptive(n, float(D["h"]), vx, vy, f1, f2, Kb[d], float(dts[d]),
+                                              int(ns_plan[d]), p.delta, chunks=32)
+        # the oracle chunks its own plan; the GPU chunks the range's longest plan
+        assert int(taken[d]) >= t_or - 2 * max(C, -(-int(ns_plan[d]) // 32)), (d, taken[d], t_or)
+    say("  steps taken / planned: %.2f" % (taken.sum() / ns_plan.sum()))
+    assert taken.sum() < ns_plan.sum()
+    H.close()
+
+
+def test_quasi_stationary_pass_matches_the_planned_pass(torch):
+    """A whole two-level pass with the adaptive stop against the oracle's
+    fully planned pass (the two-level cellular flow): every level result
+    within 1e-5, with fewer steps in all."""
+    p = flowgen.config_two_level_cellular()
+    say("case quasi-stationary pass")
+    H = hier(p, keep_psi=False)
+    H.run(adaptive=True)
+    r = H.result()
+    ref = oracle.run_hierarchy(p)
+    for d in range(H.nd):
+        assert np.max(np.abs(r.R[d] - ref.R[d])) <= 1e-5 * np.max(np.abs(ref.R[d])), (d, r.R[d], ref.R[d])
+    assert np.all(r.nsteps <= ref.nsteps + 1) and r.nsteps.sum() < ref.nsteps.sum()
+    say("  steps taken / planned: %.2f" % (r.nsteps.sum() / ref.nsteps.sum()))
+    H.close()
+
+
 def test_zero_band_returns_base_exactly(torch):
     kmax = 4
     p = flowgen.Problem(kappa=0.02, kmax=kmax, psi_hat=np.zeros((9, 9), complex), thresh=[],

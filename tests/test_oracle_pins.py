@@ -512,6 +512,36 @@ def test_macro_dirichlet_uniform_flow_reaches_the_discrete_steady_state():
     assert np.max(np.abs(u - u_ss[None, :])) <= 1e-12
 
 
+# ---------------------------------------------------------------- quasi-stationary stop
+
+def test_quasi_stationary_stop_keeps_k_within_its_bound():
+    """HMM step 2 evolves each local problem until it is quasi-stationary.  The
+    adaptive stop ends a solve once the change of the correctors over a chunk
+    bounds the remaining error of K below delta times the base; against the
+    steady K (a plan to delta = 1e-12) the stopped K must be inside that
+    bound (relative to K), with fewer steps than the a-priori plan to
+    delta = 1e-6."""
+    p = flowgen.config_four_level_cellular(n=32, lattice=2)
+    r = oracle.run_hierarchy(p)
+    lv, pt = oracle.band_split(p.kmax, p.thresh)
+    for d in (0, 4, 8, 12):                          # one patch per level
+        D = r.domains[d]
+        psi = oracle.synth_patch(p.psi_hat, p.kmax, oracle.band_mask(lv, pt, D.level, DIAG), D.N, D.I0, D.J0, D.n)
+        vx, vy, f1, f2 = oracle.staggered(psi, D.h)
+        Kb = r.K_base[d]
+        vb = oracle.advection_bound(vx, vy)
+        dt6, ns6 = oracle.plan_steps(D.n, D.h, Kb, vb, 0.5, 1e-6)
+        dt12, ns12 = oracle.plan_steps(D.n, D.h, Kb, vb, 0.5, 1e-12)
+        w, taken = oracle.local_solve_adaptive(D.n, D.h, vx, vy, f1, f2, Kb, dt6, ns6, 1e-6)
+        ws = oracle.local_solve_batch([D.n], [D.h], vx.ravel(), vy.ravel(), f1.ravel(), f2.ravel(), Kb[None, :],
+                                      [dt12], [ns12])
+        n = D.n
+        K = oracle.estimate(f1, f2, w[0].reshape(n, n), w[1].reshape(n, n), Kb)
+        Ks = oracle.estimate(f1, f2, ws[0].reshape(n, n), ws[1].reshape(n, n), Kb)
+        assert np.max(np.abs(K - Ks)) <= 1e-6 * np.max(np.abs(K)), (d, K, Ks)
+        assert taken < 0.6 * ns6, (d, taken, ns6)
+
+
 # ---------------------------------------------------------------- Section 4, Tests 2 and 3
 
 def _paper_gap(test):
