@@ -495,7 +495,7 @@ def main():
             "steps_taken_fraction": round(ra.point_steps / res.point_steps, 4),
             "speedup_vs_planned": round(el / el_a, 2),
             "max_rel_K_vs_planned": float(rel.max()),
-            "rule": "stop when rms(f) rms(dw) rho/(1-rho) <= delta max|K_b|, chunks of plan/32"}
+            "rule": "stop when rms(f) rms(dw) rho/(1-rho) <= delta max|K|, chunks of plan/32"}
         log(f"adaptive: {out['adaptive']}")
     H.close()
     if not args.no_continuous:
