@@ -109,7 +109,7 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
     per = max(1, 1024 // (lattice * lattice))          # about 1024 finest patches per batch
     batches = ([flowgen.config_batched_instance(100000 + i + j, n=128, lattice=lattice)
                 for j in range(min(per, flows_train - i))] for i in range(0, flows_train, per))
-    data = GS.labelled_set(batches, log=log)
+    data = GS.labelled_set(batches, log=log, adaptive=True)
     t_label = time.perf_counter() - t0
     held, train = GS.split(data, 0.1, seed=0)
     rng = np.random.default_rng(1)
@@ -147,8 +147,27 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
     t_plain, t_surr = b - a, c - b
     act = ph.active
     n_est = int(act.sum())
-    errs = [GS.relative_frobenius(Ks.cpu().numpy()[act], Kp.cpu().numpy()[act])]
+    Kp_h, Ks_h = Kp.cpu().numpy().copy(), Ks.cpu().numpy().copy()
+    errs = [GS.relative_frobenius(Ks_h[act], Kp_h[act])]
     flagged = [ph.flags.cpu().numpy()[act].astype(bool)]
+    # both forms again with the quasi-stationary stop (plain solves and fallback)
+    ph.prepare()
+    planned_steps = ph.point_steps
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    ph.prepare()
+    Kpa = ph.plain(adaptive=True)
+    torch.cuda.synchronize()
+    b = time.perf_counter()
+    tab = ph.H.ctx.shmm_ctx_table()[0][ph.first:ph.first + ph.count]
+    taken = int(np.sum(tab["n"].astype(np.int64) ** 2 * tab["nsteps"].astype(np.int64)))
+    Kpa_h = Kpa.cpu().numpy().copy()
+    ph.prepare()
+    Ksa = ph.surrogate(ens, lo, hi, tau, emax, adaptive=True)
+    torch.cuda.synchronize()
+    c = time.perf_counter()
+    t_plain_a, t_surr_a = b - a, c - b
+    err_a = GS.relative_frobenius(Ksa.cpu().numpy()[act], Kp_h[act])
     ph.close()
     err = np.concatenate(errs)
     fl = np.concatenate(flagged)
@@ -160,6 +179,13 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
         "err_vs_plain": {"mean": float(err.mean()), "p99": float(np.quantile(err, 0.99)),
                          "max": float(err.max()), "frac_over_1pct": float(np.mean(err > 0.01))},
         "fallback_frac": float(fl.mean()),
+        "adaptive": {"estimates_per_s": round(n_est / t_surr_a, 1),
+                     "plain_estimates_per_s": round(n_est / t_plain_a, 1),
+                     "speedup": round(t_plain_a / t_surr_a, 2),
+                     "plain_steps_taken_fraction": round(taken / planned_steps, 4),
+                     "plain_max_rel_K_vs_planned": float(np.max(GS.relative_frobenius(Kpa_h[act], Kp_h[act]))),
+                     "err_vs_planned_plain": {"mean": float(err_a.mean()), "p99": float(np.quantile(err_a, 0.99)),
+                                              "max": float(err_a.max())}},
         "tau": tau, "emax": emax if math.isfinite(emax) else None, "held_out_accepted": round(held_acc, 4),
         "eval": f"{flows_eval} continuous-spectrum flows (kappa 1e-3, 1<=|k|<=512, |psi_k|~|k|^-7/3) x "
                 f"256 finest-level 128^2 patches, isotropic base; {n_est} estimates",

@@ -363,13 +363,16 @@ int shmm_surrogate_infer(shmm_ctx *ctx, const void *d_models, int32_t E, const f
 
 /* Plain-solve fallback for the flagged domains of [first, first + count)
  * (d_flags[i] for domain first + i): zero their correctors, run the planned
- * local solves and write their effective diffusivity into d_K_out
- * [n_domains][3] (overwriting the surrogate's), setting SHMM_DOM_FALLBACK in
- * d_status.  Reads the flags back to the host (synchronises the stream). */
+ * local solves (chunks = 0) or the quasi-stationary stop of
+ * shmm_local_solve_adaptive with `chunks` and `tol` (chunks >= 1), and write
+ * their effective diffusivity into d_K_out [n_domains][3] (overwriting the
+ * surrogate's), setting SHMM_DOM_FALLBACK in d_status.  Reads the flags back
+ * to the host (synchronises the stream).  Errors: SHMM_EINVAL for a range
+ * that was never planned, chunks < 0, or a negative or non-finite tol. */
 int shmm_fallback_solve(shmm_ctx *ctx, int64_t first, int64_t count, const uint8_t *d_flags,
                         const float *d_vx, const float *d_vy, const float *d_f1, const float *d_f2,
-                        const double *d_K_base, float *d_w, double *d_K_out, int32_t *d_status,
-                        void *stream);
+                        const double *d_K_base, float *d_w, double *d_K_out, int32_t chunks, double tol,
+                        int32_t *d_status, void *stream);
 
 #ifdef __cplusplus
 }

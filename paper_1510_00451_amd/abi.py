@@ -82,7 +82,7 @@ def lib() -> ctypes.CDLL:
             "shmm_surrogate_refresh": [P, P, P],
             "shmm_surrogate_train_step": [P, P, P, P, P, P, i64, ctypes.c_float, ctypes.c_float, i32, P, P, P],
             "shmm_surrogate_infer": [P, P, i32, P, P, i64, P, P, f64, f64, P, P, P, P, P],
-            "shmm_fallback_solve": [P, i64, i64, P, P, P, P, P, P, P, P, P, P],
+            "shmm_fallback_solve": [P, i64, i64, P, P, P, P, P, P, P, P, i32, f64, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -246,9 +246,10 @@ class Context:
                                          d_K_members or None, stream), "shmm_surrogate_infer")
 
     def shmm_fallback_solve(self, first, count, d_flags, d_vx, d_vy, d_f1, d_f2, d_K_base, d_w, d_K_out,
-                            d_status=0, stream=0):
+                            chunks=0, tol=0.0, d_status=0, stream=0):
         check(lib().shmm_fallback_solve(self.h, first, count, d_flags, d_vx, d_vy, d_f1, d_f2, d_K_base,
-                                        d_w, d_K_out, d_status or None, stream), "shmm_fallback_solve")
+                                        d_w, d_K_out, int(chunks), float(tol), d_status or None, stream),
+              "shmm_fallback_solve")
 
     def shmm_macro_step(self, N, bc, g0, g1, d_vx, d_vy, d_K, K_is_field, dt, nsteps, d_u, dtype, stream=0):
         check(lib().shmm_macro_step(self.h, N, int(bc), float(g0), float(g1), d_vx or None, d_vy or None, d_K,

@@ -328,6 +328,94 @@ static bool range_ok(shmm_ctx *ctx, int64_t first, int64_t count) {
     return ctx && first >= 0 && count >= 0 && first + count <= (int64_t)ctx->table.size();
 }
 
+// Quasi-stationary stop (HMM step 2) over the domains `ids`: contiguous in
+// the table when d_list is null, else all of one size with d_list their
+// device copy.  advance(s0, C) runs steps [s0, s0 + C) of every listed domain
+// (capped by its plan).  After each chunk the change of both correctors over
+// the chunk, the forcings and <f_i w_j> are measured in FP64.  The step
+// operator contracts the error w - chi (chi the steady corrector) at least by
+// rho = exp(-mu C dt) per chunk in the mean square, mu the Poincare rate of
+// the step plan, so rms(w - chi) <= rho / (1 - rho) rms(w - w_prev), and every
+// entry of K - K_b = <f_i w_j> is within rms(f_i) rms(w_j - chi_j) of its
+// limit.  A domain stops once that is at most tol (0: its instance's delta)
+// times the largest entry of its current K: its plan is cut to the steps
+// taken.  Synchronises the stream after every chunk.
+template <typename Advance>
+static int adaptive_loop(shmm_ctx *ctx, const std::vector<int32_t> &ids, const int32_t *d_list, const float *d_f1,
+                         const float *d_f2, const double *d_K_base, float *d_w, int32_t chunks, double tol,
+                         hipStream_t s, Advance advance) {
+    const int64_t count = (int64_t)ids.size();
+    if (count == 0) return SHMM_OK;
+    int32_t longest = 0;
+    for (int32_t d : ids) longest = std::max(longest, ctx->table[d].nsteps);
+    if (longest == 0) return SHMM_OK;
+    const int32_t C = (int32_t)(((int64_t)longest + chunks - 1) / chunks);
+    int64_t base = 0, rcells = 0;
+    if (d_list) {
+        rcells = count * (int64_t)ctx->table[ids[0]].n * ctx->table[ids[0]].n;
+    } else {
+        const shmm_domain &last = ctx->table[ids.back()];
+        base = ctx->table[ids[0]].offset;
+        rcells = last.offset + (int64_t)last.n * last.n - base;
+    }
+    const size_t prev_bytes = (size_t)2 * rcells * sizeof(float);
+    int rc = ctx->ensure_adapt(prev_bytes + (size_t)8 * count * sizeof(double));
+    if (rc) return rc;
+    float *w_prev = (float *)ctx->adapt;
+    double *d_stats = (double *)((char *)ctx->adapt + prev_bytes);
+    const int64_t nd = (int64_t)ctx->table.size();
+    std::vector<double> Kb(3 * nd), stats(8 * count);
+    SHMM_HIP_CHECK(hipMemcpyAsync(Kb.data(), d_K_base, Kb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    // w_prev <- the initial correctors (the statistics of this pass are discarded)
+    if ((rc = launch_chunk_delta(ctx->d_table, ids[0], d_list, count, d_f1, d_f2, d_w, ctx->cells, w_prev, rcells,
+                                 base, d_stats, s)))
+        return rc;
+    SHMM_HIP_CHECK(hipStreamSynchronize(s));
+    for (int32_t s0 = 0; s0 < longest; s0 += C) {
+        if ((rc = advance(s0, C))) return rc;
+        if ((rc = launch_chunk_delta(ctx->d_table, ids[0], d_list, count, d_f1, d_f2, d_w, ctx->cells, w_prev,
+                                     rcells, base, d_stats, s)))
+            return rc;
+        SHMM_HIP_CHECK(hipMemcpyAsync(stats.data(), d_stats, stats.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        SHMM_HIP_CHECK(hipStreamSynchronize(s));
+        const int64_t done = (int64_t)s0 + C;
+        bool running = false, changed = false;
+        for (int64_t i = 0; i < count; ++i) {
+            shmm_domain &D = ctx->table[ids[i]];
+            if ((int64_t)D.nsteps <= done) continue;   // finished with this chunk, or never started
+            const double *k = Kb.data() + 3 * (int64_t)ids[i];
+            const double lam = 0.5 * (k[0] + k[2]) - std::sqrt(0.25 * (k[0] - k[2]) * (k[0] - k[2]) + k[1] * k[1]);
+            const double sn = std::sin(M_PI / D.n);
+            const double mu = lam * 4.0 * sn * sn / (D.h * D.h);
+            const double rho = std::exp(-mu * (double)C * D.dt);
+            const double cells = (double)D.n * D.n;
+            const double *st = stats.data() + 8 * i;
+            const double dw = std::sqrt(std::max(st[0], st[1]) / cells), fr = std::sqrt(std::max(st[2], st[3]) / cells);
+            const double bound = fr * dw * rho / (1.0 - rho);
+            const double t = tol > 0.0 ? tol : ctx->probs[D.instance].delta;
+            const double K11 = k[0] + st[4] / cells, K12 = k[1] + 0.5 * (st[5] + st[6]) / cells,
+                         K22 = k[2] + st[7] / cells;
+            const double scale = std::max(std::fabs(K11), std::max(std::fabs(K12), std::fabs(K22)));
+            if (rho < 1.0 && bound <= t * scale) {
+                D.nsteps = (int32_t)done;
+                changed = true;
+            } else {
+                running = true;
+            }
+        }
+        if (changed) {
+            if (d_list)
+                SHMM_HIP_CHECK(hipMemcpy(ctx->d_table, ctx->table.data(), nd * sizeof(shmm_domain),
+                                         hipMemcpyHostToDevice));
+            else
+                SHMM_HIP_CHECK(hipMemcpy(ctx->d_table + ids[0], ctx->table.data() + ids[0],
+                                         count * sizeof(shmm_domain), hipMemcpyHostToDevice));
+        }
+        if (!running) break;
+    }
+    return SHMM_OK;
+}
+
 extern "C" {
 
 int shmm_ctx_create(shmm_ctx **ctx, int device) {
@@ -624,72 +712,13 @@ int shmm_local_solve_adaptive(shmm_ctx *ctx, int64_t first, int64_t count, const
         if (ctx->table[d].nsteps < 0 || ctx->table[d].dt < 0.0) return SHMM_EINVAL;   // unplanned
     int rc = set_device(ctx);
     if (rc) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    int32_t longest = 0;
-    for (int64_t d = first; d < first + count; ++d) longest = std::max(longest, ctx->table[d].nsteps);
-    if (longest == 0) return SHMM_OK;
-    const int32_t C = (int32_t)(((int64_t)longest + chunks - 1) / chunks);
-    const shmm_domain &last = ctx->table[first + count - 1];
-    const int64_t base = ctx->table[first].offset;
-    const int64_t rcells = last.offset + (int64_t)last.n * last.n - base;
-    const size_t prev_bytes = (size_t)2 * rcells * sizeof(float);
-    if ((rc = ctx->ensure_adapt(prev_bytes + (size_t)8 * count * sizeof(double)))) return rc;
-    float *w_prev = (float *)ctx->adapt;
-    double *d_stats = (double *)((char *)ctx->adapt + prev_bytes);
-    std::vector<double> Kb(3 * count), stats(8 * count);
-    SHMM_HIP_CHECK(hipMemcpyAsync(Kb.data(), d_K_base + 3 * first, Kb.size() * sizeof(double),
-                                  hipMemcpyDeviceToHost, s));
-    for (int j = 0; j < 2; ++j)
-        SHMM_HIP_CHECK(hipMemcpyAsync(w_prev + j * rcells, d_w + j * ctx->cells + base, rcells * sizeof(float),
-                                      hipMemcpyDeviceToDevice, s));
-    SHMM_HIP_CHECK(hipStreamSynchronize(s));
-    for (int32_t s0 = 0; s0 < longest; s0 += C) {
-        if ((rc = shmm_local_solve_batch(ctx, first, count, d_vx, d_vy, d_f1, d_f2, d_K_base, d_w, s0, C, d_status,
-                                         stream)))
-            return rc;
-        if ((rc = launch_chunk_delta(ctx->d_table, first, count, d_f1, d_f2, d_w, ctx->cells, w_prev, rcells, base,
-                                     d_stats, s)))
-            return rc;
-        SHMM_HIP_CHECK(hipMemcpyAsync(stats.data(), d_stats, stats.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        SHMM_HIP_CHECK(hipStreamSynchronize(s));
-        const int64_t done = (int64_t)s0 + C;
-        bool running = false, changed = false;
-        for (int64_t i = 0; i < count; ++i) {
-            shmm_domain &D = ctx->table[first + i];
-            if ((int64_t)D.nsteps <= done) continue;   // finished with this chunk, or never started
-            // The step operator contracts the error w - chi (chi the steady
-            // corrector) at least by rho = exp(-mu C dt) per chunk in the mean
-            // square, mu the Poincare rate of the step plan, so
-            //   rms(w - chi) <= rho / (1 - rho) rms(w - w_prev),
-            // and every entry of K - K_b = <f_i w_j> is then within
-            // rms(f_i) rms(w_j - chi_j) of its limit; compared with the
-            // largest entry of the current K.
-            const double *k = Kb.data() + 3 * i;
-            const double lam = 0.5 * (k[0] + k[2]) - std::sqrt(0.25 * (k[0] - k[2]) * (k[0] - k[2]) + k[1] * k[1]);
-            const double sn = std::sin(M_PI / D.n);
-            const double mu = lam * 4.0 * sn * sn / (D.h * D.h);
-            const double rho = std::exp(-mu * (double)C * D.dt);
-            const double cells = (double)D.n * D.n;
-            const double *st = stats.data() + 8 * i;
-            const double dw = std::sqrt(std::max(st[0], st[1]) / cells), fr = std::sqrt(std::max(st[2], st[3]) / cells);
-            const double bound = fr * dw * rho / (1.0 - rho);
-            const double t = tol > 0.0 ? tol : ctx->probs[D.instance].delta;
-            const double K11 = k[0] + st[4] / cells, K12 = k[1] + 0.5 * (st[5] + st[6]) / cells,
-                         K22 = k[2] + st[7] / cells;
-            const double scale = std::max(std::fabs(K11), std::max(std::fabs(K12), std::fabs(K22)));
-            if (rho < 1.0 && bound <= t * scale) {
-                D.nsteps = (int32_t)done;
-                changed = true;
-            } else {
-                running = true;
-            }
-        }
-        if (changed)
-            SHMM_HIP_CHECK(hipMemcpy(ctx->d_table + first, ctx->table.data() + first, count * sizeof(shmm_domain),
-                                     hipMemcpyHostToDevice));
-        if (!running) break;
-    }
-    return SHMM_OK;
+    std::vector<int32_t> ids(count);
+    for (int64_t i = 0; i < count; ++i) ids[i] = (int32_t)(first + i);
+    return adaptive_loop(ctx, ids, nullptr, d_f1, d_f2, d_K_base, d_w, chunks, tol, (hipStream_t)stream,
+                         [&](int32_t s0, int32_t C) {
+                             return shmm_local_solve_batch(ctx, first, count, d_vx, d_vy, d_f1, d_f2, d_K_base,
+                                                           d_w, s0, C, d_status, stream);
+                         });
 }
 
 int shmm_effective_diffusivity(shmm_ctx *ctx, int64_t first, int64_t count, const float *d_f1,
@@ -801,10 +830,10 @@ int shmm_surrogate_infer(shmm_ctx *ctx, const void *d_models, int32_t E, const f
 
 int shmm_fallback_solve(shmm_ctx *ctx, int64_t first, int64_t count, const uint8_t *d_flags,
                         const float *d_vx, const float *d_vy, const float *d_f1, const float *d_f2,
-                        const double *d_K_base, float *d_w, double *d_K_out, int32_t *d_status,
-                        void *stream) {
+                        const double *d_K_base, float *d_w, double *d_K_out, int32_t chunks, double tol,
+                        int32_t *d_status, void *stream) {
     if (!range_ok(ctx, first, count) || !d_flags || !d_vx || !d_vy || !d_f1 || !d_f2 || !d_K_base || !d_w ||
-        !d_K_out)
+        !d_K_out || chunks < 0 || !(tol >= 0.0) || !std::isfinite(tol))
         return SHMM_EINVAL;
     if (count == 0) return SHMM_OK;
     int rc = set_device(ctx);
@@ -833,8 +862,18 @@ int shmm_fallback_solve(shmm_ctx *ctx, int64_t first, int64_t count, const uint8
         if (need && (rc = ctx->ensure_work(need))) return rc;
         const auto it = ctx->solve_variant.find(n);
         const int variant = it == ctx->solve_variant.end() ? default_solve_variant(n) : it->second;
-        rc = launch_local_solve(ctx->d_table, dl, (int32_t)ids.size(), n, max_steps, d_vx, d_vy, d_f1, d_f2,
-                                d_K_base, d_w, ctx->cells, 0, 2147483647, cells, ctx->work, variant, s);
+        if (chunks > 0) {
+            // quasi-stationary stop: the plan bounds each chunk's launches
+            rc = adaptive_loop(ctx, ids, dl, d_f1, d_f2, d_K_base, d_w, chunks, tol, s, [&](int32_t s0, int32_t C) {
+                int32_t longest = 0;
+                for (int32_t d : ids) longest = std::max(longest, ctx->table[d].nsteps);
+                return launch_local_solve(ctx->d_table, dl, (int32_t)ids.size(), n, longest, d_vx, d_vy, d_f1, d_f2,
+                                          d_K_base, d_w, ctx->cells, s0, C, cells, ctx->work, variant, s);
+            });
+        } else {
+            rc = launch_local_solve(ctx->d_table, dl, (int32_t)ids.size(), n, max_steps, d_vx, d_vy, d_f1, d_f2,
+                                    d_K_base, d_w, ctx->cells, 0, 2147483647, cells, ctx->work, variant, s);
+        }
         if (rc) return rc;
         rc = launch_effective_diffusivity_list(ctx->d_table, dl, (int64_t)ids.size(), d_f1, d_f2, d_w,
                                                ctx->cells, d_K_base, d_K_out, d_status, s);

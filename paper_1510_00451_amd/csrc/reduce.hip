@@ -98,18 +98,19 @@ __global__ __launch_bounds__(kRedThreads) void k_moments(
 // stop of the local solves: out[8 i + q] for domain first + i holds the sums
 // over its cells of (w_j - w_prev_j)^2 (q = 0, 1), f_j^2 (q = 2, 3) and
 // f_i w_j (q = 4 + 2 (i - 1) + (j - 1)), FP64 in a fixed order; then
-// w_prev <- w.  w_prev covers the range only: [2][prev_cells], cell c of
-// domain d at d.offset - prev_base + c.
+// w_prev <- w.  w_prev covers the listed domains only: [2][prev_cells], cell
+// c of domain first + i at d.offset - prev_base + c, or with a list (domains
+// of one size) cell c of list entry i at i n^2 + c.
 constexpr int kDeltaVals = 8;
 
 __global__ __launch_bounds__(kRedThreads) void k_chunk_delta(
     const shmm_domain *__restrict__ dom, int64_t first, const float *__restrict__ f1,
     const float *__restrict__ f2, const float *__restrict__ w, int64_t cells_total, float *__restrict__ w_prev,
-    int64_t prev_cells, int64_t prev_base, double *__restrict__ out) {
+    int64_t prev_cells, int64_t prev_base, const int32_t *__restrict__ list, double *__restrict__ out) {
     __shared__ double part[kRedThreads / 64][kDeltaVals];
-    const shmm_domain D = dom[first + blockIdx.x];
+    const shmm_domain D = dom[list ? (int64_t)list[blockIdx.x] : first + blockIdx.x];
     const int cells = D.n * D.n;
-    const int64_t o = D.offset, po = D.offset - prev_base;
+    const int64_t o = D.offset, po = list ? (int64_t)blockIdx.x * cells : D.offset - prev_base;
     double v[kDeltaVals];
 #pragma unroll
     for (int q = 0; q < kDeltaVals; ++q) v[q] = 0.0;
@@ -271,12 +272,12 @@ int launch_effective_diffusivity(const shmm_domain *d_dom, int64_t first, int64_
     return SHMM_OK;
 }
 
-int launch_chunk_delta(const shmm_domain *d_dom, int64_t first, int64_t count, const float *f1, const float *f2,
-                       const float *w, int64_t cells_total, float *w_prev, int64_t prev_cells, int64_t prev_base,
-                       double *out, hipStream_t s) {
+int launch_chunk_delta(const shmm_domain *d_dom, int64_t first, const int32_t *d_list, int64_t count, const float *f1,
+                       const float *f2, const float *w, int64_t cells_total, float *w_prev, int64_t prev_cells,
+                       int64_t prev_base, double *out, hipStream_t s) {
     if (count <= 0) return SHMM_OK;
     hipLaunchKernelGGL(k_chunk_delta, dim3((unsigned)count), dim3(kRedThreads), 0, s, d_dom, first, f1, f2, w,
-                       cells_total, w_prev, prev_cells, prev_base, out);
+                       cells_total, w_prev, prev_cells, prev_base, d_list, out);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
 }

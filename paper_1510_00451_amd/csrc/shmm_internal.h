@@ -83,9 +83,10 @@ int launch_effective_diffusivity(const shmm_domain *d_dom, int64_t first, int64_
                                  int64_t cells_total, const double *Kb, double *K_out,
                                  double *K_energy, double *mass, int32_t *status, hipStream_t s);
 
-int launch_chunk_delta(const shmm_domain *d_dom, int64_t first, int64_t count, const float *f1, const float *f2,
-                       const float *w, int64_t cells_total, float *w_prev, int64_t prev_cells, int64_t prev_base,
-                       double *out, hipStream_t s);
+// d_list: null for the range first..first + count - 1, else domains of one size
+int launch_chunk_delta(const shmm_domain *d_dom, int64_t first, const int32_t *d_list, int64_t count, const float *f1,
+                       const float *f2, const float *w, int64_t cells_total, float *w_prev, int64_t prev_cells,
+                       int64_t prev_base, double *out, hipStream_t s);
 
 int launch_level_chain(const shmm_domain *d_dom, const InstDev *d_inst, const int32_t *d_child_start,
                        const int32_t *d_child_idx, int64_t first, int64_t count, int32_t mode,

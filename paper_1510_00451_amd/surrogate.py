@@ -256,24 +256,32 @@ class IsotropicPhase:
     def K_base(self):
         return self.H.K_base[self.first:self.first + self.count]
 
-    def plain(self):
-        """Plain local solves and estimator of every patch; returns K [count][3] (device)."""
+    def plain(self, adaptive: bool = False):
+        """Plain local solves and estimator of every patch; returns K [count][3]
+        (device).  `adaptive`: quasi-stationary stop instead of the full plan
+        (synchronises after every chunk; the plan is cut to the steps taken)."""
         H = self.H
         s = H.stream()
         a, b = H.cell_range(self.first, self.count)
         H.w.view(2, H.cells)[:, a:b].zero_()
-        H.ctx.shmm_local_solve_batch(self.first, self.count, H.vx.data_ptr(), H.vy.data_ptr(),
-                                     H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(),
-                                     0, 2 ** 31 - 1, H.status.data_ptr(), s)
+        if adaptive:
+            H.ctx.shmm_local_solve_adaptive(self.first, self.count, H.vx.data_ptr(), H.vy.data_ptr(),
+                                            H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(),
+                                            H.adaptive_chunks, H.adaptive_tol, H.status.data_ptr(), s)
+        else:
+            H.ctx.shmm_local_solve_batch(self.first, self.count, H.vx.data_ptr(), H.vy.data_ptr(),
+                                         H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(),
+                                         0, 2 ** 31 - 1, H.status.data_ptr(), s)
         H.ctx.shmm_effective_diffusivity(self.first, self.count, H.f1.data_ptr(), H.f2.data_ptr(),
                                          H.w.data_ptr(), H.K_base.data_ptr(), H.K_solve.data_ptr(), 0, 0,
                                          H.status.data_ptr(), s)
         return H.K_solve[self.first:self.first + self.count]
 
-    def surrogate(self, ens: "Ensemble", lo, hi, tau: float, emax: float = math.inf):
+    def surrogate(self, ens: "Ensemble", lo, hi, tau: float, emax: float = math.inf, adaptive: bool = False):
         """Surrogate-with-fallback form: features, ensemble estimate and gate,
-        plain solves of the flagged patches; returns K [count][3] (device).
-        Synchronises once (the fallback reads the flags)."""
+        plain solves of the flagged patches (with the quasi-stationary stop
+        when `adaptive`); returns K [count][3] (device).  Synchronises (the
+        fallback reads the flags)."""
         H = self.H
         s = H.stream()
         self.features()
@@ -283,7 +291,8 @@ class IsotropicPhase:
                                    self.flags.data_ptr(), self.spread.data_ptr(), 0, s)
         H.ctx.shmm_fallback_solve(self.first, self.count, self.flags.data_ptr(), H.vx.data_ptr(),
                                   H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(),
-                                  H.w.data_ptr(), self.K.data_ptr(), H.status.data_ptr(), s)
+                                  H.w.data_ptr(), self.K.data_ptr(), H.adaptive_chunks if adaptive else 0,
+                                  H.adaptive_tol, H.status.data_ptr(), s)
         return sl
 
     def close(self):
@@ -297,16 +306,17 @@ def relative_frobenius(A: np.ndarray, B: np.ndarray) -> np.ndarray:
                    (B[:, 0] ** 2 + 2 * B[:, 1] ** 2 + B[:, 2] ** 2))
 
 
-def labelled_set(problem_batches, log=None) -> Dataset:
+def labelled_set(problem_batches, log=None, adaptive: bool = False) -> Dataset:
     """Features and plain-path labels of the finest-level patches of each batch
-    of flows (isotropic base kappa I), active patches only."""
+    of flows (isotropic base kappa I), active patches only (`adaptive`: the
+    solves stop at the quasi-stationary test)."""
     torch = _torch()
     xs, kbs, ks = [], [], []
     for i, probs in enumerate(problem_batches):
         ph = IsotropicPhase(probs)
         ph.prepare()
         ph.features()
-        K = ph.plain()
+        K = ph.plain(adaptive)
         act = torch.from_numpy(np.flatnonzero(ph.active)).to(ph.x.device)
         xs.append(ph.x.index_select(0, act))
         kbs.append(ph.K_base().index_select(0, act))

@@ -54,7 +54,7 @@ def test_empty_ranges_are_no_ops(torch):
     c.shmm_surrogate_infer(ens.buf.data_ptr(), 1, x.data_ptr(), H.K_base.data_ptr(), 0, lo.data_ptr(),
                            lo.data_ptr(), 0.1, 1.0, K.data_ptr(), flags.data_ptr(), 0, 0, s)
     c.shmm_fallback_solve(0, 0, flags.data_ptr(), H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(),
-                          H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(), K.data_ptr(), 0, s)
+                          H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(), K.data_ptr(), 0, 0.0, 0, s)
     u = torch.full((16 * 16,), 2.0, dtype=torch.float64, device="cuda")
     Kc = torch.tensor([[0.1, 0.0, 0.1]], dtype=torch.float64, device="cuda")
     c.shmm_macro_step(16, 0, 0.0, 0.0, 0, 0, Kc.data_ptr(), 0, 0.01, 0, u.data_ptr(), 64, s)

@@ -236,7 +236,7 @@ def test_fallback_equals_plain_solve(torch):
     H.status.zero_()
     H.w.fill_(7.0)                           # the fallback must clear the correctors itself
     H.ctx.shmm_fallback_solve(0, H.nd, flags.data_ptr(), H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(),
-                              H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(), Kout.data_ptr(),
+                              H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(), Kout.data_ptr(), 0, 0.0,
                               H.status.data_ptr(), s)
     torch.cuda.synchronize()
     got = Kout.cpu().numpy()
@@ -245,6 +245,19 @@ def test_fallback_equals_plain_solve(torch):
     assert np.all(got[~f] == -1.0)
     st = H.status.cpu().numpy()
     assert np.all((st[f] & 8) == 8) and np.all(st[~f] == 0)
+    # the same fallback with the quasi-stationary stop: K within the parity
+    # bar of the planned solve, fewer steps for the flagged patches only
+    planned = H.ctx.shmm_ctx_table()[0]["nsteps"].copy()
+    Kad = torch.full((H.nd, 3), -1.0, dtype=torch.float64, device="cuda")
+    H.w.fill_(7.0)
+    H.ctx.shmm_fallback_solve(0, H.nd, flags.data_ptr(), H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(),
+                              H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(), Kad.data_ptr(), 32, 0.0, 0, s)
+    torch.cuda.synchronize()
+    ga = Kad.cpu().numpy()
+    assert np.all(ga[~f] == -1.0)
+    assert np.max(np.abs(ga[f] - plain[f])) <= 1e-5 * np.max(np.abs(plain[f]))
+    taken = H.ctx.shmm_ctx_table()[0]["nsteps"]
+    assert np.array_equal(taken[~f], planned[~f]) and taken[f].sum() < planned[f].sum()
     H.close()
 
 
