@@ -647,9 +647,8 @@ def macro_run(N: int, vx: Optional[np.ndarray], vy: Optional[np.ndarray], K: np.
 
 def interpolate_centres(Kc: np.ndarray, M: int, N: int) -> np.ndarray:
     """Bilinear periodic interpolation of lattice values (centres 2 pi (i+1/2)/M)
-    to the N x N cell centres, component by component.  Parity unpinned beyond
-    the constant-field case (a reading: the paper does not say how the macro
-    solver receives the centre values)."""
+    to the N x N cell centres, component by component (a reading: the paper
+    does not say how the macro solver receives the centre values)."""
     Kc = np.asarray(Kc, np.float64).reshape(M, M, 3)
     out = np.zeros((N, N, 3))
     for j in range(N):

@@ -512,6 +512,32 @@ def test_macro_dirichlet_uniform_flow_reaches_the_discrete_steady_state():
     assert np.max(np.abs(u - u_ss[None, :])) <= 1e-12
 
 
+def test_interpolate_centres_is_separable_periodic_linear_interpolation():
+    """The lattice-to-grid interpolation of the macro K field: bilinear and
+    periodic means linear interpolation in x then in y with wrap-around, which
+    numpy's interp with a period computes independently; where a cell centre
+    falls on a lattice centre (N / M odd) the lattice value comes back exactly."""
+    rng = np.random.default_rng(3)
+    M, N = 4, 12
+    Kc = rng.uniform(0.5, 2.0, (M, M, 3))
+    got = oracle.interpolate_centres(Kc, M, N)
+    lat = np.arange(M) + 0.5                      # lattice centres in lattice units
+    pos = (np.arange(N) + 0.5) / N * M            # cell centres in lattice units
+    for q in range(3):
+        rows = np.array([np.interp(pos, lat, Kc[r, :, q], period=M) for r in range(M)])      # along x
+        want = np.array([np.interp(pos, lat, rows[:, i], period=M) for i in range(N)]).T    # along y
+        np.testing.assert_allclose(got[:, :, q], want, rtol=1e-14, atol=1e-14)
+    assert np.array_equal(got[1::3, 1::3], Kc)
+    M, N = 3, 16                                   # a ratio that is not an integer
+    Kc = rng.uniform(0.5, 2.0, (M, M, 3))
+    got = oracle.interpolate_centres(Kc, M, N)
+    lat = np.arange(M) + 0.5
+    pos = (np.arange(N) + 0.5) / N * M
+    rows = np.array([np.interp(pos, lat, Kc[r, :, 0], period=M) for r in range(M)])
+    want = np.array([np.interp(pos, lat, rows[:, i], period=M) for i in range(N)]).T
+    np.testing.assert_allclose(got[:, :, 0], want, rtol=1e-14, atol=1e-14)
+
+
 # ---------------------------------------------------------------- quasi-stationary stop
 
 def test_quasi_stationary_stop_keeps_k_within_its_bound():
