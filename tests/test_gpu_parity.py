@@ -625,11 +625,11 @@ def test_full_size_four_level_sampled(torch):
         vs = max(np.abs(rvx).max(), np.abs(rvy).max())
         assert np.abs(vx[o:o + n * n].reshape(n, n) - rvx).max() <= 2e-6 * vs
         assert np.abs(vy[o:o + n * n].reshape(n, n) - rvy).max() <= 2e-6 * vs
-    # first phase (finest level), 100 steps on all 64 patches
+    # first phase (finest level), 100 steps on all 64 patches, on a base chosen
+    # here (the level chain has its own parity tests)
     first, count = int(H.phase[0]), int(H.phase[1] - H.phase[0])
-    H.ctx.shmm_level_chain(first, count, 1, H.lines.data_ptr(), H.K_in.data_ptr(), H.K_off.data_ptr(),
-                           H.K_base.data_ptr(), 0, H.R.data_ptr(), 0, H.stream())
-    Kb = H.K_base.cpu().numpy()
+    Kb = np.tile([0.011, 0.0007, 0.012], (H.nd, 1))
+    H.K_base.copy_(torch.from_numpy(Kb))
     H.ctx.shmm_plan_steps(first, count, Kb)
     H.w.zero_()
     H.ctx.shmm_local_solve_batch(first, count, H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(),
@@ -648,6 +648,65 @@ def test_full_size_four_level_sampled(torch):
                                       rf2.ravel(), Kb[d:d + 1], [float(D["dt"])], [100])
         for j in range(2):
             assert relerr(w[j, o:o + n * n], wr[j]) <= 1e-5
+    H.close()
+
+
+def test_full_size_continuous_sampled(torch):
+    """The continuous-spectrum workload at its full size (five levels of 256
+    patches of 128^2, 1 <= |k| <= 512): band filter and Algorithm 2 on every
+    patch; one sampled patch per level against the oracle's direct Fourier
+    synthesis and (below the finest level) its line energies; the finest phase
+    advanced 100 steps on a base chosen here, checked on the sampled patch."""
+    p = flowgen.config_continuous(seed=0)
+    say("case full size continuous")
+    H = hier(p, keep_psi=False)
+    H.band_filter()
+    H.top_down()
+    torch.cuda.synchronize()
+    lv, pt = oracle.band_split(p.kmax, p.thresh)
+    rng = np.random.default_rng(1)
+    vx, vy, lines = H.vx.cpu().numpy(), H.vy.cpu().numpy(), H.lines.cpu().numpy()
+    picked = {}
+    for level in range(p.n_levels):
+        d = int(rng.choice(np.flatnonzero(H.table["level"] == level)))
+        picked[level] = d
+        D = H.table[d]
+        n, o = int(D["n"]), int(D["offset"])
+        say("  level %d domain %d" % (level, d))
+        ref = oracle.synth_patch(p.psi_hat, p.kmax, oracle.band_mask(lv, pt, level, DIAG), int(D["N"]),
+                                 int(D["I0"]), int(D["J0"]), n)
+        rvx, rvy, _, _ = oracle.staggered(ref, float(D["h"]))
+        vs = max(np.abs(rvx).max(), np.abs(rvy).max())
+        assert np.abs(vx[o:o + n * n].reshape(n, n) - rvx).max() <= 2e-6 * vs, level
+        assert np.abs(vy[o:o + n * n].reshape(n, n) - rvy).max() <= 2e-6 * vs, level
+        if level < p.n_levels - 1:
+            lo = int(D["line_offset"])
+            s12 = oracle.line_energies(p.psi_hat, p.kmax, oracle.band_mask(lv, pt, level, OFF12),
+                                       int(D["N"]), int(D["I0"]), n, 0)
+            s21 = oracle.line_energies(p.psi_hat, p.kmax, oracle.band_mask(lv, pt, level, OFF21),
+                                       int(D["N"]), int(D["J0"]), n, 1)
+            np.testing.assert_allclose(lines[lo:lo + n], s12, rtol=1e-11, atol=1e-300)
+            np.testing.assert_allclose(lines[lo + n:lo + 2 * n], s21, rtol=1e-11, atol=1e-300)
+    first, count = int(H.phase[0]), int(H.phase[1] - H.phase[0])
+    Kb = np.tile([1.3e-3, 1e-4, 1.1e-3], (H.nd, 1))
+    H.K_base.copy_(torch.from_numpy(Kb))
+    H.ctx.shmm_plan_steps(first, count, Kb)
+    H.w.zero_()
+    H.ctx.shmm_local_solve_batch(first, count, H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(),
+                                 H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(), 0, 100, 0, H.stream())
+    torch.cuda.synchronize()
+    table, cells, _, _ = H.ctx.shmm_ctx_table()
+    w = H.w.cpu().numpy().reshape(2, cells)
+    d = picked[p.n_levels - 1]
+    D = table[d]
+    n, o = int(D["n"]), int(D["offset"])
+    ref = oracle.synth_patch(p.psi_hat, p.kmax, oracle.band_mask(lv, pt, p.n_levels - 1, DIAG), int(D["N"]),
+                             int(D["I0"]), int(D["J0"]), n)
+    rvx, rvy, rf1, rf2 = oracle.staggered(ref, float(D["h"]))
+    wr = oracle.local_solve_batch([n], [float(D["h"])], rvx.ravel(), rvy.ravel(), rf1.ravel(), rf2.ravel(),
+                                  Kb[d:d + 1], [float(D["dt"])], [100])
+    for j in range(2):
+        assert relerr(w[j, o:o + n * n], wr[j]) <= 1e-5
     H.close()
 
 
