@@ -343,7 +343,7 @@ def paper_tests_leg(n_k: int = 128, n_dns: int = 512):
 
 SOLVE_KERNELS_256 = {0: "k_solve_band<256,32,8,16,0>", 1: "k_solve_band<256,32,8,12,0>", 2: "k_solve_stage",
                      3: "k_solve_band<256,24,12,16,0>", 4: "k_solve_band<256,16,8,32,8>",
-                     5: "k_solve_tiled<64,8,10>"}
+                     5: "k_solve_tiled<64,8,10>", 6: "k_solve_ring<256,32,8,16>"}
 
 
 def n256_leg(steps: int = 200):

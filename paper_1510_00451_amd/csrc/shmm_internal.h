@@ -70,6 +70,11 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
                        int32_t step_begin, int32_t steps, int64_t list_cells, void *work,
                        int variant, hipStream_t s);
 bool local_solve_resident(int n);
+// persistent full-width bands of 256^2 patches with a ring exchange between
+// them; work holds the exchange slabs and round counters
+int launch_ring_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n, const float *vx,
+                      const float *vy, const double *Kb, float *w, int64_t cells_total, int32_t step_begin,
+                      int32_t s_end, void *work, size_t work_bytes, hipStream_t s);
 int local_solve_variants(int n);
 size_t local_solve_workspace(int n, int64_t list_cells);
 int launch_zero_fields(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n, float *d_w,

@@ -26,31 +26,11 @@
 #include <algorithm>
 
 #include "shmm_internal.h"
+#include "solve_stage.h"
 
 namespace shmm {
 
 namespace {
-
-struct SolveConsts {
-    float cxx, cyy, cxy, cc, a, fh;
-};
-
-__device__ inline SolveConsts solve_consts(const shmm_domain &D, const double *Kb, int64_t d) {
-    const double h = D.h, dt = D.dt, h2 = h * h;
-    const double K11 = Kb[3 * d], K12 = Kb[3 * d + 1], K22 = Kb[3 * d + 2];
-    SolveConsts c;
-    c.cxx = (float)(dt * K11 / h2);
-    c.cyy = (float)(dt * K22 / h2);
-    c.cxy = (float)(dt * K12 / (2.0 * h2));
-    c.cc = (float)(-2.0 * dt * (K11 + K22) / h2);
-    c.a = (float)(dt / (2.0 * h));
-    c.fh = (float)h;
-    return c;
-}
-
-__device__ __forceinline__ float uniform(float v) {
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
 
 // One RK stage over a thread's strip.  KIND 0: r = dt (L y + f);
 // KIND 1: q = r + cw dt L y; KIND 2: q1 = r + dt/2 L y, w <- w + q1 (compensated).
@@ -184,76 +164,7 @@ __global__ __launch_bounds__(NN *NN / R) void k_solve_resident(
         solve_body<NN, R, 0>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
 }
 
-// Resident kernel, coefficient form.  With eE = cxx + aE, eW = cxx - aW,
-// eN = cyy + aN and eS = cyy - aS the dt-scaled operator is
-//   cc w_C + eE w_E + eW w_W + eN w_N + eS w_S + cxy ((w_NE - w_NW) - (w_SE - w_SW)),
-// five products instead of the split advection and diffusion terms.  A thread
-// keeps eE, eW and nb[r] = cyy + (south face of row r) for its strip, so
-// eN of row r is nb[r + 1] and eS is 2 cyy - nb[r]; the forcing is
-// h (eE - eW) (first corrector) or h (eN - eS) (second).  The x-difference of
-// a row, w_E - w_W, is formed once and used by the rows above and below.
-// OPAQUE: hide the coefficients from loop-invariant motion, so that derived
-// values are recomputed each stage instead of hoisted into R more registers
-// each.  Needed at n = 128, where hoisting spills; smaller patches are faster
-// with the derived values hoisted.
-// CL: the compensation of the first CL rows of the strip lives in LDS
-// (cl[r * cstride]) instead of registers, to relieve register pressure.
-template <int NN, int R, int FIELD, int KIND, bool OPAQUE, int CL = 0>
-__device__ __forceinline__ void rk_stage_e(const float *__restrict__ C, int offW, int offE, int offS,
-                                           int offN, float *__restrict__ out, const SolveConsts &k,
-                                           float two_cyy, float cw, float (&eE)[R], float (&eW)[R],
-                                           float (&nb)[R + 1], float (&wv)[R], float (&comp)[R],
-                                           float (&rr)[R], float *__restrict__ cl = nullptr,
-                                           int cstride = 0) {
-    if (OPAQUE) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) asm volatile("" : "+v"(eE[r]), "+v"(eW[r]));
-#pragma unroll
-        for (int r = 0; r <= R; ++r) asm volatile("" : "+v"(nb[r]));
-    }
-    const float *Wc = C + offW;
-    const float *Ec = C + offE;
-    float sC = C[offS];
-    float dS = Ec[offS] - Wc[offS];
-    float cW = Wc[0], cC = C[0], cE = Ec[0];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int rn = (r + 1 < R) ? (r + 1) * NN : offN;
-        const float nW = Wc[rn], nC = C[rn], nE = Ec[rn];
-        const float dN = nE - nW;
-        const float eS = two_cyy - nb[r];
-        float t = k.cc * cC;
-        t = fmaf(eE[r], cE, t);
-        t = fmaf(eW[r], cW, t);
-        t = fmaf(nb[r + 1], nC, t);
-        t = fmaf(eS, sC, t);
-        t = fmaf(k.cxy, dN - dS, t);
-        float o;
-        if (KIND == 0) {
-            rr[r] = FIELD == 0 ? fmaf(k.fh, eE[r] - eW[r], t) : fmaf(k.fh, nb[r + 1] - eS, t);
-            o = rr[r];
-        } else if (KIND == 1) {
-            o = fmaf(cw, t, rr[r]);
-        } else {
-            const float q1 = fmaf(0.5f, t, rr[r]);
-            const float cp = r < CL ? cl[r * cstride] : comp[r];
-            const float yk = q1 - cp;
-            const float tk = wv[r] + yk;
-            const float cn = (tk - wv[r]) - yk;
-            if (r < CL)
-                cl[r * cstride] = cn;
-            else
-                comp[r] = cn;
-            wv[r] = tk;
-            o = tk;
-        }
-        out[r * NN] = o;
-        sC = cC;
-        dS = cE - cW;
-        cW = nW; cC = nC; cE = nE;
-    }
-}
-
+// Resident kernel, coefficient form (rk_stage_e).
 template <int NN, int R, int FIELD, int CL>
 __device__ __forceinline__ void solve_body_e(float *__restrict__ buf, const shmm_domain *__restrict__ dom,
                                              const int32_t *__restrict__ list,
@@ -899,7 +810,7 @@ int launch_resident_e(const shmm_domain *d_dom, const int32_t *d_list, int32_t n
 
 bool local_solve_resident(int n) { return n == 8 || n == 16 || n == 32 || n == 64 || n == 128; }
 
-int local_solve_variants(int n) { return n == 64 ? 5 : n == 128 ? 7 : n == 256 ? 6 : 1; }
+int local_solve_variants(int n) { return n == 64 ? 5 : n == 128 ? 7 : n == 256 ? 7 : 1; }
 
 namespace {
 // Zero both corrector fields of the listed domains (one workgroup row per domain).
@@ -964,6 +875,9 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
           *comp = ws + 6 * list_cells;
     const int64_t s_end64 = (int64_t)step_begin + steps;
     const int32_t s_end = (int32_t)(s_end64 < max_steps ? s_end64 : max_steps);
+    if (n == 256 && variant == 6)   // persistent bands with a ring exchange (solve_ring.hip)
+        return launch_ring_solve(d_dom, d_list, nlist, n, vx, vy, Kb, w, cells_total, step_begin, s_end, work,
+                                 local_solve_workspace(n, list_cells), s);
     if (n == 256 && variant != 2) {
         // Overlapped regions, HALO / 4 steps per launch.  Full-width bands:
         // variant 0 32 rows with 8 above and below (768 threads), 1 the same

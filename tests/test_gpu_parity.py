@@ -147,7 +147,7 @@ def _single_level(n, seed, amp, kappa, lattice=2, radius=None):
                                              (128, 60, 3), (128, 60, 4), (128, 60, 5), (128, 60, 6),
                                              (256, 12, 0), (256, 12, 1),
                                              (256, 12, 2), (256, 12, 3), (256, 12, 4),
-                                             (256, 12, 5)])
+                                             (256, 12, 5), (256, 12, 6)])
 def test_local_solve_and_estimator_parity(torch, n, steps, variant):
     """Band filter + RK4 local solve + FP64 estimator against the oracle's own
     synthesis, solve and estimator, on an anisotropic base (every kernel variant)."""
@@ -215,7 +215,8 @@ def test_chunked_solve_matches_single_launch(torch, n):
 
 
 def test_tile_paths_follow_each_patch_plan(torch):
-    """The 256^2 region paths (full-width bands and square tiles) on 64
+    """The 256^2 region paths (full-width bands, square tiles and the
+    persistent bands with a ring exchange) on 64
     patches whose plans differ (anisotropy grows with the patch index; delta
     near 1 keeps the plans to tens of steps): a patch whose plan has ended
     drops out of the later launches, and its last state is still the one
@@ -238,7 +239,7 @@ def test_tile_paths_follow_each_patch_plan(torch):
     assert ns.min() > 0 and ns.max() > ns.min() + 8
     args = (H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(),
             H.w.data_ptr())
-    variants = (0, 1, 3, 4, 5)
+    variants = (0, 1, 3, 4, 5, 6)
     out = {}
     for v in variants:
         say("  variant", v)
@@ -249,6 +250,21 @@ def test_tile_paths_follow_each_patch_plan(torch):
         out[v] = H.w.cpu().numpy().copy()
     for v in variants[1:]:
         assert relerr(out[v], out[0]) <= 1e-6, v
+    # the ring exchange carries exactly the rows the bands would reload
+    assert np.array_equal(out[6], out[0])
+    # the same in chunks of 7 steps (windows of 2, 2, 2 and 1 step; the
+    # compensation restarts with every call on both paths)
+    chunked = {}
+    for v in (0, 6):
+        say("  variant", v, "in chunks of 7 steps")
+        H.ctx.shmm_ctx_tune(n, v)
+        H.w.zero_()
+        for b in range(0, int(ns.max()), 7):
+            H.ctx.shmm_local_solve_batch(0, nd, *args, b, 7, 0, H.stream())
+        torch.cuda.synchronize()
+        chunked[v] = H.w.cpu().numpy().copy()
+    assert np.array_equal(chunked[6], chunked[0])
+    assert relerr(chunked[6], out[0]) <= 1e-6
     cells = H.cells
     lv, pt = oracle.band_split(p.kmax, p.thresh)
     mask = oracle.band_mask(lv, pt, 0, DIAG)
