@@ -186,8 +186,9 @@ int shmm_band_filter(shmm_ctx *ctx, int64_t first, int64_t count, float *d_psi, 
  * in/out.  FP32 stencils with a compensated state update.  Requires
  * shmm_plan_steps on the range; patches planned with zero steps are skipped.
  * d_status (may be NULL) gets SHMM_DOM_* bits.  Patches with n <= 128 stay
- * resident in LDS for the whole call; n = 256 advances in overlapped regions
- * and other sizes stage by stage, both through the context's workspace
+ * resident in LDS for the whole call; n = 256 advances in full-width bands
+ * that exchange ring rows (or, as tuned, in relaunched overlapped regions)
+ * and other sizes stage by stage, all through the context's workspace
  * (32 B per listed cell, grown on demand).
  * Errors: SHMM_EINVAL for a range that was never planned; SHMM_ERANGE for
  * more than 32767 patches of one size outside 8..256 in one call. */
@@ -261,10 +262,13 @@ int shmm_level_chain(shmm_ctx *ctx, int64_t first, int64_t count, int32_t mode,
  * n = 128: 0 = split form, strips of 32; 1, 2 = rows per wavefront (16, 8);
  *   3, 4 = coefficient form, strips of 32 or 16; 5 = strips of 32 with the
  *   compensation of 8 strip rows in LDS (default); 6 = the same with 16 rows.
- * n = 256: 0 = full-width bands of 32 rows with 8-row rings, 768 threads
- *   (default); 1 = the same at 1024 threads; 2 = one launch per RK stage;
- *   3 = bands of 24 rows with 12-row rings (3 steps per launch); 4 = bands of
- *   16 rows, 256 threads; 5 = square 64 x 64 tiles with 8-cell rings.
+ * n = 256: 0 = full-width bands of 32 rows with 8-row rings, 768 threads,
+ *   relaunched every 2 steps; 1 = the same at 1024 threads; 2 = one launch per
+ *   RK stage; 3 = bands of 24 rows with 12-row rings (3 steps per launch);
+ *   4 = bands of 16 rows, 256 threads; 5 = square 64 x 64 tiles with 8-cell
+ *   rings; 6 = the bands of 0 kept resident for all steps, neighbours
+ *   exchanging their ring rows every 2 steps (default; a call whose range
+ *   also holds other patch sizes, which run concurrently, uses 0 instead).
  * Other sizes have one variant.
  * Errors: SHMM_EINVAL for an unknown key or value. */
 #define SHMM_TUNE_SOLVE_VARIANT_COUNT 0

@@ -317,7 +317,13 @@ struct shmm_ctx {
 // Kernel variant per patch size when no tuning result was set: the
 // LDS-staged kernel in coefficient form (the fastest in the measurements on
 // MI355X; sizes below 64 have no other variant).
-static int default_solve_variant(int n) { return n == 64 ? 3 : n == 128 ? 5 : 0; }
+static int default_solve_variant(int n) { return n == 64 ? 3 : n == 128 ? 5 : n == 256 ? 6 : 0; }
+
+// The ring-exchange bands (n = 256, variant 6) hold the whole device until
+// every workgroup of a group runs; beside the other sizes of a call, which
+// run concurrently on side streams, the overlapped bands (variant 0) are
+// used instead.
+static int concurrent_solve_variant(int n, int variant) { return n == 256 && variant == 6 ? 0 : variant; }
 
 static int set_device(shmm_ctx *ctx) {
     SHMM_HIP_CHECK(hipSetDevice(ctx->device));
@@ -678,7 +684,8 @@ int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const fl
         for (int64_t d = first; d < first + count; ++d)
             if (ctx->table[d].n == rl->ns[q]) max_steps = std::max(max_steps, ctx->table[d].nsteps);
         const auto it = ctx->solve_variant.find(rl->ns[q]);
-        const int variant = it == ctx->solve_variant.end() ? default_solve_variant(rl->ns[q]) : it->second;
+        int variant = it == ctx->solve_variant.end() ? default_solve_variant(rl->ns[q]) : it->second;
+        if (groups > 1) variant = concurrent_solve_variant(rl->ns[q], variant);
         hipStream_t s = main_s;
         const bool on_main = !concurrent || local_solve_workspace(rl->ns[q], rl->cells[q]) ||
                              (n_work == 0 && q == 0);

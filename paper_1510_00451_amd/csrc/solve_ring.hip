@@ -218,12 +218,18 @@ __device__ __forceinline__ void ring_body(float *__restrict__ buf, int *bad, con
                 __syncthreads();
                 if (tid == 0) {
                     __hip_atomic_store(flags + me, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    // both counters read together each pass
                     uint32_t it = 0;
-                    while ((__hip_atomic_load(flags + south, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch ||
-                            __hip_atomic_load(flags + north, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) &&
-                           ++it < spin_cap)
-                        __builtin_amdgcn_s_sleep(8);
-                    if (it >= spin_cap) *bad = 1;
+                    for (;;) {
+                        const int32_t fs = __hip_atomic_load(flags + south, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const int32_t fn = __hip_atomic_load(flags + north, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (fs >= epoch && fn >= epoch) break;
+                        if (++it >= spin_cap) {
+                            *bad = 1;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
                 }
                 __syncthreads();
                 if (*bad) {

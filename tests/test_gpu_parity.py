@@ -420,15 +420,17 @@ def test_uneven_batch_stratified(torch):
     H.close()
 
 
-def test_solve_batch_replays_from_a_captured_graph(torch):
-    """A chunk of local solves over a phase with two patch sizes (64^2
-    resident, 256^2 overlapped tiles; the sizes run on forked streams),
-    captured once into a graph and replayed three times, with eager work and
-    synchronisations between the replays: every replay equals the eager
-    result bit for bit."""
-    probs = [flowgen.config_batched_instance(2), flowgen.config_batched_instance(14)]
-    assert sorted(p.n_cells[0] for p in probs) == [64, 256]
-    say("case graph replay")
+@pytest.mark.parametrize("seeds,sizes", [((2, 14), [64, 256]), ((14,), [256])])
+def test_solve_batch_replays_from_a_captured_graph(torch, seeds, sizes):
+    """A chunk of local solves captured once into a graph and replayed three
+    times, with eager work and synchronisations between the replays: every
+    replay equals the eager result bit for bit.  Two phases: 64^2 (resident)
+    and 256^2 patches (overlapped bands), whose sizes run on forked streams;
+    and 256^2 patches alone (the ring-exchange bands, whose round counters
+    are cleared by a kernel inside the graph)."""
+    probs = [flowgen.config_batched_instance(i) for i in seeds]
+    assert sorted(p.n_cells[0] for p in probs) == sizes
+    say("case graph replay", sizes)
     H = hier(probs, keep_psi=False)
     H.band_filter()
     first, count = int(H.phase[0]), int(H.phase[1] - H.phase[0])
