@@ -35,17 +35,21 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (256 CU, 2
 # factors read off a 1 GiB device copy.  Valid only for the kernel code they
 # were taken on (first 16 hex digits of the SHA-256 of solve.hip without its
 # comments and blank lines); otherwise reported null.
-SOLVE_TRAFFIC = {"code_sha256": "20228757dcff080a", "variant": 5,
-                 "bytes_per_launch": (2 * 12631.7 + 8832.0) * 1024}
+SOLVE_TRAFFIC = {"code_sha256": "c68bb9c9ecd92bc3", "variant": 5,
+                 "bytes_per_launch": (2 * 12632.0 + 8832.0) * 1024}
 SOLVE_KERNELS_128 = {0: "k_solve_resident<128,32>", 1: "k_solve_rows<128,2,16>", 2: "k_solve_rows<128,2,8>",
                      3: "k_solve_resident_e<128,32>", 4: "k_solve_resident_e<128,16>",
                      5: "k_solve_resident_e<128,32,8>", 6: "k_solve_resident_e<128,32,16>"}
 
 
 def solve_traffic():
+    """The counted HBM bytes of one solve launch while the code of the solve
+    kernels (solve.hip and its stage header, comments aside) is the code the
+    counters were taken on; None otherwise."""
     import hashlib
-    path = os.path.join(ROOT, "paper_1510_00451_amd", "csrc", "solve.hip")
-    lines = open(path).read().split("\n")
+    lines = []
+    for f in ("solve.hip", "solve_stage.h"):
+        lines += open(os.path.join(ROOT, "paper_1510_00451_amd", "csrc", f)).read().split("\n")
     code = "\n".join(l.split("//")[0].rstrip() for l in lines if l.split("//")[0].strip())
     h = hashlib.sha256(code.encode()).hexdigest()[:16]
     return SOLVE_TRAFFIC["bytes_per_launch"] if h == SOLVE_TRAFFIC["code_sha256"] else None
