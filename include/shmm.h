@@ -267,8 +267,9 @@ int shmm_level_chain(shmm_ctx *ctx, int64_t first, int64_t count, int32_t mode,
  *   RK stage; 3 = bands of 24 rows with 12-row rings (3 steps per launch);
  *   4 = bands of 16 rows, 256 threads; 5 = square 64 x 64 tiles with 8-cell
  *   rings; 6 = the bands of 0 kept resident for all steps, neighbours
- *   exchanging their ring rows every 2 steps (default; a call whose range
- *   also holds other patch sizes, which run concurrently, uses 0 instead).
+ *   exchanging their ring rows every 2 steps (default; in a call whose range
+ *   also holds other patch sizes it runs first and alone, and the other
+ *   sizes follow, concurrently with one another).
  * Other sizes have one variant.
  * Errors: SHMM_EINVAL for an unknown key or value. */
 #define SHMM_TUNE_SOLVE_VARIANT_COUNT 0

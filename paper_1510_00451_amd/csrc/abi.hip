@@ -319,11 +319,10 @@ struct shmm_ctx {
 // MI355X; sizes below 64 have no other variant).
 static int default_solve_variant(int n) { return n == 64 ? 3 : n == 128 ? 5 : n == 256 ? 6 : 0; }
 
-// The ring-exchange bands (n = 256, variant 6) hold the whole device until
-// every workgroup of a group runs; beside the other sizes of a call, which
-// run concurrently on side streams, the overlapped bands (variant 0) are
-// used instead.
-static int concurrent_solve_variant(int n, int variant) { return n == 256 && variant == 6 ? 0 : variant; }
+// The ring-exchange bands (n = 256, variant 6) need every workgroup of a
+// group running at once; beside kernels that hold CUs for whole solves they
+// would sit partly dispatched, so they run alone.
+static bool runs_alone(int n, int variant) { return n == 256 && variant == 6; }
 
 static int set_device(shmm_ctx *ctx) {
     SHMM_HIP_CHECK(hipSetDevice(ctx->device));
@@ -659,14 +658,37 @@ int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const fl
     // Patch sizes of the range run concurrently: the group that needs the
     // workspace (at most one size does) and the first group go on the
     // caller's stream, the others on side streams forked from and joined back
-    // into it with events.
+    // into it with events.  A group that runs alone (the ring-exchange bands)
+    // goes first on the caller's stream, and the fork follows it.
+    std::vector<int> variant(groups);
+    for (size_t q = 0; q < groups; ++q) {
+        const auto it = ctx->solve_variant.find(rl->ns[q]);
+        variant[q] = it == ctx->solve_variant.end() ? default_solve_variant(rl->ns[q]) : it->second;
+    }
     size_t need = 0;
     for (size_t q = 0; q < groups; ++q) need = std::max(need, local_solve_workspace(rl->ns[q], rl->cells[q]));
     if (need && (rc = ctx->ensure_work(need))) return rc;
-    int n_work = 0;
-    for (size_t q = 0; q < groups; ++q) n_work += local_solve_workspace(rl->ns[q], rl->cells[q]) ? 1 : 0;
-    const bool concurrent = groups > 1 && n_work <= 1;
     hipStream_t main_s = (hipStream_t)stream;
+    auto max_steps_of = [&](size_t q) {
+        int32_t m = 0;
+        for (int64_t d = first; d < first + count; ++d)
+            if (ctx->table[d].n == rl->ns[q]) m = std::max(m, ctx->table[d].nsteps);
+        return m;
+    };
+    std::vector<size_t> rest;
+    for (size_t q = 0; q < groups; ++q) {
+        if (groups > 1 && runs_alone(rl->ns[q], variant[q])) {
+            rc = launch_local_solve(ctx->d_table, rl->d_lists[q], rl->counts[q], rl->ns[q], max_steps_of(q), d_vx,
+                                    d_vy, d_f1, d_f2, d_K_base, d_w, ctx->cells, step_begin, steps, rl->cells[q],
+                                    ctx->work, variant[q], main_s);
+            if (rc) return rc;
+        } else {
+            rest.push_back(q);
+        }
+    }
+    int n_work = 0;
+    for (size_t q : rest) n_work += local_solve_workspace(rl->ns[q], rl->cells[q]) ? 1 : 0;
+    const bool concurrent = rest.size() > 1 && n_work <= 1;
     bool used[kSideStreams] = {};
     if (concurrent) {
         if (!ctx->ev_fork) {
@@ -679,25 +701,20 @@ int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const fl
         SHMM_HIP_CHECK(hipEventRecord(ctx->ev_fork, main_s));
     }
     int next_side = 0;
-    for (size_t q = 0; q < groups; ++q) {
-        int32_t max_steps = 0;
-        for (int64_t d = first; d < first + count; ++d)
-            if (ctx->table[d].n == rl->ns[q]) max_steps = std::max(max_steps, ctx->table[d].nsteps);
-        const auto it = ctx->solve_variant.find(rl->ns[q]);
-        int variant = it == ctx->solve_variant.end() ? default_solve_variant(rl->ns[q]) : it->second;
-        if (groups > 1) variant = concurrent_solve_variant(rl->ns[q], variant);
+    for (size_t k = 0; k < rest.size(); ++k) {
+        const size_t q = rest[k];
         hipStream_t s = main_s;
         const bool on_main = !concurrent || local_solve_workspace(rl->ns[q], rl->cells[q]) ||
-                             (n_work == 0 && q == 0);
+                             (n_work == 0 && k == 0);
         if (!on_main) {
             const int i = next_side++ % kSideStreams;
             s = ctx->side[i];
             if (!used[i]) SHMM_HIP_CHECK(hipStreamWaitEvent(s, ctx->ev_fork, 0));
             used[i] = true;
         }
-        rc = launch_local_solve(ctx->d_table, rl->d_lists[q], rl->counts[q], rl->ns[q], max_steps,
+        rc = launch_local_solve(ctx->d_table, rl->d_lists[q], rl->counts[q], rl->ns[q], max_steps_of(q),
                                 d_vx, d_vy, d_f1, d_f2, d_K_base, d_w, ctx->cells, step_begin, steps,
-                                rl->cells[q], ctx->work, variant, s);
+                                rl->cells[q], ctx->work, variant[q], s);
         if (rc) return rc;
     }
     for (int i = 0; i < kSideStreams; ++i)
