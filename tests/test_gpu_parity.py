@@ -728,6 +728,53 @@ def test_full_size_continuous_sampled(torch):
     H.close()
 
 
+def test_full_size_256_phase_sampled(torch):
+    """One phase of 1024 patches of 256^2 (four uneven-batch instances at
+    n = 256 with 16 x 16 patches per level, as timed by the benchmark) on the
+    default ring-exchange bands, 20 steps on a base chosen here: bit-identical
+    to the relaunched bands on every patch, and sampled patches against the
+    oracle."""
+    probs = [flowgen.config_batched_instance(100 + i, n=256, lattice=16) for i in range(4)]
+    say("case full size 256^2 phase, 1024 patches")
+    H = hier(probs, keep_psi=False)
+    H.band_filter()
+    first, count = int(H.phase[0]), int(H.phase[1] - H.phase[0])
+    assert count == 1024 and set(H.table["n"][first:first + count]) == {256}
+    Kb = np.tile([0.012, 0.002, 0.009], (H.nd, 1))
+    H.K_base.copy_(torch.from_numpy(Kb))
+    H.ctx.shmm_plan_steps(first, count, Kb)
+    args = (H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(),
+            H.w.data_ptr())
+    out = {}
+    for v in (6, 0):
+        say("  variant", v)
+        H.ctx.shmm_ctx_tune(256, v)
+        H.w.zero_()
+        H.ctx.shmm_local_solve_batch(first, count, *args, 0, 20, 0, H.stream())
+        torch.cuda.synchronize()
+        out[v] = H.w.cpu().numpy().copy()
+    assert np.array_equal(out[6], out[0])
+    table, cells, _, _ = H.ctx.shmm_ctx_table()
+    w = out[6].reshape(2, cells)
+    rng = np.random.default_rng(3)
+    inst = H.table["instance"][first:first + count]
+    for q in (1, 3, 0):           # two instances with |k| <= 8, one with |k| <= 128
+        d = first + int(rng.choice(np.flatnonzero(inst == q)))
+        D = table[d]
+        p = probs[q]
+        n, o = int(D["n"]), int(D["offset"])
+        lv, pt = oracle.band_split(p.kmax, p.thresh)
+        say("  sampled domain", d, "of instance", q)
+        psi = oracle.synth_patch(p.psi_hat, p.kmax, oracle.band_mask(lv, pt, int(D["level"]), DIAG), int(D["N"]),
+                                 int(D["I0"]), int(D["J0"]), n)
+        vx, vy, f1, f2 = oracle.staggered(psi, float(D["h"]))
+        wr = oracle.local_solve_batch([n], [float(D["h"])], vx.ravel(), vy.ravel(), f1.ravel(), f2.ravel(),
+                                      Kb[d:d + 1], [float(D["dt"])], [min(20, int(D["nsteps"]))])
+        for j in range(2):
+            assert relerr(w[j, o:o + n * n], wr[j]) <= 1e-5, (d, j)
+    H.close()
+
+
 def test_two_level_cellular_end_to_end(torch):
     """The two-level cellular flow from hierarchy to macro field: the macro
     diffusivity (the level-0 result without its own diagonal band, which the
