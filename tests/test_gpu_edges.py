@@ -145,3 +145,39 @@ def test_problem_validation(torch):
         ctx.shmm_ctx_set_problem(p)
     ctx.shmm_ctx_set_problem(good)               # the context is still usable
     ctx.close()
+
+
+def test_ring_bands_single_patch_and_skipped_patch(torch):
+    """The 256^2 ring-exchange bands on a phase of two patches, one of whose
+    diagonal band is empty (planned with zero steps, so its group skips it),
+    for an odd number of steps (a last window of one step): identical to the
+    relaunched bands, and the skipped patch's correctors untouched."""
+    from paper_1510_00451_amd import abi
+    say("case ring bands, one active and one skipped 256^2 patch")
+    live = flowgen.config_continuous(seed=5, radius=24, p=-1.5, kappa=0.05, n=256, lattice=1, levels=1)
+    live.n_global = [256]
+    empty = flowgen.Problem(kappa=0.05, kmax=4, psi_hat=np.zeros((9, 9), complex), thresh=[],
+                            n_cells=[256], n_global=[256], lattice=[1])
+    from paper_1510_00451_amd.hierarchy import Hierarchy
+    H = Hierarchy([live, empty], keep_psi=False)
+    H.band_filter()
+    Kb = np.tile([0.05, 0.01, 0.04], (H.nd, 1))
+    H.K_base.copy_(torch.from_numpy(Kb))
+    H.ctx.shmm_plan_steps(0, H.nd, Kb)
+    ns = H.ctx.shmm_ctx_table()[0]["nsteps"]
+    assert H.nd == 2 and ns[0] > 5 and ns[1] == 0
+    args = (H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(),
+            H.w.data_ptr())
+    out = {}
+    for v in (6, 0):
+        H.ctx.shmm_ctx_tune(256, v)
+        H.w.fill_(0.25)
+        H.ctx.shmm_local_solve_batch(0, H.nd, *args, 0, 5, 0, H.stream())
+        torch.cuda.synchronize()
+        out[v] = H.w.cpu().numpy().copy()
+    assert np.array_equal(out[6], out[0])
+    w = out[6].reshape(2, H.cells)
+    o1 = int(H.table["offset"][1])
+    assert bool((w[:, o1:o1 + 256 * 256] == 0.25).all())
+    assert not np.allclose(w[:, :256 * 256], 0.25)
+    H.close()
