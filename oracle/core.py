@@ -375,6 +375,21 @@ def estimate(f1, f2, w1, w2, Kb) -> np.ndarray:
     return np.array([Kb[0] + p11, Kb[1] + 0.5 * (p12 + p21), Kb[2] + p22])
 
 
+def estimate_window(f1, f2, w1, w2, Kb, inner: int) -> np.ndarray:
+    """The flux-form estimate averaged over the centred inner x inner cells of
+    an n x n patch only (oversampled patches: the local problem is posed on a
+    patch larger than the region it describes, so that the seam of the
+    periodically treated patch lies away from the averaging window; aimed at
+    the non-periodicity that the continuous-spectrum example of Section 4
+    lists among the error sources).  inner = 0, or inner >= n, is the whole
+    patch."""
+    n = f1.shape[0]
+    m = inner if 0 < inner < n else n
+    a = (n - m) // 2
+    win = (slice(a, a + m), slice(a, a + m))
+    return estimate(f1[win], f2[win], w1[win], w2[win], Kb)
+
+
 def estimate_energy(w1, w2, Kb, h) -> np.ndarray:
     """Energy form K_b + sym(-<w_i, D w_j>); equals the flux form at steady state."""
     d1 = diffusion(Kb, w1, h)

@@ -733,3 +733,49 @@ def test_one_level_hierarchy_is_the_direct_cell_problem():
     K = oracle.cell_problem_dense(vx, vy, f1, f2, [0.05, 0.0, 0.05], h)
     assert len(r.domains) == 1
     np.testing.assert_allclose(r.K_total()[0], K, rtol=1e-9, atol=1e-13)
+
+
+def test_window_estimate_is_centred_and_normalised_on_its_cells():
+    """An indicator corrector: w_1 = 1 on exactly the centred m x m cells of an
+    n x n patch and f_1 = 1 everywhere, so the windowed K11 gains exactly 1,
+    while the whole-patch estimate gains m^2 / n^2.  A window that is not
+    centred, or not normalised by its own cell count, fails."""
+    n, m = 16, 6
+    a = (n - m) // 2
+    w1 = np.zeros((n, n))
+    w1[a:a + m, a:a + m] = 1.0
+    one = np.ones((n, n))
+    zero = np.zeros((n, n))
+    Kb = [0.3, 0.01, 0.2]
+    Kw = oracle.estimate_window(one, zero, w1, zero, Kb, m)
+    np.testing.assert_allclose(Kw, [1.3, 0.01, 0.2], rtol=0, atol=1e-15)
+    Kf = oracle.estimate_window(one, zero, w1, zero, Kb, 0)
+    np.testing.assert_allclose(Kf, [0.3 + m * m / n / n, 0.01, 0.2], rtol=0, atol=1e-15)
+    # shifting the indicator by one cell takes it off the window's edge rows
+    w1s = np.roll(w1, 1, axis=1)
+    assert oracle.estimate_window(one, zero, w1s, zero, Kb, m)[0] == pytest.approx(0.3 + (m - 1) / m, abs=1e-15)
+
+
+def test_window_over_one_period_of_a_periodic_flow_is_the_whole_patch():
+    """For a flow whose period divides the patch (psi = 0.3 sin 2x sin 2y on a
+    32^2 patch of side 2 pi, period 16 cells), the correctors inherit the
+    period, so the average over the centred 16^2 window (one period) equals
+    the whole-patch average up to summation order."""
+    n = 32
+    h = 2 * np.pi / n
+    x = np.arange(n) * h
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    psi = 0.3 * np.sin(2 * X) * np.sin(2 * Y)
+    vx, vy, f1, f2 = oracle.staggered(psi, h)
+    Kb = [0.05, 0.01, 0.04]
+    dt, _ = oracle.plan_steps(n, h, Kb, oracle.advection_bound(vx, vy), 0.5, 1e-6)
+    w = oracle.local_solve_batch([n], [h], vx.ravel(), vy.ravel(), f1.ravel(), f2.ravel(), np.array([Kb]),
+                                 [dt], [300])
+    w1, w2 = w[0].reshape(n, n), w[1].reshape(n, n)
+    assert np.abs(w1).max() > 1e-3
+    Kfull = oracle.estimate(f1, f2, w1, w2, Kb)
+    Kwin = oracle.estimate_window(f1, f2, w1, w2, Kb, 16)
+    np.testing.assert_allclose(Kwin, Kfull, rtol=1e-12, atol=1e-15)
+    # a window that is not a whole number of periods differs
+    K12 = oracle.estimate_window(f1, f2, w1, w2, Kb, 12)
+    assert np.abs(K12 - Kfull).max() > 1e-6 * np.abs(Kfull - Kb).max()
