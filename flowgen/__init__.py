@@ -271,6 +271,21 @@ def config_continuous(seed: int = 0, radius: int = 512, p: float = -7.0 / 3.0,
                    name=f"continuous-{levels}level-{lattice * lattice}x{n}")
 
 
+def config_band_pass(seed: int, k_lo: int, k_hi: int, kappa: float, n: int, lattice: int,
+                     n_global: int, amp: float = 1.0) -> Problem:
+    """One level of a random-phase flow with |psi_k| = amp |k|^-2 on the annulus
+    k_lo <= |k| <= k_hi only (a scale-separated field with no mode coarser
+    than the annulus): lattice^2 patches of n^2 cells at spacing 2 pi /
+    n_global.  With n * lattice = n_global the patches tile the domain; with
+    n = n_global and lattice 1 the single patch is the whole periodic domain
+    (the direct cell problem of the flow)."""
+    ph = random_power_spectrum_fast(seed, k_hi, -2.0, amp)
+    k = np.arange(-k_hi, k_hi + 1)
+    ph[(k[:, None] ** 2 + k[None, :] ** 2) < k_lo * k_lo] = 0.0
+    return Problem(kappa=kappa, kmax=k_hi, psi_hat=ph, thresh=[], n_cells=[n], n_global=[n_global],
+                   lattice=[lattice], dt_frac=0.5, delta=1e-6, name=f"band-pass-{k_lo}-{k_hi}-{n}")
+
+
 def config_batched_instance(seed: int, n: Optional[int] = None, lattice: int = 4) -> Problem:
     """One instance of the uneven batch: draws kappa, L, slope, n, then phases.
 

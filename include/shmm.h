@@ -229,6 +229,20 @@ int shmm_effective_diffusivity(shmm_ctx *ctx, int64_t first, int64_t count, cons
                                double *d_K_out, double *d_K_energy, double *d_mass,
                                int32_t *d_status, void *stream);
 
+/* The same flux-form estimate averaged over the centred inner x inner cells
+ * of each patch only (oversampled patches: the local problem is posed on a
+ * patch larger than the region it describes, so that the seam of the
+ * periodically treated patch lies away from the averaging window; aimed at
+ * the non-periodicity of the components in a local domain, which the
+ * continuous-spectrum example of Section 4 lists among the method's error
+ * sources).  inner = 0, or inner >= a patch's n, averages over the whole patch,
+ * as shmm_effective_diffusivity does (bit for bit).
+ *   d_K_out = K_b + sym(<f_i w_j>_window)                  [n_domains][3]
+ * Errors: SHMM_EINVAL for a negative or odd inner. */
+int shmm_effective_diffusivity_window(shmm_ctx *ctx, int64_t first, int64_t count, int32_t inner,
+                                      const float *d_f1, const float *d_f2, const float *d_w,
+                                      const double *d_K_base, double *d_K_out, int32_t *d_status, void *stream);
+
 /* Level combination (Algorithms 1-3, extended to L levels), FP64, for the
  * domains [first, first + count).  All tensor arrays are [n_domains][3]:
  *   mode 0 (top-down): K_in = kappa I at level 0, else K_off of the parent;

@@ -22,6 +22,7 @@ MAX_LEVELS = 8
 EXPORTS = ["shmm_ctx_create", "shmm_ctx_destroy", "shmm_build_levels", "shmm_ctx_set_problem",
            "shmm_ctx_table", "shmm_band_tags", "shmm_plan_steps", "shmm_band_filter",
            "shmm_local_solve_batch", "shmm_local_solve_adaptive", "shmm_effective_diffusivity",
+           "shmm_effective_diffusivity_window",
            "shmm_level_chain",
            "shmm_macro_step", "shmm_ctx_tune", "shmm_patch_features", "shmm_surrogate_refresh",
            "shmm_surrogate_train_step", "shmm_surrogate_infer", "shmm_fallback_solve"]
@@ -75,6 +76,7 @@ def lib() -> ctypes.CDLL:
             "shmm_local_solve_batch": [P, i64, i64, P, P, P, P, P, P, i32, i32, P, P],
             "shmm_local_solve_adaptive": [P, i64, i64, P, P, P, P, P, P, i32, f64, P, P],
             "shmm_effective_diffusivity": [P, i64, i64, P, P, P, P, P, P, P, P, P],
+            "shmm_effective_diffusivity_window": [P, i64, i64, i32, P, P, P, P, P, P, P],
             "shmm_level_chain": [P, i64, i64, i32, P, P, P, P, P, P, P, P],
             "shmm_macro_step": [P, i32, i32, f64, f64, P, P, P, i32, f64, i32, P, i32, P],
             "shmm_ctx_tune": [P, i32, i32],
@@ -210,6 +212,12 @@ class Context:
                                                d_K_out, d_K_energy or None, d_mass or None,
                                                d_status or None, stream),
               "shmm_effective_diffusivity")
+
+    def shmm_effective_diffusivity_window(self, first, count, inner, d_f1, d_f2, d_w, d_K_base, d_K_out,
+                                          d_status=0, stream=0):
+        check(lib().shmm_effective_diffusivity_window(self.h, first, count, int(inner), d_f1, d_f2, d_w,
+                                                      d_K_base, d_K_out, d_status or None, stream),
+              "shmm_effective_diffusivity_window")
 
     def shmm_level_chain(self, first, count, mode, d_lines, d_K_in, d_K_off, d_K_base=0,
                          d_K_solve=0, d_R=0, d_status=0, stream=0):

@@ -758,6 +758,18 @@ int shmm_effective_diffusivity(shmm_ctx *ctx, int64_t first, int64_t count, cons
                                         (hipStream_t)stream);
 }
 
+int shmm_effective_diffusivity_window(shmm_ctx *ctx, int64_t first, int64_t count, int32_t inner,
+                                      const float *d_f1, const float *d_f2, const float *d_w,
+                                      const double *d_K_base, double *d_K_out, int32_t *d_status, void *stream) {
+    if (!range_ok(ctx, first, count) || !d_f1 || !d_f2 || !d_w || !d_K_base || !d_K_out || inner < 0 ||
+        (inner & 1))
+        return SHMM_EINVAL;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    return launch_effective_diffusivity_window(ctx->d_table, first, count, inner, d_f1, d_f2, d_w, ctx->cells,
+                                               d_K_base, d_K_out, d_status, (hipStream_t)stream);
+}
+
 int shmm_level_chain(shmm_ctx *ctx, int64_t first, int64_t count, int32_t mode,
                      const double *d_lines, double *d_K_in, double *d_K_off, double *d_K_base,
                      const double *d_K_solve, double *d_R, int32_t *d_status, void *stream) {

@@ -20,11 +20,14 @@ __global__ __launch_bounds__(kRedThreads) void k_moments(
     const shmm_domain *__restrict__ dom, int64_t first, const float *__restrict__ f1,
     const float *__restrict__ f2, const float *__restrict__ w, int64_t cells_total,
     const double *__restrict__ Kb, double *__restrict__ K_out, double *__restrict__ K_energy,
-    double *__restrict__ mass, int32_t *__restrict__ status, const int32_t *__restrict__ list) {
+    double *__restrict__ mass, int32_t *__restrict__ status, const int32_t *__restrict__ list, int32_t inner) {
     __shared__ double part[kRedThreads / 64][kRedVals];
     const int64_t d = list ? (int64_t)list[blockIdx.x] : first + blockIdx.x;
     const shmm_domain D = dom[d];
-    const int n = D.n, mask = n - 1, cells = n * n;
+    const int n = D.n, mask = n - 1;
+    // averaging window: the centred m x m cells (the whole patch when inner
+    // is 0 or not below n)
+    const int m = inner > 0 && inner < n ? inner : n, x0 = (n - m) / 2, cells = m * m;
     const int64_t o = D.offset;
     const double K11 = Kb[3 * d], K12 = Kb[3 * d + 1], K22 = Kb[3 * d + 2];
     const double ih2 = 1.0 / (D.h * D.h);
@@ -32,8 +35,8 @@ __global__ __launch_bounds__(kRedThreads) void k_moments(
     double v[kRedVals];
 #pragma unroll
     for (int q = 0; q < kRedVals; ++q) v[q] = 0.0;
-    for (int c = threadIdx.x; c < cells; c += kRedThreads) {
-        const int y = c / n, x = c - y * n;
+    for (int i = threadIdx.x; i < cells; i += kRedThreads) {
+        const int yi = i / m, y = x0 + yi, x = x0 + (i - yi * m), c = y * n + x;
         const int xe = (x + 1) & mask, xw = (x - 1) & mask, yn = (y + 1) & mask, ys = (y - 1) & mask;
         const double a1 = f1[o + c], a2 = f2[o + c];
         const double u1 = w1[c], u2 = w2[c];
@@ -267,7 +270,18 @@ int launch_effective_diffusivity(const shmm_domain *d_dom, int64_t first, int64_
                                  double *K_energy, double *mass, int32_t *status, hipStream_t s) {
     if (count <= 0) return SHMM_OK;
     hipLaunchKernelGGL(k_moments, dim3((unsigned)count), dim3(kRedThreads), 0, s, d_dom, first, f1, f2,
-                       w, cells_total, Kb, K_out, K_energy, mass, status, (const int32_t *)nullptr);
+                       w, cells_total, Kb, K_out, K_energy, mass, status, (const int32_t *)nullptr, 0);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
+
+int launch_effective_diffusivity_window(const shmm_domain *d_dom, int64_t first, int64_t count, int32_t inner,
+                                        const float *f1, const float *f2, const float *w, int64_t cells_total,
+                                        const double *Kb, double *K_out, int32_t *status, hipStream_t s) {
+    if (count <= 0) return SHMM_OK;
+    hipLaunchKernelGGL(k_moments, dim3((unsigned)count), dim3(kRedThreads), 0, s, d_dom, first, f1, f2, w,
+                       cells_total, Kb, K_out, (double *)nullptr, (double *)nullptr, status,
+                       (const int32_t *)nullptr, inner);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
 }
@@ -287,7 +301,7 @@ int launch_effective_diffusivity_list(const shmm_domain *d_dom, const int32_t *d
                                       const double *Kb, double *K_out, int32_t *status, hipStream_t s) {
     if (count <= 0) return SHMM_OK;
     hipLaunchKernelGGL(k_moments, dim3((unsigned)count), dim3(kRedThreads), 0, s, d_dom, (int64_t)0, f1, f2, w,
-                       cells_total, Kb, K_out, (double *)nullptr, (double *)nullptr, status, d_list);
+                       cells_total, Kb, K_out, (double *)nullptr, (double *)nullptr, status, d_list, 0);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
 }

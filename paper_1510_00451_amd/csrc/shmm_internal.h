@@ -83,6 +83,9 @@ int launch_zero_fields(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
 int launch_effective_diffusivity_list(const shmm_domain *d_dom, const int32_t *d_list, int64_t count,
                                       const float *f1, const float *f2, const float *w, int64_t cells_total,
                                       const double *Kb, double *K_out, int32_t *status, hipStream_t s);
+int launch_effective_diffusivity_window(const shmm_domain *d_dom, int64_t first, int64_t count, int32_t inner,
+                                        const float *f1, const float *f2, const float *w, int64_t cells_total,
+                                        const double *Kb, double *K_out, int32_t *status, hipStream_t s);
 int launch_effective_diffusivity(const shmm_domain *d_dom, int64_t first, int64_t count,
                                  const float *f1, const float *f2, const float *w,
                                  int64_t cells_total, const double *Kb, double *K_out,

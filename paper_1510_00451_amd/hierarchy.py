@@ -75,6 +75,10 @@ class Hierarchy:
         # quasi-stationary stop: chunks per plan, tolerance (0: each instance's delta)
         self.adaptive_chunks = 32
         self.adaptive_tol = 0.0
+        # oversampled patches: average the estimator over the centred inner x
+        # inner cells of each patch (0: the whole patch; the energy form and
+        # the mass are then not formed)
+        self.estimator_inner = 0
 
     # -- pieces -------------------------------------------------------------
     def stream(self) -> int:
@@ -132,10 +136,15 @@ class Hierarchy:
             launch()
         else:
             self.solve_hook(first, count, launch)
-        c.shmm_effective_diffusivity(first, count, self.f1.data_ptr(), self.f2.data_ptr(),
-                                     self.w.data_ptr(), self.K_base.data_ptr(),
-                                     self.K_solve.data_ptr(), self.K_energy.data_ptr(),
-                                     self.mass.data_ptr(), self.status.data_ptr(), s)
+        if self.estimator_inner:
+            c.shmm_effective_diffusivity_window(first, count, self.estimator_inner, self.f1.data_ptr(),
+                                                self.f2.data_ptr(), self.w.data_ptr(), self.K_base.data_ptr(),
+                                                self.K_solve.data_ptr(), self.status.data_ptr(), s)
+        else:
+            c.shmm_effective_diffusivity(first, count, self.f1.data_ptr(), self.f2.data_ptr(),
+                                         self.w.data_ptr(), self.K_base.data_ptr(),
+                                         self.K_solve.data_ptr(), self.K_energy.data_ptr(),
+                                         self.mass.data_ptr(), self.status.data_ptr(), s)
         c.shmm_level_chain(first, count, MODE_RESULT, self.lines.data_ptr(), self.K_in.data_ptr(),
                            self.K_off.data_ptr(), self.K_base.data_ptr(), self.K_solve.data_ptr(),
                            self.R.data_ptr(), self.status.data_ptr(), s)

@@ -190,6 +190,44 @@ def test_local_solve_and_estimator_parity(torch, n, steps, variant):
     H.close()
 
 
+@pytest.mark.parametrize("n,steps,inner", [(64, 400, 32), (64, 400, 0), (128, 60, 48), (256, 12, 128)])
+def test_window_estimator_parity(torch, n, steps, inner):
+    """The estimator averaged over the centred inner x inner window of each
+    patch (oversampled patches) against the oracle's windowed estimate of its
+    own synthesis and solve; inner = 0 is the plain estimator bit for bit."""
+    p = _single_level(n, seed=n + 1, amp=0.3, kappa=0.05)
+    say("case window estimator n=%d inner=%d" % (n, inner))
+    H = hier(p, keep_psi=False)
+    H.band_filter()
+    Kb = np.tile([0.06, 0.015, 0.04], (H.nd, 1))
+    H.K_base.copy_(torch.from_numpy(Kb))
+    H.ctx.shmm_plan_steps(0, H.nd, Kb)
+    H.w.zero_()
+    H.ctx.shmm_local_solve_batch(0, H.nd, H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(),
+                                 H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(), 0, steps, 0, H.stream())
+    H.ctx.shmm_effective_diffusivity_window(0, H.nd, inner, H.f1.data_ptr(), H.f2.data_ptr(), H.w.data_ptr(),
+                                            H.K_base.data_ptr(), H.K_solve.data_ptr(), 0, H.stream())
+    torch.cuda.synchronize()
+    Kw = H.K_solve.cpu().numpy().copy()
+    if inner == 0:
+        H.ctx.shmm_effective_diffusivity(0, H.nd, H.f1.data_ptr(), H.f2.data_ptr(), H.w.data_ptr(),
+                                         H.K_base.data_ptr(), H.K_solve.data_ptr(), 0, 0, 0, H.stream())
+        torch.cuda.synchronize()
+        assert np.array_equal(H.K_solve.cpu().numpy(), Kw)
+    table = H.ctx.shmm_ctx_table()[0]
+    lv, pt = oracle.band_split(p.kmax, p.thresh)
+    mask = oracle.band_mask(lv, pt, 0, DIAG)
+    for d in range(H.nd):
+        D = table[d]
+        psi = oracle.synth_patch(p.psi_hat, p.kmax, mask, int(D["N"]), int(D["I0"]), int(D["J0"]), n)
+        vx, vy, f1, f2 = oracle.staggered(psi, float(D["h"]))
+        wr = oracle.local_solve_batch([n], [float(D["h"])], vx.ravel(), vy.ravel(), f1.ravel(), f2.ravel(),
+                                      Kb[d:d + 1], [float(D["dt"])], [min(steps, int(D["nsteps"]))])
+        Kr = oracle.estimate_window(f1, f2, wr[0].reshape(n, n), wr[1].reshape(n, n), Kb[d], inner)
+        assert np.max(np.abs(Kw[d] - Kr)) <= 1e-5 * np.max(np.abs(Kr)), (n, inner, d, Kw[d], Kr)
+    H.close()
+
+
 @pytest.mark.parametrize("n", [32, 128, 256])
 def test_chunked_solve_matches_single_launch(torch, n):
     p = _single_level(n, seed=9, amp=0.3, kappa=0.05)
