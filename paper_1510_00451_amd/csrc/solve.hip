@@ -19,9 +19,11 @@
 //   patch and to store the final state.  Two arithmetic forms: the split form
 //   above (k_solve_resident) and the coefficient form (k_solve_resident_e,
 //   the default), plus a row-per-wavefront variant (k_solve_rows).
-// * overlapped regions (n = 256): a few steps per launch on a square tile
-//   (k_solve_tiled) or a full-width band of rows (k_solve_band) plus a ring
-//   of redundant cells, state in workspace between launches.
+// * n = 256: full-width bands of rows plus a ring of redundant cells, kept
+//   resident for all steps and exchanging their rings with the neighbouring
+//   bands (k_solve_ring in solve_ring.hip, the default), or relaunched every
+//   few steps with their state in workspace between launches (k_solve_band,
+//   and k_solve_tiled on square tiles).
 // * per-stage launches (k_solve_stage): any other size.
 #include <algorithm>
 
