@@ -281,6 +281,30 @@ def staggered(psi: np.ndarray, h: float):
     return vx, vy, f1, f2
 
 
+def taper_weights(n: int, taper: int) -> np.ndarray:
+    """Node weights of the patch taper along one axis: 0 at node 0, rising as
+    sin^2 over `taper` nodes to 1, 1 in the middle, and falling back
+    symmetrically (w(n - i) = w(i)), so that the tapered stream function
+    vanishes at the patch seam and its periodic extension is smooth.  taper 0
+    leaves every weight 1."""
+    i = np.arange(n)
+    w = np.ones(n)
+    if taper > 0:
+        e = np.minimum(i, n - i).astype(np.float64)
+        w = np.where(e < taper, np.sin(0.5 * np.pi * e / taper) ** 2, 1.0)
+    return w
+
+
+def windowed_staggered(psi: np.ndarray, h: float, taper: int):
+    """The staggered fields of the tapered stream function W psi (windowed
+    patches, aimed at the non-periodicity of a component on its patch that
+    the continuous-spectrum example of Section 4 lists among the error
+    sources): W = w(x) w(y) from taper_weights, then the differences of
+    staggered(), so the discrete divergence still vanishes identically."""
+    w = taper_weights(psi.shape[0], taper)
+    return staggered(psi * np.outer(w, w), h)
+
+
 def divergence(vx, vy, h):
     return (np.roll(vx, -1, axis=1) - vx) / h + (np.roll(vy, -1, axis=0) - vy) / h
 

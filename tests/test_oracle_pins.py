@@ -779,3 +779,41 @@ def test_window_over_one_period_of_a_periodic_flow_is_the_whole_patch():
     # a window that is not a whole number of periods differs
     K12 = oracle.estimate_window(f1, f2, w1, w2, Kb, 12)
     assert np.abs(K12 - Kfull).max() > 1e-6 * np.abs(Kfull - Kb).max()
+
+
+def test_taper_weights_shape_and_symmetry():
+    """The taper is 0 at the seam node, sin^2 on its ramp, 1 inside and
+    symmetric under i -> n - i; taper 0 is no taper."""
+    w = oracle.taper_weights(16, 4)
+    assert w[0] == 0.0 and np.all(w[4:13] == 1.0)
+    np.testing.assert_allclose(w[1:4], np.sin(0.5 * np.pi * np.arange(1, 4) / 4) ** 2, rtol=0, atol=1e-16)
+    np.testing.assert_array_equal(w[1:], w[1:][::-1])
+    assert np.all(oracle.taper_weights(16, 0) == 1.0)
+
+
+def test_windowed_fields_are_divergence_free_and_untouched_inside():
+    """The tapered stream function's face velocities have zero discrete
+    divergence (they are differences of one node field), see only their
+    inner node across the seam (the tapered field is 0 on the seam nodes),
+    and equal the untapered ones on every face whose two nodes both carry
+    weight 1."""
+    n, taper = 32, 6
+    h = 2 * np.pi / n
+    rng = np.random.default_rng(2)
+    psi = rng.standard_normal((n, n))
+    vx, vy, f1, f2 = oracle.staggered(psi, h)
+    wx, wy, g1, g2 = oracle.windowed_staggered(psi, h, taper)
+    assert np.abs(oracle.divergence(wx, wy, h)).max() <= 1e-12 * np.abs(wx).max()
+    w = oracle.taper_weights(n, taper)
+    W = np.outer(w, w)
+    full = W == 1.0
+    # x-face (j, i) pairs nodes (j, i) and (j + 1, i); y-face pairs (j, i) and (j, i + 1)
+    fx = full & np.roll(full, -1, axis=0)
+    fy = full & np.roll(full, -1, axis=1)
+    assert fx.sum() > 0 and fy.sum() > 0
+    np.testing.assert_array_equal(wx[fx], vx[fx])
+    np.testing.assert_array_equal(wy[fy], vy[fy])
+    # the tapered stream function vanishes on the seam nodes (row and column
+    # 0), so the seam faces see only their inner node
+    np.testing.assert_allclose(wx[n - 1, :], w[n - 1] * w * psi[n - 1, :] / h, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(wy[:, n - 1], -w * w[n - 1] * psi[:, n - 1] / h, rtol=1e-14, atol=0)
