@@ -178,6 +178,22 @@ int shmm_plan_steps(shmm_ctx *ctx, int64_t first, int64_t count, const double *K
 int shmm_band_filter(shmm_ctx *ctx, int64_t first, int64_t count, float *d_psi, float *d_vx,
                      float *d_vy, float *d_f1, float *d_f2, double *d_lines, void *stream);
 
+/* Windowed patches (aimed at the non-periodicity of a component on its patch,
+ * which the continuous-spectrum example of Section 4 lists among the error
+ * sources): replace the face velocities, forcings and advection bounds of
+ * domains [first, first + count), which must share one patch size n, by
+ * those of the tapered stream function W psi.  W = w(x) w(y) on the patch
+ * nodes, with w(i) = sin^2(pi e / (2 taper)) for e = min(i, n - i) < taper
+ * and 1 otherwise: 0 on the seam node, so the periodic extension of W psi is
+ * smooth.  The faces are FP32 differences of W psi (zero discrete
+ * divergence).  d_psi holds psi at the patch nodes, as shmm_band_filter
+ * writes it.  taper = 0 changes nothing.  Call before shmm_plan_steps, which
+ * uses the new bounds.
+ * Errors: SHMM_EINVAL for a negative taper, 2 taper > n, or patch sizes that
+ * differ within the range. */
+int shmm_window_patches(shmm_ctx *ctx, int64_t first, int64_t count, int32_t taper, const float *d_psi,
+                        float *d_vx, float *d_vy, float *d_f1, float *d_f2, void *stream);
+
 /* Local solves of domains [first, first + count) (HMM steps 1-2; the two
  * reconstructions with orthogonal gradients of the numerical homogenization):
  * advance both correctors w_j' = div(v w_j + K_b grad w_j) + f_j by classic

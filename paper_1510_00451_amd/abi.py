@@ -22,7 +22,7 @@ MAX_LEVELS = 8
 EXPORTS = ["shmm_ctx_create", "shmm_ctx_destroy", "shmm_build_levels", "shmm_ctx_set_problem",
            "shmm_ctx_table", "shmm_band_tags", "shmm_plan_steps", "shmm_band_filter",
            "shmm_local_solve_batch", "shmm_local_solve_adaptive", "shmm_effective_diffusivity",
-           "shmm_effective_diffusivity_window",
+           "shmm_effective_diffusivity_window", "shmm_window_patches",
            "shmm_level_chain",
            "shmm_macro_step", "shmm_ctx_tune", "shmm_patch_features", "shmm_surrogate_refresh",
            "shmm_surrogate_train_step", "shmm_surrogate_infer", "shmm_fallback_solve"]
@@ -77,6 +77,7 @@ def lib() -> ctypes.CDLL:
             "shmm_local_solve_adaptive": [P, i64, i64, P, P, P, P, P, P, i32, f64, P, P],
             "shmm_effective_diffusivity": [P, i64, i64, P, P, P, P, P, P, P, P, P],
             "shmm_effective_diffusivity_window": [P, i64, i64, i32, P, P, P, P, P, P, P],
+            "shmm_window_patches": [P, i64, i64, i32, P, P, P, P, P, P],
             "shmm_level_chain": [P, i64, i64, i32, P, P, P, P, P, P, P, P],
             "shmm_macro_step": [P, i32, i32, f64, f64, P, P, P, i32, f64, i32, P, i32, P],
             "shmm_ctx_tune": [P, i32, i32],
@@ -212,6 +213,10 @@ class Context:
                                                d_K_out, d_K_energy or None, d_mass or None,
                                                d_status or None, stream),
               "shmm_effective_diffusivity")
+
+    def shmm_window_patches(self, first, count, taper, d_psi, d_vx, d_vy, d_f1, d_f2, stream=0):
+        check(lib().shmm_window_patches(self.h, first, count, int(taper), d_psi, d_vx, d_vy, d_f1, d_f2, stream),
+              "shmm_window_patches")
 
     def shmm_effective_diffusivity_window(self, first, count, inner, d_f1, d_f2, d_w, d_K_base, d_K_out,
                                           d_status=0, stream=0):

@@ -758,6 +758,21 @@ int shmm_effective_diffusivity(shmm_ctx *ctx, int64_t first, int64_t count, cons
                                         (hipStream_t)stream);
 }
 
+int shmm_window_patches(shmm_ctx *ctx, int64_t first, int64_t count, int32_t taper, const float *d_psi,
+                        float *d_vx, float *d_vy, float *d_f1, float *d_f2, void *stream) {
+    if (!range_ok(ctx, first, count) || !d_psi || !d_vx || !d_vy || !d_f1 || !d_f2 || taper < 0)
+        return SHMM_EINVAL;
+    if (count == 0 || taper == 0) return SHMM_OK;
+    const int n = ctx->table[first].n;
+    for (int64_t d = first; d < first + count; ++d)
+        if (ctx->table[d].n != n) return SHMM_EINVAL;
+    if (2 * taper > n) return SHMM_EINVAL;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    return launch_window_patches(ctx->d_table, first, count, n, taper, d_psi, d_vx, d_vy, d_f1, d_f2, ctx->d_vmax,
+                                 (hipStream_t)stream);
+}
+
 int shmm_effective_diffusivity_window(shmm_ctx *ctx, int64_t first, int64_t count, int32_t inner,
                                       const float *d_f1, const float *d_f2, const float *d_w,
                                       const double *d_K_base, double *d_K_out, int32_t *d_status, void *stream) {

@@ -1,6 +1,8 @@
 // Band filter kernels (Section 3.1): band tags, pruned separable FFT synthesis
 // of psi, vx, vy at the patch nodes, cell forcings, and line energies of the
 // off-diagonal bands.
+#include <algorithm>
+
 #include "band_core.h"
 
 namespace shmm {
@@ -64,6 +66,35 @@ __global__ void k_seam(const shmm_domain *dom, int64_t first, int n, const float
     const int64_t last = (int64_t)(n - 1) * n;
     vx[o + last + i] = -(P[i] - P[last + i]) * ih;
     vy[o + (int64_t)i * n + (n - 1)] = (P[(int64_t)i * n] - P[(int64_t)i * n + (n - 1)]) * ih;
+}
+
+// Windowed patches: the face velocities of the tapered stream function
+// W psi, W = w(x) w(y) on the nodes of each patch, with w 0 on the seam node,
+// rising as sin^2 over `taper` nodes and 1 inside (symmetric under
+// i -> n - i), so that the periodic extension of W psi is smooth.  The faces
+// are differences of that one node field (zero discrete divergence).
+__device__ inline float taper_weight(int i, int n, int taper) {
+    const int e = i < n - i ? i : n - i;
+    if (e >= taper) return 1.0f;
+    const double s = sin(0.5 * M_PI * (double)e / (double)taper);
+    return (float)(s * s);
+}
+
+__global__ void k_taper_faces(const shmm_domain *dom, int64_t first, int n, int taper, const float *psi,
+                              float *vx, float *vy) {
+    const int64_t d = first + blockIdx.y;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (int64_t)n * n) return;
+    const int64_t o = dom[d].offset;
+    const float ih = (float)(1.0 / dom[d].h);
+    const int j = (int)(c / n), i = (int)(c % n);
+    const int jn = (j + 1) & (n - 1), ie = (i + 1) & (n - 1);
+    const float wj = taper_weight(j, n, taper), wi = taper_weight(i, n, taper);
+    const float p = wj * wi * psi[o + c];
+    const float pn = taper_weight(jn, n, taper) * wi * psi[o + (int64_t)jn * n + i];
+    const float pe = wj * taper_weight(ie, n, taper) * psi[o + (int64_t)j * n + ie];
+    vx[o + c] = -(pn - p) * ih;
+    vy[o + c] = (pe - p) * ih;
 }
 
 // Gershgorin bound of the advection operator of each patch:
@@ -153,6 +184,26 @@ size_t band_filter_workspace(const InstDev &inst, const Group &g) {
     // G[3][kb1 + 1][M n], psi of the group's cells when the caller wants none,
     // then the line-energy contributions [outer wavenumbers][2 M n] (FP64)
     return line_part_offset(g) + (size_t)line_outer_count(inst, g.level) * 2 * g.M * g.n * sizeof(double);
+}
+
+int launch_window_patches(const shmm_domain *d_dom, int64_t first, int64_t count, int n, int taper,
+                          const float *d_psi, float *d_vx, float *d_vy, float *d_f1, float *d_f2, double *d_vmax,
+                          hipStream_t s) {
+    if (count <= 0 || taper <= 0) return SHMM_OK;
+    const int cells = n * n;
+    for (int64_t c0 = 0; c0 < count; c0 += 65535) {
+        const int64_t cn = std::min<int64_t>(65535, count - c0);
+        const dim3 grid((unsigned)((cells + 255) / 256), (unsigned)cn);
+        hipLaunchKernelGGL(k_taper_faces, grid, dim3(256), 0, s, d_dom, first + c0, n, taper, d_psi, d_vx, d_vy);
+        SHMM_HIP_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(k_forcing, grid, dim3(256), 0, s, d_dom, first + c0, n, (const float *)d_vx,
+                           (const float *)d_vy, d_f1, d_f2);
+        SHMM_HIP_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(k_vmax, dim3((unsigned)cn), dim3(256), 0, s, d_dom, first + c0, n, (const float *)d_vx,
+                           (const float *)d_vy, d_vmax);
+        SHMM_HIP_CHECK(hipGetLastError());
+    }
+    return SHMM_OK;
 }
 
 int launch_band_filter(const InstDev &inst, const Group &g, const shmm_domain *d_dom, float *d_psi,

@@ -63,6 +63,10 @@ int launch_band_filter(const InstDev &inst, const Group &g, const shmm_domain *d
                        float *d_psi, float *d_vx, float *d_vy, float *d_f1, float *d_f2,
                        double *d_lines, double *d_vmax, void *work, size_t work_bytes, hipStream_t s);
 size_t band_filter_workspace(const InstDev &inst, const Group &g);
+// windowed patches: faces of the tapered psi, their forcing and advection bounds
+int launch_window_patches(const shmm_domain *d_dom, int64_t first, int64_t count, int n, int taper,
+                          const float *d_psi, float *d_vx, float *d_vy, float *d_f1, float *d_f2, double *d_vmax,
+                          hipStream_t s);
 
 int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n,
                        int32_t max_steps, const float *vx, const float *vy, const float *f1,

@@ -79,6 +79,9 @@ class Hierarchy:
         # inner cells of each patch (0: the whole patch; the energy form and
         # the mass are then not formed)
         self.estimator_inner = 0
+        # windowed patches: taper the stream function over this many nodes at
+        # each patch edge after the band filter (needs keep_psi)
+        self.patch_taper = 0
 
     # -- pieces -------------------------------------------------------------
     def stream(self) -> int:
@@ -93,11 +96,24 @@ class Hierarchy:
     def band_filter(self) -> None:
         s = self.stream()
         nph = len(self.phase) - 1
+        if self.patch_taper and self.psi is None:
+            raise ValueError("windowed patches need the stream function (keep_psi=True)")
         for p in range(nph):
             first, count = int(self.phase[p]), int(self.phase[p + 1] - self.phase[p])
             self.ctx.shmm_band_filter(first, count, self.psi.data_ptr() if self.psi is not None else 0,
                                       self.vx.data_ptr(), self.vy.data_ptr(), self.f1.data_ptr(),
                                       self.f2.data_ptr(), self.lines.data_ptr(), s)
+            if self.patch_taper:
+                n = self.table["n"]
+                i = first
+                while i < first + count:   # runs of one patch size
+                    j = i
+                    while j < first + count and n[j] == n[i]:
+                        j += 1
+                    self.ctx.shmm_window_patches(i, j - i, self.patch_taper, self.psi.data_ptr(),
+                                                 self.vx.data_ptr(), self.vy.data_ptr(), self.f1.data_ptr(),
+                                                 self.f2.data_ptr(), s)
+                    i = j
 
     def top_down(self) -> None:
         s = self.stream()

@@ -117,6 +117,10 @@ def test_invalid_arguments_return_error_codes(torch):
                                           s)) == abi.SHMM_EINVAL
     assert code(lambda: c.shmm_macro_step(16, abi.BC_DIRICHLET_X, float("nan"), 0.0, 0, 0, Kc.data_ptr(), 0, 0.01,
                                           1, u16.data_ptr(), 64, s)) == abi.SHMM_EINVAL
+    # a taper wider than half a patch, or negative
+    for taper in (9, -1):
+        assert code(lambda: c.shmm_window_patches(0, nd, taper, H.vx.data_ptr(), H.vx.data_ptr(), H.vy.data_ptr(),
+                                                  H.f1.data_ptr(), H.f2.data_ptr(), s)) == abi.SHMM_EINVAL
     # an odd or negative estimator window
     for inner in (3, -2):
         assert code(lambda: c.shmm_effective_diffusivity_window(0, nd, inner, H.f1.data_ptr(), H.f2.data_ptr(),

@@ -228,6 +228,56 @@ def test_window_estimator_parity(torch, n, steps, inner):
     H.close()
 
 
+@pytest.mark.parametrize("n,taper,steps", [(64, 8, 300), (128, 16, 40)])
+def test_windowed_patches_parity(torch, n, taper, steps):
+    """Windowed patches: the faces, forcings and step plan of the tapered
+    stream function against the oracle's windowed fields from its own
+    synthesis, then the local solve and estimator on them.  The faces are
+    FP32 differences of the FP32 node field, so their bound is the node
+    bound (2e-6 of the scale of psi) carried through the difference:
+    2 x 2e-6 max|psi| / h plus FP32 rounding."""
+    p = _single_level(n, seed=n + 3, amp=0.3, kappa=0.05)
+    say("case windowed patches n=%d taper=%d" % (n, taper))
+    H = hier(p, keep_psi=True)
+    H.patch_taper = taper
+    H.band_filter()
+    Kb = np.tile([0.06, 0.015, 0.04], (H.nd, 1))
+    H.K_base.copy_(torch.from_numpy(Kb))
+    H.ctx.shmm_plan_steps(0, H.nd, Kb)
+    H.w.zero_()
+    H.ctx.shmm_local_solve_batch(0, H.nd, H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(),
+                                 H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(), 0, steps, 0, H.stream())
+    H.ctx.shmm_effective_diffusivity(0, H.nd, H.f1.data_ptr(), H.f2.data_ptr(), H.w.data_ptr(),
+                                     H.K_base.data_ptr(), H.K_solve.data_ptr(), 0, 0, 0, H.stream())
+    torch.cuda.synchronize()
+    table, cells, _, _ = H.ctx.shmm_ctx_table()
+    vx, vy = H.vx.cpu().numpy(), H.vy.cpu().numpy()
+    f1, f2 = H.f1.cpu().numpy(), H.f2.cpu().numpy()
+    w = H.w.cpu().numpy().reshape(2, cells)
+    K = H.K_solve.cpu().numpy()
+    lv, pt = oracle.band_split(p.kmax, p.thresh)
+    mask = oracle.band_mask(lv, pt, 0, DIAG)
+    for d in range(H.nd):
+        D = table[d]
+        o, h = int(D["offset"]), float(D["h"])
+        psi = oracle.synth_patch(p.psi_hat, p.kmax, mask, int(D["N"]), int(D["I0"]), int(D["J0"]), n)
+        rvx, rvy, rf1, rf2 = oracle.windowed_staggered(psi, h, taper)
+        tol = 4.5e-6 * np.abs(psi).max() / h
+        sl = slice(o, o + n * n)
+        for got, want in ((vx, rvx), (vy, rvy), (f1, rf1), (f2, rf2)):
+            assert np.abs(got[sl].reshape(n, n) - want).max() <= tol, d
+        ns_ref = oracle.plan_steps(n, h, Kb[d], oracle.advection_bound(rvx, rvy), p.dt_frac, p.delta)[1]
+        assert abs(int(D["nsteps"]) - ns_ref) <= 1, (d, int(D["nsteps"]), ns_ref)
+        ns = min(steps, int(D["nsteps"]))
+        wr = oracle.local_solve_batch([n], [h], rvx.ravel(), rvy.ravel(), rf1.ravel(), rf2.ravel(), Kb[d:d + 1],
+                                      [float(D["dt"])], [ns])
+        for j in range(2):
+            assert relerr(w[j, sl], wr[j]) <= 1e-4, (d, j)
+        Kr = oracle.estimate(rf1, rf2, wr[0].reshape(n, n), wr[1].reshape(n, n), Kb[d])
+        assert np.max(np.abs(K[d] - Kr)) <= 1e-5 * np.max(np.abs(Kr)), (d, K[d], Kr)
+    H.close()
+
+
 @pytest.mark.parametrize("n", [32, 128, 256])
 def test_chunked_solve_matches_single_launch(torch, n):
     p = _single_level(n, seed=9, amp=0.3, kappa=0.05)
