@@ -316,8 +316,11 @@ int launch_ring_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t n
         &occ, reinterpret_cast<const void *>(&k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR>), threads, 0));
     // every workgroup of the grid fits on the device at once
     int64_t groups = std::min<int64_t>(nlist, (int64_t)cus * occ / S::PER);
-    if (groups >= 8) groups -= groups % 8;
     if (groups < 1) return SHMM_EDEVICE;
+    // a multiple of 8 groups (the XCD-aware mapping) unless that adds a
+    // round of patches per group
+    const int64_t g8 = groups - groups % 8;
+    if (g8 >= 8 && (nlist + g8 - 1) / g8 == (nlist + groups - 1) / groups) groups = g8;
     const size_t need = (size_t)groups * S::PER * (2 * S::SLAB * sizeof(float) + sizeof(int32_t));
     if (!work || work_bytes < need) return SHMM_ENOMEM;
     float *slab = (float *)work;
