@@ -48,7 +48,7 @@ def _lib():
         lib.orc_synth_points.argtypes = [P, ctypes.c_int, P, i64, i64, P, P, P]
         lib.orc_line_energy.argtypes = [P, ctypes.c_int, P, i64, i64, ctypes.c_int, ctypes.c_int, P]
         lib.orc_rhs.argtypes = [ctypes.c_int, f64, P, P, P, P, P, P, P, P, P]
-        lib.orc_local_solve_batch.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, i64, P]
+        lib.orc_local_solve_batch.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, i64, P, ctypes.c_int]
         lib.orc_macro.argtypes = [ctypes.c_int, f64, P, P, P, ctypes.c_int, f64, i64, P]
         lib.orc_macro_dirichlet_x.argtypes = [ctypes.c_int, f64, f64, f64, P, P, P, ctypes.c_int, f64, i64, P]
         lib.orc_diffusion.argtypes = [ctypes.c_int, f64, P, P, P]
@@ -334,10 +334,12 @@ def diffusion(K, u, h) -> np.ndarray:
 
 def local_solve_batch(n: Sequence[int], h: Sequence[float], vx, vy, f1, f2,
                       Kb: np.ndarray, dt: Sequence[float], nsteps: Sequence[int],
-                      w0: Optional[np.ndarray] = None) -> np.ndarray:
+                      w0: Optional[np.ndarray] = None, frame: bool = False) -> np.ndarray:
     """Classic RK4 on both correctors of every domain; returns w [2][cells].
 
     vx, vy, f1, f2 are packed 1-D float64 arrays (domain after domain, [y][x]).
+    frame: the zero-frame (non-periodic) local problem, the last row and
+    column of every patch held at zero.
     """
     nn = _c(n, np.int32)
     off = np.zeros(len(nn), np.int64)
@@ -348,7 +350,7 @@ def local_solve_batch(n: Sequence[int], h: Sequence[float], vx, vy, f1, f2,
                                  _p(_c(vx, np.float64)), _p(_c(vy, np.float64)),
                                  _p(_c(f1, np.float64)), _p(_c(f2, np.float64)),
                                  _p(_c(Kb, np.float64).reshape(-1)), _p(_c(dt, np.float64)),
-                                 _p(_c(nsteps, np.int64)), total, _p(w))
+                                 _p(_c(nsteps, np.int64)), total, _p(w), 1 if frame else 0)
     return w.reshape(2, total)
 
 

@@ -159,11 +159,24 @@ void orc_rhs(int n, double h, const double *vx, const double *vy,
     free(jx); free(jy); free(ip); free(im);
 }
 
+/* Zero-frame local problems: the cells of the last row and the last column
+ * of the patch are held at zero (their right-hand side is zero), so that the
+ * corrector on the remaining (n-1)^2 cells vanishes on their boundary (a
+ * non-periodic local problem; the frame separates the patch from its
+ * periodic images, so no face across the patch seam is ever used). */
+static void zero_frame(int n, double *r)
+{
+    for (int i = 0; i < n; ++i) {
+        r[(size_t)(n - 1) * n + i] = 0.0;
+        r[(size_t)i * n + (n - 1)] = 0.0;
+    }
+}
+
 /* classic fourth-order Runge-Kutta for u' = rhs(u), nsteps steps of dt */
 static void rk4_run(int n, double h, const double *vx, const double *vy,
                     const double *kx11, const double *kx12, const double *ky12,
                     const double *ky22, const double *f, double dt, int64_t nsteps,
-                    double *u)
+                    double *u, int frame)
 {
     size_t cells = (size_t)n * n;
     double *k1 = (double *)malloc(sizeof(double) * cells);
@@ -173,12 +186,16 @@ static void rk4_run(int n, double h, const double *vx, const double *vy,
     double *y = (double *)malloc(sizeof(double) * cells);
     for (int64_t s = 0; s < nsteps; ++s) {
         orc_rhs(n, h, vx, vy, kx11, kx12, ky12, ky22, f, u, k1);
+        if (frame) zero_frame(n, k1);
         for (size_t c = 0; c < cells; ++c) y[c] = u[c] + 0.5 * dt * k1[c];
         orc_rhs(n, h, vx, vy, kx11, kx12, ky12, ky22, f, y, k2);
+        if (frame) zero_frame(n, k2);
         for (size_t c = 0; c < cells; ++c) y[c] = u[c] + 0.5 * dt * k2[c];
         orc_rhs(n, h, vx, vy, kx11, kx12, ky12, ky22, f, y, k3);
+        if (frame) zero_frame(n, k3);
         for (size_t c = 0; c < cells; ++c) y[c] = u[c] + dt * k3[c];
         orc_rhs(n, h, vx, vy, kx11, kx12, ky12, ky22, f, y, k4);
+        if (frame) zero_frame(n, k4);
         for (size_t c = 0; c < cells; ++c)
             u[c] = u[c] + dt / 6.0 * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]);
     }
@@ -201,7 +218,7 @@ static void fill(double *a, size_t m, double v) { for (size_t c = 0; c < m; ++c)
 void orc_local_solve_batch(int64_t nd, const int32_t *nn, const int64_t *off, const double *hh,
                            const double *vx, const double *vy, const double *f1,
                            const double *f2, const double *Kb, const double *dt,
-                           const int64_t *nsteps, int64_t total_cells, double *w)
+                           const int64_t *nsteps, int64_t total_cells, double *w, int frame)
 {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t t = 0; t < 2 * nd; ++t) {
@@ -224,7 +241,7 @@ void orc_local_solve_batch(int64_t nd, const int32_t *nn, const int64_t *off, co
         fill(kx12, cells, Kb[3 * d + 1]);
         fill(ky12, cells, Kb[3 * d + 1]);
         fill(ky22, cells, Kb[3 * d + 2]);
-        rk4_run(n, hh[d], vx + o, vy + o, kx11, kx12, ky12, ky22, f, dt[d], nsteps[d], u);
+        rk4_run(n, hh[d], vx + o, vy + o, kx11, kx12, ky12, ky22, f, dt[d], nsteps[d], u, frame);
         free(kx11); free(kx12); free(ky12); free(ky22);
     }
 }
@@ -259,7 +276,7 @@ void orc_macro(int N, double h, const double *vx, const double *vy, const double
                 ky22[c] = 0.5 * (Kc[3 * c + 2] + Kc[3 * cb + 2]);
             }
         }
-    rk4_run(N, h, vx, vy, kx11, kx12, ky12, ky22, NULL, dt, nsteps, u);
+    rk4_run(N, h, vx, vy, kx11, kx12, ky12, ky22, NULL, dt, nsteps, u, 0);
     free(kx11); free(kx12); free(ky12); free(ky22);
 }
 

@@ -817,3 +817,32 @@ def test_windowed_fields_are_divergence_free_and_untouched_inside():
     # 0), so the seam faces see only their inner node
     np.testing.assert_allclose(wx[n - 1, :], w[n - 1] * w * psi[n - 1, :] / h, rtol=1e-14, atol=0)
     np.testing.assert_allclose(wy[:, n - 1], -w * w[n - 1] * psi[:, n - 1] / h, rtol=1e-14, atol=0)
+
+
+def test_zero_frame_local_problem_is_the_dirichlet_mode_in_closed_form():
+    """Zero-frame local problem with no flow, K = kappa I and the forcing one
+    eigenvector of the Dirichlet Laplacian on the inner (n-1)^2 cells,
+    g = sin(pi p (i+1)/n) sin(pi q (j+1)/n) (zero on the frame row and column,
+    which the periodic wrap also puts beside cell 0).  Each RK4 step of
+    w' = lambda w + g with lambda = -(4 kappa / h^2)(sin^2(pi p/2n) +
+    sin^2(pi q/2n)) gives w_s = (g / -lambda)(1 - R(lambda dt)^s), R the RK4
+    stability polynomial; the frame stays exactly zero.  The periodic problem
+    differs."""
+    n, p_, q_, kap = 16, 2, 3, 0.07
+    h = 2 * np.pi / n
+    i = np.arange(n)
+    s1 = np.where(i < n - 1, np.sin(np.pi * p_ * (i + 1) / n), 0.0)
+    s2 = np.where(i < n - 1, np.sin(np.pi * q_ * (i + 1) / n), 0.0)
+    g = np.outer(s2, s1)                     # [y][x]
+    lam = -(4 * kap / h ** 2) * (np.sin(np.pi * p_ / (2 * n)) ** 2 + np.sin(np.pi * q_ / (2 * n)) ** 2)
+    dt, steps = 2.0 / (8 * kap / h ** 2), 37          # every mode inside the RK4 stability interval
+    z = lam * dt
+    R = 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+    zero = np.zeros(n * n)
+    w = oracle.local_solve_batch([n], [h], zero, zero, g.ravel(), zero, np.array([[kap, 0.0, kap]]), [dt], [steps],
+                                 frame=True)
+    want = g / -lam * (1 - R ** steps)
+    np.testing.assert_allclose(w[0].reshape(n, n), want, rtol=0, atol=1e-12 * np.abs(want).max())
+    assert np.all(w[0].reshape(n, n)[n - 1, :] == 0.0) and np.all(w[0].reshape(n, n)[:, n - 1] == 0.0)
+    wp = oracle.local_solve_batch([n], [h], zero, zero, g.ravel(), zero, np.array([[kap, 0.0, kap]]), [dt], [steps])
+    assert np.abs(wp[0] - w[0]).max() > 1e-3 * np.abs(want).max()
