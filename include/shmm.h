@@ -194,6 +194,22 @@ int shmm_band_filter(shmm_ctx *ctx, int64_t first, int64_t count, float *d_psi, 
 int shmm_window_patches(shmm_ctx *ctx, int64_t first, int64_t count, int32_t taper, const float *d_psi,
                         float *d_vx, float *d_vy, float *d_f1, float *d_f2, void *stream);
 
+/* Boundary of the local problems of every later local solve on the context
+ * (shmm_local_solve_batch, shmm_local_solve_adaptive, shmm_fallback_solve).
+ * SHMM_LOCAL_PERIODIC (the default): the patch is periodic (Section 2.2).
+ * SHMM_LOCAL_ZERO_FRAME: a non-periodic local problem, aimed at the
+ * non-periodicity of a component on its patch that the continuous-spectrum
+ * example of Section 4 lists among the error sources: the correctors are
+ * held at zero on the last row and the last column of every patch, so on the
+ * remaining (n - 1)^2 cells they vanish on the boundary, and no face across
+ * the patch seam is used.  These solves run stage by stage for every patch
+ * size (the workspace of the per-stage path) and are meant for oversampled
+ * patches with a windowed estimate (shmm_effective_diffusivity_window).
+ * Errors: SHMM_EINVAL for another value. */
+#define SHMM_LOCAL_PERIODIC 0
+#define SHMM_LOCAL_ZERO_FRAME 1
+int shmm_ctx_set_local_bc(shmm_ctx *ctx, int32_t bc);
+
 /* Local solves of domains [first, first + count) (HMM steps 1-2; the two
  * reconstructions with orthogonal gradients of the numerical homogenization):
  * advance both correctors w_j' = div(v w_j + K_b grad w_j) + f_j by classic

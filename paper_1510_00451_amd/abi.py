@@ -22,12 +22,13 @@ MAX_LEVELS = 8
 EXPORTS = ["shmm_ctx_create", "shmm_ctx_destroy", "shmm_build_levels", "shmm_ctx_set_problem",
            "shmm_ctx_table", "shmm_band_tags", "shmm_plan_steps", "shmm_band_filter",
            "shmm_local_solve_batch", "shmm_local_solve_adaptive", "shmm_effective_diffusivity",
-           "shmm_effective_diffusivity_window", "shmm_window_patches",
+           "shmm_effective_diffusivity_window", "shmm_window_patches", "shmm_ctx_set_local_bc",
            "shmm_level_chain",
            "shmm_macro_step", "shmm_ctx_tune", "shmm_patch_features", "shmm_surrogate_refresh",
            "shmm_surrogate_train_step", "shmm_surrogate_infer", "shmm_fallback_solve"]
 
 BC_PERIODIC, BC_DIRICHLET_X = 0, 1
+LOCAL_PERIODIC, LOCAL_ZERO_FRAME = 0, 1
 SURR_BINS, SURR_IN, SURR_WIDTH, SURR_OUT = 32, 33, 256, 3
 SURR_PARAMS, SURR_PARAMS_PADDED = 141059, 141312
 SURR_MODEL_BYTES = 4 * SURR_PARAMS_PADDED + 4 * 128 + 2 * SURR_PARAMS_PADDED
@@ -78,6 +79,7 @@ def lib() -> ctypes.CDLL:
             "shmm_effective_diffusivity": [P, i64, i64, P, P, P, P, P, P, P, P, P],
             "shmm_effective_diffusivity_window": [P, i64, i64, i32, P, P, P, P, P, P, P],
             "shmm_window_patches": [P, i64, i64, i32, P, P, P, P, P, P],
+            "shmm_ctx_set_local_bc": [P, i32],
             "shmm_level_chain": [P, i64, i64, i32, P, P, P, P, P, P, P, P],
             "shmm_macro_step": [P, i32, i32, f64, f64, P, P, P, i32, f64, i32, P, i32, P],
             "shmm_ctx_tune": [P, i32, i32],
@@ -213,6 +215,9 @@ class Context:
                                                d_K_out, d_K_energy or None, d_mass or None,
                                                d_status or None, stream),
               "shmm_effective_diffusivity")
+
+    def shmm_ctx_set_local_bc(self, bc):
+        check(lib().shmm_ctx_set_local_bc(self.h, int(bc)), "shmm_ctx_set_local_bc")
 
     def shmm_window_patches(self, first, count, taper, d_psi, d_vx, d_vy, d_f1, d_f2, stream=0):
         check(lib().shmm_window_patches(self.h, first, count, int(taper), d_psi, d_vx, d_vy, d_f1, d_f2, stream),

@@ -197,6 +197,7 @@ struct shmm_ctx {
     std::vector<std::vector<int>> empty;     // [inst][level]: diagonal band without coefficients
     std::map<std::pair<int64_t, int64_t>, RangeLists> lists;
     std::map<int, int> solve_variant;          // patch size n -> kernel variant
+    int32_t local_bc = SHMM_LOCAL_PERIODIC;    // boundary of the local problems
     void *work = nullptr;
     size_t work_bytes = 0;
     void *adapt = nullptr;                      // previous correctors and chunk statistics (adaptive stop)
@@ -666,7 +667,9 @@ int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const fl
         variant[q] = it == ctx->solve_variant.end() ? default_solve_variant(rl->ns[q]) : it->second;
     }
     size_t need = 0;
-    for (size_t q = 0; q < groups; ++q) need = std::max(need, local_solve_workspace(rl->ns[q], rl->cells[q]));
+    const bool frame = ctx->local_bc == SHMM_LOCAL_ZERO_FRAME;
+    for (size_t q = 0; q < groups; ++q)
+        need = std::max(need, local_solve_workspace(rl->ns[q], rl->cells[q], frame));
     if (need && (rc = ctx->ensure_work(need))) return rc;
     hipStream_t main_s = (hipStream_t)stream;
     auto max_steps_of = [&](size_t q) {
@@ -680,14 +683,14 @@ int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const fl
         if (groups > 1 && runs_alone(rl->ns[q], variant[q])) {
             rc = launch_local_solve(ctx->d_table, rl->d_lists[q], rl->counts[q], rl->ns[q], max_steps_of(q), d_vx,
                                     d_vy, d_f1, d_f2, d_K_base, d_w, ctx->cells, step_begin, steps, rl->cells[q],
-                                    ctx->work, variant[q], main_s);
+                                    ctx->work, variant[q], main_s, frame);
             if (rc) return rc;
         } else {
             rest.push_back(q);
         }
     }
     int n_work = 0;
-    for (size_t q : rest) n_work += local_solve_workspace(rl->ns[q], rl->cells[q]) ? 1 : 0;
+    for (size_t q : rest) n_work += local_solve_workspace(rl->ns[q], rl->cells[q], frame) ? 1 : 0;
     const bool concurrent = rest.size() > 1 && n_work <= 1;
     bool used[kSideStreams] = {};
     if (concurrent) {
@@ -704,7 +707,7 @@ int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const fl
     for (size_t k = 0; k < rest.size(); ++k) {
         const size_t q = rest[k];
         hipStream_t s = main_s;
-        const bool on_main = !concurrent || local_solve_workspace(rl->ns[q], rl->cells[q]) ||
+        const bool on_main = !concurrent || local_solve_workspace(rl->ns[q], rl->cells[q], frame) ||
                              (n_work == 0 && k == 0);
         if (!on_main) {
             const int i = next_side++ % kSideStreams;
@@ -714,7 +717,7 @@ int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const fl
         }
         rc = launch_local_solve(ctx->d_table, rl->d_lists[q], rl->counts[q], rl->ns[q], max_steps_of(q),
                                 d_vx, d_vy, d_f1, d_f2, d_K_base, d_w, ctx->cells, step_begin, steps,
-                                rl->cells[q], ctx->work, variant[q], s);
+                                rl->cells[q], ctx->work, variant[q], s, frame);
         if (rc) return rc;
     }
     for (int i = 0; i < kSideStreams; ++i)
@@ -756,6 +759,12 @@ int shmm_effective_diffusivity(shmm_ctx *ctx, int64_t first, int64_t count, cons
     return launch_effective_diffusivity(ctx->d_table, first, count, d_f1, d_f2, d_w, ctx->cells,
                                         d_K_base, d_K_out, d_K_energy, d_mass, d_status,
                                         (hipStream_t)stream);
+}
+
+int shmm_ctx_set_local_bc(shmm_ctx *ctx, int32_t bc) {
+    if (!ctx || (bc != SHMM_LOCAL_PERIODIC && bc != SHMM_LOCAL_ZERO_FRAME)) return SHMM_EINVAL;
+    ctx->local_bc = bc;
+    return SHMM_OK;
 }
 
 int shmm_window_patches(shmm_ctx *ctx, int64_t first, int64_t count, int32_t taper, const float *d_psi,
@@ -909,7 +918,8 @@ int shmm_fallback_solve(shmm_ctx *ctx, int64_t first, int64_t count, const uint8
         if ((rc = ctx->temp_list(ids, &dl))) return rc;
         if ((rc = launch_zero_fields(ctx->d_table, dl, (int32_t)ids.size(), n, d_w, ctx->cells, s))) return rc;
         const int64_t cells = (int64_t)ids.size() * n * n;
-        const size_t need = local_solve_workspace(n, cells);
+        const bool frame = ctx->local_bc == SHMM_LOCAL_ZERO_FRAME;
+        const size_t need = local_solve_workspace(n, cells, frame);
         if (need && (rc = ctx->ensure_work(need))) return rc;
         const auto it = ctx->solve_variant.find(n);
         const int variant = it == ctx->solve_variant.end() ? default_solve_variant(n) : it->second;
@@ -919,11 +929,12 @@ int shmm_fallback_solve(shmm_ctx *ctx, int64_t first, int64_t count, const uint8
                 int32_t longest = 0;
                 for (int32_t d : ids) longest = std::max(longest, ctx->table[d].nsteps);
                 return launch_local_solve(ctx->d_table, dl, (int32_t)ids.size(), n, longest, d_vx, d_vy, d_f1, d_f2,
-                                          d_K_base, d_w, ctx->cells, s0, C, cells, ctx->work, variant, s);
+                                          d_K_base, d_w, ctx->cells, s0, C, cells, ctx->work, variant, s, frame);
             });
         } else {
             rc = launch_local_solve(ctx->d_table, dl, (int32_t)ids.size(), n, max_steps, d_vx, d_vy, d_f1, d_f2,
-                                    d_K_base, d_w, ctx->cells, 0, 2147483647, cells, ctx->work, variant, s);
+                                    d_K_base, d_w, ctx->cells, 0, 2147483647, cells, ctx->work, variant, s,
+                                    frame);
         }
         if (rc) return rc;
         rc = launch_effective_diffusivity_list(ctx->d_table, dl, (int64_t)ids.size(), d_f1, d_f2, d_w,

@@ -72,7 +72,7 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
                        int32_t max_steps, const float *vx, const float *vy, const float *f1,
                        const float *f2, const double *Kb, float *w, int64_t cells_total,
                        int32_t step_begin, int32_t steps, int64_t list_cells, void *work,
-                       int variant, hipStream_t s);
+                       int variant, hipStream_t s, bool frame = false);
 bool local_solve_resident(int n);
 // persistent full-width bands of 256^2 patches with a ring exchange between
 // them; work holds the exchange slabs and round counters
@@ -80,7 +80,8 @@ int launch_ring_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t n
                       const float *vy, const double *Kb, float *w, int64_t cells_total, int32_t step_begin,
                       int32_t s_end, void *work, size_t work_bytes, hipStream_t s);
 int local_solve_variants(int n);
-size_t local_solve_workspace(int n, int64_t list_cells);
+// frame: the zero-frame (non-periodic) local problem, run stage by stage
+size_t local_solve_workspace(int n, int64_t list_cells, bool frame = false);
 int launch_zero_fields(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n, float *d_w,
                        int64_t cells, hipStream_t s);
 

@@ -723,7 +723,7 @@ __global__ __launch_bounds__(256) void k_solve_stage(
     const float *__restrict__ vx, const float *__restrict__ vy, const double *__restrict__ Kb,
     float *__restrict__ w, int64_t cells_total, const float *__restrict__ ycur,
     float *__restrict__ ynext, float *__restrict__ acc, float *__restrict__ comp,
-    int64_t list_cells, int32_t step, int st) {
+    int64_t list_cells, int32_t step, int st, int frame) {
     const int li = blockIdx.y >> 1;
     const int field = blockIdx.y & 1;
     const int64_t d = list[li];
@@ -752,6 +752,8 @@ __global__ __launch_bounds__(256) void k_solve_stage(
     t = fmaf(k.cxx, cE + cW, t);
     t = fmaf(k.cyy, nC + sC, t);
     t = fmaf(k.cxy, (nE - nW) - (sE - sW), t);
+    // zero-frame local problem: the last row and column stay at zero
+    if (frame && (x == mask || y == mask)) t = 0.0f;
     float *wf = w + (int64_t)field * cells_total + o;
     const float wc = wf[c];
     float out;
@@ -839,8 +841,8 @@ int launch_zero_fields(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
     return SHMM_OK;
 }
 
-size_t local_solve_workspace(int n, int64_t list_cells) {
-    if (local_solve_resident(n)) return 0;
+size_t local_solve_workspace(int n, int64_t list_cells, bool frame) {
+    if (local_solve_resident(n) && !frame) return 0;
     return (size_t)4 * 2 * list_cells * sizeof(float);   // ycur, ynext, acc, comp; 2 fields
 }
 
@@ -848,11 +850,12 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
                        int32_t max_steps, const float *vx, const float *vy, const float *f1,
                        const float *f2, const double *Kb, float *w, int64_t cells_total,
                        int32_t step_begin, int32_t steps, int64_t list_cells, void *work,
-                       int variant, hipStream_t s) {
+                       int variant, hipStream_t s, bool frame) {
     (void)f1;
     (void)f2;   // the forcing is rebuilt from the face velocities in registers
     if (nlist <= 0) return SHMM_OK;
-    switch (n) {
+    // the zero-frame local problem runs stage by stage for every size
+    switch (frame ? 0 : n) {
         case 8: return launch_resident_e<8, 2>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
         case 16: return launch_resident_e<16, 4>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
         case 32: return launch_resident_e<32, 8>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
@@ -877,10 +880,10 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
           *comp = ws + 6 * list_cells;
     const int64_t s_end64 = (int64_t)step_begin + steps;
     const int32_t s_end = (int32_t)(s_end64 < max_steps ? s_end64 : max_steps);
-    if (n == 256 && variant == 6)   // persistent bands with a ring exchange (solve_ring.hip)
+    if (n == 256 && variant == 6 && !frame)   // persistent bands with a ring exchange (solve_ring.hip)
         return launch_ring_solve(d_dom, d_list, nlist, n, vx, vy, Kb, w, cells_total, step_begin, s_end, work,
                                  local_solve_workspace(n, list_cells), s);
-    if (n == 256 && variant != 2) {
+    if (n == 256 && variant != 2 && !frame) {
         // Overlapped regions, HALO / 4 steps per launch.  Full-width bands:
         // variant 0 32 rows with 8 above and below (768 threads), 1 the same
         // with 1024 threads, 3 24 rows with 12 (3 steps per launch), 4 16
@@ -943,7 +946,7 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
     for (int32_t step = step_begin; step < s_end; ++step) {
         for (int st = 0; st < 4; ++st) {
             hipLaunchKernelGGL(k_solve_stage, grid, dim3(256), 0, s, d_dom, d_list, n, vx, vy, Kb, w,
-                               cells_total, ycur, ynext, acc, comp, list_cells, step, st);
+                               cells_total, ycur, ynext, acc, comp, list_cells, step, st, frame ? 1 : 0);
             SHMM_HIP_CHECK(hipGetLastError());
             float *t = ycur;
             ycur = ynext;

@@ -117,6 +117,8 @@ def test_invalid_arguments_return_error_codes(torch):
                                           s)) == abi.SHMM_EINVAL
     assert code(lambda: c.shmm_macro_step(16, abi.BC_DIRICHLET_X, float("nan"), 0.0, 0, 0, Kc.data_ptr(), 0, 0.01,
                                           1, u16.data_ptr(), 64, s)) == abi.SHMM_EINVAL
+    # an unknown boundary for the local problems
+    assert code(lambda: c.shmm_ctx_set_local_bc(2)) == abi.SHMM_EINVAL
     # a taper wider than half a patch, or negative
     for taper in (9, -1):
         assert code(lambda: c.shmm_window_patches(0, nd, taper, H.vx.data_ptr(), H.vx.data_ptr(), H.vy.data_ptr(),

@@ -278,6 +278,49 @@ def test_windowed_patches_parity(torch, n, taper, steps):
     H.close()
 
 
+@pytest.mark.parametrize("n,steps", [(32, None), (64, 400), (128, 60)])
+def test_zero_frame_local_problem_parity(torch, n, steps):
+    """Zero-frame (non-periodic) local problems: correctors against the
+    oracle's zero-frame solve of its own synthesis, the frame cells exactly
+    zero, and the estimate over the centred (n - 2)^2 window."""
+    from paper_1510_00451_amd import abi
+    p = _single_level(n, seed=n + 5, amp=0.3, kappa=0.05)
+    say("case zero-frame local problem n=%d" % n)
+    H = hier(p, keep_psi=False)
+    H.ctx.shmm_ctx_set_local_bc(abi.LOCAL_ZERO_FRAME)
+    H.band_filter()
+    Kb = np.tile([0.06, 0.015, 0.04], (H.nd, 1))
+    H.K_base.copy_(torch.from_numpy(Kb))
+    H.ctx.shmm_plan_steps(0, H.nd, Kb)
+    H.w.zero_()
+    H.ctx.shmm_local_solve_batch(0, H.nd, H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(),
+                                 H.f2.data_ptr(), H.K_base.data_ptr(), H.w.data_ptr(), 0,
+                                 2 ** 31 - 1 if steps is None else steps, 0, H.stream())
+    H.ctx.shmm_effective_diffusivity_window(0, H.nd, n - 2, H.f1.data_ptr(), H.f2.data_ptr(), H.w.data_ptr(),
+                                            H.K_base.data_ptr(), H.K_solve.data_ptr(), 0, H.stream())
+    torch.cuda.synchronize()
+    table, cells, _, _ = H.ctx.shmm_ctx_table()
+    w = H.w.cpu().numpy().reshape(2, cells)
+    K = H.K_solve.cpu().numpy()
+    lv, pt = oracle.band_split(p.kmax, p.thresh)
+    mask = oracle.band_mask(lv, pt, 0, DIAG)
+    for d in range(H.nd):
+        D = table[d]
+        o = int(D["offset"])
+        psi = oracle.synth_patch(p.psi_hat, p.kmax, mask, int(D["N"]), int(D["I0"]), int(D["J0"]), n)
+        vx, vy, f1, f2 = oracle.staggered(psi, float(D["h"]))
+        ns = int(D["nsteps"]) if steps is None else min(steps, int(D["nsteps"]))
+        wr = oracle.local_solve_batch([n], [float(D["h"])], vx.ravel(), vy.ravel(), f1.ravel(), f2.ravel(),
+                                      Kb[d:d + 1], [float(D["dt"])], [ns], frame=True)
+        for j in range(2):
+            wg = w[j, o:o + n * n].reshape(n, n)
+            assert np.all(wg[n - 1, :] == 0.0) and np.all(wg[:, n - 1] == 0.0), (d, j)
+            assert relerr(wg, wr[j].reshape(n, n)) <= 1e-5, (n, d, j)
+        Kr = oracle.estimate_window(f1, f2, wr[0].reshape(n, n), wr[1].reshape(n, n), Kb[d], n - 2)
+        assert np.max(np.abs(K[d] - Kr)) <= 1e-5 * np.max(np.abs(Kr)), (n, d, K[d], Kr)
+    H.close()
+
+
 @pytest.mark.parametrize("n", [32, 128, 256])
 def test_chunked_solve_matches_single_launch(torch, n):
     p = _single_level(n, seed=9, amp=0.3, kappa=0.05)
