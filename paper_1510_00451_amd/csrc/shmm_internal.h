@@ -80,7 +80,7 @@ int launch_ring_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t n
                       const float *vy, const double *Kb, float *w, int64_t cells_total, int32_t step_begin,
                       int32_t s_end, void *work, size_t work_bytes, hipStream_t s);
 int local_solve_variants(int n);
-// frame: the zero-frame (non-periodic) local problem, run stage by stage
+// frame: the zero-frame (non-periodic) local problem (resident up to 128^2)
 size_t local_solve_workspace(int n, int64_t list_cells, bool frame = false);
 int launch_zero_fields(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n, float *d_w,
                        int64_t cells, hipStream_t s);

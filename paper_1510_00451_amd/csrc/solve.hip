@@ -167,7 +167,7 @@ __global__ __launch_bounds__(NN *NN / R) void k_solve_resident(
 }
 
 // Resident kernel, coefficient form (rk_stage_e).
-template <int NN, int R, int FIELD, int CL>
+template <int NN, int R, int FIELD, int CL, bool FRAME = false>
 __device__ __forceinline__ void solve_body_e(float *__restrict__ buf, const shmm_domain *__restrict__ dom,
                                              const int32_t *__restrict__ list,
                                              const float *__restrict__ vx, const float *__restrict__ vy,
@@ -221,17 +221,17 @@ __device__ __forceinline__ void solve_body_e(float *__restrict__ buf, const shmm
     __syncthreads();
     constexpr bool OP = NN >= 128;
     for (int32_t s = step_begin; s < s_end; ++s) {
-        rk_stage_e<NN, R, FIELD, 0, OP, CL>(lo, offW, offE, offS, offN, hi, k, two_cyy, 0.0f, eE, eW, nb, wv, comp,
-                                            rr, cl, T);
+        rk_stage_e<NN, R, FIELD, 0, OP, CL, FRAME>(lo, offW, offE, offS, offN, hi, k, two_cyy, 0.0f, eE, eW, nb, wv, comp,
+                                            rr, cl, T, y0, x == MASK);
         __syncthreads();
-        rk_stage_e<NN, R, FIELD, 1, OP, CL>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.25f, eE, eW, nb, wv, comp,
-                                            rr, cl, T);
+        rk_stage_e<NN, R, FIELD, 1, OP, CL, FRAME>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.25f, eE, eW, nb, wv, comp,
+                                            rr, cl, T, y0, x == MASK);
         __syncthreads();
-        rk_stage_e<NN, R, FIELD, 1, OP, CL>(lo, offW, offE, offS, offN, hi, k, two_cyy, 1.0f / 3.0f, eE, eW, nb, wv,
-                                            comp, rr, cl, T);
+        rk_stage_e<NN, R, FIELD, 1, OP, CL, FRAME>(lo, offW, offE, offS, offN, hi, k, two_cyy, 1.0f / 3.0f, eE, eW, nb, wv,
+                                            comp, rr, cl, T, y0, x == MASK);
         __syncthreads();
-        rk_stage_e<NN, R, FIELD, 2, OP, CL>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.5f, eE, eW, nb, wv, comp,
-                                            rr, cl, T);
+        rk_stage_e<NN, R, FIELD, 2, OP, CL, FRAME>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.5f, eE, eW, nb, wv, comp,
+                                            rr, cl, T, y0, x == MASK);
         __syncthreads();
     }
     // a fresh base pointer: the row addresses are rebuilt here instead of
@@ -241,16 +241,16 @@ __device__ __forceinline__ void solve_body_e(float *__restrict__ buf, const shmm
     for (int r = 0; r < R; ++r) wf[r * NN] = wv[r];
 }
 
-template <int NN, int R, int CL = 0>
+template <int NN, int R, int CL = 0, bool FRAME = false>
 __global__ __launch_bounds__(NN *NN / R) void k_solve_resident_e(
     const shmm_domain *__restrict__ dom, const int32_t *__restrict__ list,
     const float *__restrict__ vx, const float *__restrict__ vy, const double *__restrict__ Kb,
     float *__restrict__ w, int64_t cells_total, int32_t step_begin, int32_t steps) {
     __shared__ float buf[2 * NN * NN + CL * (NN * NN / R)];
     if (blockIdx.x & 1)
-        solve_body_e<NN, R, 1, CL>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
+        solve_body_e<NN, R, 1, CL, FRAME>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
     else
-        solve_body_e<NN, R, 0, CL>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
+        solve_body_e<NN, R, 0, CL, FRAME>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
 }
 
 // Row-resident variant for patches whose row fits one wavefront (n = 64 C):
@@ -800,11 +800,11 @@ int launch_resident(const shmm_domain *d_dom, const int32_t *d_list, int32_t nli
     return SHMM_OK;
 }
 
-template <int NN, int R, int CL = 0>
+template <int NN, int R, int CL = 0, bool FRAME = false>
 int launch_resident_e(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, const float *vx,
                       const float *vy, const double *Kb, float *w, int64_t cells_total,
                       int32_t step_begin, int32_t steps, hipStream_t s) {
-    hipLaunchKernelGGL((k_solve_resident_e<NN, R, CL>), dim3((unsigned)(2 * nlist)), dim3(NN * NN / R), 0, s,
+    hipLaunchKernelGGL((k_solve_resident_e<NN, R, CL, FRAME>), dim3((unsigned)(2 * nlist)), dim3(NN * NN / R), 0, s,
                        d_dom, d_list, vx, vy, Kb, w, cells_total, step_begin, steps);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
@@ -842,7 +842,8 @@ int launch_zero_fields(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
 }
 
 size_t local_solve_workspace(int n, int64_t list_cells, bool frame) {
-    if (local_solve_resident(n) && !frame) return 0;
+    (void)frame;   // zero-frame solves of resident sizes stay resident too
+    if (local_solve_resident(n)) return 0;
     return (size_t)4 * 2 * list_cells * sizeof(float);   // ycur, ynext, acc, comp; 2 fields
 }
 
@@ -854,7 +855,18 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
     (void)f1;
     (void)f2;   // the forcing is rebuilt from the face velocities in registers
     if (nlist <= 0) return SHMM_OK;
-    // the zero-frame local problem runs stage by stage for every size
+    // the zero-frame local problem: the resident coefficient-form kernels
+    // with the frame held at zero up to 128^2, stage by stage above
+    if (frame) {
+        switch (n) {
+            case 8: return launch_resident_e<8, 2, 0, true>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            case 16: return launch_resident_e<16, 4, 0, true>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            case 32: return launch_resident_e<32, 8, 0, true>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            case 64: return launch_resident_e<64, 16, 0, true>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            case 128: return launch_resident_e<128, 32, 8, true>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            default: break;
+        }
+    }
     switch (frame ? 0 : n) {
         case 8: return launch_resident_e<8, 2>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
         case 16: return launch_resident_e<16, 4>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);

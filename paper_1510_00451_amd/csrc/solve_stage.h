@@ -44,13 +44,15 @@ __device__ __forceinline__ float uniform(float v) {
 // with the derived values hoisted.
 // CL: the compensation of the first CL rows of the strip lives in LDS
 // (cl[r * cstride]) instead of registers, to relieve register pressure.
-template <int NN, int R, int FIELD, int KIND, bool OPAQUE, int CL = 0>
+// FRAME: the zero-frame local problem; the cells of the patch's last column
+// (xlast) and last row (strip row y0 + r = NN - 1) keep a zero derivative.
+template <int NN, int R, int FIELD, int KIND, bool OPAQUE, int CL = 0, bool FRAME = false>
 __device__ __forceinline__ void rk_stage_e(const float *__restrict__ C, int offW, int offE, int offS,
                                            int offN, float *__restrict__ out, const SolveConsts &k,
                                            float two_cyy, float cw, float (&eE)[R], float (&eW)[R],
                                            float (&nb)[R + 1], float (&wv)[R], float (&comp)[R],
                                            float (&rr)[R], float *__restrict__ cl = nullptr,
-                                           int cstride = 0) {
+                                           int cstride = 0, int y0 = 0, bool xlast = false) {
     if (OPAQUE) {
 #pragma unroll
         for (int r = 0; r < R; ++r) asm volatile("" : "+v"(eE[r]), "+v"(eW[r]));
@@ -74,9 +76,15 @@ __device__ __forceinline__ void rk_stage_e(const float *__restrict__ C, int offW
         t = fmaf(nb[r + 1], nC, t);
         t = fmaf(eS, sC, t);
         t = fmaf(k.cxy, dN - dS, t);
+        float keep = 1.0f;
+        if (FRAME) {
+            keep = (xlast || y0 + r == NN - 1) ? 0.0f : 1.0f;
+            t *= keep;
+        }
         float o;
         if (KIND == 0) {
             rr[r] = FIELD == 0 ? fmaf(k.fh, eE[r] - eW[r], t) : fmaf(k.fh, nb[r + 1] - eS, t);
+            if (FRAME) rr[r] *= keep;
             o = rr[r];
         } else if (KIND == 1) {
             o = fmaf(cw, t, rr[r]);

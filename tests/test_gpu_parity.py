@@ -278,11 +278,12 @@ def test_windowed_patches_parity(torch, n, taper, steps):
     H.close()
 
 
-@pytest.mark.parametrize("n,steps", [(32, None), (64, 400), (128, 60)])
+@pytest.mark.parametrize("n,steps", [(32, None), (64, 400), (128, 60), (256, 12)])
 def test_zero_frame_local_problem_parity(torch, n, steps):
-    """Zero-frame (non-periodic) local problems: correctors against the
-    oracle's zero-frame solve of its own synthesis, the frame cells exactly
-    zero, and the estimate over the centred (n - 2)^2 window."""
+    """Zero-frame (non-periodic) local problems (resident kernels up to 128^2,
+    the per-stage kernel at 256^2): correctors against the oracle's
+    zero-frame solve of its own synthesis, the frame cells exactly zero, and
+    the estimate over the centred (n - 2)^2 window."""
     from paper_1510_00451_amd import abi
     p = _single_level(n, seed=n + 5, amp=0.3, kappa=0.05)
     say("case zero-frame local problem n=%d" % n)
