@@ -526,14 +526,16 @@ def macro_diffusivity(res: HierarchyResult, i: int) -> np.ndarray:
     return sum_offdiag(res.K_base[i], s12, s21)
 
 
-def level_fields(p, level_arr, part_arr, d: Domain):
-    """Diagonal-band psi, face velocities and forcings of one domain."""
+def level_fields(p, level_arr, part_arr, d: Domain, taper: int = 0):
+    """Diagonal-band psi, face velocities and forcings of one domain (with
+    taper > 0, of the tapered stream function of a windowed patch)."""
     mask = band_mask(level_arr, part_arr, d.level, DIAG)
     psi = synth_patch(p.psi_hat, p.kmax, mask, d.N, d.I0, d.J0, d.n)
-    return (psi,) + staggered(psi, d.h)
+    return (psi,) + (windowed_staggered(psi, d.h, taper) if taper > 0 else staggered(psi, d.h))
 
 
-def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = None) -> HierarchyResult:
+def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = None, inner: int = 0,
+                  taper: int = 0, frame: bool = False) -> HierarchyResult:
     """K[psi, kappa I; Omega_1] at every centre by Algorithm 3 generalised to L levels.
 
     R(l, K_in) = LS(diag_l, K_in)                                   l = finest
@@ -545,6 +547,11 @@ def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = N
     (K[psi11 + psi12 + psi21, K_net] = sum of the three effects minus twice the
     repeated base).  K_in = kappa I at the coarsest level.  When a lattice is
     finer than its parent's, K_star is the mean of the children's results.
+
+    Patch options (all levels): inner > 0 averages each estimate over the
+    centred inner x inner window (oversampled patches), taper > 0 tapers each
+    patch's stream function (windowed patches), frame holds the correctors at
+    zero on each patch's last row and column (zero-frame local problems).
     """
     if not isinstance(probs, (list, tuple)):
         probs = [probs]
@@ -602,7 +609,7 @@ def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = N
     for lev in range(maxL - 1, -1, -1):
         idx = [i for i, d in enumerate(doms) if d.level == lev]
         # fields of this level (one batch)
-        fields = [level_fields(probs[doms[i].instance], *splits[doms[i].instance], doms[i]) for i in idx]
+        fields = [level_fields(probs[doms[i].instance], *splits[doms[i].instance], doms[i], taper) for i in idx]
         # bases of this level
         for t, i in enumerate(idx):
             d = doms[i]
@@ -625,14 +632,14 @@ def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = N
         f2 = np.concatenate([f[4].reshape(-1) for f in fields])
         ns = nsteps[idx] if steps_override is None else np.full(len(idx), steps_override, np.int64)
         w = local_solve_batch([doms[i].n for i in idx], [doms[i].h for i in idx], vx, vy, f1, f2,
-                              K_base[idx], dt[idx], ns)
+                              K_base[idx], dt[idx], ns, frame=frame)
         o = 0
         for t, i in enumerate(idx):
             d = doms[i]
             m = d.n * d.n
             w1 = w[0, o:o + m].reshape(d.n, d.n)
             w2 = w[1, o:o + m].reshape(d.n, d.n)
-            K_solve[i] = estimate(fields[t][3], fields[t][4], w1, w2, K_base[i])
+            K_solve[i] = estimate_window(fields[t][3], fields[t][4], w1, w2, K_base[i], inner)
             if wkeep is not None:
                 wkeep[i] = np.stack([w1, w2])
             if lev == L_of[d.instance] - 1:

@@ -322,6 +322,29 @@ def test_zero_frame_local_problem_parity(torch, n, steps):
     H.close()
 
 
+@pytest.mark.parametrize("inner,taper,frame", [(16, 0, False), (16, 8, False), (16, 0, True), (0, 0, True)])
+def test_patch_options_pass_parity(torch, inner, taper, frame):
+    """A whole pass with the patch options (centred estimator window,
+    tapered stream function, zero-frame local problems) on a two-level
+    band-pass-like flow against the oracle's hierarchy with the same
+    options."""
+    from paper_1510_00451_amd import abi
+    p = flowgen.config_continuous(seed=6, radius=12, p=-1.5, kappa=0.1, n=32, lattice=2, levels=2)
+    p.psi_hat *= 0.5
+    say("case pass with patch options inner=%d taper=%d frame=%s" % (inner, taper, frame))
+    H = hier(p, keep_psi=taper > 0)
+    H.estimator_inner = inner
+    H.patch_taper = taper
+    H.ctx.shmm_ctx_set_local_bc(abi.LOCAL_ZERO_FRAME if frame else abi.LOCAL_PERIODIC)
+    H.run()
+    r = H.result()
+    ref = oracle.run_hierarchy(p, inner=inner, taper=taper, frame=frame)
+    scale = np.abs(ref.R).max()
+    assert np.abs(r.K_solve - ref.K_solve).max() <= 1e-5 * scale
+    assert np.abs(r.R - ref.R).max() <= 1e-5 * scale
+    H.close()
+
+
 @pytest.mark.parametrize("n", [32, 128, 256])
 def test_chunked_solve_matches_single_launch(torch, n):
     p = _single_level(n, seed=9, amp=0.3, kappa=0.05)
