@@ -201,9 +201,12 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
     }
 
 
-def continuous_leg():
+def continuous_leg(adaptive: bool = True):
     """One full pass over the five-level continuous-spectrum flow (256 patches
-    of 128^2 per level): a second throughput figure at full occupancy."""
+    of 128^2 per level): a second throughput figure at full occupancy; then
+    (adaptive) the same pass with the quasi-stationary stop: its estimates/s,
+    the fraction of the planned point-steps taken and the largest relative
+    change of the final K."""
     import torch
     import flowgen
     from paper_1510_00451_amd.hierarchy import Hierarchy
@@ -214,10 +217,21 @@ def continuous_leg():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     res = H.result()
+    out = {"workload": "continuous-5level-256x128 (kappa 1e-3, 1<=|k|<=512)",
+           "gpoint_steps_per_s": round(res.point_steps / el / 1e9, 3),
+           "kappa_eff_estimates_per_s": round(len(res.R) / el, 2), "pass_s": round(el, 3)}
+    if adaptive:
+        t0 = time.perf_counter()
+        H.run(adaptive=True)
+        torch.cuda.synchronize()
+        ela = time.perf_counter() - t0
+        ra = H.result()
+        d = np.abs(ra.K_total - res.K_total).max() / np.abs(res.K_total).max()
+        out["adaptive"] = {"kappa_eff_estimates_per_s": round(len(ra.R) / ela, 2), "pass_s": round(ela, 3),
+                           "steps_taken_fraction": round(ra.point_steps / res.point_steps, 4),
+                           "max_rel_K_vs_planned": float(d)}
     H.close()
-    return {"workload": "continuous-5level-256x128 (kappa 1e-3, 1<=|k|<=512)",
-            "gpoint_steps_per_s": round(res.point_steps / el / 1e9, 3),
-            "kappa_eff_estimates_per_s": round(len(res.R) / el, 2), "pass_s": round(el, 3)}
+    return out
 
 
 def uneven_leg(instances: int, window: int):
