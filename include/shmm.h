@@ -203,8 +203,8 @@ int shmm_window_patches(shmm_ctx *ctx, int64_t first, int64_t count, int32_t tap
  * held at zero on the last row and the last column of every patch, so on the
  * remaining (n - 1)^2 cells they vanish on the boundary, and no face across
  * the patch seam is used.  These solves run on the resident kernels up to
- * 128^2 and stage by stage (with the per-stage workspace) above, and are
- * meant for oversampled patches with a windowed estimate
+ * 128^2, on the ring-exchange bands at 256^2 and stage by stage otherwise,
+ * and are meant for oversampled patches with a windowed estimate
  * (shmm_effective_diffusivity_window).
  * Errors: SHMM_EINVAL for another value. */
 #define SHMM_LOCAL_PERIODIC 0

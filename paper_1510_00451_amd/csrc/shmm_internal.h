@@ -78,9 +78,10 @@ bool local_solve_resident(int n);
 // them; work holds the exchange slabs and round counters
 int launch_ring_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n, const float *vx,
                       const float *vy, const double *Kb, float *w, int64_t cells_total, int32_t step_begin,
-                      int32_t s_end, void *work, size_t work_bytes, hipStream_t s);
+                      int32_t s_end, void *work, size_t work_bytes, hipStream_t s, bool frame = false);
 int local_solve_variants(int n);
-// frame: the zero-frame (non-periodic) local problem (resident up to 128^2)
+// frame: the zero-frame (non-periodic) local problem (resident up to 128^2,
+// ring-exchange bands at 256^2)
 size_t local_solve_workspace(int n, int64_t list_cells, bool frame = false);
 int launch_zero_fields(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n, float *d_w,
                        int64_t cells, hipStream_t s);

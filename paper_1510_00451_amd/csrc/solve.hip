@@ -856,7 +856,8 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
     (void)f2;   // the forcing is rebuilt from the face velocities in registers
     if (nlist <= 0) return SHMM_OK;
     // the zero-frame local problem: the resident coefficient-form kernels
-    // with the frame held at zero up to 128^2, stage by stage above
+    // with the frame held at zero up to 128^2, the ring-exchange bands at
+    // 256^2 (other variants and sizes stage by stage)
     if (frame) {
         switch (n) {
             case 8: return launch_resident_e<8, 2, 0, true>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
@@ -892,9 +893,9 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
           *comp = ws + 6 * list_cells;
     const int64_t s_end64 = (int64_t)step_begin + steps;
     const int32_t s_end = (int32_t)(s_end64 < max_steps ? s_end64 : max_steps);
-    if (n == 256 && variant == 6 && !frame)   // persistent bands with a ring exchange (solve_ring.hip)
+    if (n == 256 && variant == 6)   // persistent bands with a ring exchange (solve_ring.hip)
         return launch_ring_solve(d_dom, d_list, nlist, n, vx, vy, Kb, w, cells_total, step_begin, s_end, work,
-                                 local_solve_workspace(n, list_cells), s);
+                                 local_solve_workspace(n, list_cells), s, frame);
     if (n == 256 && variant != 2 && !frame) {
         // Overlapped regions, HALO / 4 steps per launch.  Full-width bands:
         // variant 0 32 rows with 8 above and below (768 threads), 1 the same

@@ -120,7 +120,7 @@ __device__ __forceinline__ void take_rows(int st, const float *__restrict__ fs, 
     }
 }
 
-template <int NN, int TH, int HALO, int R, int FIELD>
+template <int NN, int TH, int HALO, int R, int FIELD, bool FRAME>
 __device__ __forceinline__ void ring_body(float *__restrict__ buf, int *bad, const shmm_domain *__restrict__ dom,
                                           const int32_t *__restrict__ list, int32_t count, int group,
                                           int groups, int band, const float *__restrict__ vx,
@@ -155,6 +155,10 @@ __device__ __forceinline__ void ring_body(float *__restrict__ buf, int *bad, con
         const int32_t lim = s_cap < D.nsteps ? s_cap : D.nsteps;
         if (step_begin >= lim) continue;   // the same decision in every member of the group
         const int gy0 = band * TH - HALO + y0;
+        // zero frame: the strip's first patch row (mod NN) and whether this
+        // thread's column is the patch's last
+        const int gy0m = gy0 & MASK;
+        const bool xlast = x == MASK;
         float *wf = w + (int64_t)FIELD * cells_total + D.offset;
         if (dead) {   // a wait of this group failed: poison the owned rows
 #pragma unroll
@@ -190,17 +194,18 @@ __device__ __forceinline__ void ring_body(float *__restrict__ buf, int *bad, con
             for (int32_t s = step_begin; s < lim;) {
                 const int32_t se = s + HALO / 4 < lim ? s + HALO / 4 : lim;
                 for (; s < se; ++s) {
-                    rk_stage_e<NN, R, FIELD, 0, false>(lo, offW, offE, offS, offN, hi, k, two_cyy, 0.0f, eE, eW,
-                                                       nb, wv, comp, rr);
+                    rk_stage_e<NN, R, FIELD, 0, false, 0, FRAME>(lo, offW, offE, offS, offN, hi, k, two_cyy, 0.0f, eE,
+                                                                 eW, nb, wv, comp, rr, nullptr, 0, gy0m, xlast);
                     __syncthreads();
-                    rk_stage_e<NN, R, FIELD, 1, false>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.25f, eE, eW,
-                                                       nb, wv, comp, rr);
+                    rk_stage_e<NN, R, FIELD, 1, false, 0, FRAME>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.25f, eE,
+                                                                 eW, nb, wv, comp, rr, nullptr, 0, gy0m, xlast);
                     __syncthreads();
-                    rk_stage_e<NN, R, FIELD, 1, false>(lo, offW, offE, offS, offN, hi, k, two_cyy, 1.0f / 3.0f,
-                                                       eE, eW, nb, wv, comp, rr);
+                    rk_stage_e<NN, R, FIELD, 1, false, 0, FRAME>(lo, offW, offE, offS, offN, hi, k, two_cyy,
+                                                                 1.0f / 3.0f, eE, eW, nb, wv, comp, rr, nullptr, 0,
+                                                                 gy0m, xlast);
                     __syncthreads();
-                    rk_stage_e<NN, R, FIELD, 2, false>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.5f, eE, eW,
-                                                       nb, wv, comp, rr);
+                    rk_stage_e<NN, R, FIELD, 2, false, 0, FRAME>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.5f, eE,
+                                                                 eW, nb, wv, comp, rr, nullptr, 0, gy0m, xlast);
                     __syncthreads();
                 }
                 // One round per window, also after the last one: a band
@@ -262,7 +267,7 @@ __device__ __forceinline__ void ring_body(float *__restrict__ buf, int *bad, con
 // XCD-aware (workgroup i runs on XCD i mod 8): the PER members of a group
 // take consecutive slots of one XCD, so their slabs and counters stay in that
 // XCD's L2.
-template <int NN, int TH, int HALO, int R>
+template <int NN, int TH, int HALO, int R, bool FRAME = false>
 __global__ __launch_bounds__(NN *(TH + 2 * HALO) / R) void k_solve_ring(
     const shmm_domain *__restrict__ dom, const int32_t *__restrict__ list, int32_t count,
     const float *__restrict__ vx, const float *__restrict__ vy, const double *__restrict__ Kb,
@@ -284,10 +289,10 @@ __global__ __launch_bounds__(NN *(TH + 2 * HALO) / R) void k_solve_ring(
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
     if (member & 1)
-        ring_body<NN, TH, HALO, R, 1>(buf, &bad, dom, list, count, group, groups, member >> 1, vx, vy, Kb, w,
+        ring_body<NN, TH, HALO, R, 1, FRAME>(buf, &bad, dom, list, count, group, groups, member >> 1, vx, vy, Kb, w,
                                       cells_total, slab, flags, step_begin, s_cap, spin_cap);
     else
-        ring_body<NN, TH, HALO, R, 0>(buf, &bad, dom, list, count, group, groups, member >> 1, vx, vy, Kb, w,
+        ring_body<NN, TH, HALO, R, 0, FRAME>(buf, &bad, dom, list, count, group, groups, member >> 1, vx, vy, Kb, w,
                                       cells_total, slab, flags, step_begin, s_cap, spin_cap);
 }
 
@@ -304,7 +309,7 @@ constexpr uint32_t kRingSpinCap = 1u << 25;
 
 int launch_ring_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n, const float *vx,
                       const float *vy, const double *Kb, float *w, int64_t cells_total, int32_t step_begin,
-                      int32_t s_end, void *work, size_t work_bytes, hipStream_t s) {
+                      int32_t s_end, void *work, size_t work_bytes, hipStream_t s, bool frame) {
     using S = RingShape<kRingNN, kRingTH, kRingHalo>;
     if (n != kRingNN) return SHMM_EINVAL;
     if (nlist <= 0 || step_begin >= s_end) return SHMM_OK;
@@ -328,9 +333,14 @@ int launch_ring_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t n
     const int nflags = (int)(groups * S::PER);
     hipLaunchKernelGGL(k_zero_rounds, dim3((unsigned)((nflags + 255) / 256)), dim3(256), 0, s, flags, nflags);
     SHMM_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL((k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR>), dim3((unsigned)(groups * S::PER)),
-                       dim3(threads), 0, s, d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, slab, flags,
-                       step_begin, s_end, kRingSpinCap);
+    if (frame)
+        hipLaunchKernelGGL((k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR, true>), dim3((unsigned)(groups * S::PER)),
+                           dim3(threads), 0, s, d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, slab, flags,
+                           step_begin, s_end, kRingSpinCap);
+    else
+        hipLaunchKernelGGL((k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR>), dim3((unsigned)(groups * S::PER)),
+                           dim3(threads), 0, s, d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, slab, flags,
+                           step_begin, s_end, kRingSpinCap);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
 }
