@@ -494,6 +494,38 @@ def sum_offdiag(K_in, s12, s21) -> np.ndarray:
     return offdiag_closed_form(K_in, s12, 0) + offdiag_closed_form(K_in, s21, 1) - K_in
 
 
+def lambda_min(K) -> float:
+    """Smallest eigenvalue of the symmetric 2 x 2 tensor {K11, K12, K22}
+    (LAPACK's symmetric eigensolver)."""
+    K = np.asarray(K, np.float64)
+    return float(np.linalg.eigvalsh(np.array([[K[0], K[1]], [K[1], K[2]]]))[0])
+
+
+def spd_floor(K_net, K_in) -> Tuple[np.ndarray, bool]:
+    """Base of a coarse local solve when Algorithm 3's difference is not SPD.
+
+    Step 3 of Algorithm 3 forms K_net = K_star - K_off + K_in as the base of
+    the next local solve, which must be a diffusivity.  At the steady state
+    K_star dominates K_off (every local solve only adds a positive
+    semi-definite enhancement to its base), so K_net dominates K_in.  Reading
+    used where rounding or an unfinished solve breaks this: when the smallest
+    eigenvalue of K_net falls below that of K_in (or is not a number), the
+    eigenvalues of K_net are raised to at least lambda_min(K_in), its
+    eigenvectors kept, and the domain is flagged.  Returns (K, clamped);
+    K_net is returned unchanged when no clamp is needed.
+    """
+    K_net = np.asarray(K_net, np.float64)
+    floor = lambda_min(K_in)
+    if np.all(np.isfinite(K_net)) and lambda_min(K_net) >= floor:
+        return K_net.copy(), False
+    if not np.all(np.isfinite(K_net)):
+        return np.array([floor, 0.0, floor]), True
+    lam, vec = np.linalg.eigh(np.array([[K_net[0], K_net[1]], [K_net[1], K_net[2]]]))
+    lam = np.maximum(lam, floor)
+    M = vec @ np.diag(lam) @ vec.T
+    return np.array([M[0, 0], 0.5 * (M[0, 1] + M[1, 0]), M[1, 1]]), True
+
+
 # ---------------------------------------------------------------------------
 # Whole hierarchy (Algorithm 3, extended to L levels)
 # ---------------------------------------------------------------------------
@@ -510,6 +542,7 @@ class HierarchyResult:
     nsteps: np.ndarray
     lines: np.ndarray     # packed [sum 2n] line energies (off12 columns then off21 rows)
     w: Optional[Dict[int, np.ndarray]] = None
+    clamped: Optional[List[int]] = None   # domains whose K_net was raised by spd_floor
 
     def K_total(self) -> np.ndarray:
         return np.array([self.R[i] for i, d in enumerate(self.domains) if d.level == 0])
@@ -535,7 +568,8 @@ def level_fields(p, level_arr, part_arr, d: Domain, taper: int = 0):
 
 
 def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = None, inner: int = 0,
-                  taper: int = 0, frame: bool = False) -> HierarchyResult:
+                  taper: int = 0, frame: bool = False,
+                  roots: Optional[Sequence[int]] = None) -> HierarchyResult:
     """K[psi, kappa I; Omega_1] at every centre by Algorithm 3 generalised to L levels.
 
     R(l, K_in) = LS(diag_l, K_in)                                   l = finest
@@ -552,11 +586,29 @@ def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = N
     centred inner x inner window (oversampled patches), taper > 0 tapers each
     patch's stream function (windowed patches), frame holds the correctors at
     zero on each patch's last row and column (zero-frame local problems).
+
+    roots (optional): indices of level-0 domains; only these and the domains
+    below them (their children, the children's children, ...) are computed,
+    which is all that the level results of these centres depend on.  The
+    entries of every other domain are left zero (nsteps 0).
+
+    A base K_net whose smallest eigenvalue falls below that of K_in is raised
+    to it (spd_floor); `clamped` lists the domains where that happened.
     """
     if not isinstance(probs, (list, tuple)):
         probs = [probs]
     doms = domain_table(probs)
     nd = len(doms)
+    keep = np.ones(nd, bool)
+    if roots is not None:
+        keep[:] = False
+        for r in roots:
+            if doms[r].level != 0:
+                raise ValueError("roots must be level-0 domains")
+            keep[r] = True
+        for i in sorted(range(nd), key=lambda i: doms[i].level):
+            if doms[i].level > 0 and keep[doms[i].parent]:
+                keep[i] = True
     splits = [band_split(p.kmax, p.thresh) for p in probs]
     K_in = np.zeros((nd, 3))
     K_off = np.zeros((nd, 3))
@@ -568,6 +620,8 @@ def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = N
     lines = np.zeros(sum(2 * d.n for d in doms))
     empty_band: Dict[Tuple[int, int], bool] = {}
     for i, d in enumerate(doms):
+        if not keep[i]:
+            continue
         p = probs[d.instance]
         lv, pt = splits[d.instance]
         lines[d.line_offset:d.line_offset + d.n] = line_energies(
@@ -592,6 +646,8 @@ def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = N
     order = sorted(range(nd), key=lambda i: doms[i].level)
     for i in order:
         d = doms[i]
+        if not keep[i]:
+            continue
         if d.level == 0:
             K_in[i] = [probs[d.instance].kappa, 0.0, probs[d.instance].kappa]
         else:
@@ -606,8 +662,11 @@ def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = N
 
     wkeep = {} if keep_w else None
     maxL = max(L_of)
+    clamped: List[int] = []
     for lev in range(maxL - 1, -1, -1):
-        idx = [i for i, d in enumerate(doms) if d.level == lev]
+        idx = [i for i, d in enumerate(doms) if d.level == lev and keep[i]]
+        if not idx:
+            continue
         # fields of this level (one batch)
         fields = [level_fields(probs[doms[i].instance], *splits[doms[i].instance], doms[i], taper) for i in idx]
         # bases of this level
@@ -618,7 +677,9 @@ def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = N
             else:
                 ch = children[i]
                 K_star = np.mean(np.array([R[c] for c in ch]), axis=0) if len(ch) > 1 else R[ch[0]].copy()
-                K_base[i] = K_star - K_off[i] + K_in[i]
+                K_base[i], low = spd_floor(K_star - K_off[i] + K_in[i], K_in[i])
+                if low:
+                    clamped.append(i)
             p = probs[d.instance]
             key = (d.instance, lev)
             vmax = advection_bound(fields[t][1], fields[t][2])
@@ -649,7 +710,7 @@ def run_hierarchy(probs, keep_w: bool = False, steps_override: Optional[int] = N
                 R[i] = (K_solve[i] + offdiag_closed_form(Kn, s12(i), 0)
                         + offdiag_closed_form(Kn, s21(i), 1) - 2.0 * Kn)
             o += m
-    return HierarchyResult(doms, K_in, K_off, K_base, K_solve, R, dt, nsteps, lines, wkeep)
+    return HierarchyResult(doms, K_in, K_off, K_base, K_solve, R, dt, nsteps, lines, wkeep, clamped)
 
 
 # ---------------------------------------------------------------------------

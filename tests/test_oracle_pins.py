@@ -381,6 +381,68 @@ def test_algorithm3_two_level_hand_case():
     assert np.allclose(r.K_total()[0], expect, rtol=1e-13)
 
 
+def _rot(theta, a, b):
+    """R(theta) diag(a, b) R(theta)^T as {K11, K12, K22}, written out by hand."""
+    c, s = math.cos(theta), math.sin(theta)
+    return np.array([a * c * c + b * s * s, (a - b) * c * s, a * s * s + b * c * c])
+
+
+def test_spd_floor_leaves_a_dominating_base_alone():
+    """Algorithm 3, step 3: at the steady state K_net dominates K_in, and the
+    base is then K_star - K_off + K_in exactly as formed."""
+    K_in = np.array([0.02, 0.005, 0.03])
+    K_net = K_in + _rot(0.3, 0.4, 0.001)        # K_in plus a PSD enhancement
+    out, low = oracle.spd_floor(K_net, K_in)
+    assert not low and np.array_equal(out, K_net)
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.4, -1.1, math.pi / 2])
+def test_spd_floor_raises_the_low_eigenvalue_and_keeps_the_axes(theta):
+    """A K_net whose low eigenvalue lies below lambda_min(K_in): the eigenvalue
+    is raised to lambda_min(K_in) on the same eigenvector, the other one kept
+    (closed form R diag(a, floor) R^T).  K_in is anisotropic with a cross
+    term, so taking its larger eigenvalue, or its diagonal, fails."""
+    K_in = _rot(0.7, 0.05, 0.01)                # lambda_min = 0.01, lambda_max = 0.05
+    floor = 0.01
+    out, low = oracle.spd_floor(_rot(theta, 0.3, -0.02), K_in)
+    assert low
+    np.testing.assert_allclose(out, _rot(theta, 0.3, floor), rtol=0, atol=1e-15)
+    out, low = oracle.spd_floor(_rot(theta, 0.3, 0.004), K_in)     # positive but below the floor
+    assert low
+    np.testing.assert_allclose(out, _rot(theta, 0.3, floor), rtol=0, atol=1e-15)
+
+
+def test_spd_floor_both_low_or_not_a_number_gives_the_floor():
+    K_in = np.array([0.02, 0.0, 0.03])
+    out, low = oracle.spd_floor(_rot(0.2, -0.1, -0.3), K_in)
+    assert low
+    np.testing.assert_allclose(out, [0.02, 0.0, 0.02], rtol=0, atol=1e-16)
+    out, low = oracle.spd_floor(np.array([np.nan, 0.0, 1.0]), K_in)
+    assert low and np.array_equal(out, [0.02, 0.0, 0.02])
+
+
+def test_roots_compute_exactly_the_selected_chains():
+    """The sampled-centre run (roots) gives the same numbers, bit for bit, as
+    the whole hierarchy on the chains it selects, and nothing elsewhere."""
+    p = flowgen.config_continuous(seed=4, radius=24, n=8, lattice=2, levels=3)
+    full = oracle.run_hierarchy(p)
+    lev0 = [i for i, d in enumerate(full.domains) if d.level == 0]
+    part = oracle.run_hierarchy(p, roots=[lev0[1], lev0[2]])
+    sel = {lev0[1], lev0[2]}
+    for i, d in enumerate(full.domains):
+        j, top = i, d
+        while top.level > 0:
+            j = top.parent
+            top = full.domains[j]
+        if j in sel:
+            for name in ("K_in", "K_base", "K_solve", "R"):
+                assert np.array_equal(getattr(part, name)[i], getattr(full, name)[i]), (name, i)
+            assert part.nsteps[i] == full.nsteps[i]
+        else:
+            assert np.all(part.R[i] == 0.0) and part.nsteps[i] == 0
+    assert full.clamped == [] and part.clamped == []
+
+
 # ---------------------------------------------------------------- macro
 
 def test_macro_rk4_matches_fourier_closed_form():
