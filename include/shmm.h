@@ -57,10 +57,10 @@ enum {
     SHMM_ENOMEM = -5    /* a device allocation failed */
 };
 
-enum {                          /* per-domain status bits */
+enum {                          /* per-domain status bits (bit 2 is reserved: the step
+                                   plan never exceeds the stability bound, dt_frac <= 1) */
     SHMM_DOM_NONFINITE = 1,     /* a corrector or a moment is NaN/Inf */
-    SHMM_DOM_NOT_SPD = 2,       /* K_net was not SPD; eigenvalues were clamped */
-    SHMM_DOM_DT_LIMIT = 4,      /* requested step above the stability bound */
+    SHMM_DOM_NOT_SPD = 2,       /* K_net fell below K_in; its eigenvalues were raised */
     SHMM_DOM_FALLBACK = 8       /* surrogate flagged the patch: plain solve used */
 };
 
@@ -218,7 +218,11 @@ int shmm_ctx_set_local_bc(shmm_ctx *ctx, int32_t bc);
  * d_K_base is [n_domains][3] (global index), d_w is [2][n_cells_total] FP32
  * in/out.  FP32 stencils with a compensated state update.  Requires
  * shmm_plan_steps on the range; patches planned with zero steps are skipped.
- * d_status (may be NULL) gets SHMM_DOM_* bits.  Patches with n <= 128 stay
+ * d_status (may be NULL): after the call, SHMM_DOM_NONFINITE is ORed into the
+ * word of every listed domain whose correctors hold a NaN or an infinity (a
+ * non-finite input, or a ring-exchange band that gave up waiting for a
+ * neighbour; each call re-reads the correctors of the range once to check).
+ * Patches with n <= 128 stay
  * resident in LDS for the whole call; n = 256 advances in full-width bands
  * that exchange ring rows (or, as tuned, in relaunched overlapped regions)
  * and other sizes stage by stage, all through the context's workspace
@@ -320,6 +324,14 @@ int shmm_level_chain(shmm_ctx *ctx, int64_t first, int64_t count, int32_t mode,
  * Other sizes have one variant.
  * Errors: SHMM_EINVAL for an unknown key or value. */
 #define SHMM_TUNE_SOLVE_VARIANT_COUNT 0
+/* key = SHMM_TUNE_RING_SPIN_CAP: value >= 0 is the number of polls (about a
+ * microsecond each; default 2^25, tens of seconds) after which a ring-exchange
+ * band stops waiting for a neighbour; 0 gives up at the first wait.  A band
+ * that gives up writes NaN into its rows of the current and every later patch
+ * of the call without waiting again, so every kernel still exits and the
+ * failure shows as SHMM_DOM_NONFINITE (shmm_local_solve_batch).  For callers
+ * that must bound a solve's wall time, and to test that path. */
+#define SHMM_TUNE_RING_SPIN_CAP (-1)
 int shmm_ctx_tune(shmm_ctx *ctx, int32_t key, int32_t value);
 
 /* Macro solver (HMM step 4 on eq:homo with the resolved velocity kept as
@@ -412,6 +424,25 @@ int shmm_surrogate_infer(shmm_ctx *ctx, const void *d_models, int32_t E, const f
                          const double *d_K_base, int64_t B, const float *d_lo, const float *d_hi,
                          double tau, double emax, double *d_K_out, uint8_t *d_flags, double *d_spread,
                          double *d_K_members, void *stream);
+
+/* Column statistics of a feature matrix d_x [B][33] (the input
+ * standardisation of the network and the range of the fallback gate): per
+ * column, FP64 mean, standard deviation with the B - 1 divisor, minimum and
+ * maximum over the B rows, written to d_stats [4][33] (mean, std, min, max).
+ * Fixed reduction order: bitwise reproducible.  Errors: SHMM_EINVAL for
+ * B < 2 or a null pointer. */
+int shmm_feature_stats(shmm_ctx *ctx, const float *d_x, int64_t B, double *d_stats, void *stream);
+
+/* Rescaled copies of labelled local problems for training: scaling velocity
+ * and diffusivity together by c_b = 10^d_log10c[b] leaves the corrector of a
+ * local problem unchanged, so K and K_b scale by c_b, the 32 band features
+ * (energies over det K_b, squared Peclet numbers) are unchanged and feature 32
+ * (log sqrt det K_b) moves by ln c_b.  Inputs d_x [B][33], d_K_base and
+ * d_K_true [B][3], d_log10c [B]; outputs of the same shapes (may not alias
+ * the inputs).  Errors: SHMM_EINVAL for B < 0 or a null pointer. */
+int shmm_surrogate_rescale(shmm_ctx *ctx, const float *d_x, const double *d_K_base, const double *d_K_true,
+                           const double *d_log10c, int64_t B, float *d_x_out, double *d_K_base_out,
+                           double *d_K_true_out, void *stream);
 
 /* Plain-solve fallback for the flagged domains of [first, first + count)
  * (d_flags[i] for domain first + i): zero their correctors, run the planned

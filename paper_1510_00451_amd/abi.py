@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libshmm.so")
 SHMM_OK, SHMM_EINVAL, SHMM_ERANGE, SHMM_ENOTSPD, SHMM_EDEVICE, SHMM_ENOMEM = 0, -1, -2, -3, -4, -5
 ERRORS = {SHMM_EINVAL: "SHMM_EINVAL", SHMM_ERANGE: "SHMM_ERANGE", SHMM_ENOTSPD: "SHMM_ENOTSPD",
           SHMM_EDEVICE: "SHMM_EDEVICE", SHMM_ENOMEM: "SHMM_ENOMEM"}
-DOM_NONFINITE, DOM_NOT_SPD, DOM_DT_LIMIT, DOM_FALLBACK = 1, 2, 4, 8
+DOM_NONFINITE, DOM_NOT_SPD, DOM_FALLBACK = 1, 2, 8
 MAX_LEVELS = 8
 
 EXPORTS = ["shmm_ctx_create", "shmm_ctx_destroy", "shmm_build_levels", "shmm_ctx_set_problem",
@@ -25,10 +25,12 @@ EXPORTS = ["shmm_ctx_create", "shmm_ctx_destroy", "shmm_build_levels", "shmm_ctx
            "shmm_effective_diffusivity_window", "shmm_window_patches", "shmm_ctx_set_local_bc",
            "shmm_level_chain",
            "shmm_macro_step", "shmm_ctx_tune", "shmm_patch_features", "shmm_surrogate_refresh",
-           "shmm_surrogate_train_step", "shmm_surrogate_infer", "shmm_fallback_solve"]
+           "shmm_surrogate_train_step", "shmm_surrogate_infer", "shmm_fallback_solve",
+           "shmm_feature_stats", "shmm_surrogate_rescale"]
 
 BC_PERIODIC, BC_DIRICHLET_X = 0, 1
 LOCAL_PERIODIC, LOCAL_ZERO_FRAME = 0, 1
+TUNE_SOLVE_VARIANT_COUNT, TUNE_RING_SPIN_CAP = 0, -1
 SURR_BINS, SURR_IN, SURR_WIDTH, SURR_OUT = 32, 33, 256, 3
 SURR_PARAMS, SURR_PARAMS_PADDED = 141059, 141312
 SURR_MODEL_BYTES = 4 * SURR_PARAMS_PADDED + 4 * 128 + 2 * SURR_PARAMS_PADDED
@@ -88,6 +90,8 @@ def lib() -> ctypes.CDLL:
             "shmm_surrogate_train_step": [P, P, P, P, P, P, i64, ctypes.c_float, ctypes.c_float, i32, P, P, P],
             "shmm_surrogate_infer": [P, P, i32, P, P, i64, P, P, f64, f64, P, P, P, P, P],
             "shmm_fallback_solve": [P, i64, i64, P, P, P, P, P, P, P, P, i32, f64, P, P],
+            "shmm_feature_stats": [P, P, i64, P, P],
+            "shmm_surrogate_rescale": [P, P, P, P, P, i64, P, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -269,7 +273,16 @@ class Context:
                                         d_w, d_K_out, int(chunks), float(tol), d_status or None, stream),
               "shmm_fallback_solve")
 
+    def shmm_feature_stats(self, d_x, B, d_stats, stream=0):
+        check(lib().shmm_feature_stats(self.h, d_x, int(B), d_stats, stream), "shmm_feature_stats")
+
+    def shmm_surrogate_rescale(self, d_x, d_K_base, d_K_true, d_log10c, B, d_x_out, d_K_base_out, d_K_true_out,
+                               stream=0):
+        check(lib().shmm_surrogate_rescale(self.h, d_x, d_K_base, d_K_true, d_log10c, int(B), d_x_out,
+                                           d_K_base_out, d_K_true_out, stream), "shmm_surrogate_rescale")
+
     def shmm_macro_step(self, N, bc, g0, g1, d_vx, d_vy, d_K, K_is_field, dt, nsteps, d_u, dtype, stream=0):
         check(lib().shmm_macro_step(self.h, N, int(bc), float(g0), float(g1), d_vx or None, d_vy or None, d_K,
                                     int(K_is_field), float(dt), int(nsteps), d_u, int(dtype), stream),
               "shmm_macro_step")
+

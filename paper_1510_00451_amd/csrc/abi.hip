@@ -198,6 +198,7 @@ struct shmm_ctx {
     std::map<std::pair<int64_t, int64_t>, RangeLists> lists;
     std::map<int, int> solve_variant;          // patch size n -> kernel variant
     int32_t local_bc = SHMM_LOCAL_PERIODIC;    // boundary of the local problems
+    uint32_t ring_spin_cap = kRingSpinCapDefault;   // polls before a ring-exchange wait gives up
     void *work = nullptr;
     size_t work_bytes = 0;
     void *adapt = nullptr;                      // previous correctors and chunk statistics (adaptive stop)
@@ -645,7 +646,6 @@ int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const fl
                            const float *d_vy, const float *d_f1, const float *d_f2,
                            const double *d_K_base, float *d_w, int32_t step_begin, int32_t steps,
                            int32_t *d_status, void *stream) {
-    (void)d_status;
     if (!range_ok(ctx, first, count) || !d_vx || !d_vy || !d_K_base || !d_w || step_begin < 0 ||
         steps < 0)
         return SHMM_EINVAL;
@@ -683,7 +683,7 @@ int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const fl
         if (groups > 1 && runs_alone(rl->ns[q], variant[q])) {
             rc = launch_local_solve(ctx->d_table, rl->d_lists[q], rl->counts[q], rl->ns[q], max_steps_of(q), d_vx,
                                     d_vy, d_f1, d_f2, d_K_base, d_w, ctx->cells, step_begin, steps, rl->cells[q],
-                                    ctx->work, variant[q], main_s, frame);
+                                    ctx->work, variant[q], main_s, frame, ctx->ring_spin_cap);
             if (rc) return rc;
         } else {
             rest.push_back(q);
@@ -717,7 +717,7 @@ int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const fl
         }
         rc = launch_local_solve(ctx->d_table, rl->d_lists[q], rl->counts[q], rl->ns[q], max_steps_of(q),
                                 d_vx, d_vy, d_f1, d_f2, d_K_base, d_w, ctx->cells, step_begin, steps,
-                                rl->cells[q], ctx->work, variant[q], s, frame);
+                                rl->cells[q], ctx->work, variant[q], s, frame, ctx->ring_spin_cap);
         if (rc) return rc;
     }
     for (int i = 0; i < kSideStreams; ++i)
@@ -725,6 +725,13 @@ int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const fl
             SHMM_HIP_CHECK(hipEventRecord(ctx->ev_join[i], ctx->side[i]));
             SHMM_HIP_CHECK(hipStreamWaitEvent(main_s, ctx->ev_join[i], 0));
         }
+    // status: a corrector that is NaN/Inf after the call (a non-finite input,
+    // an unstable step, or a ring-exchange band that gave up waiting)
+    if (d_status)
+        for (size_t q = 0; q < groups; ++q)
+            if ((rc = launch_mark_nonfinite(ctx->d_table, rl->d_lists[q], rl->counts[q], rl->ns[q], d_w, ctx->cells,
+                                            d_status, main_s)))
+                return rc;
     return SHMM_OK;
 }
 
@@ -811,6 +818,11 @@ int shmm_level_chain(shmm_ctx *ctx, int64_t first, int64_t count, int32_t mode,
 int shmm_ctx_tune(shmm_ctx *ctx, int32_t key, int32_t value) {
     if (!ctx) return SHMM_EINVAL;
     if (key == SHMM_TUNE_SOLVE_VARIANT_COUNT) return local_solve_variants(value);
+    if (key == SHMM_TUNE_RING_SPIN_CAP) {
+        if (value < 0) return SHMM_EINVAL;
+        ctx->ring_spin_cap = (uint32_t)value;
+        return SHMM_OK;
+    }
     if (key > 0 && key <= 4096 && (key & (key - 1)) == 0) {
         if (value < 0 || value >= local_solve_variants(key)) return SHMM_EINVAL;
         ctx->solve_variant[key] = value;
@@ -888,6 +900,26 @@ int shmm_surrogate_infer(shmm_ctx *ctx, const void *d_models, int32_t E, const f
                            ctx->work, (hipStream_t)stream);
 }
 
+int shmm_feature_stats(shmm_ctx *ctx, const float *d_x, int64_t B, double *d_stats, void *stream) {
+    if (!ctx || !d_x || !d_stats || B < 2) return SHMM_EINVAL;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    return launch_feature_stats(d_x, B, d_stats, (hipStream_t)stream);
+}
+
+int shmm_surrogate_rescale(shmm_ctx *ctx, const float *d_x, const double *d_K_base, const double *d_K_true,
+                           const double *d_log10c, int64_t B, float *d_x_out, double *d_K_base_out,
+                           double *d_K_true_out, void *stream) {
+    if (!ctx || B < 0 || !d_x || !d_K_base || !d_K_true || !d_log10c || !d_x_out || !d_K_base_out ||
+        !d_K_true_out)
+        return SHMM_EINVAL;
+    if (B == 0) return SHMM_OK;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    return launch_surrogate_rescale(d_x, d_K_base, d_K_true, d_log10c, B, d_x_out, d_K_base_out, d_K_true_out,
+                                    (hipStream_t)stream);
+}
+
 int shmm_fallback_solve(shmm_ctx *ctx, int64_t first, int64_t count, const uint8_t *d_flags,
                         const float *d_vx, const float *d_vy, const float *d_f1, const float *d_f2,
                         const double *d_K_base, float *d_w, double *d_K_out, int32_t chunks, double tol,
@@ -929,12 +961,13 @@ int shmm_fallback_solve(shmm_ctx *ctx, int64_t first, int64_t count, const uint8
                 int32_t longest = 0;
                 for (int32_t d : ids) longest = std::max(longest, ctx->table[d].nsteps);
                 return launch_local_solve(ctx->d_table, dl, (int32_t)ids.size(), n, longest, d_vx, d_vy, d_f1, d_f2,
-                                          d_K_base, d_w, ctx->cells, s0, C, cells, ctx->work, variant, s, frame);
+                                          d_K_base, d_w, ctx->cells, s0, C, cells, ctx->work, variant, s, frame,
+                                          ctx->ring_spin_cap);
             });
         } else {
             rc = launch_local_solve(ctx->d_table, dl, (int32_t)ids.size(), n, max_steps, d_vx, d_vy, d_f1, d_f2,
                                     d_K_base, d_w, ctx->cells, 0, 2147483647, cells, ctx->work, variant, s,
-                                    frame);
+                                    frame, ctx->ring_spin_cap);
         }
         if (rc) return rc;
         rc = launch_effective_diffusivity_list(ctx->d_table, dl, (int64_t)ids.size(), d_f1, d_f2, d_w,

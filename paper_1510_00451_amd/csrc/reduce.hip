@@ -255,11 +255,47 @@ __global__ void k_mark(int32_t *status, const int32_t *list, int64_t count, int3
     if (t < count) status[list[t]] |= bits;
 }
 
+// Non-finite check of the corrector fields of listed domains of one size n:
+// one workgroup per domain reads both correctors (float4) and ORs
+// SHMM_DOM_NONFINITE into the domain's status word if any value is NaN/Inf.
+__global__ __launch_bounds__(256) void k_nonfinite(const shmm_domain *__restrict__ dom,
+                                                   const int32_t *__restrict__ list, int n,
+                                                   const float *__restrict__ w, int64_t cells,
+                                                   int32_t *status) {
+    const int32_t d = list[blockIdx.x];
+    const int64_t o = dom[d].offset;
+    const int64_t nn = (int64_t)n * n;
+    int bad = 0;
+    if ((o & 3) == 0 && (cells & 3) == 0 && (nn & 3) == 0) {
+        const float4 *a = reinterpret_cast<const float4 *>(w + o);
+        const float4 *b = reinterpret_cast<const float4 *>(w + cells + o);
+        for (int64_t c = threadIdx.x; c < nn / 4; c += blockDim.x) {
+            const float4 x = a[c], y = b[c];
+            bad |= !isfinite(x.x) | !isfinite(x.y) | !isfinite(x.z) | !isfinite(x.w);
+            bad |= !isfinite(y.x) | !isfinite(y.y) | !isfinite(y.z) | !isfinite(y.w);
+        }
+    } else {
+        for (int64_t c = threadIdx.x; c < nn; c += blockDim.x)
+            bad |= !isfinite(w[o + c]) | !isfinite(w[cells + o + c]);
+    }
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0 && bad) atomicOr(status + d, (int32_t)SHMM_DOM_NONFINITE);
+}
+
 }  // namespace
 
 int launch_mark_status(int32_t *status, const int32_t *list, int64_t count, int32_t bits, hipStream_t s) {
     if (count <= 0) return SHMM_OK;
     hipLaunchKernelGGL(k_mark, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, status, list, count, bits);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
+
+int launch_mark_nonfinite(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n, const float *w,
+                          int64_t cells_total, int32_t *status, hipStream_t s) {
+    if (nlist <= 0 || !status) return SHMM_OK;
+    hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)nlist), dim3(256), 0, s, d_dom, d_list, n, w, cells_total,
+                       status);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
 }

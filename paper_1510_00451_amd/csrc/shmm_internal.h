@@ -68,17 +68,22 @@ int launch_window_patches(const shmm_domain *d_dom, int64_t first, int64_t count
                           const float *d_psi, float *d_vx, float *d_vy, float *d_f1, float *d_f2, double *d_vmax,
                           hipStream_t s);
 
+// polls of about a microsecond each before a ring-exchange wait gives up
+// (tens of seconds)
+constexpr uint32_t kRingSpinCapDefault = 1u << 25;
 int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n,
                        int32_t max_steps, const float *vx, const float *vy, const float *f1,
                        const float *f2, const double *Kb, float *w, int64_t cells_total,
                        int32_t step_begin, int32_t steps, int64_t list_cells, void *work,
-                       int variant, hipStream_t s, bool frame = false);
+                       int variant, hipStream_t s, bool frame = false,
+                       uint32_t ring_spin_cap = kRingSpinCapDefault);
 bool local_solve_resident(int n);
 // persistent full-width bands of 256^2 patches with a ring exchange between
 // them; work holds the exchange slabs and round counters
 int launch_ring_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n, const float *vx,
                       const float *vy, const double *Kb, float *w, int64_t cells_total, int32_t step_begin,
-                      int32_t s_end, void *work, size_t work_bytes, hipStream_t s, bool frame = false);
+                      int32_t s_end, void *work, size_t work_bytes, hipStream_t s, bool frame = false,
+                      uint32_t spin_cap = kRingSpinCapDefault);
 int local_solve_variants(int n);
 // frame: the zero-frame (non-periodic) local problem (resident up to 128^2,
 // ring-exchange bands at 256^2)
@@ -120,7 +125,14 @@ int surrogate_infer(const void *models, int32_t E, const float *x, const double 
                     const float *lo, const float *hi, double tau, double emax, double *K_out, uint8_t *flags,
                     double *spread, double *K_members, void *work, hipStream_t s);
 
+int launch_feature_stats(const float *x, int64_t B, double *stats, hipStream_t s);
+int launch_surrogate_rescale(const float *x, const double *Kb, const double *K, const double *log10c, int64_t B,
+                             float *xo, double *Kbo, double *Ko, hipStream_t s);
+
 int launch_mark_status(int32_t *status, const int32_t *list, int64_t count, int32_t bits, hipStream_t s);
+// OR SHMM_DOM_NONFINITE into the status of listed domains (one size n) whose correctors hold a NaN/Inf
+int launch_mark_nonfinite(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n, const float *w,
+                          int64_t cells_total, int32_t *status, hipStream_t s);
 
 int launch_macro(int32_t N, int32_t bc, double g0, double g1, const void *vx, const void *vy, const double *K,
                  int32_t K_is_field, double dt, int32_t nsteps, void *u, int32_t dtype, void *work, hipStream_t s);

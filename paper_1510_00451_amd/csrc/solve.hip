@@ -851,7 +851,7 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
                        int32_t max_steps, const float *vx, const float *vy, const float *f1,
                        const float *f2, const double *Kb, float *w, int64_t cells_total,
                        int32_t step_begin, int32_t steps, int64_t list_cells, void *work,
-                       int variant, hipStream_t s, bool frame) {
+                       int variant, hipStream_t s, bool frame, uint32_t ring_spin_cap) {
     (void)f1;
     (void)f2;   // the forcing is rebuilt from the face velocities in registers
     if (nlist <= 0) return SHMM_OK;
@@ -893,9 +893,14 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
           *comp = ws + 6 * list_cells;
     const int64_t s_end64 = (int64_t)step_begin + steps;
     const int32_t s_end = (int32_t)(s_end64 < max_steps ? s_end64 : max_steps);
-    if (n == 256 && variant == 6)   // persistent bands with a ring exchange (solve_ring.hip)
-        return launch_ring_solve(d_dom, d_list, nlist, n, vx, vy, Kb, w, cells_total, step_begin, s_end, work,
-                                 local_solve_workspace(n, list_cells), s, frame);
+    if (n == 256 && variant == 6) {   // persistent bands with a ring exchange (solve_ring.hip)
+        // each patch stops at min(step_begin + steps, its plan) inside the
+        // kernel, so the launch does not depend on the host's plan (a
+        // captured graph stays valid when the plans change)
+        const int32_t s_cap = (int32_t)std::min<int64_t>(s_end64, 2147483647);
+        return launch_ring_solve(d_dom, d_list, nlist, n, vx, vy, Kb, w, cells_total, step_begin, s_cap, work,
+                                 local_solve_workspace(n, list_cells), s, frame, ring_spin_cap);
+    }
     if (n == 256 && variant != 2 && !frame) {
         // Overlapped regions, HALO / 4 steps per launch.  Full-width bands:
         // variant 0 32 rows with 8 above and below (768 threads), 1 the same

@@ -25,7 +25,9 @@
 // list.  Each wait is bounded: a workgroup that waits longer than the spin
 // limit (tens of seconds) writes NaN into its owned rows of this and every
 // later patch of its group, without waiting again, so every wave exits and
-// the failure shows as a non-finite estimate.
+// the failure shows as a non-finite corrector (SHMM_DOM_NONFINITE in the
+// status of the local solve) and a non-finite estimate.  The spin limit is
+// a context setting (SHMM_TUNE_RING_SPIN_CAP).
 #include <algorithm>
 
 #include "shmm_internal.h"
@@ -223,16 +225,18 @@ __device__ __forceinline__ void ring_body(float *__restrict__ buf, int *bad, con
                 __syncthreads();
                 if (tid == 0) {
                     __hip_atomic_store(flags + me, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    // both counters read together each pass
+                    // both counters read together each pass; at most
+                    // spin_cap polls (0: give up without polling)
                     uint32_t it = 0;
                     for (;;) {
-                        const int32_t fs = __hip_atomic_load(flags + south, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        const int32_t fn = __hip_atomic_load(flags + north, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        if (fs >= epoch && fn >= epoch) break;
-                        if (++it >= spin_cap) {
+                        if (it >= spin_cap) {
                             *bad = 1;
                             break;
                         }
+                        const int32_t fs = __hip_atomic_load(flags + south, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const int32_t fn = __hip_atomic_load(flags + north, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (fs >= epoch && fn >= epoch) break;
+                        ++it;
                         __builtin_amdgcn_s_sleep(1);
                     }
                 }
@@ -302,14 +306,13 @@ __global__ void k_zero_rounds(int32_t *flags, int n) {
 }
 
 constexpr int kRingNN = 256, kRingTH = 32, kRingHalo = 8, kRingR = 16;
-// polls of about a microsecond each: tens of seconds before a wait gives up
-constexpr uint32_t kRingSpinCap = 1u << 25;
 
 }  // namespace
 
 int launch_ring_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n, const float *vx,
                       const float *vy, const double *Kb, float *w, int64_t cells_total, int32_t step_begin,
-                      int32_t s_end, void *work, size_t work_bytes, hipStream_t s, bool frame) {
+                      int32_t s_end, void *work, size_t work_bytes, hipStream_t s, bool frame,
+                      uint32_t spin_cap) {
     using S = RingShape<kRingNN, kRingTH, kRingHalo>;
     if (n != kRingNN) return SHMM_EINVAL;
     if (nlist <= 0 || step_begin >= s_end) return SHMM_OK;
@@ -317,8 +320,10 @@ int launch_ring_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t n
     int dev = 0, cus = 0, occ = 0;
     SHMM_HIP_CHECK(hipGetDevice(&dev));
     SHMM_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    SHMM_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &occ, reinterpret_cast<const void *>(&k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR>), threads, 0));
+    // occupancy of the instantiation that is launched
+    const void *fn = frame ? reinterpret_cast<const void *>(&k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR, true>)
+                           : reinterpret_cast<const void *>(&k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR>);
+    SHMM_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, threads, 0));
     // every workgroup of the grid fits on the device at once
     int64_t groups = std::min<int64_t>(nlist, (int64_t)cus * occ / S::PER);
     if (groups < 1) return SHMM_EDEVICE;
@@ -336,11 +341,11 @@ int launch_ring_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t n
     if (frame)
         hipLaunchKernelGGL((k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR, true>), dim3((unsigned)(groups * S::PER)),
                            dim3(threads), 0, s, d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, slab, flags,
-                           step_begin, s_end, kRingSpinCap);
+                           step_begin, s_end, spin_cap);
     else
         hipLaunchKernelGGL((k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR>), dim3((unsigned)(groups * S::PER)),
                            dim3(threads), 0, s, d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, slab, flags,
-                           step_begin, s_end, kRingSpinCap);
+                           step_begin, s_end, spin_cap);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
 }

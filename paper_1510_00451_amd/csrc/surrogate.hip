@@ -695,4 +695,94 @@ int surrogate_infer(const void *models, int32_t E, const float *x, const double 
     return SHMM_OK;
 }
 
+// ------------------------------------------------------------------ dataset statistics
+
+namespace {
+
+// Column c of x [B][33]: FP64 mean, standard deviation (divisor B - 1),
+// minimum and maximum, one workgroup per column.  Thread t takes rows t,
+// t + 256, ...; partial sums meet in a fixed tree, so the result does not
+// depend on scheduling.  Two passes (the mean, then the squared deviations).
+__global__ __launch_bounds__(256) void k_feature_stats(const float *__restrict__ x, int64_t B,
+                                                       double *__restrict__ stats) {
+    __shared__ double red[256];
+    __shared__ double lo[256], hi[256];
+    const int c = blockIdx.x, t = threadIdx.x;
+    double sum = 0.0, mn = INFINITY, mx = -INFINITY;
+    for (int64_t r = t; r < B; r += 256) {
+        const double v = (double)x[r * SHMM_SURR_IN + c];
+        sum += v;
+        mn = v < mn ? v : mn;
+        mx = v > mx ? v : mx;
+    }
+    red[t] = sum;
+    lo[t] = mn;
+    hi[t] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            red[t] += red[t + w];
+            lo[t] = lo[t + w] < lo[t] ? lo[t + w] : lo[t];
+            hi[t] = hi[t + w] > hi[t] ? hi[t + w] : hi[t];
+        }
+        __syncthreads();
+    }
+    const double mean = red[0] / (double)B;
+    __syncthreads();
+    double sq = 0.0;
+    for (int64_t r = t; r < B; r += 256) {
+        const double d = (double)x[r * SHMM_SURR_IN + c] - mean;
+        sq += d * d;
+    }
+    red[t] = sq;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        stats[c] = mean;
+        stats[SHMM_SURR_IN + c] = sqrt(red[0] / (double)(B - 1));
+        stats[2 * SHMM_SURR_IN + c] = lo[0];
+        stats[3 * SHMM_SURR_IN + c] = hi[0];
+    }
+}
+
+// Rescaled copy of labelled local problems: velocity and diffusivity scaled
+// together by c = 10^log10c[b] leave the corrector unchanged, so K and K_b
+// scale by c, the band features (squared Peclet numbers) stay and feature 32
+// (log sqrt det K_b) moves by ln c.
+__global__ void k_rescale(const float *__restrict__ x, const double *__restrict__ Kb, const double *__restrict__ K,
+                          const double *__restrict__ log10c, int64_t B, float *__restrict__ xo,
+                          double *__restrict__ Kbo, double *__restrict__ Ko) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const double c = exp(log10c[b] * 2.302585092994045684);
+    for (int i = 0; i < SHMM_SURR_IN; ++i) {
+        const float v = x[b * SHMM_SURR_IN + i];
+        xo[b * SHMM_SURR_IN + i] = i == SHMM_SURR_BINS ? (float)((double)v + log(c)) : v;
+    }
+    for (int q = 0; q < 3; ++q) {
+        Kbo[3 * b + q] = Kb[3 * b + q] * c;
+        Ko[3 * b + q] = K[3 * b + q] * c;
+    }
+}
+
+}  // namespace
+
+int launch_feature_stats(const float *x, int64_t B, double *stats, hipStream_t s) {
+    hipLaunchKernelGGL(k_feature_stats, dim3(SHMM_SURR_IN), dim3(256), 0, s, x, B, stats);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
+
+int launch_surrogate_rescale(const float *x, const double *Kb, const double *K, const double *log10c, int64_t B,
+                             float *xo, double *Kbo, double *Ko, hipStream_t s) {
+    if (B <= 0) return SHMM_OK;
+    hipLaunchKernelGGL(k_rescale, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, x, Kb, K, log10c, B, xo,
+                       Kbo, Ko);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
+
 }  // namespace shmm

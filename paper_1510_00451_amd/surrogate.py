@@ -128,16 +128,21 @@ class Dataset:
     Kb: "object"       # torch float64 [S][3]
     K: "object"        # torch float64 [S][3]
 
-    def rescaled(self, log10_c):
+    def rescaled(self, ctx: abi.Context, log10_c):
         """The same local problems with velocity and diffusivity scaled by
-        c = 10^log10_c (one factor per sample, host array [S]): the corrector
-        is unchanged, so K and K_b scale by c, the 32 band features (squared
-        Peclet numbers) are unchanged and feature 32 shifts by ln c."""
+        c = 10^log10_c (one factor per sample, host array [S]), computed by
+        shmm_surrogate_rescale: the corrector is unchanged, so K and K_b scale
+        by c, the 32 band features (squared Peclet numbers) are unchanged and
+        feature 32 shifts by ln c."""
         torch = _torch()
-        c = torch.from_numpy(10.0 ** np.asarray(log10_c, np.float64)).to(self.K.device)
-        x = self.x.clone()
-        x[:, abi.SURR_BINS] += torch.log(c).to(torch.float32)
-        return Dataset(x, self.Kb * c[:, None], self.K * c[:, None])
+        S = self.x.shape[0]
+        lc = torch.from_numpy(np.ascontiguousarray(log10_c, np.float64)).to(self.K.device)
+        out = Dataset(torch.empty_like(self.x), torch.empty_like(self.Kb), torch.empty_like(self.K))
+        ctx.shmm_surrogate_rescale(self.x.data_ptr(), self.Kb.data_ptr(), self.K.data_ptr(), lc.data_ptr(), S,
+                                   out.x.data_ptr(), out.Kb.data_ptr(), out.K.data_ptr(),
+                                   torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        return out
 
     @staticmethod
     def concat(parts):
@@ -338,12 +343,24 @@ def split(data: Dataset, frac: float, seed: int):
     return pick(perm[:k]), pick(perm[k:])
 
 
-def gate_range(data: Dataset, margin: float = 0.1):
-    """Per-feature training range widened by `margin` of its width (device float32)."""
-    lo = data.x.min(0).values
-    hi = data.x.max(0).values
+def feature_stats(ctx: abi.Context, x):
+    """(mean, std, min, max) of every feature column of x [S][33] (device),
+    FP64 host arrays, from shmm_feature_stats."""
+    torch = _torch()
+    st = torch.empty(4, abi.SURR_IN, dtype=torch.float64, device=x.device)
+    ctx.shmm_feature_stats(x.data_ptr(), x.shape[0], st.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    h = st.cpu().numpy()
+    return h[0], h[1], h[2], h[3]
+
+
+def gate_range(ctx: abi.Context, data: Dataset, margin: float = 0.1):
+    """Per-feature training range widened by `margin` of its width (device
+    float32, the gate's bounds; the range itself from shmm_feature_stats)."""
+    torch = _torch()
+    _, _, lo, hi = feature_stats(ctx, data.x)
     w = hi - lo
-    return lo - margin * w, hi + margin * w
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(data.x.device)
+    return dev(lo - margin * w), dev(hi + margin * w)
 
 
 def calibrate_gate(ens: Ensemble, held: Dataset, lo, hi, target: float = 0.01, quantile: float = 0.99,

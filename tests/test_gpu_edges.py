@@ -192,3 +192,140 @@ def test_ring_bands_single_patch_and_skipped_patch(torch):
     assert bool((w[:, o1:o1 + 256 * 256] == 0.25).all())
     assert not np.allclose(w[:, :256 * 256], 0.25)
     H.close()
+
+
+# ---------------------------------------------------------------- per-domain status words
+
+def _rot(theta, a, b):
+    c, s = np.cos(theta), np.sin(theta)
+    return np.array([a * c * c + b * s * s, (a - b) * c * s, a * s * s + b * c * c])
+
+
+@pytest.mark.parametrize("n", [32, 128, 256])
+def test_nonfinite_patch_sets_its_status_bit(torch, n):
+    """A NaN in one patch's face velocity: the local solve ORs
+    SHMM_DOM_NONFINITE into that domain's status word and no other, and the
+    estimator agrees; the other patches' correctors are finite (resident
+    kernels at 32^2 and 128^2, ring-exchange bands at 256^2)."""
+    from paper_1510_00451_amd import abi
+    from paper_1510_00451_amd.hierarchy import Hierarchy
+    p = flowgen.config_continuous(seed=n, radius=max(2, n // 8), p=-1.5, kappa=0.05, n=n, lattice=2, levels=1)
+    p.psi_hat *= 0.3
+    p.n_global = [2 * n]
+    say("case non-finite patch, n =", n)
+    H = Hierarchy(p, keep_psi=False)
+    H.band_filter()
+    Kb = np.tile([0.06, 0.015, 0.04], (H.nd, 1))
+    H.K_base.copy_(torch.from_numpy(Kb))
+    H.ctx.shmm_plan_steps(0, H.nd, Kb)
+    bad = 2
+    o = int(H.table["offset"][bad])
+    H.vx[o + 7] = float("nan")
+    H.w.zero_()
+    H.status.zero_()
+    H.ctx.shmm_local_solve_batch(0, H.nd, H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(),
+                                 H.K_base.data_ptr(), H.w.data_ptr(), 0, 12, H.status.data_ptr(), H.stream())
+    torch.cuda.synchronize()
+    st = H.status.cpu().numpy()
+    assert st[bad] == abi.DOM_NONFINITE and np.all(np.delete(st, bad) == 0), st
+    w = H.w.cpu().numpy().reshape(2, H.cells)
+    for d in range(H.nd):
+        od = int(H.table["offset"][d])
+        fin = np.isfinite(w[:, od:od + n * n]).all()
+        assert fin == (d != bad), d
+    H.status.zero_()
+    H.ctx.shmm_effective_diffusivity(0, H.nd, H.f1.data_ptr(), H.f2.data_ptr(), H.w.data_ptr(),
+                                     H.K_base.data_ptr(), H.K_solve.data_ptr(), 0, 0, H.status.data_ptr(),
+                                     H.stream())
+    torch.cuda.synchronize()
+    st = H.status.cpu().numpy()
+    assert st[bad] == abi.DOM_NONFINITE and np.all(np.delete(st, bad) == 0), st
+    H.close()
+
+
+def test_level_chain_raises_a_base_that_falls_below_k_in(torch):
+    """Algorithm 3, step 3 with hand-built finer results: where K_star - K_off
+    + K_in falls below K_in (its low eigenvalue under lambda_min(K_in), or not
+    a number), the base is the oracle's spd_floor of it and the domain is
+    flagged SHMM_DOM_NOT_SPD; a dominating difference passes unchanged and
+    unflagged."""
+    import oracle
+    from paper_1510_00451_amd import abi
+    from paper_1510_00451_amd.hierarchy import MODE_BASE
+    say("case non-SPD base")
+    H = _hier()
+    H.band_filter()
+    H.top_down()
+    torch.cuda.synchronize()
+    first, count = int(H.phase[1]), int(H.phase[2] - H.phase[1])     # level above the finest
+    K_in, K_off = H.K_in.cpu().numpy(), H.K_off.cpu().numpy()
+    R = np.zeros((H.nd, 3))
+    par = H.table["parent"]
+    targets = {}
+    for t, d in enumerate(range(first, first + count)):
+        floor = oracle.lambda_min(K_in[d])
+        net = [_rot(0.4, 3 * floor, 0.3 * floor),            # low eigenvalue below the floor
+               _rot(-1.0, 2 * floor, -0.5 * floor),          # indefinite
+               K_in[d] + _rot(0.2, 0.5 * floor, 0.1 * floor),  # dominates K_in: unchanged
+               np.array([np.nan, 0.0, floor])][t % 4]        # not a number
+        targets[d] = net
+        kids = np.flatnonzero(par == d)
+        assert len(kids) == 1
+        R[kids[0]] = net + K_off[d] - K_in[d]               # K_star of the parent
+    H.R.copy_(torch.from_numpy(R))
+    H.status.zero_()
+    H.ctx.shmm_level_chain(first, count, MODE_BASE, H.lines.data_ptr(), H.K_in.data_ptr(), H.K_off.data_ptr(),
+                           H.K_base.data_ptr(), 0, H.R.data_ptr(), H.status.data_ptr(), H.stream())
+    torch.cuda.synchronize()
+    Kb, st = H.K_base.cpu().numpy(), H.status.cpu().numpy()
+    for d in range(first, first + count):
+        kids = np.flatnonzero(par == d)
+        want, low = oracle.spd_floor(R[kids[0]] - K_off[d] + K_in[d], K_in[d])
+        assert (st[d] == abi.DOM_NOT_SPD) == low, (d, st[d])
+        np.testing.assert_allclose(Kb[d], want, rtol=0, atol=1e-12 * np.max(np.abs(want)))
+    assert sum(1 for d in range(first, first + count) if st[d]) == sum(
+        1 for t in range(count) if t % 4 != 2)
+    H.close()
+
+
+def test_ring_wait_gives_up_from_the_host(torch):
+    """The ring-exchange bands with their wait limit set to zero polls
+    (SHMM_TUNE_RING_SPIN_CAP): every band gives up at its first exchange,
+    writes NaN into its rows and exits, and the local solve flags every
+    patch SHMM_DOM_NONFINITE.  With the default limit restored the same
+    context solves the phase again, finite and equal to the relaunched bands."""
+    from paper_1510_00451_amd import abi
+    from paper_1510_00451_amd.hierarchy import Hierarchy
+    say("case ring wait limit 0")
+    probs = [flowgen.config_batched_instance(14)]                 # n = 256
+    H = Hierarchy(probs, keep_psi=False)
+    H.band_filter()
+    first, count = int(H.phase[0]), int(H.phase[1] - H.phase[0])
+    assert set(H.table["n"][first:first + count]) == {256}
+    Kb = np.tile([0.012, 0.002, 0.009], (H.nd, 1))
+    H.K_base.copy_(torch.from_numpy(Kb))
+    H.ctx.shmm_plan_steps(first, count, Kb)
+    args = (H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(),
+            H.w.data_ptr())
+    H.ctx.shmm_ctx_tune(256, 6)
+    H.ctx.shmm_ctx_tune(abi.TUNE_RING_SPIN_CAP, 0)
+    H.w.zero_()
+    H.status.zero_()
+    H.ctx.shmm_local_solve_batch(first, count, *args, 0, 10, H.status.data_ptr(), H.stream())
+    torch.cuda.synchronize()
+    st = H.status.cpu().numpy()[first:first + count]
+    assert np.all(st == abi.DOM_NONFINITE), st
+    a, b = H.cell_range(first, count)
+    assert np.isnan(H.w.view(2, H.cells)[:, a:b].cpu().numpy()).any()
+    out = {}
+    H.ctx.shmm_ctx_tune(abi.TUNE_RING_SPIN_CAP, 1 << 25)
+    for v in (6, 0):
+        H.ctx.shmm_ctx_tune(256, v)
+        H.w.zero_()
+        H.status.zero_()
+        H.ctx.shmm_local_solve_batch(first, count, *args, 0, 10, H.status.data_ptr(), H.stream())
+        torch.cuda.synchronize()
+        assert int(H.status.max()) == 0
+        out[v] = H.w.cpu().numpy().copy()
+    assert np.array_equal(out[6], out[0]) and np.isfinite(out[6]).all()
+    H.close()

@@ -140,15 +140,20 @@ def test_inference_and_gate_parity(torch):
     ctx.close()
 
 
-def test_train_step_parity(torch):
+@pytest.mark.parametrize("B", [96, 2500, 4096])
+def test_train_step_parity(torch, B):
+    """One training step (forward, loss, backward, gradient norm, Adam) and a
+    second one with clipping active, against the oracle fed the same
+    BF16-rounded operands.  B = 2500 and 4096 (the training batch) take the
+    split-K path of the weight-gradient products (K = B >= 2048 over 16 output
+    tiles: 16 slices added in a fixed order)."""
     from paper_1510_00451_amd import abi
     rng = np.random.default_rng(5)
     net = _to32(_random_member(21, rng))
-    B = 96
     x = rng.standard_normal((B, 33)).astype(np.float32).astype(np.float64)
     Kb = np.stack([rng.uniform(0.01, 0.1, B), rng.uniform(-0.003, 0.003, B), rng.uniform(0.01, 0.1, B)], 1)
     Kt = Kb * rng.uniform(1.0, 2.5, (B, 1))
-    say("case train step")
+    say("case train step, B =", B)
     ctx = abi.Context(0)
     model = _pack(torch, [net])
     s = torch.cuda.current_stream().cuda_stream
@@ -338,4 +343,45 @@ def test_ensemble_prune_drops_a_member_that_failed(torch):
     assert losses[1] > 3 * min(losses[0], losses[2])
     assert ens.E == 2
     assert torch.equal(ens.buf[:words], keep0) and torch.equal(ens.buf[words:], keep2)
+    ctx.close()
+
+
+def test_feature_stats_and_rescale(torch):
+    """Column statistics of a feature matrix (the standardisation and the gate
+    range) against numpy in FP64, bitwise reproducible; rescaled labels: K
+    and K_b times c, the band features unchanged, feature 32 moved by ln c."""
+    from paper_1510_00451_amd import abi
+    rng = np.random.default_rng(9)
+    B = 5000
+    x = (rng.standard_normal((B, 33)) * rng.uniform(0.1, 3.0, 33) + rng.uniform(-5, 5, 33)).astype(np.float32)
+    say("case feature statistics and rescaling")
+    ctx = abi.Context(0)
+    s = torch.cuda.current_stream().cuda_stream
+    dx = torch.tensor(x, device="cuda")
+    st = torch.empty(4, 33, dtype=torch.float64, device="cuda")
+    ctx.shmm_feature_stats(dx.data_ptr(), B, st.data_ptr(), s)
+    torch.cuda.synchronize()
+    got = st.cpu().numpy()
+    xd = x.astype(np.float64)
+    np.testing.assert_allclose(got[0], xd.mean(0), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(got[1], xd.std(0, ddof=1), rtol=1e-11)
+    assert np.array_equal(got[2], xd.min(0)) and np.array_equal(got[3], xd.max(0))
+    ctx.shmm_feature_stats(dx.data_ptr(), B, st.data_ptr(), s)
+    torch.cuda.synchronize()
+    assert np.array_equal(st.cpu().numpy(), got)
+    Kb = np.stack([rng.uniform(0.01, 0.1, B), rng.uniform(-0.003, 0.003, B), rng.uniform(0.01, 0.1, B)], 1)
+    Kt = Kb * rng.uniform(1.0, 2.5, (B, 1))
+    lc = rng.uniform(-1.5, 1.5, B)
+    dKb, dKt, dlc = (torch.tensor(a, device="cuda") for a in (Kb, Kt, lc))
+    xo = torch.empty_like(dx)
+    Kbo, Kto = torch.empty_like(dKb), torch.empty_like(dKt)
+    ctx.shmm_surrogate_rescale(dx.data_ptr(), dKb.data_ptr(), dKt.data_ptr(), dlc.data_ptr(), B, xo.data_ptr(),
+                               Kbo.data_ptr(), Kto.data_ptr(), s)
+    torch.cuda.synchronize()
+    c = 10.0 ** lc
+    np.testing.assert_allclose(Kbo.cpu().numpy(), Kb * c[:, None], rtol=1e-14)
+    np.testing.assert_allclose(Kto.cpu().numpy(), Kt * c[:, None], rtol=1e-14)
+    xg = xo.cpu().numpy()
+    assert np.array_equal(xg[:, :32], x[:, :32])
+    np.testing.assert_allclose(xg[:, 32], x[:, 32].astype(np.float64) + np.log(c), rtol=0, atol=2e-6)
     ctx.close()
