@@ -1,12 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the SHMM hot path on one MI355X.
 
-One step = one pass of the hot path over the four-level cellular workload
-(psi = sum_{k=1,4,16,64} k^(-4/3) sin(kx+p1) sin(ky+p2), kappa = 1e-2, 4 levels
-of 64 patches of 128^2 cells) plus the shear check instance v = (0, sin 16x):
-band filter, top-down Algorithm 2, then every phase (base, step plan, local
-solves, FP64 effective diffusivity, level combination), all on the GPU with
-the inputs resident in HBM.
+Headline workload: the five-level continuous-spectrum flow (random-phase
+|psi_k| ~ |k|^-7/3 for 1 <= |k| <= 512, kappa = 1e-3, band edges 4, 16, 64,
+256, five levels of 256 patches of 128^2 cells).  One step = one level phase
+of the hot path: the phase's base (Algorithm 3), its step plan, the local
+solves of its 256 patches to the planned quasi-stationary state, the FP64
+effective diffusivity and the level result; the first phase of every pass
+also runs the band filter and Algorithm 2.  Five steps are one whole pass
+(K_total at every centre); all inputs are resident in HBM.  The value is
+Gpoint-steps/s over the timed steps (one point-step: one cell of one patch
+advanced one RK4 step, both correctors).
+
+Extras on the same JSON line: the four-level cellular workload with the
+shear check, the quasi-stationary stop, the uneven batch (graph-replayed
+solves), every 256^2 kernel variant, the Section 4 examples, oversampled
+patches, the surrogate against the plain solve, and the FP64 oracle on the
+host's cores.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -14,6 +24,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -24,56 +35,71 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "κ_eff estimates/s + Gpoint-steps/s; surrogate vs plain at ≤1% κ_eff error"
+# Algorithmic HBM traffic of one point-step of a streaming stencil: read w1,
+# w2 and psi, write w1 and w2 (FP32).  The roofline is 8 TB/s / 20 B.
+BYTES_PER_POINT_STEP = 20
+HBM_PEAK_GBS = 8000.0            # MI355X published HBM3E bandwidth
 # Algorithmic FP32 work of one point-step (one cell of one patch, one classic
 # RK4 step, both correctors): per corrector 4 evaluations of the 9-point
 # operator with forcing (6 FMA + 4 ADD = 16 flop), 3 stage inputs (2 flop each)
 # and the final update (8 flop): 78 flop; two correctors.
 FLOP_PER_POINT_STEP = 156
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (256 CU, 2.4 GHz)
-# HBM bytes per full-phase launch of k_solve_resident_e<128, 32, 8> on this
-# workload, from rocprofv3 FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0), the scale
-# factors read off a 1 GiB device copy.  Valid only for the kernel code they
-# were taken on (first 16 hex digits of the SHA-256 of solve.hip without its
-# comments and blank lines); otherwise reported null.
-SOLVE_TRAFFIC = {"code_sha256": "20887aa200990312", "variant": 5,
-                 "bytes_per_launch": (2 * 12634.9 + 8832.0) * 1024}
+# HBM bytes per full-phase launch of k_solve_resident_e<128, 32, 8> on the
+# headline workload, from rocprofv3 FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0),
+# the scale factors read off a 1 GiB device copy.  Valid only for the kernel
+# code they were taken on (first 16 hex digits of the SHA-256 of solve.hip and
+# solve_stage.h without comments and blank lines); otherwise reported null.
+SOLVE_TRAFFIC = {"code_sha256": None, "variant": 5, "bytes_per_launch": None}
 SOLVE_KERNELS_128 = {0: "k_solve_resident<128,32>", 1: "k_solve_rows<128,2,16>", 2: "k_solve_rows<128,2,8>",
                      3: "k_solve_resident_e<128,32>", 4: "k_solve_resident_e<128,16>",
                      5: "k_solve_resident_e<128,32,8>", 6: "k_solve_resident_e<128,32,16>"}
 
 
-def solve_traffic():
-    """The counted HBM bytes of one solve launch while the code of the solve
-    kernels (solve.hip and its stage header, comments aside) is the code the
-    counters were taken on; None otherwise."""
+def solve_code_hash():
     import hashlib
     lines = []
     for f in ("solve.hip", "solve_stage.h"):
         lines += open(os.path.join(ROOT, "paper_1510_00451_amd", "csrc", f)).read().split("\n")
     code = "\n".join(l.split("//")[0].rstrip() for l in lines if l.split("//")[0].strip())
-    h = hashlib.sha256(code.encode()).hexdigest()[:16]
-    return SOLVE_TRAFFIC["bytes_per_launch"] if h == SOLVE_TRAFFIC["code_sha256"] else None
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
+
+
+def solve_traffic():
+    """The counted HBM bytes of one solve launch of the headline while the
+    code of the solve kernels (solve.hip and its stage header, comments aside)
+    is the code the counters were taken on; None otherwise."""
+    if SOLVE_TRAFFIC["code_sha256"] is None or solve_code_hash() != SOLVE_TRAFFIC["code_sha256"]:
+        return None
+    return SOLVE_TRAFFIC["bytes_per_launch"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def workload():
-    import flowgen
-    main = flowgen.config_four_level_cellular(seed=0, n=128, lattice=8)
-    shear = flowgen.config_shear(k=16, V=1.0, kappa=1e-2, n=128, levels=2, thresh=[8])
-    return [main, shear]
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def cpu_baseline(steps_sample: int = 10000, domains_sample: int = 32):
-    """The FP64 oracle, as it stands, on a bounded sample of the same workload:
-    the finest-level patches of the four-level instance, a fixed number of RK4
-    steps each, OpenMP over (patch, corrector)."""
+def cpu_sample(domains_sample: int, steps_sample: int) -> dict:
+    """The FP64 oracle, as it stands, on a bounded sample of the headline
+    workload: the first `domains_sample` coarsest-level patches (128^2, side
+    2 pi) of the continuous-spectrum flow, their fields synthesised by the
+    oracle's direct Fourier sums, base kappa I, the oracle's own step size,
+    `steps_sample` classic RK4 steps of both correctors each; OpenMP over
+    (patch, corrector) on OMP_NUM_THREADS threads.  Runs on the host only."""
     import oracle
     import flowgen
-    p = flowgen.config_four_level_cellular(seed=0, n=128, lattice=8)
-    doms = [d for d in oracle.domain_table(p) if d.level == 3][:domains_sample]
+    p = flowgen.config_continuous(seed=0)
+    doms = [d for d in oracle.domain_table(p) if d.level == 0][:domains_sample]
     lv, pt = oracle.band_split(p.kmax, p.thresh)
     fields = [oracle.level_fields(p, lv, pt, d) for d in doms]
     vx = np.concatenate([f[1].ravel() for f in fields])
@@ -88,10 +114,27 @@ def cpu_baseline(steps_sample: int = 10000, domains_sample: int = 32):
                              [dt] * len(doms), [steps_sample] * len(doms))
     el = time.perf_counter() - t0
     pts = sum(d.n * d.n for d in doms) * steps_sample
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": pts / el / 1e9, "unit": "Gpoint-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(doms)} finest-level 128^2 patches x {steps_sample} RK4 steps "
-                      f"(both correctors, FP64), {el:.1f} s"}
+    return {"value": pts / el / 1e9, "seconds": el, "point_steps": pts, "domains": len(doms),
+            "steps": steps_sample}
+
+
+def cpu_baseline() -> dict:
+    """The oracle timed on the host: all cores (OMP_NUM_THREADS, else every
+    core this process may use) in this process, then one core in a child
+    process (OMP_NUM_THREADS=1); the child touches no GPU."""
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    allc = cpu_sample(32, 3000)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-sample-only", "2", "3000"],
+                       env=env, capture_output=True, text=True, timeout=600)
+    one = json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else None
+    return {"value": round(allc["value"], 4), "unit": "Gpoint-steps/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"{allc['domains']} coarsest-level 128^2 patches of the continuous-spectrum flow x "
+                      f"{allc['steps']} RK4 steps (both correctors, FP64, OpenMP), {allc['seconds']:.1f} s",
+            "one_core": None if one is None else {
+                "value": round(one["value"], 5), "cores": 1,
+                "sample": f"{one['domains']} patches x {one['steps']} steps, {one['seconds']:.1f} s"}}
 
 
 def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members: int = 4, lattice: int = 16):
@@ -117,11 +160,11 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
     t_label = time.perf_counter() - t0
     held, train = GS.split(data, 0.1, seed=0)
     rng = np.random.default_rng(1)
-    train = GS.Dataset.concat([train] + [train.rescaled(rng.uniform(-1.5, 1.5, train.x.shape[0]))
-                                         for _ in range(2)])
     ctx = abi.Context(0)
-    mu = train.x.double().mean(0).cpu().numpy()
-    sg = train.x.double().std(0).cpu().numpy() + 1e-6
+    train = GS.Dataset.concat([train] + [train.rescaled(ctx, rng.uniform(-1.5, 1.5, train.x.shape[0]))
+                                         for _ in range(2)])
+    mu, sg, _, _ = GS.feature_stats(ctx, train.x)
+    sg = sg + 1e-6
     ens = GS.Ensemble(ctx, members, mu, sg, seed0=11)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -130,7 +173,7 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
     t_train = time.perf_counter() - t1
     member_losses = ens.prune(held)
     log(f"surrogate: held-out member losses {member_losses}, {ens.E} kept")
-    lo, hi = GS.gate_range(train, 0.1)
+    lo, hi = GS.gate_range(ctx, train, 0.1)
     tau, emax, held_acc = GS.calibrate_gate(ens, held, lo, hi)
     log(f"surrogate: {data.x.shape[0]} labels in {t_label:.1f} s, trained in {t_train:.1f} s, "
         f"tau {tau}, emax {emax}, held-out accepted {held_acc:.3f}")
@@ -201,67 +244,243 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
     }
 
 
-def continuous_leg(adaptive: bool = True):
-    """One full pass over the five-level continuous-spectrum flow (256 patches
-    of 128^2 per level): a second throughput figure at full occupancy; then
-    (adaptive) the same pass with the quasi-stationary stop: its estimates/s,
-    the fraction of the planned point-steps taken and the largest relative
-    change of the final K."""
+def golden_check(res, case: str):
+    """Largest relative error of the pass's level results against the stored
+    FP64 oracle values of `case` (tests/golden, written by the oracle alone),
+    or None if the file is absent."""
+    path = os.path.join(ROOT, "tests", "golden", f"full_plan_{case}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        gold = json.load(f)
+    worst = 0.0
+    for g in gold["domains"]:
+        want = np.array(g["R"])
+        worst = max(worst, float(np.max(np.abs(res.R[g["index"]] - want)) / np.max(np.abs(want))))
+    return {"domains": len(gold["domains"]), "max_rel_err_R": worst,
+            "K_total_centres": sum(1 for g in gold["domains"] if g["level"] == 0)}
+
+
+def headline_leg(args):
+    """The continuous-spectrum flow, one level phase per step (see the module
+    docstring).  Returns (JSON fields, Hierarchy)."""
     import torch
     import flowgen
     from paper_1510_00451_amd.hierarchy import Hierarchy
+    from paper_1510_00451_amd import autotune
     H = Hierarchy([flowgen.config_continuous(seed=0)], keep_psi=False)
+    nph = len(H.phase) - 1
+    log(f"headline: domains {H.nd}, cells {H.cells}, phases {nph}")
+    tuned = {} if args.retune else autotune.apply_cached(H.ctx, [128])
+
+    def step(k):
+        p = k % nph
+        if p == 0:
+            H.status.zero_()
+            H.band_filter()
+            H.top_down()
+        H.phase_solve(p)
+        return p
+
+    def phase_points(p):
+        t = H.ctx.shmm_ctx_table()[0]
+        a, b = int(H.phase[p]), int(H.phase[p + 1])
+        return int(np.sum(t["n"][a:b].astype(np.int64) ** 2 * t["nsteps"][a:b].astype(np.int64)))
+
+    k = 0
+    for k in range(args.warmup):
+        step(k)
+        torch.cuda.synchronize()
+        log(f"warmup step {k} (phase {k % nph}) done")
+    k = args.warmup
+    if 128 not in tuned:
+        if k == 0:
+            step(0)
+            k = 1
+        res_t = autotune.tune_solve(H, phase=0, steps=300, sizes=[128])
+        autotune.record(res_t, workload="continuous-5level-256x128, phase 0, 300 steps")
+        tuned = {n: v for n, v in res_t.items()}
+        log(f"autotune: {tuned}")
+    events = []
+
+    def timed_solve(first, count, fn):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        events.append((first, count, a, b))
+
+    H.solve_hook = timed_solve
+    pts, est = 0, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    for kk in range(k, k + args.steps):
+        p = step(kk)
+        pts += phase_points(p)
+        est += int(H.phase[p + 1] - H.phase[p])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    H.solve_hook = None
+    log(f"timed {args.steps} steps in {el:.3f} s")
+    kk = k + args.steps
+    while kk % nph:                       # finish the pass the timed steps ended in
+        step(kk)
+        kk += 1
+    res = H.result()
+    table = H.ctx.shmm_ctx_table()[0]
+    ms_launch, pts_launch = [], []
+    for first, count, a, b in events:
+        ms_launch.append(a.elapsed_time(b))
+        pts_launch.append(int(np.sum(table["n"][first:first + count].astype(np.int64) ** 2
+                                     * table["nsteps"][first:first + count].astype(np.int64))))
+    avg_ms = float(np.mean(ms_launch))
+    avg_pts = float(np.mean(pts_launch))
+    achieved_gbs = BYTES_PER_POINT_STEP * avg_pts / (avg_ms * 1e-3) / 1e9
+    achieved_tflops = FLOP_PER_POINT_STEP * avg_pts / (avg_ms * 1e-3) / 1e12
+    variant = int(tuned.get(128, {"variant": 5})["variant"])
+    traffic = solve_traffic() if variant == SOLVE_TRAFFIC["variant"] else None
+    fields = {
+        "value": round(pts / el / 1e9, 3),
+        "ms_per_step": round(el / args.steps * 1e3, 3),
+        "config": {"workload": "continuous-5level-256x128 (kappa 1e-3, 1<=|k|<=512, |psi_k|~|k|^-7/3)",
+                   "levels": 5, "patches_per_level": 256, "n": 128, "kappa": 1e-3,
+                   "band_edges": [4, 16, 64, 256], "delta": 1e-6, "dt_frac": 0.5,
+                   "step": "one level phase (5 steps = one whole pass)",
+                   "point_steps_per_pass": res.point_steps, "estimates_per_pass": int(H.nd),
+                   "timed_point_steps": pts},
+        "kappa_eff_estimates_per_s": round(est / el, 3),
+        "kappa_eff_totals_per_s": round(est / el / nph, 3),
+        "autotune": {str(n): v for n, v in tuned.items()},
+        "K_total_mean": np.mean(res.K_total, axis=0).round(10).tolist(),
+        "oracle_check": golden_check(res, "continuous5"),
+        "status_max": int(H.status.max()),
+        "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "bytes_per_point_step": BYTES_PER_POINT_STEP,
+                     "kernel": SOLVE_KERNELS_128[variant], "launches": len(ms_launch),
+                     "avg_launch_ms": round(avg_ms, 3), "avg_point_steps_per_launch": avg_pts,
+                     "valu": {"achieved_tflops": round(achieved_tflops, 3), "peak_tflops": FP32_VECTOR_PEAK_TFLOPS,
+                              "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+                              "frac_of_non_packed_peak": round(achieved_tflops / (FP32_VECTOR_PEAK_TFLOPS / 2), 4),
+                              "flop_per_point_step": FLOP_PER_POINT_STEP}},
+    }
+    return fields, H
+
+
+def headline_adaptive(H, planned):
+    """The headline pass again with the quasi-stationary stop of HMM step 2:
+    estimates/s, the fraction of the planned point-steps taken and the largest
+    relative change of K_total."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H.run(adaptive=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ra = H.result()
+    d = np.abs(ra.K_total - planned.K_total).max() / np.abs(planned.K_total).max()
+    return {"kappa_eff_estimates_per_s": round(len(ra.R) / el, 2), "pass_s": round(el, 3),
+            "steps_taken_fraction": round(ra.point_steps / planned.point_steps, 4),
+            "max_rel_K_vs_planned": float(d),
+            "rule": "stop when rms(f) rms(dw) rho/(1-rho) <= delta max|K|, chunks of plan/32"}
+
+
+def cellular_leg(passes: int, adaptive: bool):
+    """The four-level cellular workload (64 patches of 128^2 per level) with
+    the shear check instance v = (0, sin 16x): whole passes, and the same with
+    the quasi-stationary stop."""
+    import torch
+    import flowgen
+    from paper_1510_00451_amd.hierarchy import Hierarchy
+    from paper_1510_00451_amd import autotune
+    main = flowgen.config_four_level_cellular(seed=0, n=128, lattice=8)
+    shear = flowgen.config_shear(k=16, V=1.0, kappa=1e-2, n=128, levels=2, thresh=[8])
+    H = Hierarchy([main, shear], keep_psi=False)
+    autotune.apply_cached(H.ctx, [128])
     H.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(passes):
+        H.run()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     res = H.result()
-    out = {"workload": "continuous-5level-256x128 (kappa 1e-3, 1<=|k|<=512)",
-           "gpoint_steps_per_s": round(res.point_steps / el / 1e9, 3),
-           "kappa_eff_estimates_per_s": round(len(res.R) / el, 2), "pass_s": round(el, 3)}
+    table = H.ctx.shmm_ctx_table()[0]
+    shear_idx = [i for i, d in enumerate(table) if d["instance"] == 1 and d["level"] == 0][0]
+    main0 = [i for i, d in enumerate(table) if d["instance"] == 0 and d["level"] == 0]
+    out = {"workload": "cellular-4level-64x128 + shear-k16 (kappa 1e-2, 4 levels of 64 patches of 128^2)",
+           "gpoint_steps_per_s": round(res.point_steps * passes / el / 1e9, 3),
+           "kappa_eff_estimates_per_s": round(H.nd * passes / el, 2), "ms_per_pass": round(el / passes * 1e3, 3),
+           "K_total_mean": np.mean(res.R[main0], axis=0).round(10).tolist(),
+           "shear_Kyy": float(res.R[shear_idx][2]), "shear_Kyy_closed_form": 0.2053125}
     if adaptive:
-        t0 = time.perf_counter()
-        H.run(adaptive=True)
         torch.cuda.synchronize()
-        ela = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for _ in range(passes):
+            H.run(adaptive=True)
+        torch.cuda.synchronize()
+        el_a = time.perf_counter() - t0
         ra = H.result()
-        d = np.abs(ra.K_total - res.K_total).max() / np.abs(res.K_total).max()
-        out["adaptive"] = {"kappa_eff_estimates_per_s": round(len(ra.R) / ela, 2), "pass_s": round(ela, 3),
+        rel = np.max(np.abs(ra.K_total - res.K_total), axis=1) / np.max(np.abs(res.K_total), axis=1)
+        out["adaptive"] = {"kappa_eff_estimates_per_s": round(len(ra.R) * passes / el_a, 2),
+                           "ms_per_pass": round(el_a * 1e3 / passes, 3),
                            "steps_taken_fraction": round(ra.point_steps / res.point_steps, 4),
-                           "max_rel_K_vs_planned": float(d)}
+                           "speedup_vs_planned": round(el / el_a, 2), "max_rel_K_vs_planned": float(rel.max())}
     H.close()
     return out
 
 
-def uneven_leg(instances: int, window: int):
+def uneven_leg(instances: int, window: int, retune: bool):
     """The uneven batch (generator seeds 0.., kappa, levels, slope and patch size
     drawn per instance; 4 x 4 patches per level, n from 32 to 256 mixed in
     every phase): one pass with every local solve capped at `window` steps,
-    after tuning the kernels on the first phase."""
+    each phase's solves replayed from a captured HIP graph, kernel variants
+    and steps per launch from the autotuner's cache (tuned on the first phase
+    when the cache lacks them)."""
     import torch
     import flowgen
     from paper_1510_00451_amd.hierarchy import Hierarchy
     from paper_1510_00451_amd import autotune
     H = Hierarchy([flowgen.config_batched_instance(s) for s in range(instances)], keep_psi=False)
+    sizes = sorted(set(int(n) for n in H.table["n"]))
+    cached = {} if retune else autotune.apply_cached(H.ctx, sizes)
     H.run(steps=1)
     torch.cuda.synchronize()
-    tuned = autotune.tune_solve(H, phase=0, steps=50, repeats=1)
+    missing = [n for n in sizes if n not in cached]
+    tuned = {}
+    if missing:
+        tuned = autotune.tune_solve(H, phase=0, steps=50, repeats=1, sizes=missing)
+        autotune.record(tuned, workload=f"uneven batch, {instances} instances, phase 0, 50 steps")
+    variants = {str(n): int(cached.get(n, tuned.get(n, {"variant": -1}))["variant"]) for n in sizes}
+    cache = autotune.load().get(autotune.arch(), {})
+    chunk = cache.get("chunk_uneven")
+    if chunk is None or retune:
+        chunk = autotune.tune_chunk(H, 0, window)
+        c = autotune.load()
+        c.setdefault(autotune.arch(), {})["chunk_uneven"] = chunk
+        autotune.save(c)
+    H.solve_chunk = int(chunk["chunk"])
+    H.graph_solves = True
+    H.run(steps=window)                 # eager: launch lists and workspace
+    H.run(steps=window)                 # captures each phase's solves and replays them
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    H.run(steps=window)
+    H.run(steps=window)                 # replays
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     table = H.ctx.shmm_ctx_table()[0]
     ns = np.minimum(table["nsteps"].astype(np.int64), window)
     pts = int(np.sum(table["n"].astype(np.int64) ** 2 * ns))
-    sizes = {int(n): int(np.sum(table["n"] == n)) for n in sorted(set(table["n"].tolist()))}
+    counts = {int(n): int(np.sum(table["n"] == n)) for n in sizes}
     full = int(np.sum(table["n"].astype(np.int64) ** 2 * table["nsteps"].astype(np.int64)))
+    graphs = len(H._graphs)
     H.close()
     return {"workload": f"uneven batch, {instances} instances (seeds 0-{instances - 1}), every solve capped "
                         f"at {window} steps",
             "gpoint_steps_per_s": round(pts / el / 1e9, 3), "window_s": round(el, 3),
-            "domains_by_n": sizes, "autotune": {str(k): v["variant"] for k, v in tuned.items()},
+            "domains_by_n": {str(k): v for k, v in counts.items()}, "autotune_variants": variants,
+            "steps_per_launch": chunk, "graphs_replayed": graphs,
             "full_run_point_steps_planned": full}
 
 
@@ -457,15 +676,17 @@ def n256_leg(steps: int = 200):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10, help="timed steps (level phases of the headline)")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed steps before them")
+    ap.add_argument("--headline-only", action="store_true", help="the headline workload alone")
+    ap.add_argument("--retune", action="store_true", help="tune again instead of using the autotuner's cache")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-flows", type=int, default=64)
     ap.add_argument("--surrogate-eval-flows", type=int, default=32)
     ap.add_argument("--surrogate-steps", type=int, default=1500)
     ap.add_argument("--surrogate-lattice", type=int, default=16)
-    ap.add_argument("--no-continuous", action="store_true")
+    ap.add_argument("--no-cellular", action="store_true", help="skip the four-level cellular workload")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--uneven-instances", type=int, default=256)
     ap.add_argument("--uneven-window", type=int, default=2000)
@@ -475,17 +696,21 @@ def main():
     ap.add_argument("--no-adaptive", action="store_true", help="skip the quasi-stationary-stop passes")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="copy this many MiB once before the passes (reference for HBM byte counters)")
+    ap.add_argument("--cpu-sample-only", nargs=2, type=int, metavar=("DOMAINS", "STEPS"),
+                    help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_sample_only:                      # child process of cpu_baseline: host only
+        print(json.dumps(cpu_sample(*args.cpu_sample_only)), flush=True)
+        return 0
     if args.gpus != 1:
         log("bench.py measures one GPU only: the hot path runs on a single MI355X; patches are "
             "independent, so more GPUs would each take a share of the centres. Use --gpus 1.")
-        sys.exit(2)
+        return 2
 
     import torch
-    from paper_1510_00451_amd.hierarchy import Hierarchy
     if not torch.cuda.is_available():
         log("no HIP device: the benchmark needs an MI355X")
-        sys.exit(1)
+        return 1
     torch.cuda.set_device(0)
     if args.copy_probe_mib > 0:
         src = torch.full((args.copy_probe_mib << 20,), 1, dtype=torch.uint8, device="cuda")
@@ -493,128 +718,74 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    probs = workload()
-    H = Hierarchy(probs, keep_psi=False)
-    log(f"domains {H.nd}, cells {H.cells}, phases {len(H.phase) - 1}")
-
-    events = []
-
-    def timed_solve(first, count, fn):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        fn()
-        b.record()
-        events.append((first, count, a, b))
-
-    for i in range(max(1, args.warmup)):
-        H.run()
-        torch.cuda.synchronize()
-        log(f"warmup pass {i} done")
-        if i == 0:
-            from paper_1510_00451_amd import autotune
-            tuned = autotune.tune_solve(H, phase=0, steps=300)
-            log(f"autotune: {tuned}")
-    H.solve_hook = timed_solve
-    events.clear()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        H.run()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    el = t1 - t0
-    res = H.result()
-    log(f"timed {args.steps} passes in {el:.3f} s")
-
-    # per-launch kernel time of the local solves (HIP events on the launch stream)
-    table = H.ctx.shmm_ctx_table()[0]
-    pts_launch, ms_launch = [], []
-    for first, count, a, b in events:
-        ms_launch.append(a.elapsed_time(b))
-        pts_launch.append(int(np.sum(table["n"][first:first + count].astype(np.int64) ** 2
-                                     * table["nsteps"][first:first + count].astype(np.int64))))
-    avg_ms = float(np.mean(ms_launch))
-    avg_flop = FLOP_PER_POINT_STEP * float(np.mean(pts_launch))
-    achieved_tflops = avg_flop / (avg_ms * 1e-3) / 1e12
-
-    pass_pts = res.point_steps
-    gpts = pass_pts * args.steps / el / 1e9
-    est = H.nd * args.steps / el
-    shear_idx = [i for i, d in enumerate(table) if d["instance"] == 1 and d["level"] == 0][0]
+    head, H = headline_leg(args)
     out = {
         "metric": METRIC,
-        "value": round(gpts, 3),
+        "value": head.pop("value"),
         "unit": "Gpoint-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(el / args.steps * 1e3, 3),
+        "ms_per_step": head.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 stencils, f64 reductions",
         "data": "synthetic",
-        "config": {"workload": "cellular-4level-64x128 + shear-k16",
-                   "levels": 4, "patches_per_level": 64, "n": 128, "kappa": 1e-2,
-                   "band_edges": [2, 8, 32], "delta": 1e-6, "dt_frac": 0.5,
-                   "point_steps_per_pass": pass_pts, "estimates_per_pass": int(H.nd)},
-        "kappa_eff_estimates_per_s": round(est, 2),
-        "autotune": {str(k): v for k, v in tuned.items()},
-        "K_total_mean": np.mean(res.K_total[:64], axis=0).round(10).tolist(),
-        "shear_Kyy": float(res.R[shear_idx][2]),
-        "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3),
-                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-                     "traffic": solve_traffic() if tuned.get(128, {"variant": 5})["variant"] == SOLVE_TRAFFIC["variant"]
-                     else None,
-                     "kernel": SOLVE_KERNELS_128[tuned.get(128, {"variant": 0})["variant"]],
-                     "launches": len(ms_launch), "avg_launch_ms": round(avg_ms, 3)},
     }
-    if not args.no_adaptive:
-        # the same passes with the quasi-stationary stop of HMM step 2
-        H.solve_hook = None
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            H.run(adaptive=True)
-        torch.cuda.synchronize()
-        el_a = time.perf_counter() - t0
-        ra = H.result()
-        rel = np.max(np.abs(ra.K_total - res.K_total), axis=1) / np.max(np.abs(res.K_total), axis=1)
-        out["adaptive"] = {
-            "kappa_eff_estimates_per_s": round(len(ra.R) * args.steps / el_a, 2),
-            "ms_per_pass": round(el_a * 1e3 / args.steps, 3),
-            "steps_taken_fraction": round(ra.point_steps / res.point_steps, 4),
-            "speedup_vs_planned": round(el / el_a, 2),
-            "max_rel_K_vs_planned": float(rel.max()),
-            "rule": "stop when rms(f) rms(dw) rho/(1-rho) <= delta max|K|, chunks of plan/32"}
-        log(f"adaptive: {out['adaptive']}")
+    out.update(head)
+    extras = not args.headline_only
+    if extras and not args.no_adaptive:
+        log("headline pass with the quasi-stationary stop ...")
+        out["adaptive"] = headline_adaptive(H, H.result())
     H.close()
-    if not args.no_continuous:
-        log("continuous-spectrum pass ...")
-        out["continuous_5level"] = continuous_leg()
-    if not args.no_uneven:
+    if extras and not args.no_cellular:
+        log("four-level cellular workload ...")
+        out["cellular_4level"] = cellular_leg(3, not args.no_adaptive)
+    if extras and not args.no_uneven:
         log("uneven batch ...")
-        out["uneven_batch"] = uneven_leg(args.uneven_instances, args.uneven_window)
-    if not args.no_n256:
+        out["uneven_batch"] = uneven_leg(args.uneven_instances, args.uneven_window, args.retune)
+    if extras and not args.no_n256:
         log("256^2 kernel variants ...")
         out["n256_variants"] = n256_leg()
-    if not args.no_paper:
+    if extras and not args.no_paper:
         log("Section 4 examples ...")
         out["paper_tests"] = paper_tests_leg()
-    if not args.no_oversampling:
+    if extras and not args.no_oversampling:
         log("oversampled patches ...")
         out["oversampling"] = oversampling_leg()
-    if not args.no_surrogate:
+    if extras and not args.no_surrogate:
         log("surrogate ...")
         out["surrogate"] = surrogate_leg(args.surrogate_flows, args.surrogate_eval_flows,
                                          steps=args.surrogate_steps, lattice=args.surrogate_lattice)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline()
+        cb = cpu_baseline()
+        pps = out["config"]["point_steps_per_pass"]
+        cb["kappa_eff_estimates_per_s_extrapolated"] = round(
+            cb["value"] * 1e9 * out["config"]["estimates_per_pass"] / pps, 6)
+        out["cpu_baseline"] = cb
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
+    return 0
+
+
+def _exit_clean(rc: int) -> None:
+    """End the process without leaving anything behind: wait for (or end)
+    any child process, then leave without the interpreter's teardown."""
+    try:
+        import psutil
+        kids = psutil.Process().children(recursive=True)
+        for k in kids:
+            log(f"child process still running at exit: pid {k.pid} {k.name()}; ending it")
+            k.terminate()
+        psutil.wait_procs(kids, timeout=10)
+    except Exception as e:  # noqa: BLE001 (best effort: the exit below happens regardless)
+        log(f"child check skipped: {e}")
+    sys.stdout.flush()
+    sys.stderr.flush()
+    os._exit(rc)
 
 
 if __name__ == "__main__":
-    main()
+    _exit_clean(main())

@@ -82,6 +82,15 @@ class Hierarchy:
         # windowed patches: taper the stream function over this many nodes at
         # each patch edge after the band filter (needs keep_psi)
         self.patch_taper = 0
+        # steps per launch of the planned local solves (0: one call for all;
+        # the autotuner's chunk)
+        self.solve_chunk = 0
+        # replay each phase's planned local solves from a captured HIP graph:
+        # the first pass runs them eagerly (which also sets up the launch lists
+        # and the workspace), later passes capture once and replay
+        self.graph_solves = False
+        self._graphs = {}
+        self._graph_seen = set()
 
     # -- pieces -------------------------------------------------------------
     def stream(self) -> int:
@@ -143,11 +152,17 @@ class Hierarchy:
                                             self.w.data_ptr(), self.adaptive_chunks, self.adaptive_tol,
                                             self.status.data_ptr(), s)
                 return
-            c.shmm_local_solve_batch(first, count, self.vx.data_ptr(), self.vy.data_ptr(),
-                                     self.f1.data_ptr(), self.f2.data_ptr(), self.K_base.data_ptr(),
-                                     self.w.data_ptr(), 0, 2 ** 31 - 1 if steps is None else steps,
-                                     self.status.data_ptr(), s)
+            self._planned_solve(first, count, steps, s)
 
+        if self.graph_solves and not adaptive:
+            key = (p, steps)
+            if key in self._graphs:
+                launch = self._graphs[key].replay
+            elif key in self._graph_seen:
+                self._graphs[key] = self._capture(lambda st: self._planned_solve(first, count, steps, st))
+                launch = self._graphs[key].replay
+            else:
+                self._graph_seen.add(key)
         if self.solve_hook is None:
             launch()
         else:
@@ -164,6 +179,33 @@ class Hierarchy:
         c.shmm_level_chain(first, count, MODE_RESULT, self.lines.data_ptr(), self.K_in.data_ptr(),
                            self.K_off.data_ptr(), self.K_base.data_ptr(), self.K_solve.data_ptr(),
                            self.R.data_ptr(), self.status.data_ptr(), s)
+
+    def _planned_solve(self, first: int, count: int, steps: Optional[int], stream: int) -> None:
+        """The planned local solves of [first, first + count): steps [0, steps)
+        of each plan (all of it when steps is None), in launches of
+        solve_chunk steps (one launch when 0)."""
+        total = 2 ** 31 - 1 if steps is None else steps
+        if steps is None and self.solve_chunk > 0:
+            t = self.ctx.shmm_ctx_table()[0]
+            total = int(t["nsteps"][first:first + count].max()) if count else 0
+        per = total if self.solve_chunk <= 0 else self.solve_chunk
+        for s0 in range(0, max(total, 1), max(per, 1)):
+            self.ctx.shmm_local_solve_batch(first, count, self.vx.data_ptr(), self.vy.data_ptr(),
+                                            self.f1.data_ptr(), self.f2.data_ptr(), self.K_base.data_ptr(),
+                                            self.w.data_ptr(), s0, min(per, total - s0),
+                                            self.status.data_ptr(), stream)
+
+    def _capture(self, issue):
+        """A HIP graph of the launches that issue(stream) enqueues, captured on
+        a side stream (the library's work for the range is already set up)."""
+        torch = self.torch
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.graph(g, stream=side):
+            issue(torch.cuda.current_stream(self.device).cuda_stream)
+        torch.cuda.current_stream(self.device).wait_stream(side)
+        return g
 
     def run(self, steps: Optional[int] = None, adaptive: bool = False) -> None:
         """One pass of the hot path (asynchronous apart from the per-phase plan;
@@ -187,4 +229,5 @@ class Hierarchy:
                                                  * table["nsteps"].astype(np.int64))))
 
     def close(self):
+        self._graphs.clear()
         self.ctx.close()
