@@ -358,6 +358,23 @@ int shmm_macro_step(shmm_ctx *ctx, int32_t N, int32_t bc, double g0, double g1, 
                     const void *d_vy, const double *d_K, int32_t K_is_field, double dt, int32_t nsteps,
                     void *d_u, int32_t dtype, void *stream);
 
+/* The macro step of shmm_macro_step without any device allocation, for
+ * callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, kernels and
+ * results (bit for bit) as shmm_macro_step; its three RK4 planes live in a
+ * static buffer of the library (3 N^2 doubles for N up to
+ * SHMM_MACRO_NOALLOC_MAX_N: 6 MiB, which every GPU the library runs on holds
+ * until the process ends) instead of the context's growable workspace.  The
+ * buffer needs no clearing (every plane is written before it is read).  All
+ * calls on one GPU share that GPU's buffer: calls that overlap on one GPU (on
+ * different streams, or from different contexts or threads) race, so
+ * serialise them on one stream.
+ * Errors: as shmm_macro_step; SHMM_ERANGE for N > SHMM_MACRO_NOALLOC_MAX_N. */
+#define SHMM_MACRO_NOALLOC_MAX_N 512
+int shmm_macro_step_noalloc(shmm_ctx *ctx, int32_t N, int32_t bc, double g0, double g1, const void *d_vx,
+                            const void *d_vy, const double *d_K, int32_t K_is_field, double dt, int32_t nsteps,
+                            void *d_u, int32_t dtype, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Learned surrogate of the local solve (not part of the paper's method).
  * A patch is described by 33 features.  Features 0..31 are log band energies

@@ -24,13 +24,14 @@ EXPORTS = ["shmm_ctx_create", "shmm_ctx_destroy", "shmm_build_levels", "shmm_ctx
            "shmm_local_solve_batch", "shmm_local_solve_adaptive", "shmm_effective_diffusivity",
            "shmm_effective_diffusivity_window", "shmm_window_patches", "shmm_ctx_set_local_bc",
            "shmm_level_chain",
-           "shmm_macro_step", "shmm_ctx_tune", "shmm_patch_features", "shmm_surrogate_refresh",
+           "shmm_macro_step", "shmm_macro_step_noalloc", "shmm_ctx_tune", "shmm_patch_features", "shmm_surrogate_refresh",
            "shmm_surrogate_train_step", "shmm_surrogate_infer", "shmm_fallback_solve",
            "shmm_feature_stats", "shmm_surrogate_rescale"]
 
 BC_PERIODIC, BC_DIRICHLET_X = 0, 1
 LOCAL_PERIODIC, LOCAL_ZERO_FRAME = 0, 1
 TUNE_SOLVE_VARIANT_COUNT, TUNE_RING_SPIN_CAP = 0, -1
+MACRO_NOALLOC_MAX_N = 512
 SURR_BINS, SURR_IN, SURR_WIDTH, SURR_OUT = 32, 33, 256, 3
 SURR_PARAMS, SURR_PARAMS_PADDED = 141059, 141312
 SURR_MODEL_BYTES = 4 * SURR_PARAMS_PADDED + 4 * 128 + 2 * SURR_PARAMS_PADDED
@@ -84,6 +85,7 @@ def lib() -> ctypes.CDLL:
             "shmm_ctx_set_local_bc": [P, i32],
             "shmm_level_chain": [P, i64, i64, i32, P, P, P, P, P, P, P, P],
             "shmm_macro_step": [P, i32, i32, f64, f64, P, P, P, i32, f64, i32, P, i32, P],
+            "shmm_macro_step_noalloc": [P, i32, i32, f64, f64, P, P, P, i32, f64, i32, P, i32, P],
             "shmm_ctx_tune": [P, i32, i32],
             "shmm_patch_features": [P, i64, i64, P, P, P, P, P],
             "shmm_surrogate_refresh": [P, P, P],
@@ -285,4 +287,10 @@ class Context:
         check(lib().shmm_macro_step(self.h, N, int(bc), float(g0), float(g1), d_vx or None, d_vy or None, d_K,
                                     int(K_is_field), float(dt), int(nsteps), d_u, int(dtype), stream),
               "shmm_macro_step")
+
+    def shmm_macro_step_noalloc(self, N, bc, g0, g1, d_vx, d_vy, d_K, K_is_field, dt, nsteps, d_u, dtype,
+                                stream=0):
+        check(lib().shmm_macro_step_noalloc(self.h, N, int(bc), float(g0), float(g1), d_vx or None,
+                                            d_vy or None, d_K, int(K_is_field), float(dt), int(nsteps), d_u,
+                                            int(dtype), stream), "shmm_macro_step_noalloc")
 

@@ -431,6 +431,9 @@ int shmm_ctx_create(shmm_ctx **ctx, int device) {
     SHMM_HIP_CHECK(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return SHMM_EINVAL;
     SHMM_HIP_CHECK(hipSetDevice(device));
+    // once per device: the address of the allocation-free macro step's scratch
+    int rc = macro_scratch_setup(device);
+    if (rc) return rc;
     shmm_ctx *c = new shmm_ctx();
     c->device = device;
     *ctx = c;
@@ -843,6 +846,25 @@ int shmm_macro_step(shmm_ctx *ctx, int32_t N, int32_t bc, double g0, double g1, 
     if (rc) return rc;
     if ((rc = ctx->ensure_work(macro_workspace(N, dtype)))) return rc;
     return launch_macro(N, bc, g0, g1, d_vx, d_vy, d_K, K_is_field, dt, nsteps, d_u, dtype, ctx->work,
+                        (hipStream_t)stream);
+}
+
+int shmm_macro_step_noalloc(shmm_ctx *ctx, int32_t N, int32_t bc, double g0, double g1, const void *d_vx,
+                            const void *d_vy, const double *d_K, int32_t K_is_field, double dt, int32_t nsteps,
+                            void *d_u, int32_t dtype, void *stream) {
+    if (!ctx || N < 4 || !pow2(N) || !d_K || !d_u || (dtype != 32 && dtype != 64) || nsteps < 0)
+        return SHMM_EINVAL;
+    if (bc != SHMM_BC_PERIODIC && bc != SHMM_BC_DIRICHLET_X) return SHMM_EINVAL;
+    if (bc == SHMM_BC_DIRICHLET_X && !(std::isfinite(g0) && std::isfinite(g1))) return SHMM_EINVAL;
+    if ((d_vx == nullptr) != (d_vy == nullptr)) return SHMM_EINVAL;
+    if (N > SHMM_MACRO_NOALLOC_MAX_N) return SHMM_ERANGE;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    size_t bytes = 0;
+    void *work = macro_scratch(ctx->device, &bytes);
+    if (!work) return SHMM_EDEVICE;   // shmm_ctx_create sets it up
+    if (macro_workspace(N, dtype) > bytes) return SHMM_ERANGE;
+    return launch_macro(N, bc, g0, g1, d_vx, d_vy, d_K, K_is_field, dt, nsteps, d_u, dtype, work,
                         (hipStream_t)stream);
 }
 

@@ -10,6 +10,9 @@
 // half cell, no tangential term (u is constant along the boundary); the
 // tangential x-difference on the y-faces of the first and last columns uses
 // the ghost value 2 g - u on the line through the boundary value.
+#include <map>
+#include <mutex>
+
 #include "shmm_internal.h"
 
 namespace shmm {
@@ -160,6 +163,33 @@ int run(int32_t N, int32_t bc, double g0, double g1, const void *vx, const void 
 }
 
 }  // namespace
+
+// Scratch of the allocation-free macro step (shmm_macro_step_noalloc): the
+// three RK4 planes of an N x N grid, FP64, up to N = SHMM_MACRO_NOALLOC_MAX_N.
+// Every GPU the library runs on holds its own copy until the process ends;
+// host code reaches it only through the device address that
+// macro_scratch_setup() takes with the device current.
+static constexpr size_t kMacroScratchWords = (size_t)3 * SHMM_MACRO_NOALLOC_MAX_N * SHMM_MACRO_NOALLOC_MAX_N;
+static __device__ __align__(256) double scratch[kMacroScratchWords];
+static std::mutex scratch_lock;
+static std::map<int, void *> scratch_ptr;   // device -> address of `scratch` on it
+
+int macro_scratch_setup(int device) {
+    std::lock_guard<std::mutex> g(scratch_lock);
+    if (scratch_ptr.count(device)) return SHMM_OK;
+    void *p = nullptr;
+    SHMM_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return SHMM_EDEVICE;
+    scratch_ptr[device] = p;
+    return SHMM_OK;
+}
+
+void *macro_scratch(int device, size_t *bytes) {
+    std::lock_guard<std::mutex> g(scratch_lock);
+    const auto it = scratch_ptr.find(device);
+    if (bytes) *bytes = kMacroScratchWords * sizeof(double);
+    return it == scratch_ptr.end() ? nullptr : it->second;
+}
 
 size_t macro_workspace(int32_t N, int32_t dtype) {
     return (size_t)3 * N * N * (dtype == 64 ? sizeof(double) : sizeof(float));

@@ -137,5 +137,10 @@ int launch_mark_nonfinite(const shmm_domain *d_dom, const int32_t *d_list, int32
 int launch_macro(int32_t N, int32_t bc, double g0, double g1, const void *vx, const void *vy, const double *K,
                  int32_t K_is_field, double dt, int32_t nsteps, void *u, int32_t dtype, void *work, hipStream_t s);
 size_t macro_workspace(int32_t N, int32_t dtype);
+// the static scratch of the allocation-free macro step: take its address on
+// `device` (which must be current) once; macro_scratch returns it (null if
+// never set up) and its size
+int macro_scratch_setup(int device);
+void *macro_scratch(int device, size_t *bytes);
 
 }  // namespace shmm

@@ -1,0 +1,71 @@
+"""The allocation-free macro step (shmm_macro_step_noalloc) against the
+allocating one (shmm_macro_step) through the C ABI: two calls in a row, the
+second on a smaller grid, bit-identical results; a grid above the static
+buffer's limit is refused with SHMM_ERANGE and leaves its field untouched."""
+import math
+
+import numpy as np
+import pytest
+
+import flowgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a HIP device"
+    return t
+
+
+def _case(torch, N, dtype, field):
+    """A cellular velocity, a K field (or a constant K) and the Gaussian initial field on N x N."""
+    h = 2 * np.pi / N
+    x = np.arange(N) * h
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    vx, vy, _, _ = oracle.staggered(0.7 * np.sin(X) * np.sin(2 * Y), h)
+    xc = (np.arange(N) + 0.5) * h
+    XC, YC = np.meshgrid(xc, xc, indexing="xy")
+    K = (np.stack([0.1 + 0.03 * np.cos(XC), 0.01 * np.sin(YC), 0.12 + 0.0 * XC], -1).reshape(-1, 3) if field
+         else np.array([[0.1, 0.02, 0.08]]))
+    tdt = torch.float64 if dtype == 64 else torch.float32
+    dev = lambda a, t=tdt: torch.tensor(np.ascontiguousarray(a), dtype=t, device="cuda").contiguous()
+    u0 = flowgen.macro_initial_gaussian(N)
+    dt, ns = oracle.macro_plan(N, K, 1.5, 0.3, 0.05)
+    return dev(vx), dev(vy), dev(K, torch.float64), dev(u0), dev(u0), dt, ns
+
+
+def test_macro_step_noalloc_matches_the_allocating_call(torch):
+    from paper_1510_00451_amd import abi
+    ctx = abi.Context(0)
+    s = torch.cuda.current_stream().cuda_stream
+    # two calls in a row, the second on a smaller grid (and another dtype, boundary and K)
+    for N, dtype, bc, field in ((512, 64, abi.BC_PERIODIC, 1), (128, 32, abi.BC_DIRICHLET_X, 0),
+                                (64, 64, abi.BC_DIRICHLET_X, 1)):
+        say("case macro step without allocation, N =", N, "dtype", dtype, "bc", bc)
+        vx, vy, K, u_ref, u_got, dt, ns = _case(torch, N, dtype, field)
+        ctx.shmm_macro_step(N, bc, 1.0, 0.0, vx.data_ptr(), vy.data_ptr(), K.data_ptr(), field, dt, ns,
+                            u_ref.data_ptr(), dtype, s)
+        ctx.shmm_macro_step_noalloc(N, bc, 1.0, 0.0, vx.data_ptr(), vy.data_ptr(), K.data_ptr(), field, dt, ns,
+                                    u_got.data_ptr(), dtype, s)
+        torch.cuda.synchronize()
+        ref, got = u_ref.cpu().numpy(), u_got.cpu().numpy()
+        assert np.isfinite(ref).all() and not np.array_equal(ref, flowgen.macro_initial_gaussian(N))
+        assert np.array_equal(got, ref), float(np.abs(got - ref).max())
+    # above the limit: refused, nothing written
+    N = 2 * abi.MACRO_NOALLOC_MAX_N
+    u = torch.full((N * N,), 3.0, dtype=torch.float64, device="cuda")
+    K1 = torch.tensor([[0.1, 0.0, 0.1]], dtype=torch.float64, device="cuda")
+    with pytest.raises(abi.ShmmError) as e:
+        ctx.shmm_macro_step_noalloc(N, abi.BC_PERIODIC, 0.0, 0.0, 0, 0, K1.data_ptr(), 0, 1e-3, 2, u.data_ptr(),
+                                    64, s)
+    assert e.value.code == abi.SHMM_ERANGE
+    torch.cuda.synchronize()
+    assert bool((u == 3.0).all())
+    ctx.close()
