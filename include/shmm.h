@@ -228,7 +228,9 @@ int shmm_ctx_set_local_bc(shmm_ctx *ctx, int32_t bc);
  * and other sizes stage by stage, all through the context's workspace
  * (32 B per listed cell, grown on demand).
  * Errors: SHMM_EINVAL for a range that was never planned; SHMM_ERANGE for
- * more than 32767 patches of one size outside 8..256 in one call. */
+ * more than 32767 patches in one call of a size that runs stage by stage:
+ * sizes outside 8..256, the per-stage variant of 256^2 (tuned), and zero-frame
+ * 256^2 patches on a tuned variant other than the ring-exchange bands. */
 int shmm_local_solve_batch(shmm_ctx *ctx, int64_t first, int64_t count, const float *d_vx,
                            const float *d_vy, const float *d_f1, const float *d_f2,
                            const double *d_K_base, float *d_w, int32_t step_begin,
@@ -377,7 +379,7 @@ int shmm_macro_step_noalloc(shmm_ctx *ctx, int32_t N, int32_t bc, double g0, dou
 
 /* ---------------------------------------------------------------------------
  * Learned surrogate of the local solve (not part of the paper's method).
- * A patch is described by 33 features.  Features 0..31 are log band energies
+ * A patch is described by 35 features.  Features 0..31 are log band energies
  * of the velocity spectrum of the patch samples (treated as periodic, DFT
  * normalised by 1/n^2, scaled by (L / 2 pi)^2) over the base: feature 8c + b
  * is log((E_cb + 1e-8 E_tot + 1e-30) / det K_b), where E_cb sums channel c
@@ -385,7 +387,13 @@ int shmm_macro_step_noalloc(shmm_ctx *ctx, int32_t N, int32_t bc, double g0, dou
  * (patch-relative integers) with 2^b <= k1^2 + k2^2 < 2^(b+1), b = 0..7; the
  * channels are |Vx|^2, |Vy|^2, |Vx + Vy|^2 / 2 and |Vx - Vy|^2 / 2, and E_tot
  * is the sum of channels 0 and 1 over the bins.  Feature 32 is
- * log sqrt(det K_b).  A 33 -> 256 -> 256 -> 256 -> 3 GELU network maps the
+ * log sqrt(det K_b).  Features 33 and 34 carry the anisotropy of the base:
+ * the entries (1,1) and (1,2) of the traceless part of log K_b, that is
+ * g(rho) (K11 - K22) / (K11 + K22) and g(rho) 2 K12 / (K11 + K22) with
+ * rho = sqrt((K11 - K22)^2 + 4 K12^2) / (K11 + K22) and g(rho) = atanh(rho) / rho
+ * (g(0) = 1): zero for an isotropic base, unchanged when K_b is scaled, and
+ * turning with twice the angle of the base's principal axes.
+ * A 35 -> 256 -> 256 -> 256 -> 3 GELU network maps the
  * standardised features to o, and K = K_b + sqrt(det K_b) L L^T with
  * L = [[e^o1, 0], [o2, e^o3]] (the enhancement K - K_b is positive
  * semi-definite).  Matrix products run on the matrix cores with BF16 operands
@@ -393,20 +401,20 @@ int shmm_macro_step_noalloc(shmm_ctx *ctx, int32_t N, int32_t bc, double g0, dou
  *
  * One ensemble member ("model") is SHMM_SURR_MODEL_BYTES of device memory:
  *   float    params[SHMM_SURR_PARAMS_PADDED]  W1 b1 W2 b2 W3 b3 W4 b4, W_l row-major [out][in]
- *   float    mu[64], sigma[64]                input standardisation (first 33 used)
+ *   float    mu[64], sigma[64]                input standardisation (first 35 used)
  *   uint16_t bf16[SHMM_SURR_PARAMS_PADDED]    bfloat16 copy of params
  * Members of an ensemble are stored back to back.
  * ------------------------------------------------------------------------- */
 #define SHMM_SURR_BINS 32
-#define SHMM_SURR_IN 33
+#define SHMM_SURR_IN 35
 #define SHMM_SURR_WIDTH 256
 #define SHMM_SURR_OUT 3
-#define SHMM_SURR_PARAMS 141059
-#define SHMM_SURR_PARAMS_PADDED 141312
+#define SHMM_SURR_PARAMS 141571
+#define SHMM_SURR_PARAMS_PADDED 141824
 #define SHMM_SURR_MODEL_BYTES (4 * SHMM_SURR_PARAMS_PADDED + 4 * 128 + 2 * SHMM_SURR_PARAMS_PADDED)
 
 /* Features of domains [first, first + count), which must share one patch size
- * n (8 <= n <= 256): d_features[count][33] FP32, row i for domain first + i,
+ * n (8 <= n <= 256): d_features[count][35] FP32, row i for domain first + i,
  * from the face velocities d_vx, d_vy and the bases d_K_base [n_domains][3].
  * In-house FP32 FFT; bin sums in a fixed order. */
 int shmm_patch_features(shmm_ctx *ctx, int64_t first, int64_t count, const float *d_vx,
@@ -421,7 +429,7 @@ int shmm_surrogate_refresh(shmm_ctx *ctx, void *d_model, void *stream);
  * scaled by min(1, clip / norm) when clip > 0), and an Adam step (beta 0.9 /
  * 0.999, eps 1e-8, step t >= 1 for the bias correction, learning rate lr) on
  * the FP32 params; refreshes the bf16 copy.  d_adam holds m then v,
- * 2 * SHMM_SURR_PARAMS_PADDED floats (zero at t = 1).  d_x [B][33], d_K_base
+ * 2 * SHMM_SURR_PARAMS_PADDED floats (zero at t = 1).  d_x [B][35], d_K_base
  * and d_K_true [B][3], d_loss [2].  d_grad (optional, SHMM_SURR_PARAMS floats)
  * receives the gradient of this step before clipping. */
 int shmm_surrogate_train_step(shmm_ctx *ctx, void *d_model, float *d_adam, const float *d_x,
@@ -430,7 +438,7 @@ int shmm_surrogate_train_step(shmm_ctx *ctx, void *d_model, float *d_adam, const
 
 /* Ensemble inference with the fallback gate: E members at d_models; the
  * estimate is the member mean; a patch is flagged (d_flags[b] = 1) when a
- * feature lies outside [d_lo, d_hi] (33 floats each, the training range), when
+ * feature lies outside [d_lo, d_hi] (35 floats each, the training range), when
  * the largest member deviation from the mean exceeds tau in relative
  * Frobenius norm, or when the predicted enhancement |K - K_b|_F / |K_b|_F
  * exceeds emax (the regime where the network was not shown accurate; pass
@@ -442,10 +450,25 @@ int shmm_surrogate_infer(shmm_ctx *ctx, const void *d_models, int32_t E, const f
                          double tau, double emax, double *d_K_out, uint8_t *d_flags, double *d_spread,
                          double *d_K_members, void *stream);
 
-/* Column statistics of a feature matrix d_x [B][33] (the input
+/* Chain-aware gate for the surrogate inside the level chain (Algorithm 3):
+ * a finer level's result enters its parent's base K_net = K_star - K_off +
+ * K_in after K_off is subtracted, so its absolute error must stay well below
+ * the parent's K_in.  For domain first + i, i < count: sets d_flags[i] = 1
+ * when d_spread[i] |d_K_hat[i]|_F (the ensemble's largest relative member
+ * deviation, as shmm_surrogate_infer writes it, times the estimate's norm)
+ * exceeds tol lambda_min(K_in of the domain's parent); flags of domains
+ * without a parent (level 0) are left as they are.  d_K_hat [count][3],
+ * d_spread [count], d_K_in [n_domains][3] (global index, as the level chain
+ * fills it), d_flags [count].  Errors: SHMM_EINVAL for a bad range, a null
+ * pointer or tol <= 0. */
+int shmm_surrogate_chain_gate(shmm_ctx *ctx, int64_t first, int64_t count, const double *d_K_hat,
+                              const double *d_spread, const double *d_K_in, double tol, uint8_t *d_flags,
+                              void *stream);
+
+/* Column statistics of a feature matrix d_x [B][35] (the input
  * standardisation of the network and the range of the fallback gate): per
  * column, FP64 mean, standard deviation with the B - 1 divisor, minimum and
- * maximum over the B rows, written to d_stats [4][33] (mean, std, min, max).
+ * maximum over the B rows, written to d_stats [4][35] (mean, std, min, max).
  * Fixed reduction order: bitwise reproducible.  Errors: SHMM_EINVAL for
  * B < 2 or a null pointer. */
 int shmm_feature_stats(shmm_ctx *ctx, const float *d_x, int64_t B, double *d_stats, void *stream);
@@ -454,7 +477,8 @@ int shmm_feature_stats(shmm_ctx *ctx, const float *d_x, int64_t B, double *d_sta
  * and diffusivity together by c_b = 10^d_log10c[b] leaves the corrector of a
  * local problem unchanged, so K and K_b scale by c_b, the 32 band features
  * (energies over det K_b, squared Peclet numbers) are unchanged and feature 32
- * (log sqrt det K_b) moves by ln c_b.  Inputs d_x [B][33], d_K_base and
+ * (log sqrt det K_b) moves by ln c_b; features 33 and 34 are scale free.
+ * Inputs d_x [B][35], d_K_base and
  * d_K_true [B][3], d_log10c [B]; outputs of the same shapes (may not alias
  * the inputs).  Errors: SHMM_EINVAL for B < 0 or a null pointer. */
 int shmm_surrogate_rescale(shmm_ctx *ctx, const float *d_x, const double *d_K_base, const double *d_K_true,

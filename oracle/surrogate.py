@@ -3,7 +3,7 @@ ONLY (see the package docstring).
 
 The paper has no surrogate; these definitions are this project's readings:
 
-* Features of a patch (33): band energies of the patch velocity spectrum in 4
+* Features of a patch (35): band energies of the patch velocity spectrum in 4
   channels x 8 radial bins.  With the patch samples treated as periodic and
   the DFT normalised so that sum_k |vx^(k)|^2 = mean(vx^2), the channels of a
   mode k are |vx^|^2, |vy^|^2, |vx^ + vy^|^2 / 2 and |vx^ - vy^|^2 / 2 (the
@@ -18,7 +18,12 @@ The paper has no surrogate; these definitions are this project's readings:
   in FP32 and FP64).  Dividing by det K_b makes these 32 features squared
   Peclet numbers: for an isotropic base the local problem is invariant under
   scaling velocity and diffusivity together (K scales with them), so K / kappa
-  depends on them alone.  Feature 32 is log sqrt(det K_b).  At small
+  depends on them alone.  Feature 32 is log sqrt(det K_b).  Features 33 and
+  34 carry the anisotropy of the base: the (1,1) and (1,2) entries of the
+  traceless part of the matrix logarithm log K_b (zero for an isotropic base,
+  unchanged when the base is scaled, turning with twice the angle of its
+  principal axes), so that a base from a coarser level's chain (Algorithm 3)
+  can be given to the network.  At small
   Peclet number K - K_b is, to first order, a sum over modes of these channel
   energies divided by q^2 and kappa, so the directional channels give the
   network the anisotropy that radial energies alone cannot.
@@ -26,7 +31,7 @@ The paper has no surrogate; these definitions are this project's readings:
   training range, when the ensemble disagrees (spread > tau), or when the
   predicted enhancement is beyond emax (the regime where the network was not
   shown accurate).
-* Network: 33 -> 256 -> 256 -> 256 -> 3 with exact (erf) GELU; inputs are
+* Network: 35 -> 256 -> 256 -> 256 -> 3 with exact (erf) GELU; inputs are
   standardised with stored means and scales.  Head: L = [[e^o1, 0], [o2, e^o3]],
   K = K_b + sqrt(det K_b) L L^T: the enhancement K - K_b is positive
   semi-definite (the local solve only adds diffusivity), and its logarithmic
@@ -48,7 +53,7 @@ from typing import Dict, List, Optional, Tuple
 import numpy as np
 
 N_BINS = 32
-N_IN = 33
+N_IN = 35
 WIDTH = 256
 N_OUT = 3
 LAYERS = [(N_IN, WIDTH), (WIDTH, WIDTH), (WIDTH, WIDTH), (WIDTH, N_OUT)]
@@ -86,8 +91,18 @@ def channel_energies(vx: np.ndarray, vy: np.ndarray, n: int, N: int) -> np.ndarr
     return E
 
 
+def log_base_anisotropy(K_base) -> Tuple[float, float]:
+    """(T11, T12) of T = log K_b - (1/2) tr(log K_b) I, the traceless part of
+    the matrix logarithm of the base (its eigen-decomposition by LAPACK)."""
+    K11, K12, K22 = [float(v) for v in K_base]
+    lam, vec = np.linalg.eigh(np.array([[K11, K12], [K12, K22]]))
+    L = vec @ np.diag(np.log(lam)) @ vec.T
+    T = L - 0.5 * np.trace(L) * np.eye(2)
+    return float(T[0, 0]), float(0.5 * (T[0, 1] + T[1, 0]))
+
+
 def patch_features(vx: np.ndarray, vy: np.ndarray, n: int, N: int, K_base) -> np.ndarray:
-    """33 features of one n x n patch (velocities [y][x]) with spacing 2 pi / N."""
+    """35 features of one n x n patch (velocities [y][x]) with spacing 2 pi / N."""
     E = channel_energies(vx, vy, n, N)
     floor = 1e-8 * float(np.sum(E[0]) + np.sum(E[1])) + 1e-30
     K11, K12, K22 = [float(v) for v in K_base]
@@ -97,6 +112,7 @@ def patch_features(vx: np.ndarray, vy: np.ndarray, n: int, N: int, K_base) -> np
         for b in range(N_RADIAL):
             out[N_RADIAL * c + b] = math.log(E[c, b] + floor) - logdet
     out[N_BINS] = 0.5 * logdet
+    out[N_BINS + 1], out[N_BINS + 2] = log_base_anisotropy(K_base)
     return out
 
 

@@ -26,14 +26,14 @@ EXPORTS = ["shmm_ctx_create", "shmm_ctx_destroy", "shmm_build_levels", "shmm_ctx
            "shmm_level_chain",
            "shmm_macro_step", "shmm_macro_step_noalloc", "shmm_ctx_tune", "shmm_patch_features", "shmm_surrogate_refresh",
            "shmm_surrogate_train_step", "shmm_surrogate_infer", "shmm_fallback_solve",
-           "shmm_feature_stats", "shmm_surrogate_rescale"]
+           "shmm_feature_stats", "shmm_surrogate_rescale", "shmm_surrogate_chain_gate"]
 
 BC_PERIODIC, BC_DIRICHLET_X = 0, 1
 LOCAL_PERIODIC, LOCAL_ZERO_FRAME = 0, 1
 TUNE_SOLVE_VARIANT_COUNT, TUNE_RING_SPIN_CAP = 0, -1
 MACRO_NOALLOC_MAX_N = 512
-SURR_BINS, SURR_IN, SURR_WIDTH, SURR_OUT = 32, 33, 256, 3
-SURR_PARAMS, SURR_PARAMS_PADDED = 141059, 141312
+SURR_BINS, SURR_IN, SURR_WIDTH, SURR_OUT = 32, 35, 256, 3
+SURR_PARAMS, SURR_PARAMS_PADDED = 141571, 141824
 SURR_MODEL_BYTES = 4 * SURR_PARAMS_PADDED + 4 * 128 + 2 * SURR_PARAMS_PADDED
 
 
@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
             "shmm_fallback_solve": [P, i64, i64, P, P, P, P, P, P, P, P, i32, f64, P, P],
             "shmm_feature_stats": [P, P, i64, P, P],
             "shmm_surrogate_rescale": [P, P, P, P, P, i64, P, P, P, P],
+            "shmm_surrogate_chain_gate": [P, i64, i64, P, P, P, f64, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -275,6 +276,10 @@ class Context:
                                         d_w, d_K_out, int(chunks), float(tol), d_status or None, stream),
               "shmm_fallback_solve")
 
+    def shmm_surrogate_chain_gate(self, first, count, d_K_hat, d_spread, d_K_in, tol, d_flags, stream=0):
+        check(lib().shmm_surrogate_chain_gate(self.h, first, count, d_K_hat, d_spread, d_K_in, float(tol), d_flags,
+                                              stream), "shmm_surrogate_chain_gate")
+
     def shmm_feature_stats(self, d_x, B, d_stats, stream=0):
         check(lib().shmm_feature_stats(self.h, d_x, int(B), d_stats, stream), "shmm_feature_stats")
 
@@ -293,4 +298,3 @@ class Context:
         check(lib().shmm_macro_step_noalloc(self.h, N, int(bc), float(g0), float(g1), d_vx or None,
                                             d_vy or None, d_K, int(K_is_field), float(dt), int(nsteps), d_u,
                                             int(dtype), stream), "shmm_macro_step_noalloc")
-

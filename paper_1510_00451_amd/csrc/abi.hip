@@ -922,6 +922,18 @@ int shmm_surrogate_infer(shmm_ctx *ctx, const void *d_models, int32_t E, const f
                            ctx->work, (hipStream_t)stream);
 }
 
+int shmm_surrogate_chain_gate(shmm_ctx *ctx, int64_t first, int64_t count, const double *d_K_hat,
+                              const double *d_spread, const double *d_K_in, double tol, uint8_t *d_flags,
+                              void *stream) {
+    if (!range_ok(ctx, first, count) || !d_K_hat || !d_spread || !d_K_in || !d_flags || !(tol > 0.0) ||
+        !std::isfinite(tol))
+        return SHMM_EINVAL;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    return launch_chain_gate(ctx->d_table, first, count, d_K_hat, d_spread, d_K_in, tol, d_flags,
+                             (hipStream_t)stream);
+}
+
 int shmm_feature_stats(shmm_ctx *ctx, const float *d_x, int64_t B, double *d_stats, void *stream) {
     if (!ctx || !d_x || !d_stats || B < 2) return SHMM_EINVAL;
     int rc = set_device(ctx);

@@ -126,6 +126,8 @@ int surrogate_infer(const void *models, int32_t E, const float *x, const double 
                     double *spread, double *K_members, void *work, hipStream_t s);
 
 int launch_feature_stats(const float *x, int64_t B, double *stats, hipStream_t s);
+int launch_chain_gate(const shmm_domain *dom, int64_t first, int64_t count, const double *K_hat, const double *spread,
+                      const double *K_in, double tol, uint8_t *flags, hipStream_t s);
 int launch_surrogate_rescale(const float *x, const double *Kb, const double *K, const double *log10c, int64_t B,
                              float *xo, double *Kbo, double *Ko, hipStream_t s);
 

@@ -12,7 +12,6 @@ namespace shmm {
 
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {   // round to nearest, ties to even
@@ -129,6 +128,17 @@ __global__ __launch_bounds__(256) void k_feat_bins(const shmm_domain *dom, const
         features[(int64_t)li * SHMM_SURR_IN + threadIdx.x] = logf(E[threadIdx.x] + floor) - (float)logdet;
     }
     if (threadIdx.x == SHMM_SURR_BINS) features[(int64_t)li * SHMM_SURR_IN + SHMM_SURR_BINS] = (float)(0.5 * logdet);
+    if (threadIdx.x == SHMM_SURR_BINS + 1) {
+        // anisotropy of the base: the traceless part of log K_b, whose (1,1)
+        // and (1,2) entries are g(rho) q / m and g(rho) K12 / m with m the mean
+        // and r the half gap of the eigenvalues, rho = r / m, g = atanh(rho) / rho
+        const double k11 = Kb[3 * d], k12 = Kb[3 * d + 1], k22 = Kb[3 * d + 2];
+        const double m = 0.5 * (k11 + k22), q = 0.5 * (k11 - k22);
+        const double rho = sqrt(q * q + k12 * k12) / m;
+        const double g = rho < 1e-4 ? 1.0 + rho * rho / 3.0 : atanh(rho) / rho;
+        features[(int64_t)li * SHMM_SURR_IN + SHMM_SURR_BINS + 1] = (float)(g * q / m);
+        features[(int64_t)li * SHMM_SURR_IN + SHMM_SURR_BINS + 2] = (float)(g * k12 / m);
+    }
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -153,16 +163,83 @@ struct GemmArgs {
     int kchunk;            // K per slice when split
 };
 
-constexpr int TM = 64, TN = 64, TK = 32, PADK = 8;
+constexpr int TM = 64, TN = 64, TK = 64, LDK = TK + 8;   // LDS row pitch 144 B (16-byte aligned rows)
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// How a workgroup stages one operand tile from global memory: element by
+// element (any strides), or 16-byte vectors of 8 elements along the
+// operand's contiguous dimension (K, or M / N), when that dimension has unit
+// stride, the other stride is a multiple of 8 and the base is 16-byte aligned.
+enum { LD_SCALAR = 0, LD_VEC_K = 1, LD_VEC_MN = 2 };
+
+// Tile [rows][TK] of an operand X with X(r, k) at base[r * sr + k * sk],
+// stored to LDS as dst[r][k] (row pitch LDK) for rows r0 + [0, 64) < R and
+// k in [k0, k0 + TK) within [k0, kend); zero elsewhere.  256 threads.
+template <int MODE>
+__device__ __forceinline__ void stage_tile(uint16_t (*dst)[LDK], const uint16_t *__restrict__ base, int64_t sr,
+                                           int64_t sk, int r0, int R, int k0, int kend) {
+    const int t = threadIdx.x;
+    if constexpr (MODE == LD_VEC_K) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int idx = t + 256 * j;
+            const int r = idx >> 3, kk = (idx & 7) * 8;
+            const int gr = r0 + r, gk = k0 + kk;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (gr < R && gk + 7 < kend) {
+                v = *reinterpret_cast<const uint4 *>(base + gr * sr + gk);
+            } else if (gr < R) {
+                uint16_t e[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) e[i] = gk + i < kend ? base[gr * sr + gk + i] : (uint16_t)0;
+                v.x = e[0] | ((uint32_t)e[1] << 16);
+                v.y = e[2] | ((uint32_t)e[3] << 16);
+                v.z = e[4] | ((uint32_t)e[5] << 16);
+                v.w = e[6] | ((uint32_t)e[7] << 16);
+            }
+            *reinterpret_cast<uint4 *>(&dst[r][kk]) = v;
+        }
+    } else if constexpr (MODE == LD_VEC_MN) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int idx = t + 256 * j;
+            const int k = idx >> 3, rr = (idx & 7) * 8;
+            const int gk = k0 + k, gr = r0 + rr;
+            uint16_t e[8];
+            if (gk < kend && gr + 7 < R) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(base + gk * sk + gr);
+                e[0] = (uint16_t)v.x; e[1] = (uint16_t)(v.x >> 16);
+                e[2] = (uint16_t)v.y; e[3] = (uint16_t)(v.y >> 16);
+                e[4] = (uint16_t)v.z; e[5] = (uint16_t)(v.z >> 16);
+                e[6] = (uint16_t)v.w; e[7] = (uint16_t)(v.w >> 16);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) e[i] = (gk < kend && gr + i < R) ? base[gk * sk + gr + i] : (uint16_t)0;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) dst[rr + i][k] = e[i];
+        }
+    } else {
+        for (int idx = t; idx < 64 * TK; idx += 256) {
+            const int r = idx / TK, k = idx - r * TK;
+            const int gr = r0 + r, gk = k0 + k;
+            dst[r][k] = (gr < R && gk < kend) ? base[gr * sr + gk * sk] : (uint16_t)0;
+        }
+    }
+}
 
 // C[M][N] = A[M][K] B[K][N]: BF16 operands from arbitrary strides, FP32
-// accumulation on v_mfma_f32_16x16x16bf16_1k.  64 x 64 tile per workgroup,
-// four wavefronts of 32 x 32 (2 x 2 matrix-core tiles).  Operand layout of the
-// 16x16x16 instruction: lane l holds A[l % 16][4 (l / 16) + i] and
-// B[4 (l / 16) + i][l % 16], i < 4, and receives D[4 (l / 16) + i][l % 16].
+// accumulation on gfx950's v_mfma_f32_16x16x32_bf16.  64 x 64 tile per
+// workgroup, four wavefronts of 32 x 32 (2 x 2 matrix-core tiles), K in steps
+// of 64 staged through LDS (A as [m][k], B as [n][k]: k contiguous, so each
+// lane's 8 operand elements are one 16-byte LDS read).  Operand layout of the
+// 16x16x32 instruction: lane l holds A[l % 16][8 (l / 16) + i] and
+// B[8 (l / 16) + i][l % 16], i < 8, and receives D[4 (l / 16) + r][l % 16], r < 4.
+template <int MA, int MB>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
-    __shared__ uint16_t As[TM][TK + PADK];
-    __shared__ uint16_t Bt[TN][TK + PADK];   // B stored transposed: k contiguous
+    __shared__ __align__(16) uint16_t As[TM][LDK];
+    __shared__ __align__(16) uint16_t Bt[TN][LDK];
     const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -172,29 +249,23 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     for (int k0 = kbeg; k0 < kend; k0 += TK) {
-        for (int t = threadIdx.x; t < TM * TK; t += blockDim.x) {
-            const int m = t / TK, k = t - m * TK;
-            const int gm = m0 + m, gk = k0 + k;
-            As[m][k] = (gm < g.M && gk < kend) ? g.A[gm * g.sam + gk * g.sak] : (uint16_t)0;
-        }
-        for (int t = threadIdx.x; t < TN * TK; t += blockDim.x) {
-            const int nn = t / TK, k = t - nn * TK;
-            const int gn = n0 + nn, gk = k0 + k;
-            Bt[nn][k] = (gn < g.N && gk < kend) ? g.B[gk * g.sbk + gn * g.sbn] : (uint16_t)0;
-        }
+        stage_tile<MA>(As, g.A, g.sam, g.sak, m0, g.M, k0, kend);
+        stage_tile<MB>(Bt, g.B, g.sbn, g.sbk, n0, g.N, k0, kend);
         __syncthreads();
-        for (int kk = 0; kk < TK; kk += 16) {
-            const int kq = kk + 4 * (lane >> 4);
-            bf16x4 a[2], b[2];
+#pragma unroll
+        for (int kk = 0; kk < TK; kk += 32) {
+            const int kq = kk + 8 * (lane >> 4);
+            bf16x8 a[2], b[2];
+#pragma unroll
             for (int i = 0; i < 2; ++i) {
-                const uint16_t *pa = &As[wm * 32 + i * 16 + (lane & 15)][kq];
-                a[i] = bf16x4{(short)pa[0], (short)pa[1], (short)pa[2], (short)pa[3]};
-                const uint16_t *pb = &Bt[wn * 32 + i * 16 + (lane & 15)][kq];
-                b[i] = bf16x4{(short)pb[0], (short)pb[1], (short)pb[2], (short)pb[3]};
+                a[i] = *reinterpret_cast<const bf16x8 *>(&As[wm * 32 + i * 16 + (lane & 15)][kq]);
+                b[i] = *reinterpret_cast<const bf16x8 *>(&Bt[wn * 32 + i * 16 + (lane & 15)][kq]);
             }
+#pragma unroll
             for (int i = 0; i < 2; ++i)
+#pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
@@ -216,6 +287,32 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
             }
 }
 
+// staging mode of an operand with X(r, k) at base[r * sr + k * sk] (host side)
+int load_mode(const uint16_t *base, int64_t sr, int64_t sk) {
+    if (((uintptr_t)base & 15) != 0) return LD_SCALAR;
+    if (sk == 1 && sr % 8 == 0) return LD_VEC_K;
+    if (sr == 1 && sk % 8 == 0) return LD_VEC_MN;
+    return LD_SCALAR;
+}
+
+template <int MA>
+void launch_gemm_b(int mb, dim3 grid, const GemmArgs &g, hipStream_t s) {
+    switch (mb) {
+        case LD_VEC_K: hipLaunchKernelGGL((k_gemm_bf16<MA, LD_VEC_K>), grid, dim3(256), 0, s, g); break;
+        case LD_VEC_MN: hipLaunchKernelGGL((k_gemm_bf16<MA, LD_VEC_MN>), grid, dim3(256), 0, s, g); break;
+        default: hipLaunchKernelGGL((k_gemm_bf16<MA, LD_SCALAR>), grid, dim3(256), 0, s, g); break;
+    }
+}
+
+void launch_gemm_kernel(dim3 grid, const GemmArgs &g, hipStream_t s) {
+    const int ma = load_mode(g.A, g.sam, g.sak), mb = load_mode(g.B, g.sbn, g.sbk);
+    switch (ma) {
+        case LD_VEC_K: launch_gemm_b<LD_VEC_K>(mb, grid, g, s); break;
+        case LD_VEC_MN: launch_gemm_b<LD_VEC_MN>(mb, grid, g, s); break;
+        default: launch_gemm_b<LD_SCALAR>(mb, grid, g, s); break;
+    }
+}
+
 // out[r][c] = sum over the slices z = 0, 1, ... of partial[z][r][c], in that order.
 __global__ void k_splitk_sum(const float *partial, int slices, int M, int N, float *out, int64_t ldo) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -227,17 +324,18 @@ __global__ void k_splitk_sum(const float *partial, int slices, int M, int N, flo
 }
 
 constexpr int kSplitSlices = 16;   // K slices of the weight-gradient products
+constexpr int kSplitMinK = 2048;   // split K from this length on (few output tiles)
 
 int gemm(GemmArgs g, hipStream_t s, float *split_work = nullptr) {
     if (g.M <= 0 || g.N <= 0) return SHMM_OK;
     const dim3 tiles((unsigned)((g.N + TN - 1) / TN), (unsigned)((g.M + TM - 1) / TM));
     // few output tiles over a long K (weight gradients: K = batch): split K
     // into slices, then add the slices in a fixed order
-    if (split_work && g.epi == EPI_F32 && tiles.x * tiles.y < 64 && g.K >= 4 * TK * kSplitSlices) {
+    if (split_work && g.epi == EPI_F32 && tiles.x * tiles.y < 64 && g.K >= kSplitMinK) {
         g.kchunk = (g.K / kSplitSlices + TK - 1) / TK * TK;
         const int slices = (g.K + g.kchunk - 1) / g.kchunk;
         g.partial = split_work;
-        hipLaunchKernelGGL(k_gemm_bf16, dim3(tiles.x, tiles.y, (unsigned)slices), dim3(256), 0, s, g);
+        launch_gemm_kernel(dim3(tiles.x, tiles.y, (unsigned)slices), g, s);
         SHMM_HIP_CHECK(hipGetLastError());
         const int64_t cnt = (int64_t)g.M * g.N;
         hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
@@ -247,7 +345,7 @@ int gemm(GemmArgs g, hipStream_t s, float *split_work = nullptr) {
     }
     g.partial = nullptr;
     g.kchunk = 0;
-    hipLaunchKernelGGL(k_gemm_bf16, tiles, dim3(256), 0, s, g);
+    launch_gemm_kernel(tiles, g, s);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
 }
@@ -769,6 +867,39 @@ __global__ void k_rescale(const float *__restrict__ x, const double *__restrict_
 }
 
 }  // namespace
+
+namespace {
+
+// Chain-aware gate (the surrogate inside Algorithm 3): a finer level's result
+// enters its parent's base K_net = K_star - K_off + K_in after K_off is
+// subtracted, so its absolute error must stay well below the parent's K_in.
+// Flags domain d when spread_d |K_hat_d|_F (the ensemble's largest member
+// deviation, absolute) exceeds tol lambda_min(K_in of d's parent); domains
+// without a parent keep their flag.
+__global__ void k_chain_gate(const shmm_domain *__restrict__ dom, int64_t first, int64_t count,
+                             const double *__restrict__ K_hat, const double *__restrict__ spread,
+                             const double *__restrict__ K_in, double tol, uint8_t *__restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int32_t parent = dom[first + i].parent;
+    if (parent < 0) return;
+    const double *k = K_hat + 3 * i, *kp = K_in + 3 * (int64_t)parent;
+    const double fro = sqrt(k[0] * k[0] + 2.0 * k[1] * k[1] + k[2] * k[2]);
+    const double m = 0.5 * (kp[0] + kp[2]), q = 0.5 * (kp[0] - kp[2]);
+    const double lam = m - sqrt(q * q + kp[1] * kp[1]);
+    if (!(spread[i] * fro <= tol * lam)) flags[i] = 1;
+}
+
+}  // namespace
+
+int launch_chain_gate(const shmm_domain *dom, int64_t first, int64_t count, const double *K_hat, const double *spread,
+                      const double *K_in, double tol, uint8_t *flags, hipStream_t s) {
+    if (count <= 0) return SHMM_OK;
+    hipLaunchKernelGGL(k_chain_gate, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, dom, first, count, K_hat,
+                       spread, K_in, tol, flags);
+    SHMM_HIP_CHECK(hipGetLastError());
+    return SHMM_OK;
+}
 
 int launch_feature_stats(const float *x, int64_t B, double *stats, hipStream_t s) {
     hipLaunchKernelGGL(k_feature_stats, dim3(SHMM_SURR_IN), dim3(256), 0, s, x, B, stats);

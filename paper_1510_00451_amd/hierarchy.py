@@ -91,6 +91,10 @@ class Hierarchy:
         self.graph_solves = False
         self._graphs = {}
         self._graph_seen = set()
+        # learned surrogate in place of the planned local solves (see
+        # use_surrogate); per-phase flags of the patches it sent to the plain solve
+        self.surrogate = None
+        self.surrogate_flags = {}
 
     # -- pieces -------------------------------------------------------------
     def stream(self) -> int:
@@ -132,6 +136,49 @@ class Hierarchy:
             self.ctx.shmm_level_chain(first, count, MODE_TOPDOWN, self.lines.data_ptr(),
                                       self.K_in.data_ptr(), self.K_off.data_ptr(), stream=s)
 
+    def use_surrogate(self, models_ptr: int, E: int, lo, hi, tau: float, emax: float,
+                      chain_tol: Optional[float] = None) -> None:
+        """Replace every phase's planned local solves by the ensemble surrogate
+        (shmm_patch_features, shmm_surrogate_infer) with the plain solve as
+        its fallback for the flagged patches (shmm_fallback_solve); the bases
+        are the level chain's own (Algorithm 3), anisotropic in general.
+        models_ptr: E members back to back (device); lo, hi: device [35]
+        feature range of the gate.  chain_tol: also flag a patch whose
+        ensemble spread, in absolute terms, exceeds chain_tol times the
+        smallest eigenvalue of its parent's K_in (shmm_surrogate_chain_gate:
+        the accuracy Algorithm 3 needs of a finer result, which enters the
+        parent's base after K_off is subtracted)."""
+        torch = self.torch
+        self.surrogate = (models_ptr, E, lo, hi, tau, emax, chain_tol)
+        self._x = torch.zeros(self.nd, abi.SURR_IN, dtype=torch.float32, device=self.device)
+        self._flags = torch.zeros(self.nd, dtype=torch.uint8, device=self.device)
+        self._spread = torch.zeros(self.nd, dtype=torch.float64, device=self.device)
+
+    def _surrogate_phase(self, first: int, count: int, s: int) -> None:
+        c = self.ctx
+        models, E, lo, hi, tau, emax, chain_tol = self.surrogate
+        t = c.shmm_ctx_table()[0]
+        if np.any(t["nsteps"][first:first + count] == 0):
+            raise NotImplementedError("a phase with an empty diagonal band: its exact result is the base")
+        n = t["n"]
+        i = first
+        while i < first + count:          # features: runs of one patch size
+            j = i
+            while j < first + count and n[j] == n[i]:
+                j += 1
+            c.shmm_patch_features(i, j - i, self.vx.data_ptr(), self.vy.data_ptr(), self.K_base.data_ptr(),
+                                  self._x[i].data_ptr(), s)
+            i = j
+        c.shmm_surrogate_infer(models, E, self._x[first].data_ptr(), self.K_base[first].data_ptr(), count,
+                               lo.data_ptr(), hi.data_ptr(), tau, emax, self.K_solve[first].data_ptr(),
+                               self._flags[first].data_ptr(), self._spread[first].data_ptr(), 0, s)
+        if chain_tol is not None:
+            c.shmm_surrogate_chain_gate(first, count, self.K_solve[first].data_ptr(), self._spread[first].data_ptr(),
+                                        self.K_in.data_ptr(), chain_tol, self._flags[first].data_ptr(), s)
+        c.shmm_fallback_solve(first, count, self._flags[first].data_ptr(), self.vx.data_ptr(), self.vy.data_ptr(),
+                              self.f1.data_ptr(), self.f2.data_ptr(), self.K_base.data_ptr(), self.w.data_ptr(),
+                              self.K_solve.data_ptr(), 0, 0.0, self.status.data_ptr(), s)
+
     def phase_solve(self, p: int, steps: Optional[int] = None, adaptive: bool = False) -> None:
         s = self.stream()
         first, count = int(self.phase[p]), int(self.phase[p + 1] - self.phase[p])
@@ -144,6 +191,13 @@ class Hierarchy:
         c.shmm_plan_steps(first, count, self.host_K)
         a, b = self.cell_range(first, count)
         self.w.view(2, self.cells)[:, a:b].zero_()
+        if self.surrogate is not None and steps is None and not adaptive:
+            self._surrogate_phase(first, count, s)
+            self.surrogate_flags[p] = self._flags[first:first + count].cpu().numpy().copy()
+            c.shmm_level_chain(first, count, MODE_RESULT, self.lines.data_ptr(), self.K_in.data_ptr(),
+                               self.K_off.data_ptr(), self.K_base.data_ptr(), self.K_solve.data_ptr(),
+                               self.R.data_ptr(), self.status.data_ptr(), s)
+            return
         def launch():
             if adaptive:
                 # quasi-stationary stop (plans cut to the steps taken)

@@ -124,7 +124,7 @@ class Ensemble:
 
 @dataclass
 class Dataset:
-    x: "object"        # torch float32 [S][33] on device
+    x: "object"        # torch float32 [S][35] on device
     Kb: "object"       # torch float64 [S][3]
     K: "object"        # torch float64 [S][3]
 
@@ -333,6 +333,41 @@ def labelled_set(problem_batches, log=None, adaptive: bool = False) -> Dataset:
     return Dataset(torch.cat(xs), torch.cat(kbs), torch.cat(ks))
 
 
+def chained_set(problem_batches, log=None, adaptive: bool = True) -> Dataset:
+    """Features and plain-path labels of every level's patches of whole
+    hierarchy passes (Algorithm 3 bases: the finest level's from the
+    off-diagonal chain above it, the coarser levels' from K_star - K_off +
+    K_in; anisotropic in general), one pass per batch of flows, the local
+    solves stopped at the quasi-stationary test when `adaptive`.  Patches with
+    an empty diagonal band (their result is the base) are left out."""
+    from .hierarchy import Hierarchy
+    torch = _torch()
+    xs, kbs, ks = [], [], []
+    for i, probs in enumerate(problem_batches):
+        H = Hierarchy(probs)
+        H.run(adaptive=adaptive)
+        x = torch.zeros(H.nd, abi.SURR_IN, dtype=torch.float32, device=H.device)
+        t = H.ctx.shmm_ctx_table()[0]
+        n = t["n"]
+        d = 0
+        while d < H.nd:                    # runs of one patch size
+            e = d
+            while e < H.nd and n[e] == n[d]:
+                e += 1
+            H.ctx.shmm_patch_features(d, e - d, H.vx.data_ptr(), H.vy.data_ptr(), H.K_base.data_ptr(),
+                                      x[d].data_ptr(), H.stream())
+            d = e
+        act = torch.from_numpy(np.flatnonzero(t["nsteps"] > 0)).to(H.device)
+        xs.append(x.index_select(0, act))
+        kbs.append(H.K_base.index_select(0, act))
+        ks.append(H.K_solve.index_select(0, act))
+        torch.cuda.synchronize()
+        H.close()
+        if log is not None:
+            log(f"chained labels: batch {i}, {sum(len(v) for v in xs)} patches")
+    return Dataset(torch.cat(xs), torch.cat(kbs), torch.cat(ks))
+
+
 def split(data: Dataset, frac: float, seed: int):
     """(held-out, rest) by a seeded permutation."""
     torch = _torch()
@@ -344,7 +379,7 @@ def split(data: Dataset, frac: float, seed: int):
 
 
 def feature_stats(ctx: abi.Context, x):
-    """(mean, std, min, max) of every feature column of x [S][33] (device),
+    """(mean, std, min, max) of every feature column of x [S][35] (device),
     FP64 host arrays, from shmm_feature_stats."""
     torch = _torch()
     st = torch.empty(4, abi.SURR_IN, dtype=torch.float64, device=x.device)

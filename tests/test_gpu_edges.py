@@ -45,12 +45,12 @@ def test_empty_ranges_are_no_ops(torch):
     for mode in (0, 1, 2):
         c.shmm_level_chain(0, 0, mode, H.lines.data_ptr(), H.K_in.data_ptr(), H.K_off.data_ptr(),
                            H.K_base.data_ptr(), H.K_solve.data_ptr(), H.R.data_ptr(), 0, s)
-    x = torch.zeros(1, 33, dtype=torch.float32, device="cuda")
+    x = torch.zeros(1, abi.SURR_IN, dtype=torch.float32, device="cuda")
     c.shmm_patch_features(0, 0, H.vx.data_ptr(), H.vy.data_ptr(), H.K_base.data_ptr(), x.data_ptr(), s)
-    ens = GS.Ensemble(c, 1, np.zeros(33), np.ones(33))
+    ens = GS.Ensemble(c, 1, np.zeros(abi.SURR_IN), np.ones(abi.SURR_IN))
     K = torch.full((1, 3), -1.0, dtype=torch.float64, device="cuda")
     flags = torch.full((1,), 7, dtype=torch.uint8, device="cuda")
-    lo = torch.zeros(33, dtype=torch.float32, device="cuda")
+    lo = torch.zeros(abi.SURR_IN, dtype=torch.float32, device="cuda")
     c.shmm_surrogate_infer(ens.buf.data_ptr(), 1, x.data_ptr(), H.K_base.data_ptr(), 0, lo.data_ptr(),
                            lo.data_ptr(), 0.1, 1.0, K.data_ptr(), flags.data_ptr(), 0, 0, s)
     c.shmm_fallback_solve(0, 0, flags.data_ptr(), H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(),

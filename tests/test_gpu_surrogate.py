@@ -18,6 +18,7 @@ import flowgen
 import oracle
 from oracle import DIAG
 from oracle import surrogate as OS
+from paper_1510_00451_amd import abi
 
 pytestmark = pytest.mark.gpu
 
@@ -53,7 +54,7 @@ def test_patch_features_parity(torch, n):
     Kb = np.stack([rng.uniform(0.01, 0.1, H.nd), rng.uniform(-0.003, 0.003, H.nd),
                    rng.uniform(0.01, 0.1, H.nd)], 1)
     H.K_base.copy_(torch.from_numpy(Kb))
-    feats = torch.zeros(H.nd, 33, dtype=torch.float32, device="cuda")
+    feats = torch.zeros(H.nd, abi.SURR_IN, dtype=torch.float32, device="cuda")
     H.ctx.shmm_patch_features(0, H.nd, H.vx.data_ptr(), H.vy.data_ptr(), H.K_base.data_ptr(),
                               feats.data_ptr(), H.stream())
     torch.cuda.synchronize()
@@ -73,8 +74,8 @@ def _random_member(seed, rng):
     net = OS.init_net(seed)
     for l in range(4):
         net.b[l] = rng.standard_normal(net.b[l].shape) * 0.05
-    net.mu = rng.standard_normal(33)
-    net.sigma = rng.uniform(0.5, 2.0, 33)
+    net.mu = rng.standard_normal(abi.SURR_IN)
+    net.sigma = rng.uniform(0.5, 2.0, abi.SURR_IN)
     return net
 
 
@@ -99,10 +100,10 @@ def test_inference_and_gate_parity(torch):
     rng = np.random.default_rng(7)
     nets = [_to32(_random_member(s, rng)) for s in (11, 12)]
     B = 200                                  # not a multiple of the 64-row tile
-    x = rng.standard_normal((B, 33)).astype(np.float32).astype(np.float64)
+    x = rng.standard_normal((B, abi.SURR_IN)).astype(np.float32).astype(np.float64)
     Kb = np.stack([rng.uniform(0.01, 0.1, B), rng.uniform(-0.003, 0.003, B), rng.uniform(0.01, 0.1, B)], 1)
-    lo = np.full(33, -3.5, np.float32)
-    hi = np.full(33, 3.5, np.float32)
+    lo = np.full(abi.SURR_IN, -3.5, np.float32)
+    hi = np.full(abi.SURR_IN, 3.5, np.float32)
     say("case inference")
     ctx = abi.Context(0)
     models = _pack(torch, nets)
@@ -150,7 +151,7 @@ def test_train_step_parity(torch, B):
     from paper_1510_00451_amd import abi
     rng = np.random.default_rng(5)
     net = _to32(_random_member(21, rng))
-    x = rng.standard_normal((B, 33)).astype(np.float32).astype(np.float64)
+    x = rng.standard_normal((B, abi.SURR_IN)).astype(np.float32).astype(np.float64)
     Kb = np.stack([rng.uniform(0.01, 0.1, B), rng.uniform(-0.003, 0.003, B), rng.uniform(0.01, 0.1, B)], 1)
     Kt = Kb * rng.uniform(1.0, 2.5, (B, 1))
     say("case train step, B =", B)
@@ -273,18 +274,18 @@ def test_training_reduces_loss(torch):
     from paper_1510_00451_amd import surrogate as GS
     rng = np.random.default_rng(9)
     S = 2048
-    x = rng.standard_normal((S, 33))
+    x = rng.standard_normal((S, abi.SURR_IN))
     Kb = np.tile([0.02, 0.0, 0.02], (S, 1))
     enh = 1.5 + 0.5 * np.tanh(x[:, 0]) + 0.2 * x[:, 1] ** 2     # K >= K_b, as the head requires
     Kt = Kb * enh[:, None]
     say("case training")
     ctx = abi.Context(0)
-    ens = GS.Ensemble(ctx, 1, np.zeros(33), np.ones(33), seed0=3)
+    ens = GS.Ensemble(ctx, 1, np.zeros(abi.SURR_IN), np.ones(abi.SURR_IN), seed0=3)
     data = GS.Dataset(torch.tensor(x, dtype=torch.float32, device="cuda"), torch.tensor(Kb, device="cuda"),
                       torch.tensor(Kt, device="cuda"))
     hist = GS.train(ens, data, steps=300, batch=256, lr0=3e-3, log=lambda *a: None, clip=1.0)
-    K, flags, spread = GS.infer(ens, data.x, data.Kb, torch.full((33,), -1e9, device="cuda"),
-                                torch.full((33,), 1e9, device="cuda"), 1.0)
+    K, flags, spread = GS.infer(ens, data.x, data.Kb, torch.full((abi.SURR_IN,), -1e9, device="cuda"),
+                                torch.full((abi.SURR_IN,), 1e9, device="cuda"), 1.0)
     torch.cuda.synchronize()
     err = np.abs(K.cpu().numpy()[:, 0] - Kt[:, 0]) / Kt[:, 0]
     assert np.median(err) < 0.02, np.median(err)
@@ -303,9 +304,9 @@ def test_surrogate_form_gates_and_falls_back(torch):
     ph.prepare()
     plain = ph.plain().cpu().numpy().copy()
     ctx = abi.Context(0)
-    ens = GS.Ensemble(ctx, 2, np.zeros(33), np.ones(33), seed0=4)
-    wide_lo = torch.full((33,), -1e30, dtype=torch.float32, device="cuda")
-    wide_hi = torch.full((33,), 1e30, dtype=torch.float32, device="cuda")
+    ens = GS.Ensemble(ctx, 2, np.zeros(abi.SURR_IN), np.ones(abi.SURR_IN), seed0=4)
+    wide_lo = torch.full((abi.SURR_IN,), -1e30, dtype=torch.float32, device="cuda")
+    wide_hi = torch.full((abi.SURR_IN,), 1e30, dtype=torch.float32, device="cuda")
     K_all = ph.surrogate(ens, wide_lo, wide_hi, -1.0).cpu().numpy().copy()
     assert ph.flags.cpu().numpy().all()
     assert np.array_equal(K_all, plain)
@@ -326,17 +327,17 @@ def test_ensemble_prune_drops_a_member_that_failed(torch):
     from paper_1510_00451_amd import surrogate as GS
     rng = np.random.default_rng(12)
     S = 1024
-    x = rng.standard_normal((S, 33))
+    x = rng.standard_normal((S, abi.SURR_IN))
     Kb = np.tile([0.02, 0.0, 0.02], (S, 1))
     Kt = Kb * (1.5 + 0.5 * np.tanh(x[:, :1]))
     say("case prune")
     ctx = abi.Context(0)
-    ens = GS.Ensemble(ctx, 3, np.zeros(33), np.ones(33), seed0=5)
+    ens = GS.Ensemble(ctx, 3, np.zeros(abi.SURR_IN), np.ones(abi.SURR_IN), seed0=5)
     data = GS.Dataset(torch.tensor(x, dtype=torch.float32, device="cuda"), torch.tensor(Kb, device="cuda"),
                       torch.tensor(Kt, device="cuda"))
     GS.train(ens, data, steps=200, batch=256, lr0=3e-3)
     words = abi.SURR_MODEL_BYTES // 4
-    fresh = GS.Ensemble(ctx, 1, np.zeros(33), np.ones(33), seed0=99)
+    fresh = GS.Ensemble(ctx, 1, np.zeros(abi.SURR_IN), np.ones(abi.SURR_IN), seed0=99)
     ens.buf[words:2 * words] = fresh.buf        # member 1 reverts to untrained weights
     keep0, keep2 = ens.buf[:words].clone(), ens.buf[2 * words:].clone()
     losses = ens.prune(data)
@@ -353,12 +354,12 @@ def test_feature_stats_and_rescale(torch):
     from paper_1510_00451_amd import abi
     rng = np.random.default_rng(9)
     B = 5000
-    x = (rng.standard_normal((B, 33)) * rng.uniform(0.1, 3.0, 33) + rng.uniform(-5, 5, 33)).astype(np.float32)
+    x = (rng.standard_normal((B, abi.SURR_IN)) * rng.uniform(0.1, 3.0, abi.SURR_IN) + rng.uniform(-5, 5, abi.SURR_IN)).astype(np.float32)
     say("case feature statistics and rescaling")
     ctx = abi.Context(0)
     s = torch.cuda.current_stream().cuda_stream
     dx = torch.tensor(x, device="cuda")
-    st = torch.empty(4, 33, dtype=torch.float64, device="cuda")
+    st = torch.empty(4, abi.SURR_IN, dtype=torch.float64, device="cuda")
     ctx.shmm_feature_stats(dx.data_ptr(), B, st.data_ptr(), s)
     torch.cuda.synchronize()
     got = st.cpu().numpy()
@@ -385,3 +386,50 @@ def test_feature_stats_and_rescale(torch):
     assert np.array_equal(xg[:, :32], x[:, :32])
     np.testing.assert_allclose(xg[:, 32], x[:, 32].astype(np.float64) + np.log(c), rtol=0, atol=2e-6)
     ctx.close()
+
+
+def test_surrogate_through_every_level(torch):
+    """The surrogate in place of every phase's local solves (Hierarchy.use_surrogate):
+    with a gate that flags every patch the pass is the plain pass bit for bit
+    (the fallback runs the same solves and moments); with a gate that flags
+    none, every level result follows the network on the chain's own bases."""
+    from paper_1510_00451_amd import surrogate as GS
+    from paper_1510_00451_amd.hierarchy import Hierarchy
+    p = flowgen.config_four_level_cellular(n=16, lattice=2)
+    say("case surrogate through every level")
+    H = Hierarchy(p, keep_psi=False)
+    H.run()
+    plain = H.result()
+    ens = GS.Ensemble(H.ctx, 2, np.zeros(abi.SURR_IN), np.ones(abi.SURR_IN), seed0=7)
+    big = torch.full((abi.SURR_IN,), 1e30, dtype=torch.float32, device="cuda")
+    H.use_surrogate(ens.buf.data_ptr(), ens.E, big, big, 1.0, float("inf"))
+    H.run()
+    r = H.result()
+    assert np.array_equal(r.R, plain.R)
+    assert all(f.all() for f in H.surrogate_flags.values()) and len(H.surrogate_flags) == 4
+    H.use_surrogate(ens.buf.data_ptr(), ens.E, -big, big, float("inf"), float("inf"))
+    H.run()
+    r = H.result()
+    assert not any(f.any() for f in H.surrogate_flags.values())
+    assert np.isfinite(r.R).all() and not np.array_equal(r.R, plain.R)
+    # the chain-aware gate with a vanishing tolerance sends every patch that
+    # has a parent to the plain solve and leaves the coarsest level alone
+    H.use_surrogate(ens.buf.data_ptr(), ens.E, -big, big, float("inf"), float("inf"), chain_tol=1e-300)
+    H.run()
+    lev = H.table["level"]
+    for p_, f in H.surrogate_flags.items():
+        assert f.all() == (lev[int(H.phase[p_])] > 0) and f.any() == (lev[int(H.phase[p_])] > 0), p_
+    # ... and with a huge one it flags nothing
+    H.use_surrogate(ens.buf.data_ptr(), ens.E, -big, big, float("inf"), float("inf"), chain_tol=1e300)
+    H.run()
+    r = H.result()
+    assert not any(f.any() for f in H.surrogate_flags.values())
+    # the finest phase's estimates are the ensemble's on its features and bases
+    first, count = int(H.phase[0]), int(H.phase[1] - H.phase[0])
+    x = torch.zeros(count, abi.SURR_IN, dtype=torch.float32, device="cuda")
+    H.ctx.shmm_patch_features(first, count, H.vx.data_ptr(), H.vy.data_ptr(), H.K_base.data_ptr(), x.data_ptr(),
+                              H.stream())
+    K, flags, _ = GS.infer(ens, x, H.K_base[first:first + count], -big, big, float("inf"), float("inf"))
+    torch.cuda.synchronize()
+    assert np.array_equal(K.cpu().numpy(), r.K_solve[first:first + count])
+    H.close()

@@ -34,10 +34,11 @@ def test_features_single_mode_closed_form():
     Etot = E[0] + E[1]
     fl = 1e-8 * Etot + 1e-30
     det = 0.02 * 0.03 - 0.005 ** 2
-    expect = np.full(33, math.log(fl / det))
+    expect = np.full(S.N_IN, math.log(fl / det))
     for c in range(4):
         expect[8 * c + bq] = math.log((E[c] + fl) / det)
     expect[32] = 0.5 * math.log(det)
+    expect[33:35] = S.log_base_anisotropy(Kb)
     np.testing.assert_allclose(f, expect, rtol=1e-12, atol=1e-12)
 
 
@@ -52,6 +53,35 @@ def test_features_scale_invariance():
     g = S.patch_features(c * vx, c * vy, n, N, c * Kb)
     np.testing.assert_allclose(g[:32], f[:32], rtol=0, atol=1e-12)
     assert abs(g[32] - f[32] - math.log(c)) <= 1e-12
+    np.testing.assert_allclose(g[33:], f[33:], rtol=0, atol=1e-12)
+
+
+def _rot(theta, a, b):
+    c, s = math.cos(theta), math.sin(theta)
+    return [a * c * c + b * s * s, (a - b) * c * s, a * s * s + b * c * c]
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.3, -1.2, math.pi / 2, 2.5])
+def test_base_anisotropy_features_closed_form(theta):
+    """Features 33-34 of a base with eigenvalues a > b along the angle theta:
+    log K_b = R diag(ln a, ln b) R^T, whose traceless part is
+    (1/2) ln(a / b) [[cos 2 theta, sin 2 theta], [sin 2 theta, -cos 2 theta]]."""
+    a, b = 0.07, 0.013
+    t11, t12 = S.log_base_anisotropy(_rot(theta, a, b))
+    h = 0.5 * math.log(a / b)
+    assert abs(t11 - h * math.cos(2 * theta)) <= 1e-14
+    assert abs(t12 - h * math.sin(2 * theta)) <= 1e-14
+
+
+def test_base_anisotropy_features_isotropic_and_scale_free():
+    """An isotropic base gives zero; scaling the base leaves the pair unchanged;
+    exchanging the axes (K11 <-> K22) flips the sign of the first entry."""
+    assert S.log_base_anisotropy([0.02, 0.0, 0.02]) == pytest.approx((0.0, 0.0), abs=1e-15)
+    K = [0.031, -0.004, 0.012]
+    f = np.array(S.log_base_anisotropy(K))
+    np.testing.assert_allclose(S.log_base_anisotropy([9.0 * v for v in K]), f, rtol=0, atol=1e-14)
+    g = np.array(S.log_base_anisotropy([K[2], K[1], K[0]]))
+    np.testing.assert_allclose(g, [-f[0], f[1]], rtol=0, atol=1e-14)
 
 
 def test_features_quadrature_has_no_cross_spectrum():
@@ -103,10 +133,10 @@ def _torch_net(net):
 def test_forward_backward_match_torch_autograd():
     rng = np.random.default_rng(1)
     net = S.init_net(3)
-    net.mu = rng.standard_normal(33)
-    net.sigma = rng.uniform(0.5, 2.0, 33)
+    net.mu = rng.standard_normal(S.N_IN)
+    net.sigma = rng.uniform(0.5, 2.0, S.N_IN)
     B = 7
-    x = rng.standard_normal((B, 33))
+    x = rng.standard_normal((B, S.N_IN))
     Kb = np.stack([rng.uniform(0.01, 0.1, B), rng.uniform(-0.002, 0.002, B), rng.uniform(0.01, 0.1, B)], 1)
     Kt = Kb * rng.uniform(1.0, 3.0, (B, 1))
     o, cache = S.forward(net, x)
