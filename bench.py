@@ -50,7 +50,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (256 CU, 2
 # the scale factors read off a 1 GiB device copy.  Valid only for the kernel
 # code they were taken on (first 16 hex digits of the SHA-256 of solve.hip and
 # solve_stage.h without comments and blank lines); otherwise reported null.
-SOLVE_TRAFFIC = {"code_sha256": None, "variant": 5, "bytes_per_launch": None}
+SOLVE_TRAFFIC = {"code_sha256": "7716f7888ddc9b81", "variant": 5,
+                 "bytes_per_launch": (2 * 50172.5 + 35262.45) * 1024}
 SOLVE_KERNELS_128 = {0: "k_solve_resident<128,32>", 1: "k_solve_rows<128,2,16>", 2: "k_solve_rows<128,2,8>",
                      3: "k_solve_resident_e<128,32>", 4: "k_solve_resident_e<128,16>",
                      5: "k_solve_resident_e<128,32,8>", 6: "k_solve_resident_e<128,32,16>"}
@@ -241,6 +242,213 @@ def surrogate_leg(flows_train: int, flows_eval: int, steps: int = 1500, members:
                   "train_s": round(t_train, 2), "steps": steps, "batch": 4096, "clip": 1.0, "members": members,
                   "members_kept": ens.E, "held_out_member_losses": [round(float(v), 6) for v in member_losses],
                   "final_loss": hist[-1] if hist else None},
+    }
+
+
+def surrogate_chained_leg(plain, plain_pass_s: float, label_flows: int = 32, steps: int = 2000, members: int = 4,
+                          chain_tol: float = 1e-2):
+    """The surrogate through every level of the hierarchy (anisotropic bases,
+    35 inputs): labels from whole passes over uneven-batch flows (seeds
+    100000+, n = 128, 4 x 4 patches per level, every level's patches on the
+    bases the level chain gives them, local solves with the quasi-stationary
+    stop); the same training and gate calibration as the finest-level
+    surrogate; then the five-level continuous-spectrum pass with the
+    surrogate and plain-solve fallback in every phase, against the plain pass
+    of the headline (`plain`, its PassResult, and its time): once with the
+    gate of the finest-level surrogate alone, once with the chain-aware gate
+    as well (shmm_surrogate_chain_gate, chain_tol): pass times, fallback
+    fraction per level and the error of K_total at the 256 centres."""
+    import torch
+    import flowgen
+    from paper_1510_00451_amd import abi
+    from paper_1510_00451_amd import surrogate as GS
+    from paper_1510_00451_amd.hierarchy import Hierarchy
+    from paper_1510_00451_amd import autotune
+    t0 = time.perf_counter()
+    per = 16
+    batches = ([flowgen.config_batched_instance(100000 + i + j, n=128, lattice=4)
+                for j in range(min(per, label_flows - i))] for i in range(0, label_flows, per))
+    data = GS.chained_set(batches, log=log, adaptive=True)
+    t_label = time.perf_counter() - t0
+    held, train = GS.split(data, 0.1, seed=0)
+    rng = np.random.default_rng(1)
+    ctx = abi.Context(0)
+    train = GS.Dataset.concat([train] + [train.rescaled(ctx, rng.uniform(-1.5, 1.5, train.x.shape[0]))
+                                         for _ in range(2)])
+    mu, sg, _, _ = GS.feature_stats(ctx, train.x)
+    ens = GS.Ensemble(ctx, members, mu, sg + 1e-6, seed0=21)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    GS.train(ens, train, steps=steps, batch=4096, lr0=1e-3, seed=6, log=log, clip=1.0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    member_losses = ens.prune(held)
+    lo, hi = GS.gate_range(ctx, train, 0.1)
+    tau, emax, held_acc = GS.calibrate_gate(ens, held, lo, hi)
+    enh_held = GS.relative_frobenius(held.K.cpu().numpy(), held.Kb.cpu().numpy())
+    log(f"chained surrogate: {data.x.shape[0]} labels in {t_label:.1f} s, trained in {t_train:.1f} s, "
+        f"tau {tau}, emax {emax}, held-out accepted {held_acc:.3f}")
+    out = {"labels": int(data.x.shape[0]), "label_flows": label_flows, "label_s": round(t_label, 1),
+           "train_s": round(t_train, 1), "steps": steps, "members_kept": ens.E,
+           "held_out_member_losses": [round(float(v), 6) for v in member_losses],
+           "label_enhancement_median": float(np.median(enh_held)),
+           "tau": tau, "emax": emax if math.isfinite(emax) else None, "held_out_accepted": round(held_acc, 4)}
+    enh = GS.relative_frobenius(plain.K_solve, plain.K_base)
+    out["plain_pass_s"] = round(plain_pass_s, 3)
+    for name, ct in (("gate", None), ("chain_gate", chain_tol)):
+        H = Hierarchy([flowgen.config_continuous(seed=0)], keep_psi=False)
+        autotune.apply_cached(H.ctx, [128])
+        H.use_surrogate(ens.buf.data_ptr(), ens.E, lo, hi, tau, emax, chain_tol=ct)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        H.run()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - a
+        r = H.result()
+        lev = H.ctx.shmm_ctx_table()[0]["level"]
+        err = GS.relative_frobenius(r.K_total, plain.K_total)
+        out[name] = {"chain_tol": ct, "surrogate_pass_s": round(el, 3), "speedup": round(plain_pass_s / el, 3),
+                     "fallback_frac_by_level": {str(int(lev[int(H.phase[p])])): round(float(f.mean()), 4)
+                                                for p, f in sorted(H.surrogate_flags.items())},
+                     "K_total_err_vs_plain": {"mean": float(err.mean()), "p99": float(np.quantile(err, 0.99)),
+                                              "max": float(err.max())}}
+        H.close()
+        log(f"chained surrogate ({name}): {out[name]}")
+    out["workload"] = "continuous-5level-256x128 (kappa 1e-3), every phase"
+    out["enhancement_median_by_level"] = {str(l): float(np.median(enh[lev == l])) for l in sorted(set(lev.tolist()))}
+    ctx.close()
+    return out
+
+
+def _spectra_prefetch(seeds, make, workers: int = 8, ahead: int = 128):
+    """Host spectra of the flows `seeds` (make(seed) -> Problem), generated on a
+    thread pool at most `ahead` flows ahead of use; yields them in order."""
+    from collections import deque
+    from concurrent.futures import ThreadPoolExecutor
+    seeds = list(seeds)
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        window = deque(pool.submit(make, q) for q in seeds[:ahead])
+        nxt = len(window)
+        while window:
+            f = window.popleft()
+            if nxt < len(seeds):
+                window.append(pool.submit(make, seeds[nxt]))
+                nxt += 1
+            yield f.result()
+
+
+def surrogate_full_leg(label_flows: int = 1960, eval_flows: int = 4096, sample_every: int = 64,
+                       steps: int = 6000, members: int = 4, batch_flows: int = 64, label_batch_flows: int = 16,
+                       save: str = ""):
+    """The learned surrogate at its full size: about 500k labels from the
+    uneven-batch generator (finest-level patches of 128^2, 16 x 16 per flow,
+    isotropic base, labels by the plain path with the quasi-stationary stop),
+    an ensemble trained with Adam at batch 4096, and the surrogate-with-
+    fallback form on the 2^20 finest-level patches of 4096 continuous-spectrum
+    flows (seeds 200000-204095).  The plain form runs on every
+    `sample_every`-th flow (a seed-stratified sample): its time gives the plain
+    estimates/s and its K the error of the surrogate form.  The gate is
+    calibrated on held-out labels twice: for the 99th percentile and for the
+    maximum of the accepted errors within 1%; the evaluation runs with the
+    second (stricter) gate and reports the error distribution on the sample."""
+    import torch
+    import flowgen
+    from paper_1510_00451_amd import abi
+    from paper_1510_00451_amd import surrogate as GS
+    lattice = 16
+    t0 = time.perf_counter()
+    label_seeds = list(range(100000, 100000 + label_flows))
+    probs = _spectra_prefetch(label_seeds, lambda q: flowgen.config_batched_instance(q, n=128, lattice=lattice))
+    batches = ([next(probs) for _ in range(min(label_batch_flows, label_flows - i))]
+               for i in range(0, label_flows, label_batch_flows))
+    data = GS.labelled_set(batches, log=log, adaptive=True)
+    t_label = time.perf_counter() - t0
+    log(f"surrogate at size: {data.x.shape[0]} labels in {t_label:.1f} s")
+    held, train = GS.split(data, 0.1, seed=0)
+    rng = np.random.default_rng(1)
+    ctx = abi.Context(0)
+    train = GS.Dataset.concat([train] + [train.rescaled(ctx, rng.uniform(-1.5, 1.5, train.x.shape[0]))
+                                         for _ in range(2)])
+    mu, sg, _, _ = GS.feature_stats(ctx, train.x)
+    ens = GS.Ensemble(ctx, members, mu, sg + 1e-6, seed0=11)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = GS.train(ens, train, steps=steps, batch=4096, lr0=1e-3, seed=5, log=log, clip=1.0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    member_losses = ens.prune(held)
+    lo, hi = GS.gate_range(ctx, train, 0.1)
+    gates = {}
+    for name, q in (("p99", 0.99), ("max", 1.0)):
+        tau, emax, acc = GS.calibrate_gate(ens, held, lo, hi, quantile=q)
+        gates[name] = {"tau": tau, "emax": emax if math.isfinite(emax) else None, "held_out_accepted": round(acc, 4)}
+    tau, emax = gates["max"]["tau"], gates["max"]["emax"] if gates["max"]["emax"] is not None else math.inf
+    log(f"surrogate at size: trained in {t_train:.1f} s, members kept {ens.E}, gates {gates}")
+    if save:   # the trained ensemble and its gate, for the record
+        np.savez_compressed(save, models=ens.buf.cpu().numpy(), E=ens.E, lo=lo.cpu().numpy(), hi=hi.cpu().numpy(),
+                            tau=tau, emax=emax, labels=int(data.x.shape[0]))
+
+    eval_seeds = list(range(200000, 200000 + eval_flows))
+    sampled = [q for q in eval_seeds if (q - 200000) % sample_every == 0]
+    stream = _spectra_prefetch(eval_seeds, lambda q: flowgen.config_continuous(seed=q))
+    t_surr, n_est, n_flag = 0.0, 0, 0
+    Ks_sample = {}
+    for i0 in range(0, eval_flows, batch_flows):
+        seeds = eval_seeds[i0:i0 + batch_flows]
+        ph = GS.IsotropicPhase([next(stream) for _ in seeds])
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        ph.prepare()
+        Ks = ph.surrogate(ens, lo, hi, tau, emax)
+        torch.cuda.synchronize()
+        t_surr += time.perf_counter() - a
+        act = ph.active
+        n_est += int(act.sum())
+        n_flag += int(ph.flags.cpu().numpy()[act].astype(bool).sum())
+        per = ph.count // len(seeds)
+        Ks_h = Ks.cpu().numpy()
+        for j, q in enumerate(seeds):
+            if q in sampled:
+                Ks_sample[q] = (Ks_h[j * per:(j + 1) * per].copy(), act[j * per:(j + 1) * per].copy())
+        ph.close()
+        log(f"surrogate at size: evaluated {i0 + len(seeds)} flows, {n_est} estimates, "
+            f"{t_surr:.1f} s, fallback {n_flag / max(1, n_est):.4f}")
+    # the plain form on the sampled flows, in one phase: its time and its K
+    ph = GS.IsotropicPhase([flowgen.config_continuous(seed=q) for q in sampled])
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    ph.prepare()
+    Kp = ph.plain()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - a
+    n_plain = int(ph.active.sum())
+    Kp_h = Kp.cpu().numpy()
+    per = ph.count // len(sampled)
+    errs = []
+    for j, q in enumerate(sampled):
+        Ksq, actq = Ks_sample[q]
+        assert np.array_equal(actq, ph.active[j * per:(j + 1) * per])
+        errs.append(GS.relative_frobenius(Ksq[actq], Kp_h[j * per:(j + 1) * per][actq]))
+    ph.close()
+    err = np.concatenate(errs)
+    ctx.close()
+    est_s = n_est / t_surr
+    plain_s = n_plain / t_plain
+    return {
+        "workload": f"{eval_flows} continuous-spectrum flows (seeds 200000-{200000 + eval_flows - 1}, kappa 1e-3, "
+                    f"1<=|k|<=512) x 256 finest-level 128^2 patches, isotropic base",
+        "estimates": n_est, "estimates_per_s": round(est_s, 1), "plain_estimates_per_s": round(plain_s, 1),
+        "speedup": round(est_s / plain_s, 2), "fallback_frac": round(n_flag / max(1, n_est), 5),
+        "plain_sample": f"every {sample_every}th flow ({len(sampled)} flows, {n_plain} patches, one phase): "
+                        f"the plain form timed on them, {t_plain:.1f} s",
+        "err_vs_plain": {"mean": float(err.mean()), "p99": float(np.quantile(err, 0.99)), "max": float(err.max()),
+                         "frac_over_1pct": float(np.mean(err > 0.01)), "patches": int(err.size)},
+        "gate": {"used": "max", **gates},
+        "train": {"labels": int(data.x.shape[0]), "flows": label_flows, "label_s": round(t_label, 1),
+                  "train_s": round(t_train, 1), "steps": steps, "batch": 4096, "clip": 1.0, "members": members,
+                  "members_kept": ens.E, "held_out_member_losses": [round(float(v), 6) for v in member_losses],
+                  "final_loss": hist[-1] if hist else None},
+        "eval_s": round(t_surr, 1),
     }
 
 
@@ -452,7 +660,7 @@ def uneven_leg(instances: int, window: int, retune: bool):
     if missing:
         tuned = autotune.tune_solve(H, phase=0, steps=50, repeats=1, sizes=missing)
         autotune.record(tuned, workload=f"uneven batch, {instances} instances, phase 0, 50 steps")
-    variants = {str(n): int(cached.get(n, tuned.get(n, {"variant": -1}))["variant"]) for n in sizes}
+    variants = {str(n): int(cached.get(n, tuned.get(n, {"variant": 0}))["variant"]) for n in sizes}
     cache = autotune.load().get(autotune.arch(), {})
     chunk = cache.get("chunk_uneven")
     if chunk is None or retune:
@@ -473,13 +681,16 @@ def uneven_leg(instances: int, window: int, retune: bool):
     ns = np.minimum(table["nsteps"].astype(np.int64), window)
     pts = int(np.sum(table["n"].astype(np.int64) ** 2 * ns))
     counts = {int(n): int(np.sum(table["n"] == n)) for n in sizes}
+    share = {str(int(n)): round(float(np.sum((table["n"] == n) * table["n"].astype(np.int64) ** 2 * ns)) / pts, 4)
+             for n in sizes}
     full = int(np.sum(table["n"].astype(np.int64) ** 2 * table["nsteps"].astype(np.int64)))
     graphs = len(H._graphs)
     H.close()
     return {"workload": f"uneven batch, {instances} instances (seeds 0-{instances - 1}), every solve capped "
                         f"at {window} steps",
             "gpoint_steps_per_s": round(pts / el / 1e9, 3), "window_s": round(el, 3),
-            "domains_by_n": {str(k): v for k, v in counts.items()}, "autotune_variants": variants,
+            "domains_by_n": {str(k): v for k, v in counts.items()}, "work_share_by_n": share,
+            "autotune_variants": variants,
             "steps_per_launch": chunk, "graphs_replayed": graphs,
             "full_run_point_steps_planned": full}
 
@@ -686,7 +897,13 @@ def main():
     ap.add_argument("--surrogate-eval-flows", type=int, default=32)
     ap.add_argument("--surrogate-steps", type=int, default=1500)
     ap.add_argument("--surrogate-lattice", type=int, default=16)
+    ap.add_argument("--surrogate-full", action="store_true",
+                    help="only the surrogate at its full size (500k labels, 2^20 evaluation patches)")
+    ap.add_argument("--surrogate-full-eval-flows", type=int, default=4096)
+    ap.add_argument("--surrogate-full-label-flows", type=int, default=1960)
+    ap.add_argument("--surrogate-full-save", default="", help="write the trained ensemble and gate here (.npz)")
     ap.add_argument("--no-cellular", action="store_true", help="skip the four-level cellular workload")
+    ap.add_argument("--no-chained", action="store_true", help="skip the surrogate through every level")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--uneven-instances", type=int, default=256)
     ap.add_argument("--uneven-window", type=int, default=2000)
@@ -712,6 +929,11 @@ def main():
         log("no HIP device: the benchmark needs an MI355X")
         return 1
     torch.cuda.set_device(0)
+    if args.surrogate_full:
+        r = surrogate_full_leg(label_flows=args.surrogate_full_label_flows, eval_flows=args.surrogate_full_eval_flows,
+                               save=args.surrogate_full_save)
+        print(json.dumps({"surrogate_full": r}), flush=True)
+        return 0
     if args.copy_probe_mib > 0:
         src = torch.full((args.copy_probe_mib << 20,), 1, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -735,9 +957,10 @@ def main():
     }
     out.update(head)
     extras = not args.headline_only
+    planned = H.result()
     if extras and not args.no_adaptive:
         log("headline pass with the quasi-stationary stop ...")
-        out["adaptive"] = headline_adaptive(H, H.result())
+        out["adaptive"] = headline_adaptive(H, planned)
     H.close()
     if extras and not args.no_cellular:
         log("four-level cellular workload ...")
@@ -758,6 +981,9 @@ def main():
         log("surrogate ...")
         out["surrogate"] = surrogate_leg(args.surrogate_flows, args.surrogate_eval_flows,
                                          steps=args.surrogate_steps, lattice=args.surrogate_lattice)
+    if extras and not args.no_surrogate and not args.no_chained:
+        log("chained surrogate ...")
+        out["surrogate_chained"] = surrogate_chained_leg(planned, out["ms_per_step"] * 5 / 1e3)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         cb = cpu_baseline()
@@ -772,7 +998,8 @@ def main():
 
 def _exit_clean(rc: int) -> None:
     """End the process without leaving anything behind: wait for (or end)
-    any child process, then leave without the interpreter's teardown."""
+    any child process, then exit normally (profilers attached to the process
+    write their results at exit)."""
     try:
         import psutil
         kids = psutil.Process().children(recursive=True)
@@ -784,7 +1011,7 @@ def _exit_clean(rc: int) -> None:
         log(f"child check skipped: {e}")
     sys.stdout.flush()
     sys.stderr.flush()
-    os._exit(rc)
+    sys.exit(rc)
 
 
 if __name__ == "__main__":

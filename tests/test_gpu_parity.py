@@ -278,17 +278,21 @@ def test_windowed_patches_parity(torch, n, taper, steps):
     H.close()
 
 
-@pytest.mark.parametrize("n,steps", [(32, None), (64, 400), (128, 60), (256, 12)])
-def test_zero_frame_local_problem_parity(torch, n, steps):
-    """Zero-frame (non-periodic) local problems (resident kernels up to 128^2,
-    the per-stage kernel at 256^2): correctors against the oracle's
-    zero-frame solve of its own synthesis, the frame cells exactly zero, and
-    the estimate over the centred (n - 2)^2 window."""
+@pytest.mark.parametrize("n,steps,variant", [(32, None, None), (64, 400, None), (128, 60, None), (256, 12, None),
+                                             (256, 300, 6), (256, 300, 2)])
+def test_zero_frame_local_problem_parity(torch, n, steps, variant):
+    """Zero-frame (non-periodic) local problems (resident kernels up to 128^2;
+    at 256^2 the ring-exchange bands, the default, and the per-stage kernel,
+    variant 2): correctors against the oracle's zero-frame solve of its own
+    synthesis, the frame cells exactly zero, and the estimate over the
+    centred (n - 2)^2 window."""
     from paper_1510_00451_amd import abi
     p = _single_level(n, seed=n + 5, amp=0.3, kappa=0.05)
-    say("case zero-frame local problem n=%d" % n)
+    say("case zero-frame local problem n=%d steps=%s variant=%s" % (n, steps, variant))
     H = hier(p, keep_psi=False)
     H.ctx.shmm_ctx_set_local_bc(abi.LOCAL_ZERO_FRAME)
+    if variant is not None:
+        H.ctx.shmm_ctx_tune(n, variant)
     H.band_filter()
     Kb = np.tile([0.06, 0.015, 0.04], (H.nd, 1))
     H.K_base.copy_(torch.from_numpy(Kb))
