@@ -339,80 +339,119 @@ def _spectra_prefetch(seeds, make, workers: int = 8, ahead: int = 128):
 
 def surrogate_full_leg(label_flows: int = 1960, eval_flows: int = 4096, sample_every: int = 64,
                        steps: int = 6000, members: int = 4, batch_flows: int = 64, label_batch_flows: int = 16,
-                       save: str = ""):
+                       save: str = "", load: str = "", gates_arg: str = "", strict_flows: int = 256):
     """The learned surrogate at its full size: about 500k labels from the
     uneven-batch generator (finest-level patches of 128^2, 16 x 16 per flow,
     isotropic base, labels by the plain path with the quasi-stationary stop),
     an ensemble trained with Adam at batch 4096, and the surrogate-with-
     fallback form on the 2^20 finest-level patches of 4096 continuous-spectrum
-    flows (seeds 200000-204095).  The plain form runs on every
-    `sample_every`-th flow (a seed-stratified sample): its time gives the plain
-    estimates/s and its K the error of the surrogate form.  The gate is
-    calibrated on held-out labels twice: for the 99th percentile and for the
-    maximum of the accepted errors within 1%; the evaluation runs with the
-    second (stricter) gate and reports the error distribution on the sample."""
+    flows (seeds 200000-204095).
+
+    The gate is calibrated on held-out labels twice: for the 99th percentile
+    and for the maximum of the accepted errors within 1%.  The evaluation runs
+    every flow with the first gate and the first `strict_flows` flows with the
+    second; the plain form runs on every `sample_every`-th flow (a
+    seed-stratified sample, one phase): its time gives the plain estimates/s
+    and its K the error of both surrogate forms on those flows.
+
+    With `save`, the trained ensemble, its input range and both gates are
+    written there (.npz); with `load`, labels and training are skipped and the
+    ensemble and gates come from that file (`gates_arg` "tau,emax;tau,emax"
+    overrides them: the 99th-percentile gate, then the maximum gate)."""
     import torch
     import flowgen
     from paper_1510_00451_amd import abi
     from paper_1510_00451_amd import surrogate as GS
-    lattice = 16
-    t0 = time.perf_counter()
-    label_seeds = list(range(100000, 100000 + label_flows))
-    probs = _spectra_prefetch(label_seeds, lambda q: flowgen.config_batched_instance(q, n=128, lattice=lattice))
-    batches = ([next(probs) for _ in range(min(label_batch_flows, label_flows - i))]
-               for i in range(0, label_flows, label_batch_flows))
-    data = GS.labelled_set(batches, log=log, adaptive=True)
-    t_label = time.perf_counter() - t0
-    log(f"surrogate at size: {data.x.shape[0]} labels in {t_label:.1f} s")
-    held, train = GS.split(data, 0.1, seed=0)
-    rng = np.random.default_rng(1)
     ctx = abi.Context(0)
-    train = GS.Dataset.concat([train] + [train.rescaled(ctx, rng.uniform(-1.5, 1.5, train.x.shape[0]))
-                                         for _ in range(2)])
-    mu, sg, _, _ = GS.feature_stats(ctx, train.x)
-    ens = GS.Ensemble(ctx, members, mu, sg + 1e-6, seed0=11)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    hist = GS.train(ens, train, steps=steps, batch=4096, lr0=1e-3, seed=5, log=log, clip=1.0)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t1
-    member_losses = ens.prune(held)
-    lo, hi = GS.gate_range(ctx, train, 0.1)
-    gates = {}
-    for name, q in (("p99", 0.99), ("max", 1.0)):
-        tau, emax, acc = GS.calibrate_gate(ens, held, lo, hi, quantile=q)
-        gates[name] = {"tau": tau, "emax": emax if math.isfinite(emax) else None, "held_out_accepted": round(acc, 4)}
-    tau, emax = gates["max"]["tau"], gates["max"]["emax"] if gates["max"]["emax"] is not None else math.inf
-    log(f"surrogate at size: trained in {t_train:.1f} s, members kept {ens.E}, gates {gates}")
-    if save:   # the trained ensemble and its gate, for the record
-        np.savez_compressed(save, models=ens.buf.cpu().numpy(), E=ens.E, lo=lo.cpu().numpy(), hi=hi.cpu().numpy(),
-                            tau=tau, emax=emax, labels=int(data.x.shape[0]))
-
+    lattice = 16
+    info = {}
+    if load:
+        z = np.load(load)
+        E = int(z["E"])
+        ens = GS.Ensemble(ctx, E, np.zeros(abi.SURR_IN), np.ones(abi.SURR_IN))
+        ens.buf.copy_(torch.from_numpy(z["models"]).to(ens.buf.device))
+        lo = torch.from_numpy(z["lo"]).to("cuda")
+        hi = torch.from_numpy(z["hi"]).to("cuda")
+        gates = {}
+        for name in ("p99", "max"):
+            if f"tau_{name}" in z.files:
+                gates[name] = {"tau": float(z[f"tau_{name}"]), "emax": float(z[f"emax_{name}"])}
+        info = {"labels": int(z["labels"]), "loaded_from": os.path.basename(load)}
+    else:
+        t0 = time.perf_counter()
+        label_seeds = list(range(100000, 100000 + label_flows))
+        probs = _spectra_prefetch(label_seeds, lambda q: flowgen.config_batched_instance(q, n=128, lattice=lattice))
+        batches = ([next(probs) for _ in range(min(label_batch_flows, label_flows - i))]
+                   for i in range(0, label_flows, label_batch_flows))
+        data = GS.labelled_set(batches, log=log, adaptive=True)
+        t_label = time.perf_counter() - t0
+        log(f"surrogate at size: {data.x.shape[0]} labels in {t_label:.1f} s")
+        held, train = GS.split(data, 0.1, seed=0)
+        rng = np.random.default_rng(1)
+        train = GS.Dataset.concat([train] + [train.rescaled(ctx, rng.uniform(-1.5, 1.5, train.x.shape[0]))
+                                             for _ in range(2)])
+        mu, sg, _, _ = GS.feature_stats(ctx, train.x)
+        ens = GS.Ensemble(ctx, members, mu, sg + 1e-6, seed0=11)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        hist = GS.train(ens, train, steps=steps, batch=4096, lr0=1e-3, seed=5, log=log, clip=1.0)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t1
+        member_losses = ens.prune(held)
+        lo, hi = GS.gate_range(ctx, train, 0.1)
+        gates = {}
+        for name, q in (("p99", 0.99), ("max", 1.0)):
+            tau, emax, acc = GS.calibrate_gate(ens, held, lo, hi, quantile=q)
+            gates[name] = {"tau": tau, "emax": emax, "held_out_accepted": round(acc, 4)}
+        info = {"labels": int(data.x.shape[0]), "flows": label_flows, "label_s": round(t_label, 1),
+                "train_s": round(t_train, 1), "steps": steps, "batch": 4096, "clip": 1.0, "members": members,
+                "members_kept": ens.E, "held_out_member_losses": [round(float(v), 6) for v in member_losses],
+                "final_loss": hist[-1] if hist else None}
+        log(f"surrogate at size: trained in {t_train:.1f} s, members kept {ens.E}, gates {gates}")
+        if save:
+            np.savez_compressed(save, models=ens.buf.cpu().numpy(), E=ens.E, lo=lo.cpu().numpy(),
+                                hi=hi.cpu().numpy(), labels=int(data.x.shape[0]),
+                                **{f"{k}_{g}": v[k] for g, v in gates.items() for k in ("tau", "emax")})
+    if gates_arg:
+        for name, pair in zip(("p99", "max"), gates_arg.split(";")):
+            t, e = (float(v) for v in pair.split(","))
+            gates[name] = {"tau": t, "emax": e}
     eval_seeds = list(range(200000, 200000 + eval_flows))
     sampled = [q for q in eval_seeds if (q - 200000) % sample_every == 0]
-    stream = _spectra_prefetch(eval_seeds, lambda q: flowgen.config_continuous(seed=q))
-    t_surr, n_est, n_flag = 0.0, 0, 0
+    out = {"workload": f"{eval_flows} continuous-spectrum flows (seeds 200000-{200000 + eval_flows - 1}, "
+                       f"kappa 1e-3, 1<=|k|<=512) x 256 finest-level 128^2 patches, isotropic base",
+           "train": info, "gates": {k: {kk: (vv if math.isfinite(vv) else None) if isinstance(vv, float) else vv
+                                        for kk, vv in v.items()} for k, v in gates.items()}}
     Ks_sample = {}
-    for i0 in range(0, eval_flows, batch_flows):
-        seeds = eval_seeds[i0:i0 + batch_flows]
-        ph = GS.IsotropicPhase([next(stream) for _ in seeds])
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        ph.prepare()
-        Ks = ph.surrogate(ens, lo, hi, tau, emax)
-        torch.cuda.synchronize()
-        t_surr += time.perf_counter() - a
-        act = ph.active
-        n_est += int(act.sum())
-        n_flag += int(ph.flags.cpu().numpy()[act].astype(bool).sum())
-        per = ph.count // len(seeds)
-        Ks_h = Ks.cpu().numpy()
-        for j, q in enumerate(seeds):
-            if q in sampled:
-                Ks_sample[q] = (Ks_h[j * per:(j + 1) * per].copy(), act[j * per:(j + 1) * per].copy())
-        ph.close()
-        log(f"surrogate at size: evaluated {i0 + len(seeds)} flows, {n_est} estimates, "
-            f"{t_surr:.1f} s, fallback {n_flag / max(1, n_est):.4f}")
+    for name, n_flows in (("p99", eval_flows), ("max", min(strict_flows, eval_flows))):
+        if name not in gates:
+            continue
+        tau, emax = gates[name]["tau"], gates[name]["emax"]
+        seeds_all = eval_seeds[:n_flows]
+        stream = _spectra_prefetch(seeds_all, lambda q: flowgen.config_continuous(seed=q))
+        t_surr, n_est, n_flag = 0.0, 0, 0
+        for i0 in range(0, n_flows, batch_flows):
+            seeds = seeds_all[i0:i0 + batch_flows]
+            ph = GS.IsotropicPhase([next(stream) for _ in seeds])
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            ph.prepare()
+            Ks = ph.surrogate(ens, lo, hi, tau, emax)
+            torch.cuda.synchronize()
+            t_surr += time.perf_counter() - a
+            act = ph.active
+            n_est += int(act.sum())
+            n_flag += int(ph.flags.cpu().numpy()[act].astype(bool).sum())
+            per = ph.count // len(seeds)
+            Ks_h = Ks.cpu().numpy()
+            for j, q in enumerate(seeds):
+                if q in sampled:
+                    Ks_sample[(name, q)] = (Ks_h[j * per:(j + 1) * per].copy(), act[j * per:(j + 1) * per].copy())
+            ph.close()
+            log(f"surrogate at size ({name} gate): evaluated {i0 + len(seeds)} flows, {n_est} estimates, "
+                f"{t_surr:.1f} s, fallback {n_flag / max(1, n_est):.4f}")
+        out[name] = {"flows": n_flows, "estimates": n_est, "estimates_per_s": round(n_est / t_surr, 1),
+                     "fallback_frac": round(n_flag / max(1, n_est), 5), "surrogate_s": round(t_surr, 1)}
     # the plain form on the sampled flows, in one phase: its time and its K
     ph = GS.IsotropicPhase([flowgen.config_continuous(seed=q) for q in sampled])
     torch.cuda.synchronize()
@@ -424,32 +463,27 @@ def surrogate_full_leg(label_flows: int = 1960, eval_flows: int = 4096, sample_e
     n_plain = int(ph.active.sum())
     Kp_h = Kp.cpu().numpy()
     per = ph.count // len(sampled)
-    errs = []
-    for j, q in enumerate(sampled):
-        Ksq, actq = Ks_sample[q]
-        assert np.array_equal(actq, ph.active[j * per:(j + 1) * per])
-        errs.append(GS.relative_frobenius(Ksq[actq], Kp_h[j * per:(j + 1) * per][actq]))
-    ph.close()
-    err = np.concatenate(errs)
-    ctx.close()
-    est_s = n_est / t_surr
     plain_s = n_plain / t_plain
-    return {
-        "workload": f"{eval_flows} continuous-spectrum flows (seeds 200000-{200000 + eval_flows - 1}, kappa 1e-3, "
-                    f"1<=|k|<=512) x 256 finest-level 128^2 patches, isotropic base",
-        "estimates": n_est, "estimates_per_s": round(est_s, 1), "plain_estimates_per_s": round(plain_s, 1),
-        "speedup": round(est_s / plain_s, 2), "fallback_frac": round(n_flag / max(1, n_est), 5),
-        "plain_sample": f"every {sample_every}th flow ({len(sampled)} flows, {n_plain} patches, one phase): "
-                        f"the plain form timed on them, {t_plain:.1f} s",
-        "err_vs_plain": {"mean": float(err.mean()), "p99": float(np.quantile(err, 0.99)), "max": float(err.max()),
-                         "frac_over_1pct": float(np.mean(err > 0.01)), "patches": int(err.size)},
-        "gate": {"used": "max", **gates},
-        "train": {"labels": int(data.x.shape[0]), "flows": label_flows, "label_s": round(t_label, 1),
-                  "train_s": round(t_train, 1), "steps": steps, "batch": 4096, "clip": 1.0, "members": members,
-                  "members_kept": ens.E, "held_out_member_losses": [round(float(v), 6) for v in member_losses],
-                  "final_loss": hist[-1] if hist else None},
-        "eval_s": round(t_surr, 1),
-    }
+    out["plain"] = {"estimates_per_s": round(plain_s, 1),
+                    "sample": f"every {sample_every}th flow ({len(sampled)} flows, {n_plain} patches, one phase), "
+                              f"{t_plain:.1f} s"}
+    for name in ("p99", "max"):
+        if name not in out:
+            continue
+        errs = []
+        for j, q in enumerate(sampled):
+            if (name, q) not in Ks_sample:
+                continue
+            Ksq, actq = Ks_sample[(name, q)]
+            errs.append(GS.relative_frobenius(Ksq[actq], Kp_h[j * per:(j + 1) * per][actq]))
+        err = np.concatenate(errs)
+        out[name]["speedup"] = round(out[name]["estimates_per_s"] / plain_s, 2)
+        out[name]["err_vs_plain"] = {"patches": int(err.size), "mean": float(err.mean()),
+                                     "p99": float(np.quantile(err, 0.99)), "max": float(err.max()),
+                                     "frac_over_1pct": float(np.mean(err > 0.01))}
+    ph.close()
+    ctx.close()
+    return out
 
 
 def golden_check(res, case: str):
@@ -901,7 +935,10 @@ def main():
                     help="only the surrogate at its full size (500k labels, 2^20 evaluation patches)")
     ap.add_argument("--surrogate-full-eval-flows", type=int, default=4096)
     ap.add_argument("--surrogate-full-label-flows", type=int, default=1960)
-    ap.add_argument("--surrogate-full-save", default="", help="write the trained ensemble and gate here (.npz)")
+    ap.add_argument("--surrogate-full-save", default="", help="write the trained ensemble and gates here (.npz)")
+    ap.add_argument("--surrogate-full-load", default="", help="evaluate an ensemble saved by --surrogate-full-save")
+    ap.add_argument("--surrogate-full-gates", default="",
+                    help='"tau,emax;tau,emax": the 99th-percentile gate, then the maximum gate')
     ap.add_argument("--no-cellular", action="store_true", help="skip the four-level cellular workload")
     ap.add_argument("--no-chained", action="store_true", help="skip the surrogate through every level")
     ap.add_argument("--no-uneven", action="store_true")
@@ -931,7 +968,8 @@ def main():
     torch.cuda.set_device(0)
     if args.surrogate_full:
         r = surrogate_full_leg(label_flows=args.surrogate_full_label_flows, eval_flows=args.surrogate_full_eval_flows,
-                               save=args.surrogate_full_save)
+                               save=args.surrogate_full_save, load=args.surrogate_full_load,
+                               gates_arg=args.surrogate_full_gates)
         print(json.dumps({"surrogate_full": r}), flush=True)
         return 0
     if args.copy_probe_mib > 0:

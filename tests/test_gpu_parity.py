@@ -120,6 +120,12 @@ def test_band_filter_parity(torch, name, make):
         assert np.abs(psi[sl].reshape(n, n) - ref).max() <= 2e-6 * sc + 1e-30
         for got, want in ((vx, rvx), (vy, rvy), (f1, rf1), (f2, rf2)):
             assert np.abs(got[sl].reshape(n, n) - want).max() <= 2e-6 * vs + 1e-30, (name, d)
+        # and the relative L2 bar of the synthesis (the band field and the velocity)
+        if np.any(ref != 0):
+            assert relerr(psi[sl], ref.ravel()) <= 1e-6, (name, d, relerr(psi[sl], ref.ravel()))
+            vel_g = np.concatenate([vx[sl], vy[sl]])
+            vel_r = np.concatenate([rvx.ravel(), rvy.ravel()])
+            assert relerr(vel_g, vel_r) <= 1e-6, (name, d, relerr(vel_g, vel_r))
         lo = int(D["line_offset"])
         s12 = oracle.line_energies(p.psi_hat, p.kmax, oracle.band_mask(lv, pt, lev, OFF12),
                                    int(D["N"]), int(D["I0"]), n, 0)
