@@ -339,7 +339,8 @@ def _spectra_prefetch(seeds, make, workers: int = 8, ahead: int = 128):
 
 def surrogate_full_leg(label_flows: int = 1960, eval_flows: int = 4096, sample_every: int = 64,
                        steps: int = 6000, members: int = 4, batch_flows: int = 64, label_batch_flows: int = 16,
-                       save: str = "", load: str = "", gates_arg: str = "", strict_flows: int = 256):
+                       save: str = "", load: str = "", gates_arg: str = "", strict_flows: int = 256,
+                       calib_flows: int = 64, dump: str = ""):
     """The learned surrogate at its full size: about 500k labels from the
     uneven-batch generator (finest-level patches of 128^2, 16 x 16 per flow,
     isotropic base, labels by the plain path with the quasi-stationary stop),
@@ -353,6 +354,13 @@ def surrogate_full_leg(label_flows: int = 1960, eval_flows: int = 4096, sample_e
     second; the plain form runs on every `sample_every`-th flow (a
     seed-stratified sample, one phase): its time gives the plain estimates/s
     and its K the error of both surrogate forms on those flows.
+
+    A third gate comes from the evaluation family itself: `calib_flows`
+    continuous-spectrum flows with seeds disjoint from the evaluation's
+    (300000 on), labelled by the plain form over the full plan, and the gate
+    that keeps the maximum of their accepted errors within 1%; it runs on every
+    evaluation flow.  `dump` writes the calibration patches' errors,
+    predicted enhancements, spreads and range tests there (.npz).
 
     With `save`, the trained ensemble, its input range and both gates are
     written there (.npz); with `load`, labels and training are skipped and the
@@ -416,6 +424,24 @@ def surrogate_full_leg(label_flows: int = 1960, eval_flows: int = 4096, sample_e
         for name, pair in zip(("p99", "max"), gates_arg.split(";")):
             t, e = (float(v) for v in pair.split(","))
             gates[name] = {"tau": t, "emax": e}
+    if calib_flows:
+        t0 = time.perf_counter()
+        cal = GS.IsotropicPhase([flowgen.config_continuous(seed=q) for q in range(300000, 300000 + calib_flows)])
+        cal.prepare()
+        cal.features()
+        Kc = cal.plain()
+        act = torch.from_numpy(np.flatnonzero(cal.active)).to(Kc.device)
+        cdata = GS.Dataset(cal.x.index_select(0, act), cal.K_base().index_select(0, act), Kc.index_select(0, act))
+        tau, emax, acc = GS.calibrate_gate(ens, cdata, lo, hi, quantile=1.0)
+        if dump:
+            err_c, enh_c, spread_c, inside_c = GS.gate_inputs(ens, cdata, lo, hi)
+            np.savez_compressed(dump, err=err_c, enh=enh_c, spread=spread_c, inside=inside_c)
+        torch.cuda.synchronize()
+        cal.close()
+        gates["family"] = {"tau": tau, "emax": emax, "calibration_accepted": round(acc, 4),
+                           "calibration": f"{calib_flows} flows, seeds 300000-{300000 + calib_flows - 1}, "
+                                          f"{int(act.numel())} patches, {time.perf_counter() - t0:.1f} s"}
+        log(f"surrogate at size: family gate {gates['family']}")
     eval_seeds = list(range(200000, 200000 + eval_flows))
     sampled = [q for q in eval_seeds if (q - 200000) % sample_every == 0]
     out = {"workload": f"{eval_flows} continuous-spectrum flows (seeds 200000-{200000 + eval_flows - 1}, "
@@ -423,7 +449,7 @@ def surrogate_full_leg(label_flows: int = 1960, eval_flows: int = 4096, sample_e
            "train": info, "gates": {k: {kk: (vv if math.isfinite(vv) else None) if isinstance(vv, float) else vv
                                         for kk, vv in v.items()} for k, v in gates.items()}}
     Ks_sample = {}
-    for name, n_flows in (("p99", eval_flows), ("max", min(strict_flows, eval_flows))):
+    for name, n_flows in (("p99", eval_flows), ("max", min(strict_flows, eval_flows)), ("family", eval_flows)):
         if name not in gates:
             continue
         tau, emax = gates[name]["tau"], gates[name]["emax"]
@@ -467,7 +493,7 @@ def surrogate_full_leg(label_flows: int = 1960, eval_flows: int = 4096, sample_e
     out["plain"] = {"estimates_per_s": round(plain_s, 1),
                     "sample": f"every {sample_every}th flow ({len(sampled)} flows, {n_plain} patches, one phase), "
                               f"{t_plain:.1f} s"}
-    for name in ("p99", "max"):
+    for name in ("p99", "max", "family"):
         if name not in out:
             continue
         errs = []
@@ -939,6 +965,10 @@ def main():
     ap.add_argument("--surrogate-full-load", default="", help="evaluate an ensemble saved by --surrogate-full-save")
     ap.add_argument("--surrogate-full-gates", default="",
                     help='"tau,emax;tau,emax": the 99th-percentile gate, then the maximum gate')
+    ap.add_argument("--surrogate-full-calib-flows", type=int, default=64,
+                    help="flows of the evaluation family (seeds 300000 on) that calibrate the third gate; 0: none")
+    ap.add_argument("--surrogate-full-dump", default="",
+                    help="write the third gate's calibration errors, enhancements and spreads here (.npz)")
     ap.add_argument("--no-cellular", action="store_true", help="skip the four-level cellular workload")
     ap.add_argument("--no-chained", action="store_true", help="skip the surrogate through every level")
     ap.add_argument("--no-uneven", action="store_true")
@@ -969,7 +999,8 @@ def main():
     if args.surrogate_full:
         r = surrogate_full_leg(label_flows=args.surrogate_full_label_flows, eval_flows=args.surrogate_full_eval_flows,
                                save=args.surrogate_full_save, load=args.surrogate_full_load,
-                               gates_arg=args.surrogate_full_gates)
+                               gates_arg=args.surrogate_full_gates, calib_flows=args.surrogate_full_calib_flows,
+                               dump=args.surrogate_full_dump)
         print(json.dumps({"surrogate_full": r}), flush=True)
         return 0
     if args.copy_probe_mib > 0:
@@ -978,7 +1009,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    t_start = time.perf_counter()
     head, H = headline_leg(args)
+    t_head = time.perf_counter() - t_start
     out = {
         "metric": METRIC,
         "value": head.pop("value"),
@@ -994,42 +1027,63 @@ def main():
         "data": "synthetic",
     }
     out.update(head)
+    wall = {"headline": round(t_head, 1)}      # wall-clock seconds of each part of this run
     extras = not args.headline_only
     planned = H.result()
     if extras and not args.no_adaptive:
         log("headline pass with the quasi-stationary stop ...")
+        t_leg = time.perf_counter()
         out["adaptive"] = headline_adaptive(H, planned)
+        wall["adaptive"] = round(time.perf_counter() - t_leg, 1)
     H.close()
     if extras and not args.no_cellular:
         log("four-level cellular workload ...")
+        t_leg = time.perf_counter()
         out["cellular_4level"] = cellular_leg(3, not args.no_adaptive)
+        wall["cellular_4level"] = round(time.perf_counter() - t_leg, 1)
     if extras and not args.no_uneven:
         log("uneven batch ...")
+        t_leg = time.perf_counter()
         out["uneven_batch"] = uneven_leg(args.uneven_instances, args.uneven_window, args.retune)
+        wall["uneven_batch"] = round(time.perf_counter() - t_leg, 1)
     if extras and not args.no_n256:
         log("256^2 kernel variants ...")
+        t_leg = time.perf_counter()
         out["n256_variants"] = n256_leg()
+        wall["n256_variants"] = round(time.perf_counter() - t_leg, 1)
     if extras and not args.no_paper:
         log("Section 4 examples ...")
+        t_leg = time.perf_counter()
         out["paper_tests"] = paper_tests_leg()
+        wall["paper_tests"] = round(time.perf_counter() - t_leg, 1)
     if extras and not args.no_oversampling:
         log("oversampled patches ...")
+        t_leg = time.perf_counter()
         out["oversampling"] = oversampling_leg()
+        wall["oversampling"] = round(time.perf_counter() - t_leg, 1)
     if extras and not args.no_surrogate:
         log("surrogate ...")
+        t_leg = time.perf_counter()
         out["surrogate"] = surrogate_leg(args.surrogate_flows, args.surrogate_eval_flows,
                                          steps=args.surrogate_steps, lattice=args.surrogate_lattice)
+        wall["surrogate"] = round(time.perf_counter() - t_leg, 1)
     if extras and not args.no_surrogate and not args.no_chained:
         log("chained surrogate ...")
+        t_leg = time.perf_counter()
         out["surrogate_chained"] = surrogate_chained_leg(planned, out["ms_per_step"] * 5 / 1e3)
+        wall["surrogate_chained"] = round(time.perf_counter() - t_leg, 1)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
+        t_leg = time.perf_counter()
         cb = cpu_baseline()
+        wall["cpu_baseline"] = round(time.perf_counter() - t_leg, 1)
         pps = out["config"]["point_steps_per_pass"]
         cb["kappa_eff_estimates_per_s_extrapolated"] = round(
             cb["value"] * 1e9 * out["config"]["estimates_per_pass"] / pps, 6)
         out["cpu_baseline"] = cb
     torch.cuda.synchronize()
+    wall["total"] = round(time.perf_counter() - t_start, 1)
+    out["wall_s"] = wall
     print(json.dumps(out), flush=True)
     return 0
 

@@ -398,20 +398,26 @@ def gate_range(ctx: abi.Context, data: Dataset, margin: float = 0.1):
     return dev(lo - margin * w), dev(hi + margin * w)
 
 
+def gate_inputs(ens: Ensemble, data: Dataset, lo, hi):
+    """Per labelled patch (host arrays): the relative Frobenius error of the
+    ensemble mean against the label, the predicted enhancement
+    |K_hat - K_b|_F / |K_b|_F, the ensemble spread, and whether every feature
+    lies inside the gate's range."""
+    K, flags, spread = infer(ens, data.x, data.Kb, lo, hi, math.inf, math.inf)
+    Kn, Kt, Kb = K.cpu().numpy(), data.K.cpu().numpy(), data.Kb.cpu().numpy()
+    return (relative_frobenius(Kn, Kt), relative_frobenius(Kn, Kb), spread.cpu().numpy(),
+            ~flags.cpu().numpy().astype(bool))
+
+
 def calibrate_gate(ens: Ensemble, held: Dataset, lo, hi, target: float = 0.01, quantile: float = 0.99,
                    taus=(5e-4, 1e-3, 1.5e-3, 2e-3, 2.5e-3, 3e-3, 4e-3, 5e-3, 6e-3, 7.5e-3, 1e-2, 1.5e-2,
                          2e-2, 3e-2),
-                   emaxes=(0.01, 0.02, 0.05, 0.1, 0.2, 0.5, 1.0, 2.0, 5.0, math.inf)):
+                   emaxes=(0.01, 0.02, 0.03, 0.05, 0.07, 0.1, 0.15, 0.2, 0.5, 1.0, 2.0, 5.0, math.inf)):
     """Spread threshold tau and enhancement limit emax of the gate: the pair
     that accepts the most held-out patches while the `quantile` of their
     relative Frobenius error stays within `target`.  Ties go to the larger
     thresholds.  Returns (tau, emax, accepted fraction)."""
-    K, flags, spread = infer(ens, held.x, held.Kb, lo, hi, math.inf, math.inf)
-    Kn, Kt, Kb = K.cpu().numpy(), held.K.cpu().numpy(), held.Kb.cpu().numpy()
-    err = relative_frobenius(Kn, Kt)
-    enh = relative_frobenius(Kn, Kb)
-    spread = spread.cpu().numpy()
-    inside = ~flags.cpu().numpy().astype(bool)
+    err, enh, spread, inside = gate_inputs(ens, held, lo, hi)
     best = (taus[0], emaxes[0], -1.0)
     for tau in taus:
         for emax in emaxes:
