@@ -54,7 +54,8 @@ SOLVE_TRAFFIC = {"code_sha256": "7716f7888ddc9b81", "variant": 5,
                  "bytes_per_launch": (2 * 50172.5 + 35262.45) * 1024}
 SOLVE_KERNELS_128 = {0: "k_solve_resident<128,32>", 1: "k_solve_rows<128,2,16>", 2: "k_solve_rows<128,2,8>",
                      3: "k_solve_resident_e<128,32>", 4: "k_solve_resident_e<128,16>",
-                     5: "k_solve_resident_e<128,32,8>", 6: "k_solve_resident_e<128,32,16>"}
+                     5: "k_solve_resident_e<128,32,8>", 6: "k_solve_resident_e<128,32,16>",
+                     7: "k_solve_resident_e<128,32,8,pipelined>", 8: "k_solve_resident_e<128,32,16,pipelined>"}
 
 
 def solve_code_hash():
@@ -124,9 +125,9 @@ def cpu_baseline() -> dict:
     core this process may use) in this process, then one core in a child
     process (OMP_NUM_THREADS=1); the child touches no GPU."""
     threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
-    allc = cpu_sample(32, 3000)
+    allc = cpu_sample(32, 9000)
     env = dict(os.environ, OMP_NUM_THREADS="1")
-    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-sample-only", "2", "3000"],
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-sample-only", "2", "9000"],
                        env=env, capture_output=True, text=True, timeout=600)
     one = json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else None
     return {"value": round(allc["value"], 4), "unit": "Gpoint-steps/s", "cores": threads, "kind": "oracle",
@@ -899,7 +900,8 @@ def paper_tests_leg(n_k: int = 128, n_dns: int = 512):
 
 SOLVE_KERNELS_256 = {0: "k_solve_band<256,32,8,16,0>", 1: "k_solve_band<256,32,8,12,0>", 2: "k_solve_stage",
                      3: "k_solve_band<256,24,12,16,0>", 4: "k_solve_band<256,16,8,32,8>",
-                     5: "k_solve_tiled<64,8,10>", 6: "k_solve_ring<256,32,8,16>"}
+                     5: "k_solve_tiled<64,8,10>", 6: "k_solve_ring<256,32,8,16>",
+                     7: "k_solve_ring<256,32,8,16,pipelined>"}
 
 
 def n256_leg(steps: int = 200):

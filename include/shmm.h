@@ -311,10 +311,13 @@ int shmm_level_chain(shmm_ctx *ctx, int64_t first, int64_t count, int32_t mode,
  * key = SHMM_TUNE_SOLVE_VARIANT_COUNT with value = n (a non-negative return).
  * n = 64: 0 = whole patch in LDS, column strips of 16 (split operator form);
  *   1, 2 = rows per wavefront, 16 or 8 rows per thread; 3 = whole patch in
- *   LDS, coefficient form, strips of 16 (default); 4 = the same, strips of 8.
+ *   LDS, coefficient form, strips of 16 (default); 4 = the same, strips of 8;
+ *   5, 6 = 3 and 4 with the stage input read a row further ahead (pipelined
+ *   LDS reads, bit-identical results).
  * n = 128: 0 = split form, strips of 32; 1, 2 = rows per wavefront (16, 8);
  *   3, 4 = coefficient form, strips of 32 or 16; 5 = strips of 32 with the
- *   compensation of 8 strip rows in LDS (default); 6 = the same with 16 rows.
+ *   compensation of 8 strip rows in LDS (default); 6 = the same with 16 rows;
+ *   7, 8 = 5 and 6 with pipelined LDS reads (bit-identical results).
  * n = 256: 0 = full-width bands of 32 rows with 8-row rings, 768 threads,
  *   relaunched every 2 steps; 1 = the same at 1024 threads; 2 = one launch per
  *   RK stage; 3 = bands of 24 rows with 12-row rings (3 steps per launch);
@@ -322,7 +325,8 @@ int shmm_level_chain(shmm_ctx *ctx, int64_t first, int64_t count, int32_t mode,
  *   rings; 6 = the bands of 0 kept resident for all steps, neighbours
  *   exchanging their ring rows every 2 steps (default; in a call whose range
  *   also holds other patch sizes it runs first and alone, and the other
- *   sizes follow, concurrently with one another).
+ *   sizes follow, concurrently with one another); 7 = 6 with pipelined LDS
+ *   reads (bit-identical results, also run alone).
  * Other sizes have one variant.
  * Errors: SHMM_EINVAL for an unknown key or value. */
 #define SHMM_TUNE_SOLVE_VARIANT_COUNT 0
@@ -452,18 +456,25 @@ int shmm_surrogate_infer(shmm_ctx *ctx, const void *d_models, int32_t E, const f
 
 /* Chain-aware gate for the surrogate inside the level chain (Algorithm 3):
  * a finer level's result enters its parent's base K_net = K_star - K_off +
- * K_in after K_off is subtracted, so its absolute error must stay well below
- * the parent's K_in.  For domain first + i, i < count: sets d_flags[i] = 1
- * when d_spread[i] |d_K_hat[i]|_F (the ensemble's largest relative member
- * deviation, as shmm_surrogate_infer writes it, times the estimate's norm)
- * exceeds tol lambda_min(K_in of the domain's parent); flags of domains
- * without a parent (level 0) are left as they are.  d_K_hat [count][3],
+ * K_in after K_off is subtracted, and from there (the parent's result is
+ * close to its base where the enhancement is small) the bases of every level
+ * above it, so its absolute error must stay well below the K_in of each
+ * ancestor, the smallest being kappa I at the coarsest level.  For domain
+ * first + i, i < count: sets d_flags[i] = 1 when
+ * |d_K_hat[i] - d_K_base[i]|_F + d_spread[i] |d_K_hat[i]|_F (the predicted
+ * change of the base plus the ensemble's largest relative member deviation,
+ * as shmm_surrogate_infer writes it, times the estimate's norm) exceeds
+ * tol times the smallest lambda_min(K_in) over the domain's parent and the
+ * parent's ancestors; flags of domains without a parent (level 0) are left
+ * as they are.  The predicted change is
+ * there because the members share the error the features cannot resolve, so
+ * the spread alone does not bound it.  d_K_hat, d_K_base [count][3],
  * d_spread [count], d_K_in [n_domains][3] (global index, as the level chain
  * fills it), d_flags [count].  Errors: SHMM_EINVAL for a bad range, a null
  * pointer or tol <= 0. */
 int shmm_surrogate_chain_gate(shmm_ctx *ctx, int64_t first, int64_t count, const double *d_K_hat,
-                              const double *d_spread, const double *d_K_in, double tol, uint8_t *d_flags,
-                              void *stream);
+                              const double *d_K_base, const double *d_spread, const double *d_K_in, double tol,
+                              uint8_t *d_flags, void *stream);
 
 /* Column statistics of a feature matrix d_x [B][35] (the input
  * standardisation of the network and the range of the fallback gate): per

@@ -94,7 +94,7 @@ def lib() -> ctypes.CDLL:
             "shmm_fallback_solve": [P, i64, i64, P, P, P, P, P, P, P, P, i32, f64, P, P],
             "shmm_feature_stats": [P, P, i64, P, P],
             "shmm_surrogate_rescale": [P, P, P, P, P, i64, P, P, P, P],
-            "shmm_surrogate_chain_gate": [P, i64, i64, P, P, P, f64, P, P],
+            "shmm_surrogate_chain_gate": [P, i64, i64, P, P, P, P, f64, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -276,9 +276,9 @@ class Context:
                                         d_w, d_K_out, int(chunks), float(tol), d_status or None, stream),
               "shmm_fallback_solve")
 
-    def shmm_surrogate_chain_gate(self, first, count, d_K_hat, d_spread, d_K_in, tol, d_flags, stream=0):
-        check(lib().shmm_surrogate_chain_gate(self.h, first, count, d_K_hat, d_spread, d_K_in, float(tol), d_flags,
-                                              stream), "shmm_surrogate_chain_gate")
+    def shmm_surrogate_chain_gate(self, first, count, d_K_hat, d_K_base, d_spread, d_K_in, tol, d_flags, stream=0):
+        check(lib().shmm_surrogate_chain_gate(self.h, first, count, d_K_hat, d_K_base, d_spread, d_K_in, float(tol),
+                                              d_flags, stream), "shmm_surrogate_chain_gate")
 
     def shmm_feature_stats(self, d_x, B, d_stats, stream=0):
         check(lib().shmm_feature_stats(self.h, d_x, int(B), d_stats, stream), "shmm_feature_stats")

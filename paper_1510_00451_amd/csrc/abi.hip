@@ -324,7 +324,7 @@ static int default_solve_variant(int n) { return n == 64 ? 3 : n == 128 ? 5 : n 
 // The ring-exchange bands (n = 256, variant 6) need every workgroup of a
 // group running at once; beside kernels that hold CUs for whole solves they
 // would sit partly dispatched, so they run alone.
-static bool runs_alone(int n, int variant) { return n == 256 && variant == 6; }
+static bool runs_alone(int n, int variant) { return n == 256 && (variant == 6 || variant == 7); }
 
 static int set_device(shmm_ctx *ctx) {
     SHMM_HIP_CHECK(hipSetDevice(ctx->device));
@@ -923,14 +923,14 @@ int shmm_surrogate_infer(shmm_ctx *ctx, const void *d_models, int32_t E, const f
 }
 
 int shmm_surrogate_chain_gate(shmm_ctx *ctx, int64_t first, int64_t count, const double *d_K_hat,
-                              const double *d_spread, const double *d_K_in, double tol, uint8_t *d_flags,
-                              void *stream) {
-    if (!range_ok(ctx, first, count) || !d_K_hat || !d_spread || !d_K_in || !d_flags || !(tol > 0.0) ||
-        !std::isfinite(tol))
+                              const double *d_K_base, const double *d_spread, const double *d_K_in, double tol,
+                              uint8_t *d_flags, void *stream) {
+    if (!range_ok(ctx, first, count) || !d_K_hat || !d_K_base || !d_spread || !d_K_in || !d_flags ||
+        !(tol > 0.0) || !std::isfinite(tol))
         return SHMM_EINVAL;
     int rc = set_device(ctx);
     if (rc) return rc;
-    return launch_chain_gate(ctx->d_table, first, count, d_K_hat, d_spread, d_K_in, tol, d_flags,
+    return launch_chain_gate(ctx->d_table, first, count, d_K_hat, d_K_base, d_spread, d_K_in, tol, d_flags,
                              (hipStream_t)stream);
 }
 

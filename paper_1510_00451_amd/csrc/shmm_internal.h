@@ -79,11 +79,12 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
                        uint32_t ring_spin_cap = kRingSpinCapDefault);
 bool local_solve_resident(int n);
 // persistent full-width bands of 256^2 patches with a ring exchange between
-// them; work holds the exchange slabs and round counters
+// them; work holds the exchange slabs and round counters; pipe: the stage
+// input read a row further ahead (same results)
 int launch_ring_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n, const float *vx,
                       const float *vy, const double *Kb, float *w, int64_t cells_total, int32_t step_begin,
                       int32_t s_end, void *work, size_t work_bytes, hipStream_t s, bool frame = false,
-                      uint32_t spin_cap = kRingSpinCapDefault);
+                      uint32_t spin_cap = kRingSpinCapDefault, bool pipe = false);
 int local_solve_variants(int n);
 // frame: the zero-frame (non-periodic) local problem (resident up to 128^2,
 // ring-exchange bands at 256^2)
@@ -126,8 +127,9 @@ int surrogate_infer(const void *models, int32_t E, const float *x, const double 
                     double *spread, double *K_members, void *work, hipStream_t s);
 
 int launch_feature_stats(const float *x, int64_t B, double *stats, hipStream_t s);
-int launch_chain_gate(const shmm_domain *dom, int64_t first, int64_t count, const double *K_hat, const double *spread,
-                      const double *K_in, double tol, uint8_t *flags, hipStream_t s);
+int launch_chain_gate(const shmm_domain *dom, int64_t first, int64_t count, const double *K_hat,
+                      const double *K_base, const double *spread, const double *K_in, double tol, uint8_t *flags,
+                      hipStream_t s);
 int launch_surrogate_rescale(const float *x, const double *Kb, const double *K, const double *log10c, int64_t B,
                              float *xo, double *Kbo, double *Ko, hipStream_t s);
 

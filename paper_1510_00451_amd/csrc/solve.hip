@@ -167,7 +167,7 @@ __global__ __launch_bounds__(NN *NN / R) void k_solve_resident(
 }
 
 // Resident kernel, coefficient form (rk_stage_e).
-template <int NN, int R, int FIELD, int CL, bool FRAME = false>
+template <int NN, int R, int FIELD, int CL, bool FRAME = false, bool PIPE = false>
 __device__ __forceinline__ void solve_body_e(float *__restrict__ buf, const shmm_domain *__restrict__ dom,
                                              const int32_t *__restrict__ list,
                                              const float *__restrict__ vx, const float *__restrict__ vy,
@@ -221,16 +221,16 @@ __device__ __forceinline__ void solve_body_e(float *__restrict__ buf, const shmm
     __syncthreads();
     constexpr bool OP = NN >= 128;
     for (int32_t s = step_begin; s < s_end; ++s) {
-        rk_stage_e<NN, R, FIELD, 0, OP, CL, FRAME>(lo, offW, offE, offS, offN, hi, k, two_cyy, 0.0f, eE, eW, nb, wv, comp,
+        rk_stage_e<NN, R, FIELD, 0, OP, CL, FRAME, PIPE>(lo, offW, offE, offS, offN, hi, k, two_cyy, 0.0f, eE, eW, nb, wv, comp,
                                             rr, cl, T, y0, x == MASK);
         __syncthreads();
-        rk_stage_e<NN, R, FIELD, 1, OP, CL, FRAME>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.25f, eE, eW, nb, wv, comp,
+        rk_stage_e<NN, R, FIELD, 1, OP, CL, FRAME, PIPE>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.25f, eE, eW, nb, wv, comp,
                                             rr, cl, T, y0, x == MASK);
         __syncthreads();
-        rk_stage_e<NN, R, FIELD, 1, OP, CL, FRAME>(lo, offW, offE, offS, offN, hi, k, two_cyy, 1.0f / 3.0f, eE, eW, nb, wv,
+        rk_stage_e<NN, R, FIELD, 1, OP, CL, FRAME, PIPE>(lo, offW, offE, offS, offN, hi, k, two_cyy, 1.0f / 3.0f, eE, eW, nb, wv,
                                             comp, rr, cl, T, y0, x == MASK);
         __syncthreads();
-        rk_stage_e<NN, R, FIELD, 2, OP, CL, FRAME>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.5f, eE, eW, nb, wv, comp,
+        rk_stage_e<NN, R, FIELD, 2, OP, CL, FRAME, PIPE>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.5f, eE, eW, nb, wv, comp,
                                             rr, cl, T, y0, x == MASK);
         __syncthreads();
     }
@@ -241,16 +241,16 @@ __device__ __forceinline__ void solve_body_e(float *__restrict__ buf, const shmm
     for (int r = 0; r < R; ++r) wf[r * NN] = wv[r];
 }
 
-template <int NN, int R, int CL = 0, bool FRAME = false>
+template <int NN, int R, int CL = 0, bool FRAME = false, bool PIPE = false>
 __global__ __launch_bounds__(NN *NN / R) void k_solve_resident_e(
     const shmm_domain *__restrict__ dom, const int32_t *__restrict__ list,
     const float *__restrict__ vx, const float *__restrict__ vy, const double *__restrict__ Kb,
     float *__restrict__ w, int64_t cells_total, int32_t step_begin, int32_t steps) {
     __shared__ float buf[2 * NN * NN + CL * (NN * NN / R)];
     if (blockIdx.x & 1)
-        solve_body_e<NN, R, 1, CL, FRAME>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
+        solve_body_e<NN, R, 1, CL, FRAME, PIPE>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
     else
-        solve_body_e<NN, R, 0, CL, FRAME>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
+        solve_body_e<NN, R, 0, CL, FRAME, PIPE>(buf, dom, list, vx, vy, Kb, w, cells_total, step_begin, steps);
 }
 
 // Row-resident variant for patches whose row fits one wavefront (n = 64 C):
@@ -800,11 +800,11 @@ int launch_resident(const shmm_domain *d_dom, const int32_t *d_list, int32_t nli
     return SHMM_OK;
 }
 
-template <int NN, int R, int CL = 0, bool FRAME = false>
+template <int NN, int R, int CL = 0, bool FRAME = false, bool PIPE = false>
 int launch_resident_e(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, const float *vx,
                       const float *vy, const double *Kb, float *w, int64_t cells_total,
                       int32_t step_begin, int32_t steps, hipStream_t s) {
-    hipLaunchKernelGGL((k_solve_resident_e<NN, R, CL, FRAME>), dim3((unsigned)(2 * nlist)), dim3(NN * NN / R), 0, s,
+    hipLaunchKernelGGL((k_solve_resident_e<NN, R, CL, FRAME, PIPE>), dim3((unsigned)(2 * nlist)), dim3(NN * NN / R), 0, s,
                        d_dom, d_list, vx, vy, Kb, w, cells_total, step_begin, steps);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
@@ -814,7 +814,7 @@ int launch_resident_e(const shmm_domain *d_dom, const int32_t *d_list, int32_t n
 
 bool local_solve_resident(int n) { return n == 8 || n == 16 || n == 32 || n == 64 || n == 128; }
 
-int local_solve_variants(int n) { return n == 64 ? 5 : n == 128 ? 7 : n == 256 ? 7 : 1; }
+int local_solve_variants(int n) { return n == 64 ? 7 : n == 128 ? 9 : n == 256 ? 8 : 1; }
 
 namespace {
 // Zero both corrector fields of the listed domains (one workgroup row per domain).
@@ -877,6 +877,8 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
             if (variant == 2) return launch_rows<64, 1, 8>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
             if (variant == 3) return launch_resident_e<64, 16>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
             if (variant == 4) return launch_resident_e<64, 8>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            if (variant == 5) return launch_resident_e<64, 16, 0, false, true>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            if (variant == 6) return launch_resident_e<64, 8, 0, false, true>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
             return launch_resident<64, 16>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
         case 128:
             if (variant == 1) return launch_rows<128, 2, 16>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
@@ -885,6 +887,8 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
             if (variant == 4) return launch_resident_e<128, 16>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
             if (variant == 5) return launch_resident_e<128, 32, 8>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
             if (variant == 6) return launch_resident_e<128, 32, 16>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            if (variant == 7) return launch_resident_e<128, 32, 8, false, true>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
+            if (variant == 8) return launch_resident_e<128, 32, 16, false, true>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
             return launch_resident<128, 32>(d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, step_begin, steps, s);
         default: break;
     }
@@ -893,13 +897,13 @@ int launch_local_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t 
           *comp = ws + 6 * list_cells;
     const int64_t s_end64 = (int64_t)step_begin + steps;
     const int32_t s_end = (int32_t)(s_end64 < max_steps ? s_end64 : max_steps);
-    if (n == 256 && variant == 6) {   // persistent bands with a ring exchange (solve_ring.hip)
+    if (n == 256 && (variant == 6 || variant == 7)) {   // persistent bands with a ring exchange (solve_ring.hip)
         // each patch stops at min(step_begin + steps, its plan) inside the
         // kernel, so the launch does not depend on the host's plan (a
         // captured graph stays valid when the plans change)
         const int32_t s_cap = (int32_t)std::min<int64_t>(s_end64, 2147483647);
         return launch_ring_solve(d_dom, d_list, nlist, n, vx, vy, Kb, w, cells_total, step_begin, s_cap, work,
-                                 local_solve_workspace(n, list_cells), s, frame, ring_spin_cap);
+                                 local_solve_workspace(n, list_cells), s, frame, ring_spin_cap, variant == 7);
     }
     if (n == 256 && variant != 2 && !frame) {
         // Overlapped regions, HALO / 4 steps per launch.  Full-width bands:

@@ -122,7 +122,7 @@ __device__ __forceinline__ void take_rows(int st, const float *__restrict__ fs, 
     }
 }
 
-template <int NN, int TH, int HALO, int R, int FIELD, bool FRAME>
+template <int NN, int TH, int HALO, int R, int FIELD, bool FRAME, bool PIPE>
 __device__ __forceinline__ void ring_body(float *__restrict__ buf, int *bad, const shmm_domain *__restrict__ dom,
                                           const int32_t *__restrict__ list, int32_t count, int group,
                                           int groups, int band, const float *__restrict__ vx,
@@ -196,17 +196,17 @@ __device__ __forceinline__ void ring_body(float *__restrict__ buf, int *bad, con
             for (int32_t s = step_begin; s < lim;) {
                 const int32_t se = s + HALO / 4 < lim ? s + HALO / 4 : lim;
                 for (; s < se; ++s) {
-                    rk_stage_e<NN, R, FIELD, 0, false, 0, FRAME>(lo, offW, offE, offS, offN, hi, k, two_cyy, 0.0f, eE,
+                    rk_stage_e<NN, R, FIELD, 0, false, 0, FRAME, PIPE>(lo, offW, offE, offS, offN, hi, k, two_cyy, 0.0f, eE,
                                                                  eW, nb, wv, comp, rr, nullptr, 0, gy0m, xlast);
                     __syncthreads();
-                    rk_stage_e<NN, R, FIELD, 1, false, 0, FRAME>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.25f, eE,
+                    rk_stage_e<NN, R, FIELD, 1, false, 0, FRAME, PIPE>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.25f, eE,
                                                                  eW, nb, wv, comp, rr, nullptr, 0, gy0m, xlast);
                     __syncthreads();
-                    rk_stage_e<NN, R, FIELD, 1, false, 0, FRAME>(lo, offW, offE, offS, offN, hi, k, two_cyy,
+                    rk_stage_e<NN, R, FIELD, 1, false, 0, FRAME, PIPE>(lo, offW, offE, offS, offN, hi, k, two_cyy,
                                                                  1.0f / 3.0f, eE, eW, nb, wv, comp, rr, nullptr, 0,
                                                                  gy0m, xlast);
                     __syncthreads();
-                    rk_stage_e<NN, R, FIELD, 2, false, 0, FRAME>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.5f, eE,
+                    rk_stage_e<NN, R, FIELD, 2, false, 0, FRAME, PIPE>(hi, offW, offE, offS, offN, lo, k, two_cyy, 0.5f, eE,
                                                                  eW, nb, wv, comp, rr, nullptr, 0, gy0m, xlast);
                     __syncthreads();
                 }
@@ -271,7 +271,7 @@ __device__ __forceinline__ void ring_body(float *__restrict__ buf, int *bad, con
 // XCD-aware (workgroup i runs on XCD i mod 8): the PER members of a group
 // take consecutive slots of one XCD, so their slabs and counters stay in that
 // XCD's L2.
-template <int NN, int TH, int HALO, int R, bool FRAME = false>
+template <int NN, int TH, int HALO, int R, bool FRAME = false, bool PIPE = false>
 __global__ __launch_bounds__(NN *(TH + 2 * HALO) / R) void k_solve_ring(
     const shmm_domain *__restrict__ dom, const int32_t *__restrict__ list, int32_t count,
     const float *__restrict__ vx, const float *__restrict__ vy, const double *__restrict__ Kb,
@@ -293,10 +293,10 @@ __global__ __launch_bounds__(NN *(TH + 2 * HALO) / R) void k_solve_ring(
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
     if (member & 1)
-        ring_body<NN, TH, HALO, R, 1, FRAME>(buf, &bad, dom, list, count, group, groups, member >> 1, vx, vy, Kb, w,
+        ring_body<NN, TH, HALO, R, 1, FRAME, PIPE>(buf, &bad, dom, list, count, group, groups, member >> 1, vx, vy, Kb, w,
                                       cells_total, slab, flags, step_begin, s_cap, spin_cap);
     else
-        ring_body<NN, TH, HALO, R, 0, FRAME>(buf, &bad, dom, list, count, group, groups, member >> 1, vx, vy, Kb, w,
+        ring_body<NN, TH, HALO, R, 0, FRAME, PIPE>(buf, &bad, dom, list, count, group, groups, member >> 1, vx, vy, Kb, w,
                                       cells_total, slab, flags, step_begin, s_cap, spin_cap);
 }
 
@@ -307,12 +307,17 @@ __global__ void k_zero_rounds(int32_t *flags, int n) {
 
 constexpr int kRingNN = 256, kRingTH = 32, kRingHalo = 8, kRingR = 16;
 
+template <bool FRAME, bool PIPE>
+const void *ring_kernel() {
+    return reinterpret_cast<const void *>(&k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR, FRAME, PIPE>);
+}
+
 }  // namespace
 
 int launch_ring_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t nlist, int n, const float *vx,
                       const float *vy, const double *Kb, float *w, int64_t cells_total, int32_t step_begin,
                       int32_t s_end, void *work, size_t work_bytes, hipStream_t s, bool frame,
-                      uint32_t spin_cap) {
+                      uint32_t spin_cap, bool pipe) {
     using S = RingShape<kRingNN, kRingTH, kRingHalo>;
     if (n != kRingNN) return SHMM_EINVAL;
     if (nlist <= 0 || step_begin >= s_end) return SHMM_OK;
@@ -321,8 +326,8 @@ int launch_ring_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t n
     SHMM_HIP_CHECK(hipGetDevice(&dev));
     SHMM_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     // occupancy of the instantiation that is launched
-    const void *fn = frame ? reinterpret_cast<const void *>(&k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR, true>)
-                           : reinterpret_cast<const void *>(&k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR>);
+    const void *fn = frame ? (pipe ? ring_kernel<true, true>() : ring_kernel<true, false>())
+                           : (pipe ? ring_kernel<false, true>() : ring_kernel<false, false>());
     SHMM_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, threads, 0));
     // every workgroup of the grid fits on the device at once
     int64_t groups = std::min<int64_t>(nlist, (int64_t)cus * occ / S::PER);
@@ -338,14 +343,22 @@ int launch_ring_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t n
     const int nflags = (int)(groups * S::PER);
     hipLaunchKernelGGL(k_zero_rounds, dim3((unsigned)((nflags + 255) / 256)), dim3(256), 0, s, flags, nflags);
     SHMM_HIP_CHECK(hipGetLastError());
-    if (frame)
-        hipLaunchKernelGGL((k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR, true>), dim3((unsigned)(groups * S::PER)),
-                           dim3(threads), 0, s, d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, slab, flags,
-                           step_begin, s_end, spin_cap);
+    const dim3 grid((unsigned)(groups * S::PER));
+    if (frame && pipe)
+        hipLaunchKernelGGL((k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR, true, true>), grid, dim3(threads), 0, s,
+                           d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, slab, flags, step_begin, s_end, spin_cap);
+    else if (frame)
+        hipLaunchKernelGGL((k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR, true, false>), grid, dim3(threads), 0,
+                           s, d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, slab, flags, step_begin, s_end,
+                           spin_cap);
+    else if (pipe)
+        hipLaunchKernelGGL((k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR, false, true>), grid, dim3(threads), 0,
+                           s, d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, slab, flags, step_begin, s_end,
+                           spin_cap);
     else
-        hipLaunchKernelGGL((k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR>), dim3((unsigned)(groups * S::PER)),
-                           dim3(threads), 0, s, d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, slab, flags,
-                           step_begin, s_end, spin_cap);
+        hipLaunchKernelGGL((k_solve_ring<kRingNN, kRingTH, kRingHalo, kRingR, false, false>), grid, dim3(threads), 0,
+                           s, d_dom, d_list, nlist, vx, vy, Kb, w, cells_total, slab, flags, step_begin, s_end,
+                           spin_cap);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
 }

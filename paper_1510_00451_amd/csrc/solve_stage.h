@@ -46,7 +46,12 @@ __device__ __forceinline__ float uniform(float v) {
 // (cl[r * cstride]) instead of registers, to relieve register pressure.
 // FRAME: the zero-frame local problem; the cells of the patch's last column
 // (xlast) and last row (strip row y0 + r = NN - 1) keep a zero derivative.
-template <int NN, int R, int FIELD, int KIND, bool OPAQUE, int CL = 0, bool FRAME = false>
+// PIPE: read the stage input one row further ahead (row r + 2 while row r is
+// computed) and keep each pair of rows' reads in front of the previous pair's
+// arithmetic with a scheduling barrier, so the LDS latency overlaps the
+// arithmetic instead of being waited for at the top of every pair; same
+// arithmetic, same results.
+template <int NN, int R, int FIELD, int KIND, bool OPAQUE, int CL = 0, bool FRAME = false, bool PIPE = false>
 __device__ __forceinline__ void rk_stage_e(const float *__restrict__ C, int offW, int offE, int offS,
                                            int offN, float *__restrict__ out, const SolveConsts &k,
                                            float two_cyy, float cw, float (&eE)[R], float (&eW)[R],
@@ -64,10 +69,25 @@ __device__ __forceinline__ void rk_stage_e(const float *__restrict__ C, int offW
     float sC = C[offS];
     float dS = Ec[offS] - Wc[offS];
     float cW = Wc[0], cC = C[0], cE = Ec[0];
+    float qW = 0.0f, qC = 0.0f, qE = 0.0f;       // PIPE: the row after the next
+    if (PIPE) {
+        const int r1 = 1 < R ? NN : offN;
+        qW = Wc[r1]; qC = C[r1]; qE = Ec[r1];
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int rn = (r + 1 < R) ? (r + 1) * NN : offN;
-        const float nW = Wc[rn], nC = C[rn], nE = Ec[rn];
+        float nW, nC, nE;
+        if (PIPE) {
+            nW = qW; nC = qC; nE = qE;
+            if (r + 2 <= R) {
+                const int rp = (r + 2 < R) ? (r + 2) * NN : offN;
+                qW = Wc[rp]; qC = C[rp]; qE = Ec[rp];
+            }
+            if (r & 1) __builtin_amdgcn_sched_barrier(0);
+        } else {
+            const int rn = (r + 1 < R) ? (r + 1) * NN : offN;
+            nW = Wc[rn]; nC = C[rn]; nE = Ec[rn];
+        }
         const float dN = nE - nW;
         const float eS = two_cyy - nb[r];
         float t = k.cc * cC;

@@ -876,27 +876,44 @@ namespace {
 // Flags domain d when spread_d |K_hat_d|_F (the ensemble's largest member
 // deviation, absolute) exceeds tol lambda_min(K_in of d's parent); domains
 // without a parent keep their flag.
+// Bound on the absolute error of an accepted estimate: its predicted change of
+// the base plus the ensemble's spread in absolute terms.  The members agree on
+// what the features cannot resolve, so the spread alone misses the systematic
+// part; where it was measured (finest-level patches) the error stayed below
+// the predicted change.  The reference is the smallest K_in of every
+// ancestor: an error in a result shifts its parent's base K_net = K_star -
+// K_off + K_in, and through the parent's result (nearly its base where the
+// enhancement is small) the base of every level above it, down to the
+// coarsest, where K_in is kappa I.
 __global__ void k_chain_gate(const shmm_domain *__restrict__ dom, int64_t first, int64_t count,
-                             const double *__restrict__ K_hat, const double *__restrict__ spread,
-                             const double *__restrict__ K_in, double tol, uint8_t *__restrict__ flags) {
+                             const double *__restrict__ K_hat, const double *__restrict__ K_base,
+                             const double *__restrict__ spread, const double *__restrict__ K_in, double tol,
+                             uint8_t *__restrict__ flags) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const int32_t parent = dom[first + i].parent;
-    if (parent < 0) return;
-    const double *k = K_hat + 3 * i, *kp = K_in + 3 * (int64_t)parent;
+    int32_t a = dom[first + i].parent;
+    if (a < 0) return;
+    double lam = INFINITY;
+    for (int hops = 0; a >= 0 && hops < 64; ++hops, a = dom[a].parent) {   // levels are far fewer than 64
+        const double *kp = K_in + 3 * (int64_t)a;
+        const double m = 0.5 * (kp[0] + kp[2]), q = 0.5 * (kp[0] - kp[2]);
+        lam = fmin(lam, m - sqrt(q * q + kp[1] * kp[1]));
+    }
+    const double *k = K_hat + 3 * i, *kb = K_base + 3 * i;
     const double fro = sqrt(k[0] * k[0] + 2.0 * k[1] * k[1] + k[2] * k[2]);
-    const double m = 0.5 * (kp[0] + kp[2]), q = 0.5 * (kp[0] - kp[2]);
-    const double lam = m - sqrt(q * q + kp[1] * kp[1]);
-    if (!(spread[i] * fro <= tol * lam)) flags[i] = 1;
+    const double d0 = k[0] - kb[0], d1 = k[1] - kb[1], d2 = k[2] - kb[2];
+    const double change = sqrt(d0 * d0 + 2.0 * d1 * d1 + d2 * d2);
+    if (!(change + spread[i] * fro <= tol * lam)) flags[i] = 1;
 }
 
 }  // namespace
 
-int launch_chain_gate(const shmm_domain *dom, int64_t first, int64_t count, const double *K_hat, const double *spread,
-                      const double *K_in, double tol, uint8_t *flags, hipStream_t s) {
+int launch_chain_gate(const shmm_domain *dom, int64_t first, int64_t count, const double *K_hat,
+                      const double *K_base, const double *spread, const double *K_in, double tol, uint8_t *flags,
+                      hipStream_t s) {
     if (count <= 0) return SHMM_OK;
     hipLaunchKernelGGL(k_chain_gate, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, dom, first, count, K_hat,
-                       spread, K_in, tol, flags);
+                       K_base, spread, K_in, tol, flags);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;
 }

@@ -144,10 +144,11 @@ class Hierarchy:
         are the level chain's own (Algorithm 3), anisotropic in general.
         models_ptr: E members back to back (device); lo, hi: device [35]
         feature range of the gate.  chain_tol: also flag a patch whose
-        ensemble spread, in absolute terms, exceeds chain_tol times the
-        smallest eigenvalue of its parent's K_in (shmm_surrogate_chain_gate:
-        the accuracy Algorithm 3 needs of a finer result, which enters the
-        parent's base after K_off is subtracted)."""
+        predicted change of its base plus ensemble spread, in absolute
+        terms, exceeds chain_tol times the smallest eigenvalue of the K_in
+        of its ancestors (shmm_surrogate_chain_gate: the accuracy Algorithm 3
+        needs of a finer result, which enters the parent's base after K_off
+        is subtracted and from there the bases above it)."""
         torch = self.torch
         self.surrogate = (models_ptr, E, lo, hi, tau, emax, chain_tol)
         self._x = torch.zeros(self.nd, abi.SURR_IN, dtype=torch.float32, device=self.device)
@@ -173,8 +174,9 @@ class Hierarchy:
                                lo.data_ptr(), hi.data_ptr(), tau, emax, self.K_solve[first].data_ptr(),
                                self._flags[first].data_ptr(), self._spread[first].data_ptr(), 0, s)
         if chain_tol is not None:
-            c.shmm_surrogate_chain_gate(first, count, self.K_solve[first].data_ptr(), self._spread[first].data_ptr(),
-                                        self.K_in.data_ptr(), chain_tol, self._flags[first].data_ptr(), s)
+            c.shmm_surrogate_chain_gate(first, count, self.K_solve[first].data_ptr(), self.K_base[first].data_ptr(),
+                                        self._spread[first].data_ptr(), self.K_in.data_ptr(), chain_tol,
+                                        self._flags[first].data_ptr(), s)
         c.shmm_fallback_solve(first, count, self._flags[first].data_ptr(), self.vx.data_ptr(), self.vy.data_ptr(),
                               self.f1.data_ptr(), self.f2.data_ptr(), self.K_base.data_ptr(), self.w.data_ptr(),
                               self.K_solve.data_ptr(), 0, 0.0, self.status.data_ptr(), s)

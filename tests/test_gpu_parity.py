@@ -149,11 +149,13 @@ def _single_level(n, seed, amp, kappa, lattice=2, radius=None):
 
 @pytest.mark.parametrize("n,steps,variant", [(8, None, 0), (16, None, 0), (32, None, 0),
                                              (64, 400, 0), (64, 400, 1), (64, 400, 2), (64, 400, 3),
-                                             (64, 400, 4), (128, 60, 0), (128, 60, 1), (128, 60, 2),
+                                             (64, 400, 4), (64, 400, 5), (64, 400, 6),
+                                             (128, 60, 0), (128, 60, 1), (128, 60, 2),
                                              (128, 60, 3), (128, 60, 4), (128, 60, 5), (128, 60, 6),
+                                             (128, 60, 7), (128, 60, 8),
                                              (256, 12, 0), (256, 12, 1),
                                              (256, 12, 2), (256, 12, 3), (256, 12, 4),
-                                             (256, 12, 5), (256, 12, 6)])
+                                             (256, 12, 5), (256, 12, 6), (256, 12, 7)])
 def test_local_solve_and_estimator_parity(torch, n, steps, variant):
     """Band filter + RK4 local solve + FP64 estimator against the oracle's own
     synthesis, solve and estimator, on an anisotropic base (every kernel variant)."""
@@ -285,11 +287,11 @@ def test_windowed_patches_parity(torch, n, taper, steps):
 
 
 @pytest.mark.parametrize("n,steps,variant", [(32, None, None), (64, 400, None), (128, 60, None), (256, 12, None),
-                                             (256, 300, 6), (256, 300, 2)])
+                                             (256, 300, 6), (256, 300, 7), (256, 300, 2)])
 def test_zero_frame_local_problem_parity(torch, n, steps, variant):
     """Zero-frame (non-periodic) local problems (resident kernels up to 128^2;
-    at 256^2 the ring-exchange bands, the default, and the per-stage kernel,
-    variant 2): correctors against the oracle's zero-frame solve of its own
+    at 256^2 the ring-exchange bands, the default, with and without pipelined
+    reads, and the per-stage kernel, variant 2): correctors against the oracle's zero-frame solve of its own
     synthesis, the frame cells exactly zero, and the estimate over the
     centred (n - 2)^2 window."""
     from paper_1510_00451_amd import abi
@@ -379,6 +381,34 @@ def test_chunked_solve_matches_single_launch(torch, n):
     H.close()
 
 
+@pytest.mark.parametrize("n,pairs", [(64, ((3, 5), (4, 6))), (128, ((5, 7), (6, 8)))])
+def test_pipelined_reads_are_bit_identical(torch, n, pairs):
+    """The resident kernels that read the stage input a row further ahead
+    (pipelined LDS reads) run the same arithmetic in the same order as their
+    plain counterparts: 300 steps of 16 patches agree bit for bit."""
+    p = _single_level(n, seed=n + 1, amp=0.3, kappa=0.05, lattice=4)
+    say("case pipelined reads n=%d" % n)
+    H = hier(p, keep_psi=False)
+    H.band_filter()
+    nd = H.nd
+    Kb = np.tile([0.05, 0.004, 0.06], (nd, 1))
+    H.K_base.copy_(torch.from_numpy(Kb))
+    H.ctx.shmm_plan_steps(0, nd, Kb)
+    args = (H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(),
+            H.w.data_ptr())
+    for plain, piped in pairs:
+        out = []
+        for v in (plain, piped):
+            H.ctx.shmm_ctx_tune(n, v)
+            H.w.zero_()
+            H.ctx.shmm_local_solve_batch(0, nd, *args, 0, 300, 0, H.stream())
+            torch.cuda.synchronize()
+            out.append(H.w.cpu().numpy().copy())
+        assert np.abs(out[0]).max() > 0
+        assert np.array_equal(out[0], out[1]), (plain, piped)
+    H.close()
+
+
 def test_tile_paths_follow_each_patch_plan(torch):
     """The 256^2 region paths (full-width bands, square tiles and the
     persistent bands with a ring exchange) on 64
@@ -404,7 +434,7 @@ def test_tile_paths_follow_each_patch_plan(torch):
     assert ns.min() > 0 and ns.max() > ns.min() + 8
     args = (H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(),
             H.w.data_ptr())
-    variants = (0, 1, 3, 4, 5, 6)
+    variants = (0, 1, 3, 4, 5, 6, 7)
     out = {}
     for v in variants:
         say("  variant", v)
@@ -415,8 +445,10 @@ def test_tile_paths_follow_each_patch_plan(torch):
         out[v] = H.w.cpu().numpy().copy()
     for v in variants[1:]:
         assert relerr(out[v], out[0]) <= 1e-6, v
-    # the ring exchange carries exactly the rows the bands would reload
+    # the ring exchange carries exactly the rows the bands would reload,
+    # with or without the pipelined reads
     assert np.array_equal(out[6], out[0])
+    assert np.array_equal(out[7], out[0])
     # the same in chunks of 7 steps (windows of 2, 2, 2 and 1 step; the
     # compensation restarts with every call on both paths)
     chunked = {}

@@ -388,6 +388,66 @@ def test_feature_stats_and_rescale(torch):
     ctx.close()
 
 
+def test_chain_gate_rule(torch):
+    """shmm_surrogate_chain_gate on hand-built inputs: a domain with a parent
+    is flagged when its predicted change of the base plus its spread times
+    |K_hat| exceeds tol times the smallest lambda_min(K_in) over its
+    ancestors; a flag already set stays set, and domains without a parent are
+    left alone."""
+    from paper_1510_00451_amd.hierarchy import Hierarchy
+    H = Hierarchy(flowgen.config_four_level_cellular(n=16, lattice=2), keep_psi=False)
+    say("case chain gate rule")
+    rng = np.random.default_rng(3)
+    table = H.table
+    nd, tol = H.nd, 1e-2
+    K_in = np.empty((nd, 3))
+    lam_in = rng.uniform(0.5, 2.0, nd)
+    K_in[:, 0] = lam_in + rng.uniform(0.0, 1.0, nd)
+    K_in[:, 2] = lam_in + rng.uniform(0.0, 1.0, nd)
+    K_in[:, 1] = rng.uniform(-0.3, 0.3, nd)
+    d_K_in = torch.from_numpy(K_in).cuda()
+    m_, q_ = 0.5 * (K_in[:, 0] + K_in[:, 2]), 0.5 * (K_in[:, 0] - K_in[:, 2])
+    lam_dom = m_ - np.sqrt(q_ * q_ + K_in[:, 1] ** 2)
+    lam_anc = np.full(nd, np.inf)                 # smallest over the parent and its ancestors
+    for i in range(nd):
+        a = int(table["parent"][i])
+        while a >= 0:
+            lam_anc[i] = min(lam_anc[i], lam_dom[a])
+            a = int(table["parent"][a])
+    checked, raised = 0, 0
+    for p_ in range(len(H.phase) - 1):
+        first, count = int(H.phase[p_]), int(H.phase[p_ + 1] - H.phase[p_])
+        Kb = np.stack([rng.uniform(1, 2, count), rng.uniform(-0.1, 0.1, count), rng.uniform(1, 2, count)], 1)
+        dK = rng.normal(size=(count, 3)) * 10.0 ** rng.uniform(-4, -1, (count, 1))
+        Kh = Kb + dK
+        spread = 10.0 ** rng.uniform(-5, -2, count)
+        par = table["parent"][first:first + count]
+        lam = lam_anc[first:first + count]
+        fro = lambda A: np.sqrt(A[:, 0] ** 2 + 2 * A[:, 1] ** 2 + A[:, 2] ** 2)
+        ratio = (fro(Kh - Kb) + spread * fro(Kh)) / (tol * lam)
+        keep = np.abs(ratio - 1.0) > 1e-6          # away from the threshold: FMA contraction may differ
+        pre = (rng.uniform(size=count) < 0.2).astype(np.uint8)
+        want = pre.copy()
+        want[(par >= 0) & (ratio > 1.0)] = 1
+        flags = torch.from_numpy(pre.copy()).cuda()
+        d_Kh, d_Kb, d_sp = (torch.from_numpy(a).cuda() for a in (Kh, Kb, spread))   # held until the call ends
+        H.ctx.shmm_surrogate_chain_gate(first, count, d_Kh.data_ptr(), d_Kb.data_ptr(), d_sp.data_ptr(),
+                                        d_K_in.data_ptr(), tol, flags.data_ptr(), H.stream())
+        torch.cuda.synchronize()
+        got = flags.cpu().numpy()
+        assert np.array_equal(got[keep], want[keep]), p_
+        if (par < 0).all():
+            assert np.array_equal(got, pre)
+        free = (par >= 0) & keep & (pre == 0)
+        checked += int(free.sum())
+        raised += int((free & (ratio > 1.0)).sum())
+    assert 0 < raised < checked      # both outcomes were exercised
+    with pytest.raises(abi.ShmmError):
+        H.ctx.shmm_surrogate_chain_gate(0, 1, d_K_in.data_ptr(), d_K_in.data_ptr(), d_K_in.data_ptr(),
+                                        d_K_in.data_ptr(), 0.0, d_K_in.data_ptr(), H.stream())
+    H.close()
+
+
 def test_surrogate_through_every_level(torch):
     """The surrogate in place of every phase's local solves (Hierarchy.use_surrogate):
     with a gate that flags every patch the pass is the plain pass bit for bit
