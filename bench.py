@@ -50,8 +50,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (256 CU, 2
 # the scale factors read off a 1 GiB device copy.  Valid only for the kernel
 # code they were taken on (first 16 hex digits of the SHA-256 of solve.hip and
 # solve_stage.h without comments and blank lines); otherwise reported null.
-SOLVE_TRAFFIC = {"code_sha256": "7716f7888ddc9b81", "variant": 5,
-                 "bytes_per_launch": (2 * 50172.5 + 35262.45) * 1024}
+SOLVE_TRAFFIC = {"code_sha256": "db8b6f4f1caf9ec4", "variant": 7,
+                 "bytes_per_launch": (2 * 50212.11 + 36282.65) * 1024}
 SOLVE_KERNELS_128 = {0: "k_solve_resident<128,32>", 1: "k_solve_rows<128,2,16>", 2: "k_solve_rows<128,2,8>",
                      3: "k_solve_resident_e<128,32>", 4: "k_solve_resident_e<128,16>",
                      5: "k_solve_resident_e<128,32,8>", 6: "k_solve_resident_e<128,32,16>",

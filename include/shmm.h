@@ -311,22 +311,23 @@ int shmm_level_chain(shmm_ctx *ctx, int64_t first, int64_t count, int32_t mode,
  * key = SHMM_TUNE_SOLVE_VARIANT_COUNT with value = n (a non-negative return).
  * n = 64: 0 = whole patch in LDS, column strips of 16 (split operator form);
  *   1, 2 = rows per wavefront, 16 or 8 rows per thread; 3 = whole patch in
- *   LDS, coefficient form, strips of 16 (default); 4 = the same, strips of 8;
+ *   LDS, coefficient form, strips of 16; 4 = the same, strips of 8;
  *   5, 6 = 3 and 4 with the stage input read a row further ahead (pipelined
- *   LDS reads, bit-identical results).
+ *   LDS reads, bit-identical results; 5 is the default).
  * n = 128: 0 = split form, strips of 32; 1, 2 = rows per wavefront (16, 8);
  *   3, 4 = coefficient form, strips of 32 or 16; 5 = strips of 32 with the
- *   compensation of 8 strip rows in LDS (default); 6 = the same with 16 rows;
- *   7, 8 = 5 and 6 with pipelined LDS reads (bit-identical results).
+ *   compensation of 8 strip rows in LDS; 6 = the same with 16 rows;
+ *   7, 8 = 5 and 6 with pipelined LDS reads (bit-identical results; 7 is
+ *   the default).
  * n = 256: 0 = full-width bands of 32 rows with 8-row rings, 768 threads,
  *   relaunched every 2 steps; 1 = the same at 1024 threads; 2 = one launch per
  *   RK stage; 3 = bands of 24 rows with 12-row rings (3 steps per launch);
  *   4 = bands of 16 rows, 256 threads; 5 = square 64 x 64 tiles with 8-cell
  *   rings; 6 = the bands of 0 kept resident for all steps, neighbours
- *   exchanging their ring rows every 2 steps (default; in a call whose range
- *   also holds other patch sizes it runs first and alone, and the other
- *   sizes follow, concurrently with one another); 7 = 6 with pipelined LDS
- *   reads (bit-identical results, also run alone).
+ *   exchanging their ring rows every 2 steps (in a call whose range also
+ *   holds other patch sizes it runs first and alone, and the other sizes
+ *   follow, concurrently with one another); 7 = 6 with pipelined LDS reads
+ *   (bit-identical results, also run alone; the default).
  * Other sizes have one variant.
  * Errors: SHMM_EINVAL for an unknown key or value. */
 #define SHMM_TUNE_SOLVE_VARIANT_COUNT 0

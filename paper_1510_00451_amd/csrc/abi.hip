@@ -170,9 +170,24 @@ using namespace shmm;
 struct RangeLists {
     std::vector<int> ns;               // distinct n in the range
     std::vector<int32_t *> d_lists;    // device list per n
+    std::vector<std::vector<int32_t>> h_lists;   // host copy, in launch order
     std::vector<int32_t> counts;
     std::vector<int64_t> cells;        // cells per list
 };
+
+// Launch order of a list: longest plan first.  Workgroups of one size take
+// the same time per step, one per CU for the larger sizes, and the hardware
+// hands them out in order as CUs free up, so this is longest-processing-time
+// list scheduling: the plans of a phase differ (the coarsest level of the
+// continuous-spectrum flow spans 1.36e6 to 1.71e6 steps), and table order
+// leaves the last CUs running alone for up to 5% of the phase, this order for
+// under 1%.  Results do not depend on the order.
+static bool order_by_plan(const std::vector<shmm_domain> &table, std::vector<int32_t> &ids) {
+    std::vector<int32_t> before = ids;
+    std::stable_sort(ids.begin(), ids.end(),
+                     [&](int32_t a, int32_t b) { return table[a].nsteps > table[b].nsteps; });
+    return ids != before;
+}
 
 constexpr int kSideStreams = 3;   // patch sizes of one range solved concurrently
 
@@ -301,11 +316,13 @@ struct shmm_ctx {
             for (int64_t d = first; d < first + count; ++d)
                 if (!empty[table[d].instance][table[d].level]) byn[table[d].n].push_back((int32_t)d);
             for (auto &kv : byn) {
+                order_by_plan(table, kv.second);
                 int32_t *p = nullptr;
                 int rc = upload(&p, kv.second.data(), kv.second.size());
                 if (rc) return rc;
                 rl.ns.push_back(kv.first);
                 rl.d_lists.push_back(p);
+                rl.h_lists.push_back(kv.second);
                 rl.counts.push_back((int32_t)kv.second.size());
                 rl.cells.push_back((int64_t)kv.second.size() * kv.first * kv.first);
             }
@@ -317,11 +334,12 @@ struct shmm_ctx {
 };
 
 // Kernel variant per patch size when no tuning result was set: the
-// LDS-staged kernel in coefficient form (the fastest in the measurements on
-// MI355X; sizes below 64 have no other variant).
-static int default_solve_variant(int n) { return n == 64 ? 3 : n == 128 ? 5 : n == 256 ? 6 : 0; }
+// LDS-staged kernel in coefficient form with pipelined reads, and at 256^2 the
+// ring-exchange bands with pipelined reads (the fastest in the measurements
+// on MI355X; sizes below 64 have no other variant).
+static int default_solve_variant(int n) { return n == 64 ? 5 : n == 128 ? 7 : n == 256 ? 7 : 0; }
 
-// The ring-exchange bands (n = 256, variant 6) need every workgroup of a
+// The ring-exchange bands (n = 256, variants 6 and 7) need every workgroup of a
 // group running at once; beside kernels that hold CUs for whole solves they
 // would sit partly dispatched, so they run alone.
 static bool runs_alone(int n, int variant) { return n == 256 && (variant == 6 || variant == 7); }
@@ -622,6 +640,23 @@ int shmm_plan_steps(shmm_ctx *ctx, int64_t first, int64_t count, const double *K
     if (count > 0)
         SHMM_HIP_CHECK(hipMemcpy(ctx->d_table + first, ctx->table.data() + first,
                                  count * sizeof(shmm_domain), hipMemcpyHostToDevice));
+    // launch lists of ranges that overlap the new plans: longest plan first
+    // again, rewritten in place (a captured graph keeps its list pointers)
+    bool synced = false;
+    for (auto &kv : ctx->lists) {
+        const int64_t a = kv.first.first, b = kv.first.first + kv.first.second;
+        if (b <= first || a >= first + count) continue;
+        RangeLists &rl = kv.second;
+        for (size_t q = 0; q < rl.h_lists.size(); ++q) {
+            if (!order_by_plan(ctx->table, rl.h_lists[q])) continue;
+            if (!synced) {   // no solve may be reading a list while it is rewritten
+                SHMM_HIP_CHECK(hipDeviceSynchronize());
+                synced = true;
+            }
+            SHMM_HIP_CHECK(hipMemcpy(rl.d_lists[q], rl.h_lists[q].data(), rl.h_lists[q].size() * sizeof(int32_t),
+                                     hipMemcpyHostToDevice));
+        }
+    }
     return SHMM_OK;
 }
 

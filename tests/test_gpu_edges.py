@@ -307,19 +307,20 @@ def test_ring_wait_gives_up_from_the_host(torch):
     H.ctx.shmm_plan_steps(first, count, Kb)
     args = (H.vx.data_ptr(), H.vy.data_ptr(), H.f1.data_ptr(), H.f2.data_ptr(), H.K_base.data_ptr(),
             H.w.data_ptr())
-    H.ctx.shmm_ctx_tune(256, 6)
-    H.ctx.shmm_ctx_tune(abi.TUNE_RING_SPIN_CAP, 0)
-    H.w.zero_()
-    H.status.zero_()
-    H.ctx.shmm_local_solve_batch(first, count, *args, 0, 10, H.status.data_ptr(), H.stream())
-    torch.cuda.synchronize()
-    st = H.status.cpu().numpy()[first:first + count]
-    assert np.all(st == abi.DOM_NONFINITE), st
     a, b = H.cell_range(first, count)
-    assert np.isnan(H.w.view(2, H.cells)[:, a:b].cpu().numpy()).any()
+    H.ctx.shmm_ctx_tune(abi.TUNE_RING_SPIN_CAP, 0)
+    for ring in (6, 7):                      # the ring-exchange bands, plain and with pipelined reads
+        H.ctx.shmm_ctx_tune(256, ring)
+        H.w.zero_()
+        H.status.zero_()
+        H.ctx.shmm_local_solve_batch(first, count, *args, 0, 10, H.status.data_ptr(), H.stream())
+        torch.cuda.synchronize()
+        st = H.status.cpu().numpy()[first:first + count]
+        assert np.all(st == abi.DOM_NONFINITE), (ring, st)
+        assert np.isnan(H.w.view(2, H.cells)[:, a:b].cpu().numpy()).any()
     out = {}
     H.ctx.shmm_ctx_tune(abi.TUNE_RING_SPIN_CAP, 1 << 25)
-    for v in (6, 0):
+    for v in (6, 7, 0):
         H.ctx.shmm_ctx_tune(256, v)
         H.w.zero_()
         H.status.zero_()
@@ -327,5 +328,5 @@ def test_ring_wait_gives_up_from_the_host(torch):
         torch.cuda.synchronize()
         assert int(H.status.max()) == 0
         out[v] = H.w.cpu().numpy().copy()
-    assert np.array_equal(out[6], out[0]) and np.isfinite(out[6]).all()
+    assert np.array_equal(out[6], out[0]) and np.array_equal(out[7], out[0]) and np.isfinite(out[6]).all()
     H.close()
