@@ -425,6 +425,10 @@ def surrogate_full_leg(label_flows: int = 1960, eval_flows: int = 4096, sample_e
         for name, pair in zip(("p99", "max"), gates_arg.split(";")):
             t, e = (float(v) for v in pair.split(","))
             gates[name] = {"tau": t, "emax": e}
+    if eval_flows <= 0:                 # training only (with `save`: evaluate in a later run)
+        ctx.close()
+        return {"train": info, "gates": {k: {kk: (None if isinstance(vv, float) and not math.isfinite(vv) else vv)
+                                             for kk, vv in v.items()} for k, v in gates.items()}}
     if calib_flows:
         t0 = time.perf_counter()
         cal = GS.IsotropicPhase([flowgen.config_continuous(seed=q) for q in range(300000, 300000 + calib_flows)])
@@ -963,6 +967,7 @@ def main():
                     help="only the surrogate at its full size (500k labels, 2^20 evaluation patches)")
     ap.add_argument("--surrogate-full-eval-flows", type=int, default=4096)
     ap.add_argument("--surrogate-full-label-flows", type=int, default=1960)
+    ap.add_argument("--surrogate-full-steps", type=int, default=12000, help="Adam steps of the at-size training")
     ap.add_argument("--surrogate-full-save", default="", help="write the trained ensemble and gates here (.npz)")
     ap.add_argument("--surrogate-full-load", default="", help="evaluate an ensemble saved by --surrogate-full-save")
     ap.add_argument("--surrogate-full-gates", default="",
@@ -1000,6 +1005,7 @@ def main():
     torch.cuda.set_device(0)
     if args.surrogate_full:
         r = surrogate_full_leg(label_flows=args.surrogate_full_label_flows, eval_flows=args.surrogate_full_eval_flows,
+                               steps=args.surrogate_full_steps,
                                save=args.surrogate_full_save, load=args.surrogate_full_load,
                                gates_arg=args.surrogate_full_gates, calib_flows=args.surrogate_full_calib_flows,
                                dump=args.surrogate_full_dump)

@@ -386,12 +386,15 @@ int shmm_macro_step_noalloc(shmm_ctx *ctx, int32_t N, int32_t bc, double g0, dou
  * Learned surrogate of the local solve (not part of the paper's method).
  * A patch is described by 35 features.  Features 0..31 are log band energies
  * of the velocity spectrum of the patch samples (treated as periodic, DFT
- * normalised by 1/n^2, scaled by (L / 2 pi)^2) over the base: feature 8c + b
- * is log((E_cb + 1e-8 E_tot + 1e-30) / det K_b), where E_cb sums channel c
- * over the modes k
- * (patch-relative integers) with 2^b <= k1^2 + k2^2 < 2^(b+1), b = 0..7; the
- * channels are |Vx|^2, |Vy|^2, |Vx + Vy|^2 / 2 and |Vx - Vy|^2 / 2, and E_tot
- * is the sum of channels 0 and 1 over the bins.  Feature 32 is
+ * normalised by 1/n^2) over the base: feature 8c + b is
+ * log((E_cb + 1e-8 E_tot + 1e-30) / det K_b), where E_cb sums channel c times
+ * (L / 2 pi)^2 / q^2 (one over the squared physical wavenumber) over the modes
+ * k (patch-relative integers, q = |k|) with 2^b <= q < 2^(b+1), b = 0..7
+ * (every mode of a patch of up to 256^2 but the mean); the channels are
+ * |Vx|^2, |Vy|^2, |Vx + Vy|^2 / 2 and |Vx - Vy|^2 / 2, and E_tot is the sum of
+ * channels 0 and 1 over the bins.  For an isotropic base kappa I the bin sums
+ * over kappa are the local solve's K - K_b to first order in the Peclet
+ * number (exactly for a shear flow).  Feature 32 is
  * log sqrt(det K_b).  Features 33 and 34 carry the anisotropy of the base:
  * the entries (1,1) and (1,2) of the traceless part of log K_b, that is
  * g(rho) (K11 - K22) / (K11 + K22) and g(rho) 2 K12 / (K11 + K22) with

@@ -7,26 +7,29 @@ The paper has no surrogate; these definitions are this project's readings:
   channels x 8 radial bins.  With the patch samples treated as periodic and
   the DFT normalised so that sum_k |vx^(k)|^2 = mean(vx^2), the channels of a
   mode k are |vx^|^2, |vy^|^2, |vx^ + vy^|^2 / 2 and |vx^ - vy^|^2 / 2 (the
-  last two carry the cross spectrum, which decides the sign of K12); bin b
-  holds the patch-relative integer wavenumbers with 2^b <= k1^2 + k2^2 <
-  2^(b+1), b = 0..7, so q = |k| in [1, 16) in half-octaves.  Energies are
-  scaled by (L / 2 pi)^2 (L the patch side) so the features carry
-  stream-function units (K / kappa is invariant under rescaling space).
-  feature_{8c+b} = log((E_cb + 1e-8 E_tot + 1e-30) / det K_b), E_tot the sum
-  of channels 0 and 1 over the bins (the floor sits far above the rounding
-  noise of an FP32 transform, about 1e-12 E_tot, so empty bins read the same
-  in FP32 and FP64).  Dividing by det K_b makes these 32 features squared
-  Peclet numbers: for an isotropic base the local problem is invariant under
-  scaling velocity and diffusivity together (K scales with them), so K / kappa
-  depends on them alone.  Feature 32 is log sqrt(det K_b).  Features 33 and
+  last two carry the cross spectrum, which decides the sign of K12).  Bin b
+  holds the patch-relative integer wavenumbers k with q = |k| in [2^b, 2^(b+1)),
+  b = 0..7 (octaves of q from 1 to 256: every mode of a patch of up to 256^2
+  but the mean).  Each mode enters its bin weighted by (L / 2 pi)^2 / q^2, L
+  the patch side: E_cb = sum over the bin of channel_c(k) / |k_phys|^2, with
+  k_phys = 2 pi k / L.  At small Peclet number the local solve gives, to first
+  order, K11 - K_b11 = sum_b E_0b / kappa, K22 - K_b22 = sum_b E_1b / kappa and
+  K12 - K_b12 = sum_b (E_2b - E_3b) / (2 kappa) for an isotropic base kappa I
+  (exactly, for a shear flow), so these energies carry that limit whatever the
+  width of the bins; the bins resolve where in the spectrum the energy sits,
+  which the higher orders need.  feature_{8c+b} = log((E_cb + 1e-8 E_tot +
+  1e-30) / det K_b), E_tot the sum of channels 0 and 1 over the bins (the floor
+  sits far above the rounding noise of an FP32 transform, about 1e-12 E_tot,
+  so empty bins read the same in FP32 and FP64).  Dividing by det K_b makes
+  these 32 features squared Peclet numbers: for an isotropic base the local
+  problem is invariant under scaling velocity and diffusivity together (K
+  scales with them), so K / kappa depends on them alone.  Feature 32 is log sqrt(det K_b).  Features 33 and
   34 carry the anisotropy of the base: the (1,1) and (1,2) entries of the
   traceless part of the matrix logarithm log K_b (zero for an isotropic base,
   unchanged when the base is scaled, turning with twice the angle of its
   principal axes), so that a base from a coarser level's chain (Algorithm 3)
-  can be given to the network.  At small
-  Peclet number K - K_b is, to first order, a sum over modes of these channel
-  energies divided by q^2 and kappa, so the directional channels give the
-  network the anisotropy that radial energies alone cannot.
+  can be given to the network.  The directional channels give the network
+  the anisotropy of K that radial energies alone cannot.
 * Gate: a patch falls back to the plain solve when a feature leaves the
   training range, when the ensemble disagrees (spread > tau), or when the
   predicted enhancement is beyond emax (the regime where the network was not
@@ -66,13 +69,15 @@ N_RADIAL = 8
 
 
 def bin_of(k1: int, k2: int) -> int:
-    """Radial bin of the integer wavenumber (k1, k2), or -1 outside q^2 in [1, 256)."""
+    """Octave bin of the integer wavenumber (k1, k2): b with 2^b <= |k| < 2^(b+1),
+    i.e. 4^b <= k1^2 + k2^2 < 4^(b+1); -1 for the mean and for |k| >= 256."""
     q2 = k1 * k1 + k2 * k2
-    return q2.bit_length() - 1 if 1 <= q2 < 256 else -1
+    return (q2.bit_length() - 1) // 2 if 1 <= q2 < 4 ** N_RADIAL else -1
 
 
 def channel_energies(vx: np.ndarray, vy: np.ndarray, n: int, N: int) -> np.ndarray:
-    """E[c][b]: channel c summed over radial bin b (see the module docstring)."""
+    """E[c][b]: channel c over |k_phys|^2, summed over octave bin b (see the
+    module docstring)."""
     vx = np.asarray(vx, np.float64).reshape(n, n)
     vy = np.asarray(vy, np.float64).reshape(n, n)
     X = np.fft.fft2(vx) / float(n * n)
@@ -86,8 +91,9 @@ def channel_energies(vx: np.ndarray, vy: np.ndarray, n: int, N: int) -> np.ndarr
             b = bin_of(int(k[i]), int(k[j]))
             if b < 0:
                 continue
+            q2 = float(k[i] * k[i] + k[j] * k[j])
             for c in range(N_CHANNELS):
-                E[c, b] += chans[c][j, i] * s
+                E[c, b] += chans[c][j, i] * s / q2
     return E
 
 

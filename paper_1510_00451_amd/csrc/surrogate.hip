@@ -77,46 +77,58 @@ __global__ __launch_bounds__(256) void k_feat_cols(int n, c32 *work) {
     for (int t = tid; t < n; t += per) src[(int64_t)t * n + c0 + col] = res[t];
 }
 
-constexpr int kFeatWin = 31;   // |k1|, |k2| <= 15 holds every mode with q^2 < 256
+constexpr int kFeatThreads = 256;
 
 // One workgroup per patch.  With A(k) = Vx(k) + i Vy(k) (Vx, Vy the transforms
 // of the real fields), Vx(k) = (A(k) + conj A(-k))/2 and Vy(k) = (A(k) -
 // conj A(-k))/(2i).  Channel energies per mode: |Vx|^2, |Vy|^2, |Vx+Vy|^2/2,
-// |Vx-Vy|^2/2; radial bin b = floor(log2(k1^2 + k2^2)), 0 <= b < 8.  Bin sums
-// run in a fixed mode order; the features are their logarithms over det K_b.
-__global__ __launch_bounds__(256) void k_feat_bins(const shmm_domain *dom, const int32_t *list, int n,
-                                                   const c32 *work, const double *Kb, float *features) {
-    __shared__ float ch[4][kFeatWin * kFeatWin];
-    __shared__ int8_t bin[kFeatWin * kFeatWin];
+// |Vx-Vy|^2/2, each over |k_phys|^2 = q^2 (2 pi / L)^2; octave bin
+// b = floor(log2 q), 0 <= b < 8, over every mode of the patch but the mean.
+// Each thread sums a fixed stride of the modes, then one thread per bin adds
+// the threads' partial sums in thread order: bitwise reproducible.  The
+// features are the logarithms of the bin sums over det K_b.
+__global__ __launch_bounds__(kFeatThreads) void k_feat_bins(const shmm_domain *dom, const int32_t *list, int n,
+                                                            const c32 *work, const double *Kb, float *features) {
+    __shared__ float part[SHMM_SURR_BINS][kFeatThreads];
     __shared__ float E[SHMM_SURR_BINS];
     const int li = blockIdx.x;
     const int64_t d = list[li];
     const int N = dom[d].N;
-    const int klo = -min(15, n / 2), khi = min(15, n / 2 - 1);
-    const int w = khi - klo + 1, modes = w * w;
     const c32 *A = work + (int64_t)li * n * n;
     const float scale = (float)((double)n / (double)N * (double)n / (double)N / ((double)n * n * n * n));
-    for (int m = threadIdx.x; m < modes; m += blockDim.x) {
-        const int k2 = klo + m / w, k1 = klo + m % w;
+    const int half = n / 2, mask = n - 1;
+    float acc[SHMM_SURR_BINS];
+#pragma unroll
+    for (int c = 0; c < SHMM_SURR_BINS; ++c) acc[c] = 0.0f;
+    for (int m = threadIdx.x; m < n * n; m += kFeatThreads) {
+        const int jr = m / n, ic = m - jr * n;
+        const int k1 = ic < half ? ic : ic - n, k2 = jr < half ? jr : jr - n;
         const int q2 = k1 * k1 + k2 * k2;
-        bin[m] = (int8_t)((q2 >= 1 && q2 < 256) ? 31 - __builtin_clz((unsigned)q2) : -1);
-        const c32 p = A[(int64_t)(k2 & (n - 1)) * n + (k1 & (n - 1))];
-        const c32 r = A[(int64_t)((-k2) & (n - 1)) * n + ((-k1) & (n - 1))];
-        // Vx = (p + conj r)/2, Vy = (p - conj r)/(2i)
+        const int b = q2 >= 1 ? (31 - __builtin_clz((unsigned)q2)) >> 1 : -1;
+        if (b < 0 || b >= 8) continue;
+        const c32 p = A[m];
+        const c32 r = A[(int64_t)((-k2) & mask) * n + ((-k1) & mask)];
         const float vxr = 0.5f * (p.x + r.x), vxi = 0.5f * (p.y - r.y);
         const float vyr = 0.5f * (p.y + r.y), vyi = -0.5f * (p.x - r.x);
         const float pr = vxr + vyr, pi = vxi + vyi, mr = vxr - vyr, mi = vxi - vyi;
-        ch[0][m] = (vxr * vxr + vxi * vxi) * scale;
-        ch[1][m] = (vyr * vyr + vyi * vyi) * scale;
-        ch[2][m] = 0.5f * (pr * pr + pi * pi) * scale;
-        ch[3][m] = 0.5f * (mr * mr + mi * mi) * scale;
+        const float wq = scale / (float)q2;
+        const float e0 = (vxr * vxr + vxi * vxi) * wq, e1 = (vyr * vyr + vyi * vyi) * wq;
+        const float e2 = 0.5f * (pr * pr + pi * pi) * wq, e3 = 0.5f * (mr * mr + mi * mi) * wq;
+#pragma unroll
+        for (int bb = 0; bb < 8; ++bb) {      // register accumulators: no dynamic index
+            const bool h = b == bb;
+            acc[bb] += h ? e0 : 0.0f;
+            acc[8 + bb] += h ? e1 : 0.0f;
+            acc[16 + bb] += h ? e2 : 0.0f;
+            acc[24 + bb] += h ? e3 : 0.0f;
+        }
     }
+#pragma unroll
+    for (int c = 0; c < SHMM_SURR_BINS; ++c) part[c][threadIdx.x] = acc[c];
     __syncthreads();
     if (threadIdx.x < SHMM_SURR_BINS) {
-        const int c = threadIdx.x / 8, b = threadIdx.x % 8;
         float sum = 0.0f;
-        for (int m = 0; m < modes; ++m)
-            if (bin[m] == b) sum += ch[c][m];
+        for (int t = 0; t < kFeatThreads; ++t) sum += part[threadIdx.x][t];
         E[threadIdx.x] = sum;
     }
     __syncthreads();
@@ -559,7 +571,7 @@ int launch_patch_features(const shmm_domain *d_dom, const int32_t *d_list, int32
     SHMM_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_feat_cols, grid, dim3(256), 2 * kFeatRows * n * sizeof(c32), s, n, fw);
     SHMM_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(k_feat_bins, dim3((unsigned)nlist), dim3(256), 0, s, d_dom, d_list, n, (const c32 *)fw, Kb,
+    hipLaunchKernelGGL(k_feat_bins, dim3((unsigned)nlist), dim3(kFeatThreads), 0, s, d_dom, d_list, n, (const c32 *)fw, Kb,
                        features);
     SHMM_HIP_CHECK(hipGetLastError());
     return SHMM_OK;

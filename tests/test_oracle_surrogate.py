@@ -26,9 +26,10 @@ def test_features_single_mode_closed_form():
     vx, vy = _mode(n, a, b, A, B)
     Kb = [0.02, 0.005, 0.03]
     f = S.patch_features(vx, vy, n, N, Kb)
-    bq = int(math.floor(math.log2(a * a + b * b)))          # 13 -> bin 3
-    assert bq == 3
-    s = (n / N) ** 2
+    q2 = a * a + b * b
+    bq = int(math.floor(math.log2(math.sqrt(q2))))          # |k| = 3.6 -> octave bin 1
+    assert bq == 1
+    s = (n / N) ** 2 / q2                                   # (L / 2 pi)^2 / |k|^2
     # cos splits into +-k with amplitude 1/2 each: sum over the pair of |c/2|^2 = c^2/2
     E = [A * A / 2 * s, B * B / 2 * s, (A + B) ** 2 / 4 * s, (A - B) ** 2 / 4 * s]
     Etot = E[0] + E[1]
@@ -40,6 +41,25 @@ def test_features_single_mode_closed_form():
     expect[32] = 0.5 * math.log(det)
     expect[33:35] = S.log_base_anisotropy(Kb)
     np.testing.assert_allclose(f, expect, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,N,a,V", [(32, 128, 3, 0.4), (64, 64, 5, 1.3), (128, 2048, 20, 0.05)])
+def test_features_carry_the_taylor_dispersion_of_a_shear_flow(n, N, a, V):
+    """v = (0, V sin(k x)) on a patch (k = a N / n in the units of the global
+    grid): the local problem of a shear flow is solved by K_yy = kappa +
+    V^2 / (2 kappa k^2) at every Peclet number (Taylor dispersion), and the
+    channel-1 energies summed over the bins, over kappa, give exactly that
+    enhancement; channel 0 is empty and the cross channels are equal."""
+    kappa = 0.013
+    i = np.arange(n)
+    X = np.tile(i, (n, 1))
+    vx = np.zeros((n, n))
+    vy = V * np.sin(2 * np.pi * a * X / n)
+    E = S.channel_energies(vx, vy, n, N)
+    k = a * N / n
+    assert abs(E[1].sum() / kappa - V * V / (2 * kappa * k * k)) <= 1e-12 * V * V / (2 * kappa * k * k)
+    assert E[0].sum() <= 1e-30
+    np.testing.assert_allclose(E[2], E[3], rtol=1e-12, atol=1e-30)
 
 
 def test_features_scale_invariance():
@@ -89,7 +109,8 @@ def test_features_quadrature_has_no_cross_spectrum():
     n, N = 32, 32
     vx, vy = _mode(n, 1, 4, 0.5, 0.8, quadrature=True)
     E = S.channel_energies(vx, vy, n, N)
-    b = int(math.floor(math.log2(17)))
+    b = int(math.floor(math.log2(math.sqrt(17))))          # |k| = 4.1 -> octave bin 2
+    assert b == 2
     np.testing.assert_allclose(E[2, b], E[3, b], rtol=1e-12)
     np.testing.assert_allclose(E[2, b], (E[0, b] + E[1, b]) / 2, rtol=1e-12)
 
@@ -106,15 +127,20 @@ def test_features_symmetries():
     np.testing.assert_allclose(Es[[1, 0, 2, 3]], E, rtol=1e-12)
     np.testing.assert_allclose(En[[0, 1, 3, 2]], E, rtol=1e-12)
     np.testing.assert_allclose(E[2] + E[3], E[0] + E[1], rtol=1e-12)
-    # bin populations: sum over bins of a flat spectrum counts the modes with 1 <= q^2 < 256
+    # bin populations: a flat spectrum puts sum of 1 / q^2 over the modes with
+    # 2^b <= q < 2^(b+1) into bin b (N = n: unit spacing of the wavenumbers);
+    # every mode but the mean is counted once
     ones = np.zeros((n, n))
     ones[0, 0] = n * n                    # delta at the origin: flat spectrum |X|^2 = 1
     Ef = S.channel_energies(ones, np.zeros((n, n)), n, n)
-    k = np.arange(-15, 16)
+    k = np.arange(-n // 2, n // 2)
     K1, K2 = np.meshgrid(k, k)
-    q2 = K1 ** 2 + K2 ** 2
+    q2 = (K1 ** 2 + K2 ** 2).astype(float)
+    w = np.where(q2 > 0, 1.0 / np.maximum(q2, 1.0), 0.0)
     for b in range(8):
-        assert Ef[0, b] == np.sum((q2 >= 2 ** b) & (q2 < 2 ** (b + 1)))
+        sel = (q2 >= 4 ** b) & (q2 < 4 ** (b + 1))
+        np.testing.assert_allclose(Ef[0, b], np.sum(w[sel]), rtol=1e-12)
+    np.testing.assert_allclose(Ef[0].sum(), np.sum(w), rtol=1e-12)
 
 
 def test_bf16_rounding_matches_torch():
