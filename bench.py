@@ -52,6 +52,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (256 CU, 2
 # solve_stage.h without comments and blank lines); otherwise reported null.
 SOLVE_TRAFFIC = {"code_sha256": "db8b6f4f1caf9ec4", "variant": 7,
                  "bytes_per_launch": (2 * 50212.11 + 36282.65) * 1024}
+# the ensemble trained at full size (bench.py --surrogate-full --surrogate-full-save ...)
+STORED_ENSEMBLE = os.path.join(ROOT, "paper_1510_00451_amd", "trained", "surrogate_e4_finest128.npz")
 SOLVE_KERNELS_128 = {0: "k_solve_resident<128,32>", 1: "k_solve_rows<128,2,16>", 2: "k_solve_rows<128,2,8>",
                      3: "k_solve_resident_e<128,32>", 4: "k_solve_resident_e<128,16>",
                      5: "k_solve_resident_e<128,32,8>", 6: "k_solve_resident_e<128,32,16>",
@@ -978,6 +980,9 @@ def main():
                     help="write the third gate's calibration errors, enhancements and spreads here (.npz)")
     ap.add_argument("--no-cellular", action="store_true", help="skip the four-level cellular workload")
     ap.add_argument("--no-chained", action="store_true", help="skip the surrogate through every level")
+    ap.add_argument("--no-stored", action="store_true", help="skip the stored at-size ensemble's evaluation")
+    ap.add_argument("--stored-eval-flows", type=int, default=1024,
+                    help="continuous-spectrum flows (seeds 200000 on) the stored ensemble is evaluated on")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--uneven-instances", type=int, default=256)
     ap.add_argument("--uneven-window", type=int, default=2000)
@@ -1075,6 +1080,12 @@ def main():
         out["surrogate"] = surrogate_leg(args.surrogate_flows, args.surrogate_eval_flows,
                                          steps=args.surrogate_steps, lattice=args.surrogate_lattice)
         wall["surrogate"] = round(time.perf_counter() - t_leg, 1)
+    if extras and not args.no_surrogate and not args.no_stored:
+        log("stored at-size ensemble ...")
+        t_leg = time.perf_counter()
+        out["surrogate_stored"] = surrogate_full_leg(eval_flows=args.stored_eval_flows, calib_flows=0,
+                                                     load=STORED_ENSEMBLE)
+        wall["surrogate_stored"] = round(time.perf_counter() - t_leg, 1)
     if extras and not args.no_surrogate and not args.no_chained:
         log("chained surrogate ...")
         t_leg = time.perf_counter()
