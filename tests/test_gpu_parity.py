@@ -663,6 +663,69 @@ def test_solve_batch_replays_from_a_captured_graph(torch, seeds, sizes):
     H.close()
 
 
+def test_captured_graph_follows_new_plans(torch):
+    """Launch lists run longest plan first and are rewritten in place when
+    shmm_plan_steps changes the plans.  A chunk captured under one set of
+    plans and replayed after new plans reversed that order equals an eager
+    solve of a fresh context under the new plans, bit for bit: every patch is
+    solved once, with its new dt, from the same list pointers."""
+    probs = [flowgen.config_batched_instance(i) for i in (1, 2)]          # n = 64
+    assert [p.n_cells[0] for p in probs] == [64, 64]
+    say("case graph replay after new plans")
+
+    def setup():
+        H = hier(probs, keep_psi=False)
+        H.band_filter()
+        return H
+
+    H = setup()
+    first, count = int(H.phase[0]), int(H.phase[1] - H.phase[0])
+    kap = np.array([probs[i].kappa for i in H.table["instance"]])
+    t = np.zeros(H.nd)
+    t[first:first + count] = np.arange(count) / (count - 1)
+    Kb1 = np.stack([kap, 0.1 * kap, kap * (1.0 + 3.0 * t)], 1)
+    Kb2 = np.stack([kap, 0.1 * kap, kap * (4.0 - 3.0 * t)], 1)          # the plans' order reversed
+
+    def chunk(HH, stream):
+        args = (HH.vx.data_ptr(), HH.vy.data_ptr(), HH.f1.data_ptr(), HH.f2.data_ptr(), HH.K_base.data_ptr(),
+                HH.w.data_ptr())
+        HH.ctx.shmm_local_solve_batch(first, count, *args, 0, 20, 0, stream)
+
+    H.K_base.copy_(torch.from_numpy(Kb1))
+    H.ctx.shmm_plan_steps(0, H.nd, Kb1)
+    ns1 = H.ctx.shmm_ctx_table()[0]["nsteps"][first:first + count].copy()
+    H.w.zero_()
+    chunk(H, H.stream())                   # eager: builds the launch lists
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.graph(g, stream=side):
+        chunk(H, torch.cuda.current_stream().cuda_stream)
+    H.K_base.copy_(torch.from_numpy(Kb2))
+    H.ctx.shmm_plan_steps(0, H.nd, Kb2)    # rewrites the lists in place
+    ns2 = H.ctx.shmm_ctx_table()[0]["nsteps"][first:first + count].copy()
+    assert ns1.min() > 20 and ns2.min() > 20
+    # the longest-plan-first order changed
+    assert not np.array_equal(np.argsort(-ns1, kind="stable"), np.argsort(-ns2, kind="stable"))
+    H.w.zero_()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    replay = H.w.cpu().numpy().copy()
+    del g
+    H.close()
+    R = setup()
+    R.K_base.copy_(torch.from_numpy(Kb2))
+    R.ctx.shmm_plan_steps(0, R.nd, Kb2)
+    R.w.zero_()
+    chunk(R, R.stream())
+    torch.cuda.synchronize()
+    ref = R.w.cpu().numpy().copy()
+    R.close()
+    assert np.abs(ref).max() > 0
+    assert np.array_equal(replay, ref)
+
+
 def test_pass_is_deterministic(torch):
     p = flowgen.config_four_level_cellular(n=16, lattice=2)
     say("case determinism")
