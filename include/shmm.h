@@ -156,7 +156,10 @@ int shmm_band_tags(shmm_ctx *ctx, int32_t inst, int8_t *d_tags, void *stream);
  * zero: it gets nsteps = 0, dt = 0 and the local solve leaves it untouched.
  * K_base is host [n_domains][3].  Host arithmetic in a fixed expression order
  * (bit-exact for given inputs); updates the context's table on host and device
- * (synchronous).  Errors: SHMM_ENOTSPD if a base is not positive definite;
+ * (synchronous).  The launch lists of the local solves run longest plan first:
+ * when new plans change that order for a range already solved, its lists are
+ * rewritten in place (so graphs that captured them stay valid) after a
+ * device-wide synchronisation; the order never changes results.  Errors: SHMM_ENOTSPD if a base is not positive definite;
  * SHMM_EINVAL if vmax is NULL and the band filter has not run on the range. */
 int shmm_plan_steps(shmm_ctx *ctx, int64_t first, int64_t count, const double *K_base,
                     const double *vmax);
