@@ -5,19 +5,21 @@
 // most of its time.  Here a group of 2 NN / TH workgroups, every full-width
 // band of both correctors of one patch, stays resident for all of the
 // patch's steps: the state, the compensation and the face coefficients of
-// each region remain in registers and LDS.  After every HALO / 4 steps a band
-// publishes the HALO rows nearest each of its two edges (state and
-// compensation) to a slab in global memory, waits until those stores are
-// complete, signals its round counter and waits until both neighbouring bands
-// of the same corrector have signalled the same round; it then takes its two
-// rings of HALO rows from their slabs.  Slab rows and counters are written
-// and read only as relaxed device-scope atomics, which are coherent across
-// the device by themselves; the ordering comes from the store completion
-// wait before the counter moves and from reading the slabs only after the
-// counters were seen.  No device-scope fence is needed, so no cache is
-// written back or invalidated per round.  The stage arithmetic of every owned
-// cell is that of the overlapped bands on the same inputs, so both paths give
-// identical results.
+// each region remain in registers and LDS.  After every HALO / 4 steps each
+// thread of a band publishes its cells of the HALO rows nearest the band's two
+// edges (state and compensation) to a slab in global memory and polls the
+// cells of its ring rows in the two neighbouring bands' slabs until they are
+// written: the slabs start empty (a reserved NaN bit pattern), and a taken
+// word is emptied again.  After the last window of a patch the bands instead
+// signal round counters and wait for their neighbours', so that no band
+// writes its final rows before both neighbours have loaded the patch.  Slab
+// words and counters are written and read only as relaxed device-scope
+// atomics, which are coherent across the device by themselves; the ordering
+// comes from each thread's store completion wait before it publishes again
+// and from the neighbours' dependence on each other's rows.  No device-scope
+// fence is needed, so no cache is written back or invalidated per round.  The
+// stage arithmetic of every owned cell is that of the overlapped bands on the
+// same inputs, so both paths give identical results.
 //
 // Co-residency: the grid never exceeds what the device holds at once (one
 // workgroup per CU), so every workgroup of a group is eventually running
@@ -73,33 +75,86 @@ __device__ __forceinline__ void publish_strip(float *__restrict__ mine, const fl
     }
 }
 
-// Ring rows of the strip: the lower ring from the southern neighbour's upper
-// slab rows, the upper ring from the northern neighbour's lower slab rows.
+// Bit pattern of a slab word that holds nothing yet: a NaN with every
+// payload bit set, which no arithmetic of the solve produces from finite data
+// (a NaN that arises in a solve has the default payload and passes through).
+constexpr uint32_t kSlabEmpty = 0xFFFFFFFFu;
+
+// Ring rows of the strip straight from the neighbours' slabs, polled until
+// every word of them has been written (none reads kSlabEmpty), then emptied
+// again for the round that next uses this slab parity.  A poll reads one word
+// of each neighbour until both are written, and all of the words only then,
+// so a band that waits long loads little.  At most spin_cap polls (0: give
+// up without polling); returns false when it gives up.  Strips without ring
+// rows return at once.
 template <int NN, int TH, int HALO, int R, int ST>
-__device__ __forceinline__ void take_strip(const float *__restrict__ fs, const float *__restrict__ fn,
-                                           float *__restrict__ lo, float (&wv)[R], float (&comp)[R]) {
+__device__ __forceinline__ bool take_strip_polled(uint32_t *__restrict__ fs, uint32_t *__restrict__ fn,
+                                                  float *__restrict__ lo, float (&wv)[R], float (&comp)[R],
+                                                  uint32_t spin_cap) {
+    constexpr bool kRing = ST * R < HALO || ST * R + R > TH + HALO;
+    if constexpr (!kRing) {
+        return true;
+    } else {
+        // the first ring word of each neighbour this strip reads (compile time)
+        constexpr int kFirstS = ST * R < HALO ? HALO + ST * R : -1;
+        constexpr int kFirstN = ST * R + R > TH + HALO ? (ST * R > TH + HALO ? ST * R : TH + HALO) - TH - HALO : -1;
+        uint32_t a[R], c[R];
+        for (uint32_t it = 0;; ++it) {
+            if (it >= spin_cap) return false;
+            if (it > 0) __builtin_amdgcn_s_sleep(1);
+            bool seen = true;
+            if constexpr (kFirstS >= 0)
+                seen = seen && __hip_atomic_load(fs + kFirstS * NN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kSlabEmpty;
+            if constexpr (kFirstN >= 0)
+                seen = seen && __hip_atomic_load(fn + kFirstN * NN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kSlabEmpty;
+            if (!seen) continue;
+            bool ready = true;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int yy = ST * R + r;
-        const float *src;
-        int q;
-        if (yy < HALO) {
-            src = fs;
-            q = HALO + yy;
-        } else if (yy >= TH + HALO) {
-            src = fn;
-            q = yy - TH - HALO;
-        } else {
-            continue;
+            for (int r = 0; r < R; ++r) {
+                const int yy = ST * R + r;
+                const uint32_t *src;
+                int q;
+                if (yy < HALO) {
+                    src = fs;
+                    q = HALO + yy;
+                } else if (yy >= TH + HALO) {
+                    src = fn;
+                    q = yy - TH - HALO;
+                } else {
+                    continue;
+                }
+                a[r] = __hip_atomic_load(src + q * NN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                c[r] = __hip_atomic_load(src + (2 * HALO + q) * NN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ready = ready && a[r] != kSlabEmpty && c[r] != kSlabEmpty;
+            }
+            if (ready) break;
         }
-        wv[r] = __hip_atomic_load(src + q * NN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        comp[r] = __hip_atomic_load(src + (2 * HALO + q) * NN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        lo[r * NN] = wv[r];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int yy = ST * R + r;
+            uint32_t *src;
+            int q;
+            if (yy < HALO) {
+                src = fs;
+                q = HALO + yy;
+            } else if (yy >= TH + HALO) {
+                src = fn;
+                q = yy - TH - HALO;
+            } else {
+                continue;
+            }
+            wv[r] = __uint_as_float(a[r]);
+            comp[r] = __uint_as_float(c[r]);
+            lo[r * NN] = wv[r];
+            __hip_atomic_store(src + q * NN, kSlabEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(src + (2 * HALO + q) * NN, kSlabEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return true;
     }
 }
 
-// The two above for the runtime strip index st (uniform within a
-// wavefront), dispatched to the compile-time strip ST = st.
+// The above for the runtime strip index st (uniform within a wavefront),
+// dispatched to the compile-time strip ST = st.
 template <int NN, int TH, int HALO, int R, int ST = 0>
 __device__ __forceinline__ void publish_rows(int st, float *__restrict__ mine, const float (&wv)[R],
                                              const float (&comp)[R]) {
@@ -112,14 +167,15 @@ __device__ __forceinline__ void publish_rows(int st, float *__restrict__ mine, c
 }
 
 template <int NN, int TH, int HALO, int R, int ST = 0>
-__device__ __forceinline__ void take_rows(int st, const float *__restrict__ fs, const float *__restrict__ fn,
-                                          float *__restrict__ lo, float (&wv)[R], float (&comp)[R]) {
+__device__ __forceinline__ bool take_rows_polled(int st, uint32_t *__restrict__ fs, uint32_t *__restrict__ fn,
+                                                 float *__restrict__ lo, float (&wv)[R], float (&comp)[R],
+                                                 uint32_t spin_cap) {
     if constexpr (ST < (TH + 2 * HALO) / R) {
         if (st == ST)
-            take_strip<NN, TH, HALO, R, ST>(fs, fn, lo, wv, comp);
-        else
-            take_rows<NN, TH, HALO, R, ST + 1>(st, fs, fn, lo, wv, comp);
+            return take_strip_polled<NN, TH, HALO, R, ST>(fs, fn, lo, wv, comp, spin_cap);
+        return take_rows_polled<NN, TH, HALO, R, ST + 1>(st, fs, fn, lo, wv, comp, spin_cap);
     }
+    return true;
 }
 
 template <int NN, int TH, int HALO, int R, int FIELD, bool FRAME, bool PIPE>
@@ -210,17 +266,36 @@ __device__ __forceinline__ void ring_body(float *__restrict__ buf, int *bad, con
                                                                  eW, nb, wv, comp, rr, nullptr, 0, gy0m, xlast);
                     __syncthreads();
                 }
-                // One round per window, also after the last one: a band
-                // writes its final rows only once both neighbours have
-                // loaded this patch, i.e. have signalled this round.
+                // One round per window.  Between windows each thread
+                // publishes its rows of the two published row sets and polls
+                // its ring rows in the neighbours' slabs until they are
+                // written, then empties them: one trip through memory, no
+                // counter.  Its stores (rows and emptied words) are complete
+                // before it publishes again, and a neighbour publishes into
+                // a slab parity only after taking this band's rows of the
+                // round in between, so an emptied word is never overwritten
+                // by the round it came from nor read again by it.
                 ++epoch;
                 const bool more = s < lim;
                 const int st = y0 / R;
                 if (more) {
                     float *mine = slab + ((int64_t)me * 2 + (epoch & 1)) * SLAB + x;
                     publish_rows<NN, TH, HALO, R>(st, mine, wv, comp);
+                    uint32_t *fs = reinterpret_cast<uint32_t *>(slab + ((int64_t)south * 2 + (epoch & 1)) * SLAB + x);
+                    uint32_t *fn = reinterpret_cast<uint32_t *>(slab + ((int64_t)north * 2 + (epoch & 1)) * SLAB + x);
+                    if (!take_rows_polled<NN, TH, HALO, R>(st, fs, fn, lo, wv, comp, spin_cap))
+                        __hip_atomic_store(bad, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __syncthreads();
+                    if (*bad) {
+                        dead = true;
+                        break;
+                    }
+                    continue;
                 }
-                // every wave's slab stores are complete before the counter moves
+                // After the last window: a band writes its final rows only
+                // once both neighbours have loaded this patch, i.e. have
+                // signalled this round through their counters.
                 __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
                 if (tid == 0) {
@@ -244,12 +319,6 @@ __device__ __forceinline__ void ring_body(float *__restrict__ buf, int *bad, con
                 if (*bad) {
                     dead = true;
                     break;
-                }
-                if (more) {
-                    const float *fs = slab + ((int64_t)south * 2 + (epoch & 1)) * SLAB + x;
-                    const float *fn = slab + ((int64_t)north * 2 + (epoch & 1)) * SLAB + x;
-                    take_rows<NN, TH, HALO, R>(st, fs, fn, lo, wv, comp);
-                    __syncthreads();
                 }
             }
         }
@@ -305,6 +374,12 @@ __global__ void k_zero_rounds(int32_t *flags, int n) {
     if (i < n) flags[i] = 0;
 }
 
+// Every slab word empty (kSlabEmpty) before the bands start.
+__global__ void k_empty_slabs(uint32_t *slab, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        slab[i] = kSlabEmpty;
+}
+
 constexpr int kRingNN = 256, kRingTH = 32, kRingHalo = 8, kRingR = 16;
 
 template <bool FRAME, bool PIPE>
@@ -342,6 +417,9 @@ int launch_ring_solve(const shmm_domain *d_dom, const int32_t *d_list, int32_t n
     int32_t *flags = (int32_t *)(slab + (size_t)groups * S::PER * 2 * S::SLAB);
     const int nflags = (int)(groups * S::PER);
     hipLaunchKernelGGL(k_zero_rounds, dim3((unsigned)((nflags + 255) / 256)), dim3(256), 0, s, flags, nflags);
+    SHMM_HIP_CHECK(hipGetLastError());
+    const int64_t slab_words = (int64_t)groups * S::PER * 2 * S::SLAB;
+    hipLaunchKernelGGL(k_empty_slabs, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint32_t *>(slab), slab_words);
     SHMM_HIP_CHECK(hipGetLastError());
     const dim3 grid((unsigned)(groups * S::PER));
     if (frame && pipe)
