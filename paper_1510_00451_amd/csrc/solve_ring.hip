@@ -271,21 +271,23 @@ __device__ __forceinline__ void ring_body(float *__restrict__ buf, int *bad, con
                 // its ring rows in the neighbours' slabs until they are
                 // written, then empties them: one trip through memory, no
                 // counter.  Its stores (rows and emptied words) are complete
-                // before it publishes again, and a neighbour publishes into
-                // a slab parity only after taking this band's rows of the
-                // round in between, so an emptied word is never overwritten
-                // by the round it came from nor read again by it.
+                // before it publishes again (the wait sits right before the
+                // publication, so the emptying stores drain during the
+                // window's arithmetic), and a neighbour publishes into a slab
+                // parity only after taking this band's rows of the round in
+                // between, so an emptied word is never overwritten by the
+                // round it came from nor read again by it.
                 ++epoch;
                 const bool more = s < lim;
                 const int st = y0 / R;
                 if (more) {
+                    __builtin_amdgcn_s_waitcnt(0);
                     float *mine = slab + ((int64_t)me * 2 + (epoch & 1)) * SLAB + x;
                     publish_rows<NN, TH, HALO, R>(st, mine, wv, comp);
                     uint32_t *fs = reinterpret_cast<uint32_t *>(slab + ((int64_t)south * 2 + (epoch & 1)) * SLAB + x);
                     uint32_t *fn = reinterpret_cast<uint32_t *>(slab + ((int64_t)north * 2 + (epoch & 1)) * SLAB + x);
                     if (!take_rows_polled<NN, TH, HALO, R>(st, fs, fn, lo, wv, comp, spin_cap))
                         __hip_atomic_store(bad, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    __builtin_amdgcn_s_waitcnt(0);
                     __syncthreads();
                     if (*bad) {
                         dead = true;
