@@ -18,7 +18,8 @@
 //   its face coefficients in registers.  HBM is touched only to load the
 //   patch and to store the final state.  Two arithmetic forms: the split form
 //   above (k_solve_resident) and the coefficient form (k_solve_resident_e,
-//   the default), plus a row-per-wavefront variant (k_solve_rows).
+//   the default, with the stage input read a row ahead at 64^2 and 128^2),
+//   plus a row-per-wavefront variant (k_solve_rows).
 // * n = 256: full-width bands of rows plus a ring of redundant cells, kept
 //   resident for all steps and exchanging their rings with the neighbouring
 //   bands (k_solve_ring in solve_ring.hip, the default), or relaunched every
