@@ -340,7 +340,10 @@ int shmm_level_chain(shmm_ctx *ctx, int64_t first, int64_t count, int32_t mode,
  * that gives up writes NaN into its rows of the current and every later patch
  * of the call without waiting again, so every kernel still exits and the
  * failure shows as SHMM_DOM_NONFINITE (shmm_local_solve_batch).  For callers
- * that must bound a solve's wall time, and to test that path. */
+ * that must bound a solve's wall time, and to test that path.  An empty slab
+ * word is the NaN pattern 0xFFFFFFFF: a non-finite input that puts exactly
+ * that pattern into a ring row makes the neighbour's wait run to this limit
+ * before its (already non-finite) result comes back. */
 #define SHMM_TUNE_RING_SPIN_CAP (-1)
 int shmm_ctx_tune(shmm_ctx *ctx, int32_t key, int32_t value);
 

@@ -78,6 +78,9 @@ __device__ __forceinline__ void publish_strip(float *__restrict__ mine, const fl
 // Bit pattern of a slab word that holds nothing yet: a NaN with every
 // payload bit set, which no arithmetic of the solve produces from finite data
 // (a NaN that arises in a solve has the default payload and passes through).
+// Only a non-finite input carrying this very pattern can publish it; the
+// neighbour's wait then runs to the spin limit and gives up, which ends in
+// the same NaN corrector and status bit that such an input gives anyway.
 constexpr uint32_t kSlabEmpty = 0xFFFFFFFFu;
 
 // Ring rows of the strip straight from the neighbours' slabs, polled until
