@@ -6,7 +6,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import List, Sequence, Tuple
+from typing import List, Tuple
 
 import numpy as np
 

@@ -9,7 +9,7 @@ the phase's base diffusivities (24 bytes per domain) on the host.
 from __future__ import annotations
 
 from dataclasses import dataclass
-from typing import List, Optional
+from typing import Optional
 
 import numpy as np
 

@@ -4,7 +4,6 @@ No GPU compute is called here."""
 import os
 import re
 
-import numpy as np
 import pytest
 
 import flowgen

@@ -4,7 +4,6 @@ Tolerances (floating point): effective diffusivity 1e-5 relative, macro field
 1e-6 relative L2 in FP32 and 1e-12 in FP64; band-filtered fields 2e-6 of their
 scale (FP32 FFT); line energies 1e-11 (FP64).  Integers bit-exact.
 """
-import math
 import sys
 
 import numpy as np

@@ -2,7 +2,6 @@
 allocating one (shmm_macro_step) through the C ABI: two calls in a row, the
 second on a smaller grid, bit-identical results; a grid above the static
 buffer's limit is refused with SHMM_ERANGE and leaves its field untouched."""
-import math
 
 import numpy as np
 import pytest
