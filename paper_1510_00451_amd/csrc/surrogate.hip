@@ -21,8 +21,6 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {   // round to nearest, ti
     return (uint16_t)(u >> 16);
 }
 
-__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
 
 __device__ __forceinline__ float gelu_grad(float z) {
