@@ -275,10 +275,6 @@ class Adam:
             p -= a * (m / c1) / (np.sqrt(v / c2) + self.eps)
 
 
-def cosine_lr(step: int, total: int, lr0: float) -> float:
-    return 0.5 * lr0 * (1.0 + math.cos(math.pi * min(step, total) / total))
-
-
 # ---------------------------------------------------------------- gate
 
 def ensemble_gate(K_members: np.ndarray, features: np.ndarray, lo: np.ndarray, hi: np.ndarray,

@@ -19,6 +19,25 @@ def _mode(n, a, b, A, B, quadrature=False):
     return vx, vy
 
 
+def test_octave_bins_at_their_edges():
+    """Bin b holds 2^b <= |k| < 2^(b+1): hand values on the edges (|k| = 2^b
+    exactly, the largest |k| of a 256^2 patch, the first |k| past bin 7), and
+    every (k1, k2) of [-300, 300]^2 against a search over b in integers."""
+    hand = {(0, 0): -1, (1, 0): 0, (0, -1): 0, (1, 1): 0, (2, 0): 1, (-1, 2): 1, (3, 3): 2,
+            (4, 0): 2, (0, 8): 3, (127, 0): 6, (128, 0): 7, (-128, -128): 7, (181, 181): 7,
+            (255, 0): 7, (256, 0): -1, (182, 181): -1}
+    for (k1, k2), b in hand.items():
+        assert S.bin_of(k1, k2) == b, (k1, k2)
+    for k1 in range(-300, 301):
+        for k2 in range(-300, 301):
+            q2 = k1 * k1 + k2 * k2
+            want = -1
+            for b in range(S.N_RADIAL):
+                if 4 ** b <= q2 < 4 ** (b + 1):
+                    want = b
+            assert S.bin_of(k1, k2) == want, (k1, k2)
+
+
 def test_features_single_mode_closed_form():
     """One Fourier mode in phase in both components: every channel by hand."""
     n, N = 32, 128
@@ -225,6 +244,25 @@ def test_gate_flags():
     assert list(flag) == [False, True] and spread[1] > 0.005
     K, flag, spread = S.ensemble_gate(Km, f2, np.zeros(2), np.ones(2), 0.05)
     assert list(flag) == [False, False]
+    # members that agree: only the training range decides, on either side of it
+    same = np.array([[[1.0, 0.0, 1.0]] * 3] * 2)
+    f3 = np.array([[0.5, 1.5], [-0.5, 0.5], [0.0, 1.0]])
+    _, flag, spread = S.ensemble_gate(same, f3, np.zeros(2), np.ones(2), 0.005)
+    assert list(flag) == [True, True, False] and not spread.any()
+
+
+def test_gate_spread_is_the_largest_member_deviation():
+    """Three members with K11 = 1, 1, 1.03 (K12 = 0, K22 = 1): the mean is
+    1.01, the deviations 0.01, 0.01, 0.02, so the spread is 0.02 over
+    |K_mean| = sqrt(1.01^2 + 1) (their mean, 0.0133, would pass tau = 0.012)."""
+    Km = np.array([[[1.0, 0.0, 1.0]], [[1.0, 0.0, 1.0]], [[1.03, 0.0, 1.0]]])
+    f = np.full((1, 2), 0.5)
+    K, flag, spread = S.ensemble_gate(Km, f, np.zeros(2), np.ones(2), 0.012)
+    assert abs(spread[0] - 0.02 / math.sqrt(1.01 ** 2 + 1.0)) <= 1e-12
+    np.testing.assert_allclose(K[0], [1.01, 0.0, 1.0], rtol=0, atol=1e-15)
+    assert list(flag) == [True]
+    _, flag, _ = S.ensemble_gate(Km, f, np.zeros(2), np.ones(2), 0.015)
+    assert list(flag) == [False]
 
 
 def test_gate_flags_large_enhancement():
