@@ -445,6 +445,48 @@ def test_roots_compute_exactly_the_selected_chains():
 
 # ---------------------------------------------------------------- macro
 
+def test_coarse_base_does_not_depend_on_how_its_children_are_numbered():
+    """A level-1 lattice of 2 x 2 centres under one level-0 centre whose own
+    bands are empty: the coarse base, hence K_total, is built from the four
+    children's results.  Translating the flow by one child spacing (pi in x)
+    permutes the children, so K_total must not change although the
+    children's results differ."""
+    kmax, kap = 6, 0.05
+    ph = np.zeros((2 * kmax + 1, 2 * kmax + 1), complex)
+    flowgen.add_cellular(ph, kmax, 4, 4, 0.5)
+    flowgen.add_cellular(ph, kmax, 3, 4, 0.4, 0.3, 0.7)
+    shifted = ph * ((-1.0) ** np.arange(-kmax, kmax + 1))[None, :]       # psi(x + pi, y)
+
+    def run(spec):
+        q = flowgen.Problem(kappa=kap, kmax=kmax, psi_hat=spec, thresh=[2], n_cells=[16, 16],
+                            n_global=[16, 32], lattice=[1, 2])
+        return oracle.run_hierarchy(q)
+
+    a, b = run(ph), run(shifted)
+    kids = [j for j, d in enumerate(a.domains) if d.level == 1]
+    assert len(kids) == 4
+    assert np.max(np.abs(a.R[kids[0]] - a.R[kids[1]])) >= 1e-3 * np.max(np.abs(a.R[kids[0]]))
+    np.testing.assert_allclose(b.K_total(), a.K_total(), rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("c", [0.0, -0.4, 0.4])
+def test_macro_plan_is_the_fewest_stable_steps(c):
+    """The macro grid's checkerboard is an eigenvector of its diffusion with
+    rate 4 (K11 + K22) / h^2 whatever K12 (the cross differences vanish on
+    it).  With dt_frac = 1 one planned step keeps its amplitude within RK4's
+    stability region, and for an isotropic K one step fewer over the same
+    time does not."""
+    N, kap, T = 8, 0.05, 100.0
+    K = np.array([kap, c * kap, kap])
+    cb = np.fromfunction(lambda j, i: (-1.0) ** (i + j), (N, N))
+    dt, ns = oracle.macro_plan(N, np.tile(K, (N * N, 1)), 0.0, 1.0, T)
+    g = oracle.macro_run(N, None, None, K, cb, dt, 1) / cb
+    assert np.ptp(g) <= 1e-12 and abs(g[0, 0]) <= 1.0
+    if c == 0.0:
+        g = oracle.macro_run(N, None, None, K, cb, T / (ns - 1), 1) / cb
+        assert abs(g[0, 0]) > 1.0
+
+
 def test_macro_rk4_matches_fourier_closed_form():
     """v = 0, constant K: each Fourier mode is multiplied by R(dt mu_k)^nsteps,
     R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24 (classic RK4), mu_k the symbol of the
@@ -630,6 +672,37 @@ def test_quasi_stationary_stop_keeps_k_within_its_bound():
         assert taken < 0.6 * ns6, (d, taken, ns6)
 
 
+@pytest.mark.parametrize("delta", [1e-6, 3e-7])
+def test_quasi_stationary_stop_chunk_of_a_single_mode_shear(delta):
+    """v = (0, V sin x) on the whole period: the second corrector is driven by
+    the single lowest mode, which decays at exactly the Poincare rate
+    mu = kappa 4 sin^2(pi / n) / h^2 of the isotropic base, so w_2(t) =
+    (1 - e^(-mu t)) chi with chi = f_2 / mu, and the remaining error of K22
+    is e^(-mu t) <f_2 chi> (the Cauchy-Schwarz bound is an equality for one
+    mode).  The stop must come at the first chunk of ceil(nsteps / chunks)
+    steps where that error is at most delta times K22(t), no earlier and no
+    later."""
+    n, kap, V = 16, 0.05, 1.0
+    h = 2 * np.pi / n
+    x = np.arange(n) * h
+    psi = np.tile(-V * np.cos(x), (n, 1))
+    vx, vy, f1, f2 = oracle.staggered(psi, h)
+    assert not np.any(vx) and not np.any(f1)
+    mu = kap * 4 * math.sin(math.pi / n) ** 2 / h ** 2
+    dt, nsteps, chunks = 0.2, 3301, 32
+    C = 104                                            # ceil(3301 / 32)
+    fc = float(np.mean(f2 * f2)) / mu                  # <f_2 chi>
+
+    def ratio(c):                                      # remaining error over delta K22 after c chunks
+        e = math.exp(-mu * c * C * dt)
+        return e * fc / (delta * (kap + (1 - e) * fc))
+
+    c = next(c for c in range(1, nsteps) if ratio(c) <= 1.0)
+    assert c * C < nsteps and ratio(c) < 0.9 and ratio(c - 1) > 1.1     # clear of the threshold
+    w, taken = oracle.local_solve_adaptive(n, h, vx, vy, f1, f2, [kap, 0.0, kap], dt, nsteps, delta, chunks)
+    assert taken == c * C
+
+
 # ---------------------------------------------------------------- Section 4, Tests 2 and 3
 
 def _paper_gap(test):
@@ -756,6 +829,77 @@ def test_step_plan_decay_is_tight_for_pure_diffusion():
     ev = np.linalg.eigvals(_dense(z, z, [kap, 0.0, kap], h, n))
     slow = np.sort(-ev.real)[1]
     assert abs(np.exp(-slow * dt * ns) / delta - 1) <= 1e-9
+
+
+def _rk4_gain(z):
+    """|R(z)| of classic RK4, R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24."""
+    return np.abs(1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24)
+
+
+@pytest.mark.parametrize("delta", [1e-6, 1e-3])
+def test_step_plan_is_the_fewest_stable_steps_for_pure_diffusion(delta):
+    """dt_frac = 1, no flow, isotropic base: the fastest mode (the
+    checkerboard, 8 kappa / h^2) is where the plan's diffusion bound is exact,
+    so the planned step keeps it inside RK4's real stability interval
+    (about -2.785) and one step fewer over the same time leaves it.  A cross
+    term of either sign leaves the fastest mode where it is, and the step
+    stays stable."""
+    n, kap = 8, 0.05
+    h = 2 * np.pi / n
+    z0 = np.zeros((n, n))
+    fast = 8 * kap / h ** 2
+    dt, ns = oracle.plan_steps(n, h, [kap, 0.0, kap], oracle.advection_bound(z0, z0), 1.0, delta)
+    ev = np.linalg.eigvals(_dense(z0, z0, [kap, 0.0, kap], h, n))
+    assert abs(np.max(np.abs(ev)) - fast) <= 1e-12 * fast
+    assert _rk4_gain(-dt * fast) <= 1.0
+    assert ns >= 2 and _rk4_gain(-dt * ns / (ns - 1) * fast) > 1.0
+    for c in (-0.4, 0.4, -0.9):
+        K = [kap, c * kap, kap]
+        dt, ns = oracle.plan_steps(n, h, K, 0.0, 1.0, delta)
+        ev = np.linalg.eigvals(_dense(z0, z0, K, h, n))
+        assert abs(np.max(np.abs(ev)) - fast) <= 1e-12 * fast, c
+        assert np.max(_rk4_gain(dt * ev)) <= 1 + 1e-12, c
+
+
+def test_step_plan_meets_the_imaginary_stability_edge_for_a_moving_row():
+    """One row of cells moving along x at speed U, everything else at rest,
+    and a negligible base: the advection eigenvalues are i U sin(theta) / h,
+    so the fastest is U / h, which the advection bound reaches.  With
+    dt_frac = 1 the step puts it on RK4's imaginary stability edge
+    (2 sqrt 2, where |R| = 1) to within the plan's rounded constant."""
+    n, U = 8, 0.8
+    h = 2 * np.pi / n
+    vx = np.zeros((n, n))
+    vx[3, :] = U
+    vy = np.zeros((n, n))
+    K = [1e-9, 0.0, 1e-9]
+    dt, ns = oracle.plan_steps(n, h, K, oracle.advection_bound(vx, vy), 1.0, 1e-6)
+    ev = np.linalg.eigvals(_dense(vx, vy, K, h, n))
+    top = ev[np.argmax(np.abs(ev))]
+    assert abs(abs(top) - U / h) <= 1e-9 * U / h
+    assert 0.995 <= _rk4_gain(dt * top) <= 1.0
+    assert np.max(_rk4_gain(dt * ev)) <= 1 + 1e-12
+
+
+def test_macro_diffusivity_uses_the_level_base():
+    """A shear v = (0, V sin 4x) in level 0's off-21 band and a cellular mode
+    in level 1's diagonal band: the finer level raises level 0's base K_net
+    above K_in = kappa I, and the macro diffusivity is the shear's Taylor
+    value on that base, K22 = K_b22 + V^2 / (2 k^2 K_b11), with K_b11 and
+    K_b12 passing through."""
+    kmax, k, V, kap = 6, 4, 1.0, 0.05
+    ph = np.zeros((2 * kmax + 1, 2 * kmax + 1), complex)
+    flowgen.add_cos_x(ph, kmax, k, -V / k)
+    flowgen.add_cellular(ph, kmax, 6, 6, 0.3)
+    p = flowgen.Problem(kappa=kap, kmax=kmax, psi_hat=ph, thresh=[2], n_cells=[32, 32], n_global=[32, 32],
+                        lattice=[1, 1])
+    r = oracle.run_hierarchy(p)
+    i = next(j for j, d in enumerate(r.domains) if d.level == 0)
+    Kb = r.K_base[i]
+    assert np.max(np.abs(Kb - r.K_in[i])) >= 0.1 * kap          # the base is not K_in
+    Km = oracle.macro_diffusivity(r, i)
+    assert abs(Km[0] - Kb[0]) <= 1e-16 and abs(Km[1] - Kb[1]) <= 1e-16
+    assert abs(Km[2] - (Kb[2] + V * V / (2 * k * k * Kb[0]))) <= 1e-13 * Km[2]
 
 
 def test_macro_diffusivity_of_a_resolved_shear_is_the_taylor_value():
