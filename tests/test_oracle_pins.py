@@ -487,6 +487,74 @@ def test_macro_plan_is_the_fewest_stable_steps(c):
         assert abs(g[0, 0]) > 1.0
 
 
+def test_macro_step_with_a_k_field_commutes_with_the_grid_symmetries():
+    """A random SPD K field at cell centres: the macro step must not prefer a
+    side.  Reflecting the grid in x or in y (with K12 negated) or transposing
+    it (with K11 and K22 exchanged) maps the evolved field to the evolved
+    reflected or transposed field, which holds when every face takes the
+    mean of the two cells it separates."""
+    rng = np.random.default_rng(4)
+    N, dt, ns = 12, 0.05, 7
+    Kc = np.zeros((N, N, 3))
+    Kc[..., 0] = rng.uniform(0.02, 0.2, (N, N))
+    Kc[..., 2] = rng.uniform(0.02, 0.2, (N, N))
+    Kc[..., 1] = 0.3 * np.sqrt(Kc[..., 0] * Kc[..., 2]) * rng.uniform(-1, 1, (N, N))
+    u0 = rng.standard_normal((N, N))
+
+    def run(K, u):
+        return oracle.macro_run(N, None, None, np.ascontiguousarray(K).reshape(-1, 3), np.ascontiguousarray(u),
+                                dt, ns)
+
+    base = run(Kc, u0)
+    Kx = Kc[:, ::-1].copy()
+    Kx[..., 1] *= -1
+    assert np.max(np.abs(run(Kx, u0[:, ::-1]) - base[:, ::-1])) <= 1e-14
+    Ky = Kc[::-1].copy()
+    Ky[..., 1] *= -1
+    assert np.max(np.abs(run(Ky, u0[::-1]) - base[::-1])) <= 1e-14
+    Kt = Kc.transpose(1, 0, 2)[..., ::-1]
+    assert np.max(np.abs(run(Kt, u0.T) - base.T)) <= 1e-14
+
+
+def test_macro_dirichlet_operator_is_second_order_up_to_the_walls():
+    """u = g0 + (g1 - g0) x / 2 pi + A sin(x / 2) sin y meets both wall values
+    and varies along the walls; with an anisotropic K (K12 != 0) one tiny
+    step gives the discrete operator, which must approach
+    K11 u_xx + 2 K12 u_xy + K22 u_yy at second order in every column, the
+    wall columns included (their tangential differences use ghost values
+    continued linearly through the wall)."""
+    g0, g1, A = 0.3, 1.1, 0.7
+    K = np.array([0.4, 0.15, 0.25])
+    errs = []
+    for N in (16, 32, 64):
+        h = 2 * np.pi / N
+        c = (np.arange(N) + 0.5) * h
+        X, Y = np.meshgrid(c, c, indexing="xy")
+        u0 = g0 + (g1 - g0) * X / (2 * np.pi) + A * np.sin(X / 2) * np.sin(Y)
+        exact = (K[0] * (-A / 4) * np.sin(X / 2) * np.sin(Y) + 2 * K[1] * (A / 2) * np.cos(X / 2) * np.cos(Y)
+                 + K[2] * (-A) * np.sin(X / 2) * np.sin(Y))
+        dt = 1e-6
+        u1 = oracle.macro_run(N, None, None, K, u0, dt, 1, dirichlet_x=(g0, g1))
+        errs.append(np.max(np.abs((u1 - u0) / dt - exact)))
+    assert errs[0] <= 1e-2
+    assert errs[1] <= 0.3 * errs[0] and errs[2] <= 0.3 * errs[1], errs
+
+
+def test_macro_dirichlet_time_stepping_is_fourth_order():
+    """Halving dt twice over the same time: the successive differences of
+    the Dirichlet macro solution shrink by about 2^4 (classic RK4)."""
+    g0, g1 = 0.3, 1.1
+    K = np.array([0.4, 0.15, 0.25])
+    N, T = 16, 2.0
+    h = 2 * np.pi / N
+    c = (np.arange(N) + 0.5) * h
+    X, Y = np.meshgrid(c, c, indexing="xy")
+    u0 = g0 + (g1 - g0) * X / (2 * np.pi) + 0.7 * np.sin(X / 2) * np.sin(Y) + 0.3 * np.sin(X) * np.cos(2 * Y)
+    u = [oracle.macro_run(N, None, None, K, u0, T / m, m, dirichlet_x=(g0, g1)) for m in (40, 80, 160)]
+    ratio = np.max(np.abs(u[0] - u[1])) / np.max(np.abs(u[1] - u[2]))
+    assert 12.0 <= ratio <= 20.0, ratio
+
+
 def test_macro_rk4_matches_fourier_closed_form():
     """v = 0, constant K: each Fourier mode is multiplied by R(dt mu_k)^nsteps,
     R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24 (classic RK4), mu_k the symbol of the
