@@ -71,3 +71,17 @@ def test_build_levels_rejects_bad_geometry():
     r.kappa = 0.0
     with pytest.raises(abi.ShmmError):
         abi.shmm_build_levels(r)
+    # the rest of the documented malformed geometry, one field at a time
+    bad = [("thresh", lambda t: [t.thresh[1], t.thresh[0]] + list(t.thresh[2:])),   # edges not increasing
+           ("dt_frac", lambda t: 0.0), ("dt_frac", lambda t: 1.5),
+           ("delta", lambda t: 0.0), ("delta", lambda t: 1.0),
+           ("n_global", lambda t: [t.n_global[0] + 1] + list(t.n_global[1:]))]          # origin off the grid
+    for field, value in bad:
+        t = flowgen.config_four_level_cellular(n=32, lattice=4)
+        setattr(t, field, value(t))
+        with pytest.raises(abi.ShmmError) as e:
+            abi.shmm_build_levels(t)
+        assert e.value.code == abi.SHMM_EINVAL, field
+        if field in ("thresh", "n_global"):        # geometry the oracle's table refuses too
+            with pytest.raises(oracle.BookkeepingError):
+                oracle.domain_table(t)
