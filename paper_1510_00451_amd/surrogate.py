@@ -416,9 +416,11 @@ def calibrate_gate(ens: Ensemble, held: Dataset, lo, hi, target: float = 0.01, q
     """Spread threshold tau and enhancement limit emax of the gate: the pair
     that accepts the most held-out patches while the `quantile` of their
     relative Frobenius error stays within `target`.  Ties go to the larger
-    thresholds.  Returns (tau, emax, accepted fraction)."""
+    thresholds.  Returns (tau, emax, accepted fraction); when no pair keeps
+    the quantile within `target`, (-1, -1, 0): thresholds that flag every
+    patch, so the plain path answers everywhere."""
     err, enh, spread, inside = gate_inputs(ens, held, lo, hi)
-    best = (taus[0], emaxes[0], -1.0)
+    best = (-1.0, -1.0, -1.0)
     for tau in taus:
         for emax in emaxes:
             acc = inside & (spread <= tau) & (enh <= emax)
@@ -427,4 +429,4 @@ def calibrate_gate(ens: Ensemble, held: Dataset, lo, hi, target: float = 0.01, q
             frac = float(acc.mean())
             if frac >= best[2]:
                 best = (tau, emax, frac)
-    return best
+    return best if best[2] >= 0 else (-1.0, -1.0, 0.0)
